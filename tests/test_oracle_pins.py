@@ -1,0 +1,327 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+a library Philox, the NaCl Madelung constant, closed forms, finite differences
+of the energy, Coulomb homogeneity, and the Poisson form of the normaliser."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ewald, rbe, realspace, sampler
+from oracle.philox import philox4x64, u01
+from paper_2110_14362_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [l.strip() for l in f if l.strip() and not l.startswith("#")]
+
+
+# ---------------------------------------------------------------- Philox
+
+@pytest.mark.parametrize("key,ctr", [((0x1234, 0), (0, 0, 0, 0)),
+                                     ((2**64 - 1, 7), (5, 2**64 - 1, 3, 9)),
+                                     ((0xDEADBEEF, 0xC0FFEE), (123456789, 0, 0x6B73616D, 0))])
+def test_philox_matches_numpy_library(key, ctr):
+    # numpy's Philox4x64-10 bumps the 256-bit counter before each block
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                          counter=np.array(ctr, dtype=np.uint64))
+    ref = [int(v) for v in bg.random_raw(8)]
+    c = list(ctr)
+    for blk in range(2):
+        # 256-bit increment with carry
+        for w in range(4):
+            c[w] = (c[w] + 1) & (2**64 - 1)
+            if c[w] != 0:
+                break
+        assert list(philox4x64(c, key)) == ref[4 * blk:4 * blk + 4]
+
+
+def test_u01_range():
+    assert u01(0) == 0.0
+    assert u01(2**64 - 1) == 1.0 - 2.0 ** -53
+
+
+# ---------------------------------------------------------------- Ewald
+
+@pytest.mark.parametrize("g", [1.5, 2.5, 4.0])
+def test_madelung_nacl(g):
+    M_ref = float(read_golden("nacl_madelung.txt")[0])
+    s = workloads.nacl_crystal(cells=1, a=1.0)
+    h = np.diag(s["box"])
+    res = ewald.ewald_total(s["pos"], s["q"], h, g * g, rc=6.0 / g)
+    N = len(s["q"])
+    M = -res["energy"] * s["box"][0] / N
+    assert abs(M - M_ref) < 1e-9
+    assert np.abs(res["forces"]).max() < 1e-12       # every ion sits at a symmetry centre
+
+
+def test_madelung_supercell_and_shift():
+    # 2x2x2 supercell, rigidly shifted: same constant, zero forces
+    M_ref = float(read_golden("nacl_madelung.txt")[0])
+    s = workloads.nacl_crystal(cells=2, a=1.0)
+    pos = np.mod(s["pos"] + np.array([0.37, 0.11, 0.93]), s["box"])
+    res = ewald.ewald_total(pos, s["q"], np.diag(s["box"]), 1.2 ** 2, rc=6.0 / 1.2)
+    M = -res["energy"] * 2.0 / len(s["q"])
+    assert abs(M - M_ref) < 1e-9
+    assert np.abs(res["forces"]).max() < 1e-10
+
+
+def _converged(alpha, box):
+    # real-space cutoff with erfc < 1e-15 of the pair term
+    return 6.0 / math.sqrt(alpha)
+
+
+def test_alpha_independence_total_energy():
+    s = workloads.random_neutral(48, (5.0, 5.5, 6.0), seed=11)
+    h = np.diag(s["box"])
+    Es = []
+    for g in (0.9, 1.3, 1.8):
+        res = ewald.ewald_total(s["pos"], s["q"], h, g * g, rc=_converged(g * g, s["box"]))
+        Es.append(res["energy"])
+    assert abs(Es[1] - Es[0]) < 1e-10 * abs(Es[0])
+    assert abs(Es[2] - Es[0]) < 1e-10 * abs(Es[0])
+
+
+def test_forces_are_minus_gradient():
+    s = workloads.random_neutral(10, (4.0, 4.0, 4.0), seed=5)
+    h = np.diag(s["box"])
+    a, rc = 1.2 ** 2, 6.0 / 1.2
+    F = ewald.ewald_total(s["pos"], s["q"], h, a, rc)["forces"]
+    eps = 1e-5
+    for i in (0, 3, 7):
+        for c in range(3):
+            rp = s["pos"].copy(); rp[i, c] += eps
+            rm = s["pos"].copy(); rm[i, c] -= eps
+            fd = -(ewald.ewald_total(rp, s["q"], h, a, rc)["energy"]
+                   - ewald.ewald_total(rm, s["q"], h, a, rc)["energy"]) / (2 * eps)
+            assert abs(fd - F[i, c]) < 1e-7 * max(1.0, abs(F[i, c]))
+    assert np.abs(F.sum(axis=0)).max() < 1e-10
+
+
+def _energy_deformed(s, h, E, eps, a, rc):
+    # deform the cell h -> (I + eps E) h at fixed reduced coordinates
+    D = np.eye(3) + eps * E
+    h2 = D @ h
+    sred = np.linalg.solve(h, s["pos"].T).T
+    r2 = (h2 @ sred.T).T
+    return ewald.ewald_total(r2, s["q"], h2, a, rc)["energy"]
+
+
+@pytest.mark.parametrize("ab", [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)])
+def test_virial_is_minus_cell_derivative(ab):
+    # W_ab = -dU/deps for h -> (I + eps E_ab) h at fixed s (appendix C
+    # definition of the pressure tensor); off-diagonal entries need the
+    # triclinic cell the shear produces
+    s = workloads.random_neutral(12, (4.0, 4.5, 5.0), seed=9)
+    h = np.diag(s["box"])
+    a, rc = 1.1 ** 2, 6.5 / 1.1
+    W = ewald.ewald_total(s["pos"], s["q"], h, a, rc)["virial"]
+    E = np.zeros((3, 3)); E[ab] = 1.0
+    eps = 1e-5
+    fd = -(_energy_deformed(s, h, E, eps, a, rc) - _energy_deformed(s, h, E, -eps, a, rc)) / (2 * eps)
+    assert abs(fd - W[ab]) < 2e-7 * max(1.0, np.abs(W).max())
+    assert abs(W[ab] - W[ab[::-1]]) < 1e-12 * max(1.0, np.abs(W).max())
+
+
+def test_kspace_virial_is_minus_volume_derivative_of_U1():
+    # P2 of eq. (pressurecubic) = -dU1/dV at fixed s, cubic box
+    s = workloads.random_neutral(16, (5.0, 5.0, 5.0), seed=21)
+    a = 0.8 ** 2
+    def U1(L):
+        r = s["pos"] / 5.0 * L
+        m, w = ewald.ewald_modes(np.eye(3) * L, a)
+        return ewald.kspace_weighted(r, s["q"], np.eye(3) * L, a, m, w)["energy"]
+    m, w = ewald.ewald_modes(np.eye(3) * 5.0, a)
+    W1 = ewald.kspace_weighted(s["pos"], s["q"], np.eye(3) * 5.0, a, m, w)["virial"]
+    P2 = np.trace(W1) / (3 * 125.0)
+    dV = 1e-4
+    Lp, Lm = (125.0 + dV) ** (1 / 3), (125.0 - dV) ** (1 / 3)
+    fd = -(U1(Lp) - U1(Lm)) / (2 * dV)
+    assert abs(fd - P2) < 1e-8 * max(1.0, abs(P2))
+
+
+def test_coulomb_homogeneity_trace_equals_energy():
+    # U(lambda h, fixed s) = U/lambda  =>  tr W = U for the converged total
+    s = workloads.random_neutral(20, (4.0, 5.0, 6.0), seed=3)
+    res = ewald.ewald_total(s["pos"], s["q"], np.diag(s["box"]), 1.0, 6.5)
+    assert abs(np.trace(res["virial"]) - res["energy"]) < 1e-10 * abs(res["energy"])
+
+
+def test_nearest_image_realspace_matches_all_images():
+    # with rc <= l/2 the nearest-image cutoff sum is the image sum
+    s = workloads.random_neutral(40, (8.0, 8.0, 9.0), seed=4)
+    a, rc = 0.9 ** 2, 3.9
+    ri = ewald.realspace_images(s["pos"], s["q"], np.diag(s["box"]), a, rc)
+    rn = realspace.realspace_nearest(s["pos"], s["q"], s["box"], a, rc)
+    assert abs(ri["energy"] - rn["energy"]) < 1e-12 * abs(ri["energy"])
+    assert np.abs(ri["forces"] - rn["forces"]).max() < 1e-12
+    assert np.abs(ri["virial"] - rn["virial"]).max() < 1e-12
+    rows = np.array([0, 5, 17, 39])
+    rr = realspace.realspace_nearest(s["pos"], s["q"], s["box"], a, rc, rows=rows)
+    assert np.abs(rr["forces"] - rn["forces"][rows]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- sampler
+
+@pytest.mark.parametrize("alpha,box", [(0.09, (20.0, 20.0, 20.0)),
+                                       (0.09, (66.88, 66.88, 66.88)),
+                                       (0.09, (80.0, 80.0, 100.0)),
+                                       (0.5, (3.0, 4.0, 5.0))])
+def test_normaliser_matches_poisson_form(alpha, box):
+    tb = sampler.box_tables(alpha, box)
+    S_p = sampler.normaliser_poisson(alpha, box)
+    assert abs(tb["S"] - S_p) < 1e-12 * S_p
+    # and the plain lattice sum over k != 0 (eq. S)
+    m, w = ewald.ewald_modes(np.diag(box), alpha, tol=1e-18)
+    assert abs(w.sum() - S_p) < 1e-11 * S_p
+
+
+def test_sampler_never_draws_zero_and_is_deterministic():
+    m1 = sampler.sample_k(0.09, (20.0, 20.0, 20.0), 500, seed=7, system_id=1, step=3)
+    m2 = sampler.sample_k(0.09, (20.0, 20.0, 20.0), 500, seed=7, system_id=1, step=3)
+    m3 = sampler.sample_k(0.09, (20.0, 20.0, 20.0), 500, seed=7, system_id=1, step=4)
+    assert np.array_equal(m1, m2)
+    assert not np.array_equal(m1, m3)
+    assert np.all(np.any(m1 != 0, axis=1))
+
+
+@pytest.mark.parametrize("box", [(20.0, 20.0, 20.0), (6.0, 7.0, 9.0)])
+def test_sampler_marginals_chi2(box):
+    from scipy.stats import chi2
+    alpha = 0.09 if box[0] == 20.0 else 0.3
+    n = 6000
+    m = sampler.sample_k(alpha, box, n, seed=2024, system_id=5, step=0)
+    for axis in range(3):
+        vals, counts = np.unique(m[:, axis], return_counts=True)
+        lo, hi = vals.min(), vals.max()
+        support = np.arange(lo - 2, hi + 3)
+        pmf = sampler.marginal_pmf(alpha, box, axis, support)
+        exp = pmf * n
+        obs = np.zeros_like(exp)
+        for v, c in zip(vals, counts):
+            obs[np.searchsorted(support, v)] = c
+        # pool bins with expected count < 5 into the two tails
+        keep = exp >= 5
+        e = np.concatenate([exp[keep], [exp[~keep].sum()]])
+        o = np.concatenate([obs[keep], [obs[~keep].sum()]])
+        if e[-1] < 1e-9:
+            e, o = e[:-1], o[:-1]
+        stat = ((o - e) ** 2 / e).sum()
+        dof = len(e) - 1
+        assert stat < chi2.ppf(0.9999, dof), (axis, stat, dof)
+
+
+def test_joint_law_exact_small_box():
+    # the draw's law over all m != 0 equals exp(-k^2/4a)/S (eq. probexpression),
+    # checked against the exact probabilities on a small support
+    from scipy.stats import chi2
+    alpha, box = 1.0, (2.0, 2.5, 3.0)
+    n = 8000
+    m = sampler.sample_k(alpha, box, n, seed=99, system_id=0, step=1)
+    modes, w = ewald.ewald_modes(np.diag(box), alpha, tol=1e-18)
+    prob = w / w.sum()
+    index = {tuple(v): i for i, v in enumerate(modes)}
+    obs = np.zeros(len(modes))
+    for v in m:
+        obs[index[tuple(v)]] += 1
+    exp = prob * n
+    keep = exp >= 5
+    e = np.concatenate([exp[keep], [exp[~keep].sum()]])
+    o = np.concatenate([obs[keep], [obs[~keep].sum()]])
+    stat = ((o - e) ** 2 / e).sum()
+    assert stat < chi2.ppf(0.9999, len(e) - 1)
+
+
+# ---------------------------------------------------------------- RBE estimator
+
+def test_rbe_two_charges_single_mode_closed_form():
+    # q = +1 at r1, -1 at r2, one mode k: rho = e^{ik.r1} - e^{ik.r2},
+    # F1 = S (4 pi / (V k^2)) k sin(k.(r2 - r1)),  |rho|^2 = 2 - 2 cos(k.d)
+    box = np.array([3.0, 4.0, 5.0])
+    r = np.array([[0.3, 1.1, 2.0], [2.2, 0.4, 4.1]])
+    q = np.array([1.0, -1.0])
+    m = np.array([[1, -2, 1]])
+    S, alpha, C = 7.5, 0.7, 1.3
+    res = rbe.rbe_kspace(r, q, box, alpha, m, S, coulomb=C)
+    k = 2 * math.pi * m[0] / box
+    k2 = k @ k
+    V = box.prod()
+    kd = k @ (r[1] - r[0])
+    F1 = C * S * 4 * math.pi / (V * k2) * k * math.sin(kd)
+    assert np.allclose(res["forces"][0], F1, rtol=1e-13, atol=1e-15)
+    assert np.allclose(res["forces"][1], -F1, rtol=1e-13, atol=1e-15)
+    rho2 = 2 - 2 * math.cos(kd)
+    beta = 2 * (1 / k2 + 1 / (4 * alpha))
+    W = C * 2 * math.pi / V * S * rho2 / k2 * (np.eye(3) - beta * np.outer(k, k))
+    assert np.allclose(res["virial"], W, rtol=1e-13, atol=1e-15)
+    E = C * 2 * math.pi / V * S * rho2 / k2 - C * 2 * math.sqrt(alpha / math.pi)
+    assert abs(res["energy"] - E) < 1e-13 * abs(E)
+
+
+def test_rbe_force_is_minus_gradient_of_batch_energy_and_sums_to_zero():
+    s = workloads.random_neutral(30, (6.0, 6.0, 7.0), seed=8)
+    alpha = 0.5
+    m = sampler.sample_k(alpha, s["box"], 20, seed=1, system_id=2, step=0)
+    S = sampler.box_tables(alpha, s["box"])["S"]
+    F = rbe.rbe_kspace(s["pos"], s["q"], s["box"], alpha, m, S)["forces"]
+    eps = 1e-6
+    for i in (0, 13, 29):
+        for c in range(3):
+            rp = s["pos"].copy(); rp[i, c] += eps
+            rm = s["pos"].copy(); rm[i, c] -= eps
+            fd = -(rbe.rbe_kspace(rp, s["q"], s["box"], alpha, m, S)["energy"]
+                   - rbe.rbe_kspace(rm, s["q"], s["box"], alpha, m, S)["energy"]) / (2 * eps)
+            assert abs(fd - F[i, c]) < 1e-7 * max(1.0, np.abs(F).max())
+    assert np.abs(F.sum(axis=0)).max() < 1e-11 * np.abs(F).max()
+
+
+def test_rbe_isotropic_pressure_is_third_of_trace():
+    s = workloads.random_neutral(30, (6.0, 6.0, 6.0), seed=12)
+    alpha = 0.5
+    m = sampler.sample_k(alpha, s["box"], 40, seed=1, system_id=2, step=5)
+    S = sampler.box_tables(alpha, s["box"])["S"]
+    res = rbe.rbe_kspace(s["pos"], s["q"], s["box"], alpha, m, S)
+    # eq. (apppress) written out directly
+    k = 2 * math.pi * m / s["box"]
+    k2 = (k * k).sum(1)
+    rho2 = np.abs(res["rho"]) ** 2
+    V = 216.0
+    P2 = 2 * math.pi / V ** 2 * np.sum(S / 40 * rho2 / k2 * (1 / 3 - k2 / (6 * alpha)))
+    assert abs(res["pressure2"] - P2) < 1e-12 * abs(P2)
+
+
+@pytest.mark.slow
+def test_rbe_unbiased_and_prop1_variance():
+    # Prop. 1: E F* = F_1, E P2* = P2, with the closed-form variances
+    s = workloads.random_neutral(24, (5.0, 5.0, 5.0), seed=31)
+    alpha, p, B = 0.6, 4, 2500          # 10^4 single-frequency draws
+    box = s["box"]
+    tb = sampler.box_tables(alpha, box)
+    S = tb["S"]
+    h = np.diag(box)
+    modes, w = ewald.ewald_modes(h, alpha)
+    full = ewald.kspace_weighted(s["pos"], s["q"], h, alpha, modes, w)
+    F1 = full["forces"]
+    P2 = np.trace(full["virial"]) / (3 * box.prod())
+    var_f, F1b = rbe.force_variance(s["pos"], s["q"], box, alpha, S, p)
+    var_p, P2b = rbe.pressure_variance(s["pos"], s["q"], box, alpha, S, p)
+    assert np.allclose(F1b, F1) and abs(P2b - P2) < 1e-12 * abs(P2)
+    Fs, Ps = [], []
+    for b in range(B):
+        m = sampler.sample_k(alpha, box, p, seed=77, system_id=0, step=b, tables=tb)
+        res = rbe.rbe_kspace(s["pos"], s["q"], box, alpha, m, S)
+        Fs.append(res["forces"]); Ps.append(res["pressure2"])
+    Fs = np.array(Fs); Ps = np.array(Ps)
+    # mean converges: aggregate z statistic over particles ~ 1
+    z = ((Fs.mean(0) - F1) ** 2).sum() / (var_f.sum() / B)
+    assert 0.3 < z < 2.5, z
+    zp = (Ps.mean() - P2) ** 2 / (var_p / B)
+    assert zp < 16.0, zp
+    # empirical variance matches the closed form
+    emp = ((Fs - F1) ** 2).sum(axis=(0, 2)) / B
+    assert abs(emp.sum() / var_f.sum() - 1.0) < 0.08
+    empp = ((Ps - P2) ** 2).mean()
+    assert abs(empp / var_p - 1.0) < 0.15
