@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark of the RBE Fourier-space step on one MI355X.
+
+One step = the whole Fourier-space hot path on one batch: cell update
+(rbe_rescale_box: V, sampler tables, S), batch draw (rbe_sample_k), structure
+factors, their fixed-order reduction, virial tensor and energy, and forces
+(rbe_forces_pressure).  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line (metric, value, ..., roofline, cpu_baseline).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RBE k-space (N·P)/s and ns/day, 30k-charge water NPT; served p50/p99 step ms"
+
+# MI355X: 256 CUs at 2.4 GHz.  FP32 vector peak 157.3 TFLOP/s = 128 FMA lanes
+# per CU per clock; v_sin_f32 / v_cos_f32 issue at a quarter of that, 32 per CU
+# per clock -> 256 * 2.4e9 * 32 = 1.966e13 transcendental ops/s.
+TRANS_PEAK = 256 * 2.4e9 * 32
+TRANS_PER_PAIR = 2          # sin + cos of one reduced phase per (particle, frequency)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="water_30k")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--p", type=int, default=None, help="override the batch size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def make_step(ctx, box, x, y, z, fx, fy, fz, vir, en):
+    def step(i):
+        ctx.rescale_box(box)
+        ctx.sample_k(i)
+        ctx.forces_pressure(x, y, z, fx, fy, fz, accumulate=False, virial6=vir, energy=en)
+    return step
+
+
+def time_steps(step, K, W, torch):
+    for i in range(W):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        step(i)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(sysd, seconds):
+    """The FP64 oracle, as it stands, timed on this host's cores."""
+    from threadpoolctl import threadpool_limits
+    from oracle import rbe as orbe
+    from oracle import sampler as osamp
+    N, P = len(sysd["q"]), sysd["p"]
+    reps, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        while True:
+            m = osamp.sample_k(sysd["alpha"], sysd["box"], P, seed=1, system_id=0, step=reps)
+            S = osamp.box_tables(sysd["alpha"], sysd["box"])["S"]
+            orbe.rbe_kspace(sysd["pos"], sysd["q"], sysd["box"], sysd["alpha"], m, S,
+                            coulomb=sysd["coulomb"])
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    return {"value": N * P * reps / el, "unit": "(N*P)/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full steps of %s (N=%d, P=%d): tables, draw, rho, virial, forces in "
+                      "FP64 numpy, BLAS limited to 1 thread" % (reps, sysd["config"], N, P),
+            "seconds": el}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); the multi-GPU "
+              "sharding of the Fourier-space step is described, not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2110_14362_amd import workloads
+    from paper_2110_14362_amd.rbe import RBE
+
+    dev = torch.device("cuda:0")
+    s = workloads.make(args.workload)
+    if args.p:
+        s["p"] = args.p
+    N, P = len(s["q"]), s["p"]
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    x, y, z = t(s["pos"][:, 0]), t(s["pos"][:, 1]), t(s["pos"][:, 2])
+    q = t(s["q"])
+    fx, fy, fz = (torch.zeros(N, dtype=torch.float64, device=dev) for _ in range(3))
+    vir = torch.zeros(6, dtype=torch.float64, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    box = [float(b) for b in s["box"]]
+    mode = "semiiso" if args.workload.startswith("slab") else "iso"
+
+    results = {}
+    for prec in ([args.precision] + [p for p in ("fp32", "fp64") if p != args.precision]):
+        ctx = RBE(q, box, P, s["alpha"], coulomb=s["coulomb"], precision=prec, box_mode=mode,
+                  seed=2110143620, system_id=0)
+        step = make_step(ctx, box, x, y, z, fx, fy, fz, vir, en)
+        K = args.steps if prec == args.precision else max(1, args.steps // 4)
+        el = time_steps(step, K, args.warmup, torch)
+        # per-kernel device time, HIP events on the library's stream, same steps again
+        ctx.timing_enable(K)
+        time_steps(step, K, 0, torch)
+        kt = ctx.timing_read()
+        ctx.timing_enable(0)
+        ctx.check()
+        results[prec] = dict(seconds=el, steps=K, kernels=kt)
+        ctx.close()
+
+    main_r = results[args.precision]
+    ms = main_r["seconds"] / main_r["steps"] * 1e3
+    value = N * P / (ms * 1e-3)
+    kern = {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None, "launches": v[1]}
+            for k, v in main_r["kernels"].items()}
+    dom = max(("sfac", "force"), key=lambda k: kern[k]["avg_us"] or 0.0)
+    t_dom = kern[dom]["avg_us"] * 1e-6
+    achieved = TRANS_PER_PAIR * N * P / t_dom
+    step_dev = sum((v["avg_us"] or 0.0) for v in kern.values()) * 1e-6
+    roof = {"bound": "alu", "kernel": "k_%s_%s" % (dom, args.precision),
+            "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
+            "frac": achieved / TRANS_PEAK, "traffic": None,
+            "per_unit": "2 transcendentals (sin, cos) per (particle, frequency) pair; "
+                        "%d x %d pairs per launch" % (N, P)}
+    out = {
+        "metric": METRIC, "value": value, "unit": "(N*P)/s", "n_gpus": 1,
+        "steps": main_r["steps"], "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": "%s: %s" % (s["config"], s["name"]), "n": N, "p": P,
+                   "alpha": s["alpha"], "box": box, "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "roofline_step": {"bound": "alu", "achieved": TRANS_PER_PAIR * N * P / step_dev / 1e12,
+                          "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
+                          "frac": TRANS_PER_PAIR * N * P / step_dev / TRANS_PEAK,
+                          "note": "one complex exponential per pair over the summed device "
+                                  "time of all kernels of a step"},
+        "kernels_us": kern,
+    }
+    for prec, r in results.items():
+        if prec != args.precision:
+            ms2 = r["seconds"] / r["steps"] * 1e3
+            out[prec] = {"value": N * P / (ms2 * 1e-3), "ms_per_step": ms2, "steps": r["steps"],
+                         "kernels_us": {k: (v[0] / v[1] * 1e3) if v[1] else None
+                                        for k, v in r["kernels"].items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * rbe.h -- C ABI of the random batch Ewald (RBE) Fourier-space step on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Liang, Tan, Hong, Jin, Xu, Li, "A random batch Ewald method for
+ * charged particles in the isothermal-isobaric ensemble", arXiv:2110.14362):
+ *   - section 4.1, eq. (U1fourier): the Ewald Fourier sum over k = 2 pi h^-T m;
+ *   - section 4.2, eq. (S), (psf), (probexpression): the normaliser S and the
+ *     sampling law exp(-|k|^2/(4 alpha))/S over nonzero k;
+ *   - section 4.2, eq. (appforce) and (apppress): the batch estimators of the
+ *     Fourier-space force and pressure with weight S/p;
+ *   - appendix C, eq. (pressuretensorflexible) and (pressurerect): the
+ *     pressure tensor, and the per-axis sampling of a rectangular cell.
+ *
+ * Conventions shared by every entry point
+ *   - Units: the caller's.  `coulomb` is the Coulomb constant C (1 in reduced
+ *     units, 332.0637 kcal A/(mol e^2) in "real" units).  `alpha` is the
+ *     paper's splitting parameter: the kernel splits as erf(sqrt(alpha) r)/r,
+ *     so alpha has units of 1/length^2 (for g = 0.3/A, alpha = 0.09/A^2).
+ *   - Cell: orthorhombic, h = diag(lx, ly, lz), V = lx*ly*lz.  Positions may
+ *     lie outside [0, l); they are used modulo the cell.
+ *   - Particle arrays are structure-of-arrays FP64 DEVICE pointers owned by the
+ *     caller (x, y, z, fx, fy, fz: n doubles each, no alignment beyond 8 B).
+ *   - The context owns all its device scratch, allocated once in rbe_init.
+ *     No other entry point allocates device memory.
+ *   - Work is queued on the context's HIP stream and returns without waiting,
+ *     except where an argument is a HOST output pointer (the call then waits
+ *     for the stream).
+ *   - Errors: every entry point returns rbe_status; RBE_OK is 0.  The text of
+ *     the last error of the calling thread is returned by rbe_last_error().
+ *     A failed call leaves the context usable unless it says otherwise.
+ *   - Thread safety: a context must not be used by two threads at once.
+ */
+#ifndef RBE_H
+#define RBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbe_ctx_s* rbe_ctx;
+
+typedef enum {
+  RBE_OK = 0,
+  RBE_ERR_ARG = 1,         /* invalid argument (size, value, null pointer)      */
+  RBE_ERR_ALLOC = 2,       /* device or host allocation failed                  */
+  RBE_ERR_DEVICE = 3,      /* a HIP call failed                                 */
+  RBE_ERR_STATE = 4,       /* call out of order (e.g. forces before a sample)   */
+  RBE_ERR_NONNEUTRAL = 5,  /* |sum q| > 1e-10 * sum |q| (section 4.1 assumes a
+                              neutral system; the k = 0 term is dropped)        */
+  RBE_ERR_CAPACITY = 6     /* box grew beyond the sampler-table capacity        */
+} rbe_status;
+
+typedef enum {
+  RBE_BOX_ISO = 0,      /* cubic cell, isotropic coupling (section 3.2)        */
+  RBE_BOX_SEMIISO = 1,  /* lx == ly, xy and z coupled separately (appendix A)  */
+  RBE_BOX_ANISO = 2     /* any rectangular cell                                */
+} rbe_box_mode;
+
+typedef enum {
+  /* FP64 everywhere: phases, sin/cos, sums, forces, virial.                   */
+  RBE_PREC_FP64 = 0,
+  /* Exact phase reduction (integer part removed without rounding), FP32
+     sin/cos, FP32 sums with compensation (blocked Kahan) per lane, FP64 sums
+     across lanes and blocks, FP64 virial and energy, FP32 force accumulation
+     over the batch with an FP64 store.                                        */
+  RBE_PREC_FP32 = 1
+} rbe_precision;
+
+typedef struct {
+  int64_t  n;          /* number of charges, >= 1                              */
+  int32_t  p;          /* batch size: frequencies per step, 1..65536; one
+                          batch serves force and pressure (p == p~)            */
+  int32_t  box_mode;   /* rbe_box_mode                                         */
+  int32_t  precision;  /* rbe_precision                                        */
+  int32_t  reserved;   /* must be 0                                            */
+  double   alpha;      /* splitting parameter (1/length^2), > 0               */
+  double   coulomb;    /* Coulomb constant C, > 0                              */
+  uint64_t seed;       /* Philox key word 0                                    */
+  uint64_t system_id;  /* Philox key word 1                                    */
+} rbe_config;
+
+/* Create a context.
+ *   cfg      : configuration (copied).
+ *   d_q      : DEVICE pointer to n FP64 charges; copied into the context, so
+ *              the caller may free it afterwards.  Must be neutral
+ *              (RBE_ERR_NONNEUTRAL otherwise).
+ *   box_host : HOST pointer to (lx, ly, lz) > 0.  Semi-isotropic mode needs
+ *              |lx - ly| <= 1e-12 * lx.  The sampler tables are sized for
+ *              side lengths up to 2x these values.
+ *   stream   : hipStream_t to queue work on (NULL = default stream).
+ *   out      : receives the context.
+ * Waits for the stream (the neutrality check reads a device sum).  Calls
+ * rbe_rescale_box(box_host) before returning. */
+rbe_status rbe_init(const rbe_config* cfg, const double* d_q, const double* box_host,
+                    void* stream, rbe_ctx* out);
+
+/* Set the stream used by later calls (NULL = default stream). */
+rbe_status rbe_set_stream(rbe_ctx ctx, void* stream);
+
+/* New cell (section 4.2 eq. (S), (psf); appendix C, rectangular sampling).
+ * Sets the cell from which V, the per-axis discrete-Gaussian tables
+ *   w_j(m) = exp(-pi^2 m^2 / (alpha l_j^2)),  |m| <= ceil(sqrt(53 ln2 alpha) l_j / pi),
+ * their running sums, H_j and S = H_x H_y H_z - 1 are computed.  box_host is
+ * read immediately (host pointer, 3 doubles); the device work runs inside the
+ * next kernel that needs it (normally the next rbe_forces_pressure), so a
+ * rescale, a draw and an evaluation cost two kernel launches in all.
+ * RBE_ERR_CAPACITY if a side exceeds 2x its value at rbe_init. */
+rbe_status rbe_rescale_box(rbe_ctx ctx, const double* box_host);
+
+/* Same as rbe_rescale_box with the cell read from DEVICE memory (3 doubles)
+ * when the work runs (the next kernel that needs the cell, on the stream), so
+ * a device-side barostat can feed it.  A cell outside the table capacity is
+ * clamped, recorded on the device and reported by rbe_check. */
+rbe_status rbe_rescale_box_dev(rbe_ctx ctx, const double* d_box);
+
+/* Draw the batch of step `step` (section 4.2 eq. (probexpression); section
+ * 4.3): p independent nonzero integer vectors m with probability
+ * exp(-|k|^2/(4 alpha))/S, k = 2 pi (mx/lx, my/ly, mz/lz), from the
+ * counter-based Philox4x64-10 stream keyed by (seed, system_id) with counter
+ * (step, l, 'ksam', 0) for sample l.  The same step always gives the same
+ * batch for the same cell.  Uses the cell of the last rescale.  Recorded here
+ * and drawn inside the next rbe_forces_pressure (or by rbe_get_k). */
+rbe_status rbe_sample_k(rbe_ctx ctx, uint64_t step);
+
+/* Test hook: replace the batch by p_in host vectors h_m (p_in x 3 int32,
+ * row-major, every row nonzero, |m_j| <= 2048).  p_in must equal cfg.p.
+ * Copies synchronously. */
+rbe_status rbe_set_k(rbe_ctx ctx, const int32_t* h_m, int32_t p_in);
+
+/* Copy the current batch (p x 3 int32) to host memory.  Waits. */
+rbe_status rbe_get_k(rbe_ctx ctx, int32_t* h_m);
+
+/* Fourier-space forces, virial tensor and energy of the current batch
+ * (section 4.2 eq. (appforce), (apppress); appendix C eq.
+ * (pressuretensorflexible) with exp(-k^2/4alpha) replaced by S/p):
+ *   rho_l = sum_j q_j exp(i k_l.r_j)
+ *   F_i  -= q_i sum_l c_l (cos(k_l.r_i) Im rho_l - sin(k_l.r_i) Re rho_l) k_l,
+ *           c_l = C (S/p) 4 pi / (V |k_l|^2)
+ *   W_ab  = C (2 pi / V)(S/p) sum_l |rho_l|^2/|k_l|^2
+ *           [delta_ab - 2 (1/|k_l|^2 + 1/(4 alpha)) k_la k_lb]
+ *   U1*   = C (2 pi / V)(S/p) sum_l |rho_l|^2/|k_l|^2 - C sum_i q_i^2 sqrt(alpha/pi)
+ * The Fourier-space pressure tensor is W / V; the scalar pressure P2* of eq.
+ * (apppress) is (Wxx + Wyy + Wzz)/(3V).
+ *   d_x, d_y, d_z   : DEVICE positions (n doubles each).
+ *   d_fx, d_fy, d_fz: DEVICE forces (n doubles each); overwritten, or added
+ *                     to when accumulate != 0.  May not alias the positions.
+ *   d_virial6       : DEVICE, 6 doubles (xx, yy, zz, xy, xz, yz) written, or
+ *                     NULL.
+ *   d_energy        : DEVICE, 1 double (U1*) written, or NULL.
+ * RBE_ERR_STATE if no batch was drawn or set since rbe_init.  Asynchronous. */
+rbe_status rbe_forces_pressure(rbe_ctx ctx, const double* d_x, const double* d_y,
+                               const double* d_z, double* d_fx, double* d_fy,
+                               double* d_fz, int accumulate, double* d_virial6,
+                               double* d_energy);
+
+/* Copy rho of the last rbe_forces_pressure (p complex numbers as 2p doubles:
+ * re0, im0, re1, ...) to host memory.  Waits. */
+rbe_status rbe_get_rho(rbe_ctx ctx, double* h_rho);
+
+/* Copy the cell-derived values of the last rescale to host memory.  Waits.
+ * h_info[0..9] = V, S, Hx, Hy, Hz, lx, ly, lz, mcut_x, mcut_y (as doubles);
+ * h_info[10] = mcut_z; h_info[11] = device error flags (0 = none). */
+rbe_status rbe_get_box_info(rbe_ctx ctx, double* h_info);
+
+/* Wait for the stream and report device-side errors (capacity overflow of a
+ * device rescale) as a status.  Clears the device error flags. */
+rbe_status rbe_check(rbe_ctx ctx);
+
+/* Kernel timing for measurement.  While enabled, each kernel this context
+ * launches is bracketed by two HIP events recorded on the context's stream
+ * (the stream the kernel runs on).  max_launches (>= 1) bounds the launches
+ * recorded per kernel kind; later launches run untimed.  0 disables and
+ * releases the events.  Creates host-side HIP events only (no device memory). */
+rbe_status rbe_timing_enable(rbe_ctx ctx, int32_t max_launches);
+
+/* Wait for the stream and read the timing since the last read or enable:
+ * h_ms[k] = total device milliseconds and h_count[k] = launches of kernel kind
+ * k, for k = 0 tables, 1 sample, 2 structure factors, 3 reduction, 4 batch
+ * sum (virial/energy), 5 forces.  Resets the totals (timing stays enabled). */
+rbe_status rbe_timing_read(rbe_ctx ctx, double* h_ms, int32_t* h_count);
+
+/* Release the context and its device memory (waits for the stream). */
+void rbe_destroy(rbe_ctx ctx);
+
+/* Text of the last error reported to the calling thread ("" if none). */
+const char* rbe_last_error(void);
+
+/* Library version string. */
+const char* rbe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBE_H */

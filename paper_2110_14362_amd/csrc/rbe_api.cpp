@@ -1,0 +1,479 @@
+// C ABI of the random batch Ewald Fourier-space step: argument checks,
+// context ownership and the launch sequence.  Declarations and contracts are
+// in include/rbe.h.
+#include "rbe_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace rbe;
+
+struct rbe_ctx_s {
+  rbe_config cfg;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  int p = 0;
+  int mcap[3] = {0, 0, 0};
+  int tab_stride = 0;
+  double tail_ln = 0.0;
+  double self_energy = 0.0;
+  bool have_k = false;
+  // work recorded by rbe_rescale_box* / rbe_sample_k, executed by the next
+  // kernel that needs it (the fused step, or the standalone table/draw
+  // kernels when a result is read first)
+  int32_t pend_box = BOX_COMMITTED;
+  double pend_box_val[3] = {0, 0, 0};
+  const double* pend_box_ptr = nullptr;
+  bool pend_sample = false;
+  uint64_t pend_step = 0;
+  StepArgs a{};             // launch plan, scratch pointers and constants
+  // device memory (owned)
+  double* d_q = nullptr;
+  float* d_qf = nullptr;
+  double* d_qsum = nullptr;      // 3 doubles
+  BoxState* d_bs = nullptr;
+  double* d_tab = nullptr;
+  int32_t* d_m = nullptr;        // 3p
+  double2* d_partial = nullptr;  // X * Ppad
+  double2* d_gpart = nullptr;    // NG * Ppad
+  double2* d_rho = nullptr;      // p
+  double* d_terms = nullptr;     // 8p
+  FCoef32* d_fc32 = nullptr;     // p
+  FCoef64* d_fc64 = nullptr;     // p
+  uint32_t* d_cnt = nullptr;     // Y*NG + Y + 1
+  // kernel timing (rbe_timing_enable)
+  static constexpr int kKinds = 4;
+  int timing_cap = 0;
+  std::vector<hipEvent_t> ev[kKinds];
+  int ev_used[kKinds] = {0, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+rbe_status fail(rbe_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+rbe_status fail(rbe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+rbe_status hip_fail(hipError_t e, const char* what) {
+  return fail(RBE_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ceil(sqrt(53 ln2 * alpha) * l / pi): the half-width of a one-axis table
+double axis_mcut(double tail_ln, double alpha, double l) {
+  return std::ceil(std::sqrt(tail_ln * alpha * l * l) / M_PI);
+}
+
+rbe_status check_box(const rbe_ctx_s* c, const double* box) {
+  if (!box) return fail(RBE_ERR_ARG, "box pointer is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!finite_pos(box[a])) return fail(RBE_ERR_ARG, "box[%d] = %g is not a positive finite length", a, box[a]);
+  const int mode = c->cfg.box_mode;
+  const double tol = 1e-12 * box[0];
+  if (mode == RBE_BOX_ISO && (std::fabs(box[1] - box[0]) > tol || std::fabs(box[2] - box[0]) > tol))
+    return fail(RBE_ERR_ARG, "isotropic mode needs a cubic box (got %.17g %.17g %.17g)", box[0], box[1], box[2]);
+  if (mode == RBE_BOX_SEMIISO && std::fabs(box[1] - box[0]) > tol)
+    return fail(RBE_ERR_ARG, "semi-isotropic mode needs lx == ly (got %.17g %.17g)", box[0], box[1]);
+  for (int a = 0; a < 3; ++a) {
+    const double mc = axis_mcut(c->tail_ln, c->cfg.alpha, box[a]);
+    if (mc > c->mcap[a])
+      return fail(RBE_ERR_CAPACITY, "box[%d] = %g needs %g sampler entries per side, capacity %d (2x the initial box)",
+                  a, box[a], mc, c->mcap[a]);
+  }
+  return RBE_OK;
+}
+
+long env_long(const char* name, long dflt) {
+  if (const char* e = std::getenv(name)) {
+    const long v = std::atol(e);
+    if (v > 0) return v;
+  }
+  return dflt;
+}
+
+// Launch geometry.  Structure factors: 8-wave blocks, KB frequency groups of
+// 64 per block (a power of two), 8/KB particle sub-slices per group; X
+// particle chunks x Y frequency slices, about 2 blocks per CU.  Chunk
+// partials are summed in groups of GX.  Forces: 64 particles per block, the
+// batch split over KS waves so that about 16 waves per CU are resident.
+void plan_launch(rbe_ctx_s* c) {
+  StepArgs& a = c->a;
+  const int kgroups = (c->p + kWave - 1) / kWave;
+  int KB = 1;
+  while (KB < kgroups && KB < kSfacWaves) KB <<= 1;
+  a.KB = KB;
+  a.Y = (kgroups + KB - 1) / KB;
+  a.Ppad = a.Y * KB * kWave;
+  const long target_blocks = env_long("RBE_SFAC_BLOCKS", 256);
+  long X = (target_blocks + a.Y - 1) / a.Y;
+  const long max_x = (c->n + 15) / 16;          // at least 16 particles per chunk
+  if (X > max_x) X = max_x;
+  if (X < 1) X = 1;
+  long chunk = (long)((c->n + X - 1) / X);
+  X = (long)((c->n + chunk - 1) / chunk);
+  a.X = (int)X;
+  a.chunk = (int)chunk;
+  int GX = 1;
+  while ((long)GX * GX < X) ++GX;
+  a.GX = GX;
+  a.NG = (int)((X + GX - 1) / GX);
+  const long fblocks = (c->n + kWave - 1) / kWave;
+  const long target_waves = env_long("RBE_FORCE_WAVES", 4096);
+  int KS = 1;
+  while (KS < 16 && (long)(KS * 2) * fblocks <= target_waves && KS * 2 <= c->p) KS <<= 1;
+  a.KS = KS;
+}
+
+enum Kind { K_TABLES = 0, K_SAMPLE, K_SFAC, K_FORCE };
+
+// Records the start event of a launch of kind k if timing is on; returns the
+// slot to close with timed_end, or -1.
+int timed_begin(rbe_ctx_s* c, int k) {
+  if (c->timing_cap == 0 || c->ev_used[k] >= c->timing_cap) return -1;
+  const int slot = c->ev_used[k]++;
+  if (hipEventRecord(c->ev[k][2 * slot], c->stream) != hipSuccess) return -1;
+  return slot;
+}
+
+void timed_end(rbe_ctx_s* c, int k, int slot) {
+  if (slot >= 0) (void)hipEventRecord(c->ev[k][2 * slot + 1], c->stream);
+}
+
+void destroy_events(rbe_ctx_s* c) {
+  for (int k = 0; k < rbe_ctx_s::kKinds; ++k) {
+    for (hipEvent_t e : c->ev[k])
+      if (e) (void)hipEventDestroy(e);
+    c->ev[k].clear();
+    c->ev_used[k] = 0;
+  }
+  c->timing_cap = 0;
+}
+
+void free_all(rbe_ctx_s* c) {
+  void* bufs[] = {c->d_q, c->d_qf, c->d_qsum, c->d_bs, c->d_tab, c->d_m, c->d_partial,
+                  c->d_gpart, c->d_rho, c->d_terms, c->d_fc32, c->d_fc64, c->d_cnt};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+}
+
+// StepArgs for the current call: pending cell and draw folded in.
+StepArgs step_args(rbe_ctx_s* c) {
+  StepArgs a = c->a;
+  a.box_src = c->pend_box;
+  a.box_arg[0] = c->pend_box_val[0]; a.box_arg[1] = c->pend_box_val[1]; a.box_arg[2] = c->pend_box_val[2];
+  a.box_ptr = c->pend_box_ptr;
+  a.sample = c->pend_sample ? 1 : 0;
+  a.step = c->pend_step;
+  return a;
+}
+
+void clear_pending(rbe_ctx_s* c) {
+  c->pend_box = BOX_COMMITTED;
+  c->pend_box_ptr = nullptr;
+  c->pend_sample = false;
+}
+
+// Run pending table / draw work with the standalone kernels.
+rbe_status flush(rbe_ctx_s* c) {
+  if (c->pend_box == BOX_COMMITTED && !c->pend_sample) return RBE_OK;
+  const StepArgs a = step_args(c);
+  int ts = timed_begin(c, K_TABLES);
+  hipError_t e = launch_tables(a, c->stream);
+  timed_end(c, K_TABLES, ts);
+  if (e != hipSuccess) return hip_fail(e, "table kernel");
+  if (c->pend_sample) {
+    ts = timed_begin(c, K_SAMPLE);
+    e = launch_sample(a, c->stream);
+    timed_end(c, K_SAMPLE, ts);
+    if (e != hipSuccess) return hip_fail(e, "sample kernel");
+  }
+  clear_pending(c);
+  return RBE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rbe_last_error(void) { return g_err.c_str(); }
+
+const char* rbe_version(void) { return "rbe-gfx950 0.2"; }
+
+rbe_status rbe_init(const rbe_config* cfg, const double* d_q, const double* box_host,
+                    void* stream, rbe_ctx* out) {
+  g_err.clear();
+  if (!cfg || !d_q || !box_host || !out) return fail(RBE_ERR_ARG, "NULL argument to rbe_init");
+  *out = nullptr;
+  if (cfg->n < 1) return fail(RBE_ERR_ARG, "n = %lld must be >= 1", (long long)cfg->n);
+  if (cfg->p < 1 || cfg->p > 65536) return fail(RBE_ERR_ARG, "p = %d must be in 1..65536", cfg->p);
+  if (cfg->box_mode < 0 || cfg->box_mode > 2) return fail(RBE_ERR_ARG, "unknown box_mode %d", cfg->box_mode);
+  if (cfg->precision < 0 || cfg->precision > 1) return fail(RBE_ERR_ARG, "unknown precision %d", cfg->precision);
+  if (cfg->reserved != 0) return fail(RBE_ERR_ARG, "reserved field must be 0");
+  if (!finite_pos(cfg->alpha)) return fail(RBE_ERR_ARG, "alpha = %g must be positive and finite", cfg->alpha);
+  if (!finite_pos(cfg->coulomb)) return fail(RBE_ERR_ARG, "coulomb = %g must be positive and finite", cfg->coulomb);
+
+  rbe_ctx_s* c = new (std::nothrow) rbe_ctx_s();
+  if (!c) return fail(RBE_ERR_ALLOC, "host allocation failed");
+  c->cfg = *cfg;
+  c->n = cfg->n;
+  c->p = cfg->p;
+  c->stream = (hipStream_t)stream;
+  c->tail_ln = 53.0 * std::log(2.0);
+  for (int a = 0; a < 3; ++a) {
+    if (!finite_pos(box_host[a])) { delete c; return fail(RBE_ERR_ARG, "box[%d] = %g is not a positive finite length", a, box_host[a]); }
+    const double mc = axis_mcut(c->tail_ln, cfg->alpha, 2.0 * box_host[a]);
+    if (mc > kMaxMcut) {
+      delete c;
+      return fail(RBE_ERR_ARG, "alpha*l^2 too large: axis %d needs %g sampler entries per side (limit %d)", a, mc, kMaxMcut);
+    }
+    c->mcap[a] = (int)mc;
+  }
+  c->tab_stride = 4 * (c->mcap[0] + c->mcap[1] + c->mcap[2]) + 3;
+  {
+    rbe_status st = check_box(c, box_host);
+    if (st != RBE_OK) { delete c; return st; }
+  }
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
+  plan_launch(c);
+  StepArgs& A = c->a;
+
+  const size_t n = (size_t)c->n, p = (size_t)c->p;
+  const size_t ncnt = (size_t)A.Y * A.NG + A.Y + 1;
+  bool ok = true;
+  ok = ok && hipMalloc(&c->d_q, n * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_qf, n * sizeof(float)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_qsum, 3 * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_bs, sizeof(BoxState)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_tab, (size_t)c->tab_stride * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_m, 3 * p * sizeof(int32_t)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_partial, (size_t)A.X * A.Ppad * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_gpart, (size_t)A.NG * A.Ppad * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_rho, p * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_terms, 8 * p * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_fc32, p * sizeof(FCoef32)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_fc64, p * sizeof(FCoef64)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_cnt, ncnt * sizeof(uint32_t)) == hipSuccess;
+  if (!ok) { free_all(c); delete c; return fail(RBE_ERR_ALLOC, "device allocation failed"); }
+
+  A.q = c->d_q; A.qf = c->d_qf;
+  A.p = c->p; A.n = c->n;
+  A.alpha = cfg->alpha; A.coulomb = cfg->coulomb; A.tail_ln = c->tail_ln;
+  A.seed = cfg->seed; A.sysid = cfg->system_id;
+  for (int k = 0; k < 3; ++k) A.mcap[k] = c->mcap[k];
+  A.tab_stride = c->tab_stride;
+  A.bs = c->d_bs; A.tab = c->d_tab; A.m = c->d_m;
+  A.partial = c->d_partial; A.gpart = c->d_gpart; A.rho = c->d_rho; A.terms = c->d_terms;
+  A.fc32 = c->d_fc32; A.fc64 = c->d_fc64; A.cnt = c->d_cnt;
+
+  rbe_status st = RBE_OK;
+  double qs[3] = {0, 0, 0};
+  do {
+    if ((e = hipMemsetAsync(c->d_bs, 0, sizeof(BoxState), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
+    if ((e = hipMemsetAsync(c->d_cnt, 0, ncnt * sizeof(uint32_t), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
+    if ((e = hipMemsetAsync(c->d_m, 0, 3 * p * sizeof(int32_t), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
+    if ((e = hipMemcpyAsync(c->d_q, d_q, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess) { st = hip_fail(e, "copy charges"); break; }
+    if ((e = launch_qsum(c->d_q, c->d_qf, c->d_qsum, c->n, c->stream)) != hipSuccess) { st = hip_fail(e, "charge sums"); break; }
+    if ((e = hipMemcpyAsync(qs, c->d_qsum, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) { st = hip_fail(e, "copy charge sums"); break; }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) { st = hip_fail(e, "hipStreamSynchronize"); break; }
+    if (!std::isfinite(qs[0]) || !std::isfinite(qs[1])) { st = fail(RBE_ERR_ARG, "charges are not finite"); break; }
+    if (std::fabs(qs[0]) > 1e-10 * qs[1]) { st = fail(RBE_ERR_NONNEUTRAL, "system is not neutral: sum q = %g, sum |q| = %g", qs[0], qs[1]); break; }
+  } while (0);
+  if (st != RBE_OK) { free_all(c); delete c; return st; }
+  c->self_energy = -cfg->coulomb * qs[2] * std::sqrt(cfg->alpha / M_PI);
+  A.self_energy = c->self_energy;
+  st = rbe_rescale_box(c, box_host);
+  if (st == RBE_OK) st = flush(c);     // commit the initial cell
+  if (st != RBE_OK) { free_all(c); delete c; return st; }
+  *out = c;
+  return RBE_OK;
+}
+
+rbe_status rbe_set_stream(rbe_ctx c, void* stream) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  c->stream = (hipStream_t)stream;
+  return RBE_OK;
+}
+
+rbe_status rbe_rescale_box(rbe_ctx c, const double* box_host) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  rbe_status st = check_box(c, box_host);
+  if (st != RBE_OK) return st;
+  c->pend_box = BOX_ARGS;
+  for (int k = 0; k < 3; ++k) c->pend_box_val[k] = box_host[k];
+  c->pend_box_ptr = nullptr;
+  return RBE_OK;
+}
+
+rbe_status rbe_rescale_box_dev(rbe_ctx c, const double* d_box) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (!d_box) return fail(RBE_ERR_ARG, "NULL device box");
+  c->pend_box = BOX_PTR;
+  c->pend_box_ptr = d_box;
+  return RBE_OK;
+}
+
+rbe_status rbe_sample_k(rbe_ctx c, uint64_t step) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  c->pend_sample = true;
+  c->pend_step = step;
+  c->have_k = true;
+  return RBE_OK;
+}
+
+rbe_status rbe_set_k(rbe_ctx c, const int32_t* h_m, int32_t p_in) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (!h_m) return fail(RBE_ERR_ARG, "NULL batch");
+  if (p_in != c->p) return fail(RBE_ERR_ARG, "batch size %d differs from the configured p = %d", p_in, c->p);
+  for (int l = 0; l < p_in; ++l) {
+    const int32_t* m = h_m + 3 * l;
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) return fail(RBE_ERR_ARG, "row %d of the batch is the zero vector", l);
+    for (int a = 0; a < 3; ++a)
+      if (m[a] > 2048 || m[a] < -2048) return fail(RBE_ERR_ARG, "row %d: |m| = %d exceeds 2048", l, m[a]);
+  }
+  c->pend_sample = false;               // an explicit batch replaces a pending draw
+  HIP_TRY(hipMemcpyAsync(c->d_m, h_m, 3 * (size_t)p_in * sizeof(int32_t), hipMemcpyHostToDevice, c->stream), "copy batch");
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->have_k = true;
+  return RBE_OK;
+}
+
+rbe_status rbe_get_k(rbe_ctx c, int32_t* h_m) {
+  if (!c || !h_m) return fail(RBE_ERR_ARG, "NULL argument");
+  if (!c->have_k) return fail(RBE_ERR_STATE, "no batch drawn or set yet");
+  rbe_status st = flush(c);
+  if (st != RBE_OK) return st;
+  HIP_TRY(hipMemcpyAsync(h_m, c->d_m, 3 * (size_t)c->p * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "copy batch");
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return RBE_OK;
+}
+
+rbe_status rbe_forces_pressure(rbe_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                               double* d_fx, double* d_fy, double* d_fz, int accumulate,
+                               double* d_virial6, double* d_energy) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return fail(RBE_ERR_ARG, "NULL particle array");
+  if (!c->have_k) return fail(RBE_ERR_STATE, "rbe_forces_pressure before rbe_sample_k / rbe_set_k");
+  StepArgs a = step_args(c);
+  a.x = d_x; a.y = d_y; a.z = d_z;
+  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
+  a.accumulate = accumulate ? 1 : 0;
+  a.virial6 = d_virial6; a.energy = d_energy;
+  const int prec = c->cfg.precision;
+  int ts = timed_begin(c, K_SFAC);
+  hipError_t e = launch_sfac(prec, a, c->stream);
+  timed_end(c, K_SFAC, ts);
+  if (e != hipSuccess) return hip_fail(e, "structure-factor kernel");
+  clear_pending(c);
+  ts = timed_begin(c, K_FORCE);
+  e = launch_force(prec, a, c->stream);
+  timed_end(c, K_FORCE, ts);
+  if (e != hipSuccess) return hip_fail(e, "force kernel");
+  return RBE_OK;
+}
+
+rbe_status rbe_get_rho(rbe_ctx c, double* h_rho) {
+  if (!c || !h_rho) return fail(RBE_ERR_ARG, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(h_rho, c->d_rho, (size_t)c->p * sizeof(double2), hipMemcpyDeviceToHost, c->stream), "copy rho");
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return RBE_OK;
+}
+
+rbe_status rbe_get_box_info(rbe_ctx c, double* h_info) {
+  if (!c || !h_info) return fail(RBE_ERR_ARG, "NULL argument");
+  rbe_status st = flush(c);
+  if (st != RBE_OK) return st;
+  BoxState b;
+  HIP_TRY(hipMemcpyAsync(&b, c->d_bs, sizeof b, hipMemcpyDeviceToHost, c->stream), "copy box state");
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  h_info[0] = b.V; h_info[1] = b.S;
+  h_info[2] = b.H[0]; h_info[3] = b.H[1]; h_info[4] = b.H[2];
+  h_info[5] = b.l[0]; h_info[6] = b.l[1]; h_info[7] = b.l[2];
+  h_info[8] = b.mcut[0]; h_info[9] = b.mcut[1]; h_info[10] = b.mcut[2];
+  h_info[11] = b.err;
+  return RBE_OK;
+}
+
+rbe_status rbe_check(rbe_ctx c) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  rbe_status st = flush(c);
+  if (st != RBE_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  int32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, &c->d_bs->err, sizeof err, hipMemcpyDeviceToHost), "read error flags");
+  if (err) {
+    const int32_t zero = 0;
+    HIP_TRY(hipMemcpy(&c->d_bs->err, &zero, sizeof zero, hipMemcpyHostToDevice), "clear error flags");
+    return fail(RBE_ERR_CAPACITY, "a device-side rescale met a cell outside the sampler-table capacity (flags %d)", err);
+  }
+  return RBE_OK;
+}
+
+rbe_status rbe_timing_enable(rbe_ctx c, int32_t max_launches) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (max_launches < 0) return fail(RBE_ERR_ARG, "max_launches = %d must be >= 0", max_launches);
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  destroy_events(c);
+  if (max_launches == 0) return RBE_OK;
+  for (int k = 0; k < rbe_ctx_s::kKinds; ++k) {
+    c->ev[k].assign(2 * (size_t)max_launches, nullptr);
+    for (auto& e : c->ev[k]) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        destroy_events(c);
+        return fail(RBE_ERR_DEVICE, "hipEventCreate failed");
+      }
+    }
+  }
+  c->timing_cap = max_launches;
+  return RBE_OK;
+}
+
+rbe_status rbe_timing_read(rbe_ctx c, double* h_ms, int32_t* h_count) {
+  if (!c || !h_ms || !h_count) return fail(RBE_ERR_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  for (int k = 0; k < rbe_ctx_s::kKinds; ++k) {
+    double tot = 0.0;
+    for (int i = 0; i < c->ev_used[k]; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c->ev[k][2 * i], c->ev[k][2 * i + 1]), "hipEventElapsedTime");
+      tot += ms;
+    }
+    h_ms[k] = tot;
+    h_count[k] = c->ev_used[k];
+    c->ev_used[k] = 0;
+  }
+  return RBE_OK;
+}
+
+void rbe_destroy(rbe_ctx c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  destroy_events(c);
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal declarations shared by the C ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "../../include/rbe.h"
+
+namespace rbe {
+
+// Largest |m| per axis the sampler tables may hold: keeps the three axes'
+// running-sum tables (4*mcap+1 doubles each, 31 KB in all) in LDS next to the
+// particle tiles, and |m| <= 2048 as the FP32 two-part phase product needs.
+constexpr int kMaxMcut = 320;
+constexpr int kWave = 64;
+constexpr int kSfacThreads = 512;     // structure-factor kernel: 8 waves
+constexpr int kSfacWaves = kSfacThreads / 64;
+constexpr int kTile = 512;            // particles per LDS tile
+constexpr int kKahan = 16;            // plain FP32 run between compensated folds
+
+// Cell-derived values (section 4.2 eq. (S), (psf); appendix C sampling).
+struct BoxState {
+  double l[3];       // side lengths
+  double inv_l[3];   // 1/l
+  double V;          // volume
+  double S;          // normaliser: sum over k != 0 of exp(-k^2/(4 alpha))
+  double H[3];       // one-axis sums (m = 0 term included)
+  double case_w[3];  // weights of the first-nonzero-axis cases (sum = S)
+  int32_t mcut[3];   // table half-widths in use
+  int32_t err;       // bit 0: cell outside the table capacity
+};
+
+// Force-pass constants of one frequency, FP32 path (32 B: one scalar load).
+struct alignas(32) FCoef32 {
+  float m[3];        // m (exact small integers)
+  float cA, cB;      // c Re rho, c Im rho with c = C (S/p) 4 pi / (V k^2)
+  float k[3];        // k = 2 pi m / l
+};
+// FP64 path.
+struct alignas(64) FCoef64 {
+  double m[3];
+  double cA, cB;
+  double k[3];
+};
+
+enum BoxSource : int32_t { BOX_COMMITTED = 0, BOX_ARGS = 1, BOX_PTR = 2 };
+
+// Everything one Fourier-space evaluation of one system needs (passed by value
+// as the kernel argument).
+struct StepArgs {
+  const double* x; const double* y; const double* z;
+  const double* q; const float* qf;
+  double* fx; double* fy; double* fz;
+  double* virial6; double* energy;
+  int32_t box_src;      // BoxSource
+  int32_t sample;       // 1: draw the batch of `step`; 0: use m as stored
+  int32_t accumulate;   // forces: add instead of overwrite
+  int32_t p;
+  int64_t n;
+  double box_arg[3];
+  const double* box_ptr;
+  double alpha, coulomb, self_energy, tail_ln;
+  uint64_t seed, sysid, step;
+  int32_t mcap[3];
+  int32_t tab_stride;
+  // launch plan
+  int32_t X, Y, KB, GX, NG, chunk, Ppad, KS;
+  // context-owned state and scratch
+  BoxState* bs; double* tab;
+  int32_t* m;
+  double2* partial;     // [X][Ppad]
+  double2* gpart;       // [NG][Ppad]
+  double2* rho;         // [p]
+  double* terms;        // [p][8]
+  FCoef32* fc32; FCoef64* fc64;
+  uint32_t* cnt;        // [Y*NG] + [Y] + [1] arrival counters, zero between launches
+};
+
+size_t sfac_lds_bytes(const StepArgs& a);
+
+hipError_t launch_qsum(const double* d_q, float* d_qf, double* d_out3, int64_t n, hipStream_t s);
+// standalone table and draw kernels (used when a result is read before the
+// fused kernel has run)
+hipError_t launch_tables(const StepArgs& a, hipStream_t s);
+hipError_t launch_sample(const StepArgs& a, hipStream_t s);
+// the two kernels of a step
+hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s);
+hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s);
+
+}  // namespace rbe

@@ -1,0 +1,711 @@
+// HIP kernels of the random batch Ewald Fourier-space step (gfx950).
+//
+// A step is two launches:
+//   k_sfac   every block rebuilds the per-axis sampler tables and the cell
+//            values in LDS (section 4.2 eq. (S), (psf); appendix C: the three
+//            axes of a rectangular cell are independent), draws the
+//            frequencies of its slice of the batch (eq. (probexpression)),
+//            and sums rho(k) = sum_j q_j exp(i k.r_j) (eq. (U1fourier)) over
+//            its particle chunk, one lane per frequency with the particles
+//            broadcast from LDS.  Chunk partials are then combined in a fixed
+//            order by the last-arriving blocks (two levels), which also form
+//            the force coefficients of eq. (appforce) and the virial tensor
+//            and energy of eq. (apppress) / (pressuretensorflexible).
+//   k_force  one lane per particle, the batch split across the waves of a
+//            block, frequency constants uniform across the wave (eq. (appforce)).
+// Every sum has a fixed order, so results are bitwise reproducible and do not
+// depend on which block arrives last or on what else runs on the GPU.
+#include "rbe_internal.h"
+#include <math.h>
+#include <type_traits>
+
+namespace rbe {
+
+// ---------------------------------------------------------------------------
+// helpers
+
+__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): multipliers and Weyl key
+// increments of the 4x64 variant; ten rounds, key bumped between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+constexpr uint64_t kTagKSample = 0x6B73616Dull;  // 'ksam': stream of the batch draws
+
+// ceil(sqrt(53 ln2 alpha) l / pi): weights exp(-pi^2 m^2/(alpha l^2)) >= 2^-53
+__device__ __forceinline__ int table_halfwidth(double alpha, double tail_ln, double l, int mcap,
+                                               int& err) {
+  const double mcd = ceil(sqrt(tail_ln * alpha * l * l) / M_PI);
+  if (mcd >= 1.0 && mcd <= (double)mcap) return (int)mcd;
+  err |= 1;                       // non-finite, non-positive or oversized cell
+  return mcd >= 1.0 ? mcap : 1;
+}
+
+__device__ __forceinline__ void table_offsets(const int mc[3], int off[3]) {
+  off[0] = 0;
+  off[1] = 4 * mc[0] + 1;
+  off[2] = off[1] + 4 * mc[1] + 1;
+}
+
+// Per-axis running sums of w_a(m) = exp(-pi^2 m^2 / (alpha l_a^2)) built by the
+// whole block into `tab` (LDS or global).  Axis a occupies [off[a], off[a] +
+// 4 mc_a + 1): the running sum over m = -mc..mc, then the running sum over the
+// same m without m = 0.  One wave per (axis, table); a lane owns a contiguous
+// segment, the lane totals are scanned across the wave.  Writes the cell
+// values to *out (LDS).  Must be reached by every thread of the block.
+__device__ void build_tables(const double l[3], double alpha, double tail_ln, const int mcap[3],
+                             double* tab, BoxState* out, double* sh_T) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  int err = 0, mc[3], off[3];
+  for (int a = 0; a < 3; ++a) mc[a] = table_halfwidth(alpha, tail_ln, l[a], mcap[a], err);
+  table_offsets(mc, off);
+  const double pi2 = M_PI * M_PI;
+  for (int task = wave; task < 6; task += nw) {
+    const int a = task >> 1, nz = task & 1;
+    const int n = nz ? 2 * mc[a] : 2 * mc[a] + 1;
+    double* t = tab + off[a] + (nz ? 2 * mc[a] + 1 : 0);
+    const double den = alpha * l[a] * l[a];
+    const int seg = (n + kWave - 1) / kWave;
+    const int b0 = min(n, lane * seg), b1 = min(n, b0 + seg);
+    double loc = 0.0;
+    for (int i = b0; i < b1; ++i) {
+      const int m = nz ? (i < mc[a] ? i - mc[a] : i - mc[a] + 1) : i - mc[a];
+      const double w = exp(-(pi2 * ((double)m * (double)m)) / den);
+      t[i] = w;
+      loc += w;
+    }
+    const double incl = wave_incl_scan(loc, lane);
+    const double excl = incl - loc;
+    double run = 0.0;
+    for (int i = b0; i < b1; ++i) {
+      run += t[i];
+      t[i] = excl + run;
+    }
+    if (nz && lane == kWave - 1) sh_T[a] = incl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double Tx = sh_T[0], Ty = sh_T[1], Tz = sh_T[2];
+    const double Hx = 1.0 + Tx, Hy = 1.0 + Ty, Hz = 1.0 + Tz;
+    BoxState b;
+    for (int a = 0; a < 3; ++a) { b.l[a] = l[a]; b.inv_l[a] = 1.0 / l[a]; b.mcut[a] = mc[a]; }
+    b.V = l[0] * l[1] * l[2];
+    b.H[0] = Hx; b.H[1] = Hy; b.H[2] = Hz;
+    b.case_w[0] = Tx * Hy * Hz;
+    b.case_w[1] = Ty * Hz;
+    b.case_w[2] = Tz;
+    b.S = b.case_w[0] + b.case_w[1] + b.case_w[2];
+    b.err = err;
+    *out = b;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int first_greater(const double* c, int n, double t) {
+  // smallest i with c[i] > t, or n-1 if none
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (c[mid] > t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Draw frequency l of a step.  The nonzero event is split by its first
+// nonzero axis (weights case_w, sum S); the pivot axis is drawn from its
+// m != 0 table, later axes from their full tables, earlier axes are 0.
+// Uniforms: the four Philox outputs of counter (step, l, 'ksam', 0), top 53
+// bits.  A table draw is the first index whose running sum exceeds u times
+// the table total; the three axes' binary searches run in lockstep.
+__device__ __forceinline__ void draw_frequency(const BoxState& b, const double* tab, uint64_t seed,
+                                               uint64_t sysid, uint64_t step, int l, int m[3]) {
+  int off[3];
+  table_offsets(b.mcut, off);
+  uint64_t c[4] = {step, (uint64_t)l, kTagKSample, 0ull};
+  philox4x64_10(c, seed, sysid);
+  double u[4];
+  for (int j = 0; j < 4; ++j) u[j] = (double)(c[j] >> 11) * 0x1.0p-53;
+  const double t = u[0] * b.S;
+  const int pivot = (t < b.case_w[0]) ? 0 : ((t < b.case_w[0] + b.case_w[1]) ? 1 : 2);
+  const double* base[3];
+  int lo[3], hi[3];
+  double tgt[3];
+  int nmax = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int mc = b.mcut[a];
+    const bool nz = (a == pivot);
+    const int n = nz ? 2 * mc : 2 * mc + 1;
+    base[a] = tab + off[a] + (nz ? 2 * mc + 1 : 0);
+    lo[a] = 0;
+    hi[a] = (a < pivot) ? 0 : n - 1;
+    tgt[a] = u[a + 1] * base[a][n - 1];
+    nmax = max(nmax, n);
+  }
+  const int iters = 32 - __clz(nmax);
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (lo[a] < hi[a]) {
+        const int mid = (lo[a] + hi[a]) >> 1;
+        if (base[a][mid] > tgt[a]) hi[a] = mid; else lo[a] = mid + 1;
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int mc = b.mcut[a];
+    if (a < pivot) m[a] = 0;
+    else if (a == pivot) m[a] = lo[a] < mc ? lo[a] - mc : lo[a] - mc + 1;
+    else m[a] = lo[a] - mc;
+  }
+}
+
+__device__ __forceinline__ void box_source(const StepArgs& a, double l[3]) {
+  if (a.box_src == BOX_ARGS) {
+    l[0] = a.box_arg[0]; l[1] = a.box_arg[1]; l[2] = a.box_arg[2];
+  } else if (a.box_src == BOX_PTR) {
+    l[0] = a.box_ptr[0]; l[1] = a.box_ptr[1]; l[2] = a.box_ptr[2];
+  } else {
+    l[0] = a.bs->l[0]; l[1] = a.bs->l[1]; l[2] = a.bs->l[2];
+  }
+}
+
+// Reduced coordinate s = x/l - floor(x/l) in [0,1), split as s = sh + sl with
+// sh a multiple of 2^-11 (exact in FP32) and 0 <= sl < 2^-11.  For |m| <= 2048
+// the product m.sh is a multiple of 2^-11 below 2^13 in magnitude: it and its
+// fractional part are exact in FP32, so the integer part of the phase m.s is
+// removed without rounding; m.sl is added after.
+__device__ __forceinline__ void split_coord(double x, double inv_l, float& sh, float& sl) {
+  double s = x * inv_l;
+  s -= floor(s);
+  const double h = floor(s * 2048.0) * (1.0 / 2048.0);
+  sh = (float)h;
+  sl = (float)(s - h);
+}
+
+// phase in revolutions of k = 2 pi m / l at the split coordinate, FP32 path
+__device__ __forceinline__ float phase_rev(float mx, float my, float mz, float shx, float shy,
+                                           float shz, float slx, float sly, float slz) {
+  float th = mx * shx;
+  th = fmaf(my, shy, th);
+  th = fmaf(mz, shz, th);
+  float f = __builtin_amdgcn_fractf(th);
+  f = fmaf(mx, slx, f);
+  f = fmaf(my, sly, f);
+  return fmaf(mz, slz, f);
+}
+
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float v) {
+  const float y = v - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
+// ---------------------------------------------------------------------------
+// charges: sums for the neutrality check and the self term, FP32 copy
+
+__global__ void k_qsum(const double* __restrict__ q, float* __restrict__ qf,
+                       double* __restrict__ out, int64_t n) {
+  __shared__ double s0[1024], s1[1024], s2[1024];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = t; i < n; i += blockDim.x) {
+    const double v = q[i];
+    qf[i] = (float)v;
+    a += v; b += fabs(v); c += v * v;
+  }
+  s0[t] = a; s1[t] = b; s2[t] = c;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) { s0[t] += s0[t + w]; s1[t] += s1[t + w]; s2[t] += s2[t + w]; }
+    __syncthreads();
+  }
+  if (t == 0) { out[0] = s0[0]; out[1] = s1[0]; out[2] = s2[0]; }
+}
+
+hipError_t launch_qsum(const double* d_q, float* d_qf, double* d_out3, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_qsum, dim3(1), dim3(1024), 0, s, d_q, d_qf, d_out3, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// standalone tables / draw (when the batch or the cell is read on the host
+// before a fused step has run)
+
+__global__ void __launch_bounds__(256) k_tables(StepArgs a) {
+  __shared__ BoxState sbs;
+  __shared__ double sh_T[3];
+  double l[3];
+  box_source(a, l);
+  build_tables(l, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T);
+  if (threadIdx.x == 0) {
+    BoxState b = sbs;
+    b.err |= a.bs->err;
+    *a.bs = b;
+  }
+}
+
+hipError_t launch_tables(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_sample(StepArgs a) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= a.p) return;
+  const BoxState b = *a.bs;
+  int m[3];
+  draw_frequency(b, a.tab, a.seed, a.sysid, a.step, l, m);
+  a.m[3 * l] = m[0]; a.m[3 * l + 1] = m[1]; a.m[3 * l + 2] = m[2];
+}
+
+hipError_t launch_sample(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample, dim3((a.p + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_sfac: tables, draw, structure factors, fixed-order reduction, virial
+
+// Dynamic LDS of k_sfac, three regions:
+//   R0 particle tiles (kTile x 32 B); after the main loop: wave partials and rho
+//   R1 the block's slice of the batch (3 ints per frequency)
+//   R2 the sampler tables; after the draw: the 7 x kSfacThreads virial summands
+constexpr size_t kR0 = (size_t)kTile * 32;
+constexpr size_t kR1 = (size_t)kSfacThreads * 3 * sizeof(int);
+constexpr size_t kR2min = (size_t)7 * kSfacThreads * sizeof(double);
+
+size_t sfac_lds_bytes(const StepArgs& a) {
+  const int cap = a.mcap[0] + a.mcap[1] + a.mcap[2];
+  const size_t tabs = (size_t)(4 * cap + 3) * sizeof(double);
+  return kR0 + kR1 + (tabs > kR2min ? tabs : kR2min);
+}
+
+// Data handed from block to block within a launch is stored and loaded with
+// agent-scope atomic accesses (coherent across the XCDs' separate L2 caches)
+// rather than plain accesses plus L2 write-back / invalidate fences, which
+// cost microseconds per block on this chip.
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh2(double2* p, double2 v) {
+  st_coh(&p->x, v.x);
+  st_coh(&p->y, v.y);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 ld_coh2(const double2* p) {
+  return make_double2(ld_coh(&p->x), ld_coh(&p->y));
+}
+
+// Last-arriving test.  Every block of a group increments the group counter
+// once, after all its waves' coherent stores have completed (waitcnt, then
+// barrier); the block that brings the counter to `total` gets true
+// (block-uniform) and may read the others' coherent stores.
+__device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, int* sh_flag) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    *sh_flag = (__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                total - 1u) ? 1 : 0;
+  __syncthreads();
+  return *sh_flag != 0;
+}
+
+// dst[i] = sum over r = 0..R-1 of src[r*stride + i] for i < W, in a fixed
+// order, by the whole block (W a power of two <= the block size).  Thread t
+// owns column t % W and rows t / W + RG*j (RG = threads / W); its loads are
+// issued together, then the RG row-group sums are added in order through
+// LDS.  src is read with coherent loads; dst is written with coherent stores
+// when dst_coh, else with LDS/plain stores.  Reached by every thread.
+__device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
+                               bool dst_coh, double2* scratch) {
+  const int t = threadIdx.x;
+  const int RG = kSfacThreads / W;
+  const int col = t % W, rg = t / W;
+  double2 acc = make_double2(0.0, 0.0);
+  int r = rg;
+  for (; r + 3 * RG < R; r += 4 * RG) {
+    const double2 v0 = ld_coh2(src + (int64_t)r * stride + col);
+    const double2 v1 = ld_coh2(src + (int64_t)(r + RG) * stride + col);
+    const double2 v2 = ld_coh2(src + (int64_t)(r + 2 * RG) * stride + col);
+    const double2 v3 = ld_coh2(src + (int64_t)(r + 3 * RG) * stride + col);
+    acc.x += v0.x; acc.y += v0.y; acc.x += v1.x; acc.y += v1.y;
+    acc.x += v2.x; acc.y += v2.y; acc.x += v3.x; acc.y += v3.y;
+  }
+  for (; r < R; r += RG) {
+    const double2 v = ld_coh2(src + (int64_t)r * stride + col);
+    acc.x += v.x; acc.y += v.y;
+  }
+  __syncthreads();
+  scratch[t] = acc;
+  __syncthreads();
+  if (t < W) {
+    double2 s2 = scratch[t];
+    for (int g = 1; g < RG; ++g) { const double2 v = scratch[g * W + t]; s2.x += v.x; s2.y += v.y; }
+    if (dst_coh) st_coh2(dst + t, s2); else dst[t] = s2;
+  }
+  __syncthreads();
+}
+
+template <bool F64>
+__global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BoxState sbs;
+  __shared__ double sh_T[3];
+  __shared__ int sh_flag;
+  __shared__ double sh_vs[7][kSfacWaves];
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int x = blockIdx.x, y = blockIdx.y;
+  const int KB = a.KB, SUB = kSfacWaves / KB, PB = kWave * KB;
+  unsigned char* base = lds_raw;
+  int* sm = reinterpret_cast<int*>(base + kR0);                     // batch slice, 3 ints each
+  double* tabs = reinterpret_cast<double*>(base + kR0 + kR1);
+
+  // ---- first tile of particles: loads issued now, consumed after the tables
+  const int64_t c0 = (int64_t)x * a.chunk;
+  const int64_t c1 = min(a.n, c0 + (int64_t)a.chunk);
+  const int first_cnt = (int)min((int64_t)kTile, c1 - c0);
+  double px = 0.0, py = 0.0, pz = 0.0, pq = 0.0;
+  if (tid < first_cnt) {
+    px = a.x[c0 + tid]; py = a.y[c0 + tid]; pz = a.z[c0 + tid];
+    pq = F64 ? a.q[c0 + tid] : (double)a.qf[c0 + tid];
+  }
+
+  // ---- cell values and tables
+  const bool need_tables = a.sample || a.box_src != BOX_COMMITTED;
+  if (need_tables) {
+    double l[3];
+    box_source(a, l);
+    build_tables(l, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    if (x == 0 && y == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
+      BoxState b = sbs;
+      b.err |= a.bs->err;
+      *a.bs = b;
+    }
+  } else {
+    if (tid == 0) sbs = *a.bs;
+    __syncthreads();
+  }
+
+  // ---- this block's slice of the batch
+  if (tid < PB) {
+    const int l = y * PB + tid;
+    int mv[3] = {0, 0, 0};
+    if (l < a.p) {
+      if (a.sample) {
+        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, l, mv);
+        if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
+      } else {
+        mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
+      }
+    }
+    sm[3 * tid] = mv[0]; sm[3 * tid + 1] = mv[1]; sm[3 * tid + 2] = mv[2];
+  }
+  __syncthreads();
+
+  // ---- structure factors over the chunk: lane = frequency, wave = (group, sub)
+  const int kg = wave % KB, sub = wave / KB;
+  const int lk = kg * kWave + lane;
+  const double ix = sbs.inv_l[0], iy = sbs.inv_l[1], iz = sbs.inv_l[2];
+  const int runlen = SUB * kKahan;
+  double2 part;
+  if (!F64) {
+    float4* tA = reinterpret_cast<float4*>(base);           // sh.x sh.y sh.z q
+    float4* tB = tA + kTile;                                // sl.x sl.y sl.z 0
+    const float mx = (float)sm[3 * lk], my = (float)sm[3 * lk + 1], mz = (float)sm[3 * lk + 2];
+    float SA = 0.f, CA = 0.f, SB = 0.f, CB = 0.f;
+    for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
+      const int cnt = (int)min((int64_t)kTile, c1 - t0);
+      const int cntp = (cnt + runlen - 1) / runlen * runlen;
+      __syncthreads();
+      for (int j = tid; j < cntp; j += kSfacThreads) {
+        float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < cnt) {
+          const int64_t i = t0 + j;
+          const bool pre = (t0 == c0);       // j == tid here: prefetched above
+          split_coord(pre ? px : a.x[i], ix, u.x, v.x);
+          split_coord(pre ? py : a.y[i], iy, u.y, v.y);
+          split_coord(pre ? pz : a.z[i], iz, u.z, v.z);
+          u.w = pre ? (float)pq : a.qf[i];
+        }
+        tA[j] = u; tB[j] = v;
+      }
+      __syncthreads();
+      for (int j0 = sub; j0 < cntp; j0 += runlen) {
+        float ra = 0.f, rb = 0.f;
+#pragma unroll
+        for (int u = 0; u < kKahan; ++u) {
+          const int j = j0 + u * SUB;
+          const float4 pa = tA[j], pb = tB[j];
+          const float f = phase_rev(mx, my, mz, pa.x, pa.y, pa.z, pb.x, pb.y, pb.z);
+          const float cs = __builtin_amdgcn_cosf(f);
+          const float sn = __builtin_amdgcn_sinf(f);
+          ra = fmaf(pa.w, cs, ra);
+          rb = fmaf(pa.w, sn, rb);
+        }
+        kahan_add(SA, CA, ra);
+        kahan_add(SB, CB, rb);
+      }
+    }
+    part = make_double2((double)SA - (double)CA, (double)SB - (double)CB);
+  } else {
+    double2* tA = reinterpret_cast<double2*>(base);         // s.x s.y
+    double2* tB = tA + kTile;                               // s.z q
+    const double mx = (double)sm[3 * lk], my = (double)sm[3 * lk + 1], mz = (double)sm[3 * lk + 2];
+    double A = 0.0, B = 0.0;
+    for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
+      const int cnt = (int)min((int64_t)kTile, c1 - t0);
+      const int cntp = (cnt + SUB - 1) / SUB * SUB;
+      __syncthreads();
+      for (int j = tid; j < cntp; j += kSfacThreads) {
+        double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+        if (j < cnt) {
+          const int64_t i = t0 + j;
+          const bool pre = (t0 == c0);       // j == tid here: prefetched above
+          double sx = (pre ? px : a.x[i]) * ix, sy = (pre ? py : a.y[i]) * iy;
+          double sz = (pre ? pz : a.z[i]) * iz;
+          sx -= floor(sx); sy -= floor(sy); sz -= floor(sz);
+          u = make_double2(sx, sy);
+          v = make_double2(sz, pre ? pq : a.q[i]);
+        }
+        tA[j] = u; tB[j] = v;
+      }
+      __syncthreads();
+      for (int j = sub; j < cntp; j += SUB) {
+        const double2 pa = tA[j], pb = tB[j];
+        const double t = mx * pa.x + my * pa.y + mz * pb.x;
+        const double f = t - rint(t);
+        double sn, cs;
+        sincospi(2.0 * f, &sn, &cs);
+        A = fma(pb.y, cs, A);
+        B = fma(pb.y, sn, B);
+      }
+    }
+    part = make_double2(A, B);
+  }
+  __syncthreads();                          // tiles are dead from here on
+  double2* red = reinterpret_cast<double2*>(base);                     // kSfacThreads entries
+  double2* srho = red + kSfacThreads;                                  // PB entries
+  red[tid] = part;
+  __syncthreads();
+  const int64_t slice = (int64_t)y * PB;
+  if (tid < PB) {
+    double2 s2 = make_double2(0.0, 0.0);
+    for (int sb = 0; sb < SUB; ++sb) {     // wave = sb*KB + kg  ->  index sb*PB + tid
+      const double2 v = red[sb * PB + tid];
+      s2.x += v.x; s2.y += v.y;
+    }
+    st_coh2(a.partial + (int64_t)x * a.Ppad + slice + tid, s2);
+  }
+
+  // ---- level 1: the last block of each chunk group sums the group's partials
+  const int g = x / a.GX;
+  const int gsize = min(a.GX, a.X - g * a.GX);
+  if (a.NG > 1) {
+    if (!arrive_last(&a.cnt[y * a.NG + g], (uint32_t)gsize, &sh_flag)) return;
+    block_sum_rows(a.partial + (int64_t)g * a.GX * a.Ppad + slice, a.Ppad, gsize, PB,
+                   a.gpart + (int64_t)g * a.Ppad + slice, true, red);
+    if (tid == 0) a.cnt[y * a.NG + g] = 0u;
+  }
+
+  // ---- level 2: the last group of the slice forms rho, the force
+  // coefficients and the per-frequency virial summands
+  if (!arrive_last(&a.cnt[a.Y * a.NG + y], (uint32_t)a.NG, &sh_flag)) return;
+  if (a.NG > 1)
+    block_sum_rows(a.gpart + slice, a.Ppad, a.NG, PB, srho, false, red);
+  else
+    block_sum_rows(a.partial + slice, a.Ppad, a.X, PB, srho, false, red);
+  double* stv = tabs;                       // R2: 7 x kSfacThreads summands (tables are dead)
+  double tv[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (tid < PB && slice + tid < a.p) {
+    const int l = (int)(slice + tid);
+    const double2 r = srho[tid];
+    a.rho[l] = r;
+    double km[3], kk[3];
+    for (int c = 0; c < 3; ++c) {
+      km[c] = (double)sm[3 * tid + c];
+      kk[c] = 2.0 * M_PI * km[c] * sbs.inv_l[c];
+    }
+    const double k2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
+    const double ik2 = 1.0 / k2;
+    const double cl = a.coulomb * (sbs.S / (double)a.p) * 4.0 * M_PI / sbs.V * ik2;
+    const double fac = (r.x * r.x + r.y * r.y) * ik2;
+    const double beta = 2.0 * (ik2 + 0.25 / a.alpha);
+    tv[0] = fac * (1.0 - beta * kk[0] * kk[0]);
+    tv[1] = fac * (1.0 - beta * kk[1] * kk[1]);
+    tv[2] = fac * (1.0 - beta * kk[2] * kk[2]);
+    tv[3] = -fac * beta * kk[0] * kk[1];
+    tv[4] = -fac * beta * kk[0] * kk[2];
+    tv[5] = -fac * beta * kk[1] * kk[2];
+    tv[6] = fac;
+    if (a.Y > 1) {
+      double* tr = a.terms + (int64_t)l * 8;
+      for (int c = 0; c < 7; ++c) st_coh(tr + c, tv[c]);
+    }
+    FCoef64 f;
+    FCoef32 h;
+    for (int c = 0; c < 3; ++c) {
+      f.m[c] = km[c]; f.k[c] = kk[c];
+      h.m[c] = (float)km[c]; h.k[c] = (float)kk[c];
+    }
+    f.cA = cl * r.x; f.cB = cl * r.y;
+    h.cA = (float)f.cA; h.cB = (float)f.cB;
+    a.fc64[l] = f;
+    a.fc32[l] = h;
+  }
+  if (tid == 0) a.cnt[a.Y * a.NG + y] = 0u;
+
+  // ---- level 3: the batch sum -> virial tensor and energy.  With one slice
+  // the level-2 block holds every summand; otherwise the last slice loads
+  // them back, thread t taking frequencies t, t + kSfacThreads, ...  Then a
+  // fixed-order reduction over the threads through LDS.
+  if (a.Y > 1) {
+    if (!arrive_last(&a.cnt[a.Y * a.NG + a.Y], (uint32_t)a.Y, &sh_flag)) return;
+    for (int c = 0; c < 7; ++c) tv[c] = 0.0;
+    for (int l = tid; l < a.p; l += kSfacThreads)
+      for (int c = 0; c < 7; ++c) tv[c] += ld_coh(a.terms + (int64_t)l * 8 + c);
+  }
+  for (int c = 0; c < 7; ++c) stv[c * kSfacThreads + tid] = tv[c];
+  __syncthreads();
+  if (tid < 7 * kSfacWaves) {
+    const int c = tid / kSfacWaves, part_i = tid % kSfacWaves;
+    double v = 0.0;
+    for (int l = part_i; l < kSfacThreads; l += kSfacWaves) v += stv[c * kSfacThreads + l];
+    sh_vs[c][part_i] = v;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double v = 0.0;
+    for (int w = 0; w < kSfacWaves; ++w) v += sh_vs[tid][w];
+    const double pref = a.coulomb * (2.0 * M_PI / sbs.V) * (sbs.S / (double)a.p);
+    if (tid < 6) { if (a.virial6) a.virial6[tid] = pref * v; }
+    else if (a.energy) a.energy[0] = pref * v + a.self_energy;
+  }
+  if (tid == 0 && a.Y > 1) a.cnt[a.Y * a.NG + a.Y] = 0u;
+}
+
+hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
+  const dim3 grid(a.X, a.Y);
+  const size_t lds = sfac_lds_bytes(a);
+  if (precision == RBE_PREC_FP32)
+    hipLaunchKernelGGL(k_sfac<false>, grid, dim3(kSfacThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_sfac<true>, grid, dim3(kSfacThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_force: 64 particles per block, the batch split over KS waves.  The
+// frequency constants are staged in LDS (read by every lane at the same
+// address) when they fit, else read from global memory with scalar loads.
+
+constexpr int kForceStageBytes = 32768;
+
+template <bool F64>
+__global__ void __launch_bounds__(1024) k_force(StepArgs a) {
+  using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
+  __shared__ double red[16][kWave][3];
+  __shared__ __align__(16) uint4 scoef[kForceStageBytes / 16];
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int KS = blockDim.x / kWave;
+  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+  const bool valid = i < a.n;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (valid) { xi = a.x[i]; yi = a.y[i]; zi = a.z[i]; }
+  const double ix = a.bs->inv_l[0], iy = a.bs->inv_l[1], iz = a.bs->inv_l[2];
+  const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)
+                          : reinterpret_cast<const Coef*>(a.fc32);
+  const bool staged = (size_t)a.p * sizeof(Coef) <= kForceStageBytes;
+  if (staged) {
+    const int nvec = (int)((size_t)a.p * sizeof(Coef) / 16);
+    const uint4* src = reinterpret_cast<const uint4*>(gcoef);
+    for (int v = tid; v < nvec; v += blockDim.x) scoef[v] = src[v];
+  }
+  __syncthreads();
+  const Coef* fc = staged ? reinterpret_cast<const Coef*>(scoef) : gcoef;
+  const int per = (a.p + KS - 1) / KS;
+  const int l0 = min(a.p, wave * per), l1 = min(a.p, l0 + per);
+  double gx, gy, gz;
+  if (!F64) {
+    float shx, shy, shz, slx, sly, slz;
+    split_coord(xi, ix, shx, slx);
+    split_coord(yi, iy, shy, sly);
+    split_coord(zi, iz, shz, slz);
+    float hx = 0.f, hy = 0.f, hz = 0.f;
+#pragma unroll 4
+    for (int l = l0; l < l1; ++l) {
+      const FCoef32 c = reinterpret_cast<const FCoef32*>(fc)[l];
+      const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx, shy, shz, slx, sly, slz);
+      const float cs = __builtin_amdgcn_cosf(f);
+      const float sn = __builtin_amdgcn_sinf(f);
+      const float gg = fmaf(cs, c.cB, -sn * c.cA);
+      hx = fmaf(gg, c.k[0], hx);
+      hy = fmaf(gg, c.k[1], hy);
+      hz = fmaf(gg, c.k[2], hz);
+    }
+    gx = hx; gy = hy; gz = hz;
+  } else {
+    double sx = xi * ix, sy = yi * iy, sz = zi * iz;
+    sx -= floor(sx); sy -= floor(sy); sz -= floor(sz);
+    gx = gy = gz = 0.0;
+    for (int l = l0; l < l1; ++l) {
+      const FCoef64 c = reinterpret_cast<const FCoef64*>(fc)[l];
+      const double t = c.m[0] * sx + c.m[1] * sy + c.m[2] * sz;
+      const double f = t - rint(t);
+      double sn, cs;
+      sincospi(2.0 * f, &sn, &cs);
+      const double gg = cs * c.cB - sn * c.cA;
+      gx = fma(gg, c.k[0], gx);
+      gy = fma(gg, c.k[1], gy);
+      gz = fma(gg, c.k[2], gz);
+    }
+  }
+  red[wave][lane][0] = gx; red[wave][lane][1] = gy; red[wave][lane][2] = gz;
+  __syncthreads();
+  if (wave == 0 && valid) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int w = 0; w < KS; ++w) { sx += red[w][lane][0]; sy += red[w][lane][1]; sz += red[w][lane][2]; }
+    const double qi = -a.q[i];
+    if (a.accumulate) { a.fx[i] += qi * sx; a.fy[i] += qi * sy; a.fz[i] += qi * sz; }
+    else { a.fx[i] = qi * sx; a.fy[i] = qi * sy; a.fz[i] = qi * sz; }
+  }
+}
+
+hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
+  const int64_t blocks = (a.n + kWave - 1) / kWave;
+  const dim3 block(a.KS * kWave);
+  if (precision == RBE_PREC_FP32)
+    hipLaunchKernelGGL(k_force<false>, dim3((unsigned)blocks), block, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_force<true>, dim3((unsigned)blocks), block, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rbe

@@ -1,0 +1,195 @@
+"""ctypes binding of librbe.so (C ABI declared in include/rbe.h).
+
+Argument marshalling only: every step of the Fourier-space path runs in the
+library's HIP kernels.  Device arrays are torch tensors on a ROCm device
+(float64, contiguous); torch is used for device memory and streams.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbe.so")
+
+RBE_OK = 0
+STATUS_NAMES = {0: "RBE_OK", 1: "RBE_ERR_ARG", 2: "RBE_ERR_ALLOC", 3: "RBE_ERR_DEVICE",
+                4: "RBE_ERR_STATE", 5: "RBE_ERR_NONNEUTRAL", 6: "RBE_ERR_CAPACITY"}
+BOX_MODES = {"iso": 0, "semiiso": 1, "aniso": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+# every symbol include/rbe.h declares
+EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev",
+           "rbe_sample_k", "rbe_set_k", "rbe_get_k", "rbe_forces_pressure", "rbe_get_rho",
+           "rbe_get_box_info", "rbe_check", "rbe_timing_enable", "rbe_timing_read",
+           "rbe_destroy", "rbe_last_error", "rbe_version"]
+KERNEL_KINDS = ["tables", "sample", "sfac", "force"]
+
+
+class RBEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("box_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("coulomb", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load librbe.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("librbe.so not found at %s: build it with "
+                          "`python -m paper_2110_14362_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u64, dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.c_uint64, ctypes.POINTER(ctypes.c_double))
+    sig = {
+        "rbe_init": [ctypes.POINTER(Config), vp, dp, vp, ctypes.POINTER(vp)],
+        "rbe_set_stream": [vp, vp],
+        "rbe_rescale_box": [vp, dp],
+        "rbe_rescale_box_dev": [vp, vp],
+        "rbe_sample_k": [vp, u64],
+        "rbe_set_k": [vp, ctypes.POINTER(i32), i32],
+        "rbe_get_k": [vp, ctypes.POINTER(i32)],
+        "rbe_forces_pressure": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
+        "rbe_get_rho": [vp, dp],
+        "rbe_get_box_info": [vp, dp],
+        "rbe_check": [vp],
+        "rbe_timing_enable": [vp, i32],
+        "rbe_timing_read": [vp, dp, ctypes.POINTER(i32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rbe_destroy.argtypes = [vp]
+    lib.rbe_destroy.restype = None
+    lib.rbe_last_error.argtypes = []
+    lib.rbe_last_error.restype = ctypes.c_char_p
+    lib.rbe_version.argtypes = []
+    lib.rbe_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != RBE_OK:
+        raise RBEError(status, _lib.rbe_last_error().decode())
+
+
+def _dptr(t, name, n=None, dtype="float64"):
+    """Device pointer of a contiguous float64 torch tensor on a GPU."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a torch tensor on a ROCm device" % name)
+    want = getattr(torch, dtype)
+    if t.dtype != want or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class RBE:
+    """One system's Fourier-space RBE context (rbe_init ... rbe_destroy)."""
+
+    def __init__(self, q, box, p, alpha, coulomb=1.0, precision="fp32", box_mode="iso",
+                 seed=0, system_id=0, stream=None):
+        lib = load_library()
+        n = int(q.numel())
+        cfg = Config(n=n, p=int(p), box_mode=BOX_MODES[box_mode],
+                     precision=PRECISIONS[precision], reserved=0, alpha=float(alpha),
+                     coulomb=float(coulomb), seed=int(seed) & (2**64 - 1),
+                     system_id=int(system_id) & (2**64 - 1))
+        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        ctx = ctypes.c_void_p()
+        _check(lib.rbe_init(ctypes.byref(cfg), _dptr(q, "q", n), boxarr,
+                            _stream_handle(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.n = n
+        self.p = int(p)
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.rbe_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        _check(_lib.rbe_set_stream(self._ctx, _stream_handle(stream)))
+
+    def rescale_box(self, box):
+        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        _check(_lib.rbe_rescale_box(self._ctx, boxarr))
+
+    def rescale_box_dev(self, d_box):
+        _check(_lib.rbe_rescale_box_dev(self._ctx, _dptr(d_box, "box", 3)))
+
+    def sample_k(self, step):
+        _check(_lib.rbe_sample_k(self._ctx, ctypes.c_uint64(int(step) & (2**64 - 1))))
+
+    def set_k(self, m):
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.int32).reshape(-1, 3))
+        _check(_lib.rbe_set_k(self._ctx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              m.shape[0]))
+
+    def get_k(self):
+        out = np.zeros((self.p, 3), dtype=np.int32)
+        _check(_lib.rbe_get_k(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def forces_pressure(self, x, y, z, fx, fy, fz, accumulate=False, virial6=None, energy=None):
+        n = self.n
+        _check(_lib.rbe_forces_pressure(
+            self._ctx, _dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n),
+            _dptr(fx, "fx", n), _dptr(fy, "fy", n), _dptr(fz, "fz", n), int(bool(accumulate)),
+            _dptr(virial6, "virial6", 6) if virial6 is not None else None,
+            _dptr(energy, "energy", 1) if energy is not None else None))
+
+    def get_rho(self):
+        out = np.zeros(2 * self.p, dtype=np.float64)
+        _check(_lib.rbe_get_rho(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[0::2] + 1j * out[1::2]
+
+    def get_box_info(self):
+        out = np.zeros(12, dtype=np.float64)
+        _check(_lib.rbe_get_box_info(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return dict(V=out[0], S=out[1], H=out[2:5].copy(), box=out[5:8].copy(),
+                    mcut=out[8:11].astype(int), err=int(out[11]))
+
+    def check(self):
+        _check(_lib.rbe_check(self._ctx))
+
+    def timing_enable(self, max_launches):
+        _check(_lib.rbe_timing_enable(self._ctx, int(max_launches)))
+
+    def timing_read(self):
+        """{kernel kind: (total ms, launches)} since the last read."""
+        ms = np.zeros(len(KERNEL_KINDS), dtype=np.float64)
+        cnt = np.zeros(len(KERNEL_KINDS), dtype=np.int32)
+        _check(_lib.rbe_timing_read(self._ctx, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}

@@ -1,0 +1,294 @@
+"""HIP path vs the FP64 oracle on the same batch of frequencies.
+
+Tolerances (relative): 1e-5 on the FP64 path, 1e-4 on the FP32 path, for the
+RMS force error, the Frobenius virial error, rho (scaled by sqrt(sum q^2)) and
+the energy.  Batches come from the oracle's own sampler; the GPU sampler is
+checked to draw the identical batch separately.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ewald as oew
+from oracle import sampler as osamp
+from paper_2110_14362_amd import workloads
+from tests.gpu_cases import TOL, errors, gpu_eval, oracle_eval
+
+pytestmark = pytest.mark.gpu
+
+
+def small_water(n_mol=1000, seed=5):
+    s = workloads.water(n_mol, seed=seed)
+    s.update(alpha=0.09, p=100, coulomb=332.0637)
+    return s
+
+
+def electrolyte():
+    return workloads.make("electrolyte_1k")
+
+
+def oracle_batch(sysd, p, step=0, seed=11, system_id=0):
+    return osamp.sample_k(sysd["alpha"], sysd["box"], p, seed=seed, system_id=system_id, step=step)
+
+
+def report(tag, e):
+    print("%-40s force %.2e virial %.2e rho %.2e energy %.2e" %
+          (tag, e["force"], e["virial"], e["rho"], e["energy"]), flush=True)
+
+
+# ------------------------------------------------------------------ cell tables
+
+@pytest.mark.parametrize("alpha,box,mode", [(0.09, (20.0, 20.0, 20.0), "iso"),
+                                            (0.09, (66.88004, 66.88004, 66.88004), "iso"),
+                                            (0.09, (80.0, 80.0, 100.0), "semiiso"),
+                                            (0.3, (5.0, 7.0, 11.0), "aniso")])
+def test_box_info_matches_oracle(gpu, alpha, box, mode):
+    from paper_2110_14362_amd.rbe import RBE
+    import torch
+    q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
+    ctx = RBE(q, box, 8, alpha, box_mode=mode)
+    info = ctx.get_box_info()
+    tb = osamp.box_tables(alpha, box)
+    assert abs(info["V"] - np.prod(box)) < 1e-14 * np.prod(box)
+    assert abs(info["S"] - tb["S"]) < 1e-13 * tb["S"]
+    for a in range(3):
+        assert info["mcut"][a] == osamp.axis_mcut(alpha, box[a])
+        assert abs(info["H"][a] - tb["H"][a]) < 1e-13 * tb["H"][a]
+    assert info["err"] == 0
+
+
+@pytest.mark.parametrize("alpha,box,mode,p", [(0.09, (20.0, 20.0, 20.0), "iso", 100),
+                                              (0.09, (66.88004, 66.88004, 66.88004), "iso", 100),
+                                              (0.09, (80.0, 80.0, 100.0), "semiiso", 200),
+                                              (0.3, (5.0, 7.0, 11.0), "aniso", 333)])
+def test_sampler_draws_the_oracle_batch(gpu, alpha, box, mode, p):
+    from paper_2110_14362_amd.rbe import RBE
+    import torch
+    q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
+    ctx = RBE(q, box, p, alpha, box_mode=mode, seed=2110, system_id=7)
+    for step in (0, 1, 17, 2**40 + 3):
+        ctx.sample_k(step)
+        g = ctx.get_k().astype(np.int64)
+        o = osamp.sample_k(alpha, box, p, seed=2110, system_id=7, step=step)
+        bad = np.where(np.any(g != o, axis=1))[0]
+        assert len(bad) == 0, (step, bad[:5], g[bad[:5]], o[bad[:5]])
+
+
+# ------------------------------------------------------------------ parity
+
+CASES = {
+    "electrolyte_1k": electrolyte,
+    "water_3k": small_water,
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_parity_small(gpu, case, precision):
+    s = CASES[case]()
+    m = oracle_batch(s, s["p"], step=3)
+    g = gpu_eval(s, gpu, precision, m=m)
+    o = oracle_eval(s, m)
+    e = errors(g, o, s["q"])
+    report("%s %s" % (case, precision), e)
+    for key in ("force", "virial", "rho", "energy"):
+        assert e[key] < TOL[precision], (key, e)
+    if precision == "fp64":
+        assert e["force"] < 1e-10 and e["virial"] < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_parity_slab_semiiso(gpu, precision):
+    s = workloads.make("slab_36k")
+    m = oracle_batch(s, s["p"], step=1)
+    g = gpu_eval(s, gpu, precision, m=m, box_mode="semiiso")
+    o = oracle_eval(s, m)
+    e = errors(g, o, s["q"])
+    report("slab_36k %s" % precision, e)
+    for key in ("force", "virial", "rho", "energy"):
+        assert e[key] < TOL[precision], (key, e)
+    # the semi-isotropic coupling reads Pxx + Pyy and Pzz
+    pxy_g = g["virial"][0, 0] + g["virial"][1, 1]
+    pxy_o = o["virial"][0, 0] + o["virial"][1, 1]
+    assert abs(pxy_g - pxy_o) < TOL[precision] * np.linalg.norm(o["virial"])
+    assert abs(g["virial"][2, 2] - o["virial"][2, 2]) < TOL[precision] * np.linalg.norm(o["virial"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_parity_water_30k_bench_size(gpu, precision):
+    # the benchmarked workload, sampled on the GPU, compared in full
+    s = workloads.make("water_30k")
+    g = gpu_eval(s, gpu, precision, step=12345, seed=2110143620)
+    m_o = osamp.sample_k(s["alpha"], s["box"], s["p"], seed=2110143620, system_id=0, step=12345)
+    assert np.array_equal(g["m"], m_o)
+    o = oracle_eval(s, m_o)
+    e = errors(g, o, s["q"])
+    report("water_30k %s" % precision, e)
+    for key in ("force", "virial", "rho", "energy"):
+        assert e[key] < TOL[precision], (key, e)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_parity_water_1m_p2000(gpu, precision):
+    # N = 999,999, P = 2000: the launch configuration of the large sweep.  The
+    # batch repeats 40 distinct frequencies 50 times each, so the oracle sums
+    # 40 distinct terms with weight 50 S/p (grouping equal summands).
+    s = workloads.make("water_1m")
+    p = 2000
+    distinct = oracle_batch(s, 40, step=9)
+    m = np.repeat(distinct, 50, axis=0)
+    g = gpu_eval(s, gpu, precision, m=m)
+    S = osamp.box_tables(s["alpha"], s["box"])["S"]
+    h = np.diag(s["box"])
+    rows = np.random.default_rng(0).choice(len(s["q"]), 10000, replace=False)
+    o = oew.kspace_weighted(s["pos"], s["q"], h, s["alpha"], distinct, 50.0 * S / p,
+                            coulomb=s["coulomb"], force_rows=rows)
+    go = dict(g)
+    go["forces"] = g["forces"][rows]
+    go["rho"] = g["rho"][::50]
+    o["energy"] += oew.self_energy(s["q"], s["alpha"], s["coulomb"])
+    e = errors(go, o, s["q"])
+    report("water_1m p2000 %s" % precision, e)
+    for key in ("force", "virial", "rho", "energy"):
+        assert e[key] < TOL[precision], (key, e)
+    # total force vanishes for any batch (action-reaction over the sample)
+    # (FP32: per-particle errors of ~1e-5 add up over 10^6 particles)
+    Fs = g["forces"].sum(axis=0)
+    tol = 1e-10 if precision == "fp64" else TOL[precision]
+    assert np.abs(Fs).max() < tol * np.sqrt((g["forces"] ** 2).sum())
+
+
+# ------------------------------------------------------------------ edge cases
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,p", [(2, 1), (17, 65), (4, 3), (1000, 1), (258, 129)])
+def test_ragged_sizes(gpu, precision, n, p):
+    s = workloads.random_neutral(n, (9.0, 9.0, 9.0), seed=n + p)
+    s.update(alpha=0.3, coulomb=1.0)
+    m = oracle_batch(s, p, step=p)
+    e = errors(gpu_eval(s, gpu, precision, m=m), oracle_eval(s, m), s["q"])
+    report("n=%d p=%d %s" % (n, p, precision), e)
+    for key in ("force", "virial", "rho", "energy"):
+        assert e[key] < TOL[precision], (key, e)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_table_edge_and_large_m(gpu, precision):
+    s = workloads.random_neutral(64, (7.0, 7.0, 7.0), seed=4)
+    s.update(alpha=0.3, coulomb=1.0)
+    m = np.array([[2048, -2048, 1], [-2048, 0, 0], [0, 0, 2047], [1, 0, 0], [-1, 1, -1],
+                  [1500, 3, -999]])
+    e = errors(gpu_eval(s, gpu, precision, m=m), oracle_eval(s, m), s["q"])
+    report("large m %s" % precision, e)
+    for key in ("force", "rho"):
+        assert e[key] < 10 * TOL[precision], (key, e)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_unwrapped_positions_and_accumulate(gpu, precision):
+    s = electrolyte()
+    m = oracle_batch(s, 100, step=8)
+    base = gpu_eval(s, gpu, precision, m=m)
+    shift = np.random.default_rng(3).integers(-3, 4, size=s["pos"].shape) * s["box"]
+    moved = gpu_eval(s, gpu, precision, m=m, shift=shift)
+    e = errors(moved, base, s["q"])
+    assert e["force"] < TOL[precision] and e["virial"] < TOL[precision]
+    f0 = np.random.default_rng(4).standard_normal(s["pos"].shape)
+    acc = gpu_eval(s, gpu, precision, m=m, accumulate=True, f0=f0)
+    assert np.allclose(acc["forces"] - f0, base["forces"], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bitwise_reproducible(gpu, precision):
+    s = small_water()
+    a = gpu_eval(s, gpu, precision, step=5)
+    b = gpu_eval(s, gpu, precision, step=5)
+    assert np.array_equal(a["forces"], b["forces"])
+    assert np.array_equal(a["virial"], b["virial"])
+    assert np.array_equal(a["rho"], b["rho"])
+
+
+def test_nacl_crystal_zero_forces(gpu):
+    # every ion of a perfect rocksalt crystal is a symmetry centre: F* = 0
+    s = workloads.nacl_crystal(cells=4, a=1.0)
+    s.update(alpha=1.0, coulomb=1.0)
+    m = oracle_batch(s, 64, step=0)
+    g = gpu_eval(s, gpu, "fp64", m=m)
+    o = oracle_eval(s, m)
+    scale = np.sqrt((s["q"] ** 2).sum())
+    assert np.abs(g["rho"] - o["rho"]).max() < 1e-9 * scale
+    assert np.abs(g["forces"]).max() < 1e-8
+
+
+# ------------------------------------------------------------------ errors
+
+def test_error_paths(gpu):
+    import torch
+    from paper_2110_14362_amd.rbe import RBE, RBEError
+    q = torch.tensor([1.0, -0.5], dtype=torch.float64, device=gpu)
+    with pytest.raises(RBEError) as ei:
+        RBE(q, (10.0, 10.0, 10.0), 4, 0.09)
+    assert ei.value.status == 5      # not neutral
+    q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
+    ctx = RBE(q, (10.0, 10.0, 10.0), 4, 0.09)
+    x = torch.zeros(2, dtype=torch.float64, device=gpu)
+    f = [torch.zeros(2, dtype=torch.float64, device=gpu) for _ in range(3)]
+    with pytest.raises(RBEError) as ei:
+        ctx.forces_pressure(x, x, x, *f)
+    assert ei.value.status == 4      # no batch yet
+    with pytest.raises(RBEError) as ei:
+        ctx.rescale_box((25.0, 25.0, 25.0))
+    assert ei.value.status == 6      # beyond 2x capacity
+    with pytest.raises(RBEError) as ei:
+        ctx.set_k(np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 0, 1]]))
+    assert ei.value.status == 1
+    # device-side rescale beyond capacity: flagged, reported by rbe_check
+    dbox = torch.tensor([30.0, 30.0, 30.0], dtype=torch.float64, device=gpu)
+    ctx.rescale_box_dev(dbox)
+    with pytest.raises(RBEError) as ei:
+        ctx.check()
+    assert ei.value.status == 6
+    ctx.rescale_box((10.0, 10.0, 10.0))
+    ctx.check()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case,p", [("water_30k", 100), ("water_3k", 700)])
+def test_consecutive_steps_with_changing_cell(gpu, case, precision, p):
+    # several steps on one context: new cell, new draw and new positions each
+    # step, every step checked against the oracle (no state may leak between
+    # launches: counters, partial sums, tables)
+    import torch
+    from paper_2110_14362_amd.rbe import RBE
+    s = workloads.make("water_30k") if case == "water_30k" else small_water()
+    s["p"] = p
+    q = torch.tensor(s["q"], dtype=torch.float64, device=gpu)
+    ctx = RBE(q, s["box"], p, s["alpha"], coulomb=s["coulomb"], precision=precision,
+              seed=77, system_id=3)
+    rng = np.random.default_rng(5)
+    for step in range(5):
+        scale = 1.0 + 0.002 * (step - 2)
+        box = s["box"] * scale
+        pos = np.mod(s["pos"] * scale + rng.normal(0, 0.05, s["pos"].shape), box)
+        x, y, z = (torch.tensor(pos[:, a], dtype=torch.float64, device=gpu) for a in range(3))
+        f = [torch.zeros_like(x) for _ in range(3)]
+        vir = torch.zeros(6, dtype=torch.float64, device=gpu)
+        en = torch.zeros(1, dtype=torch.float64, device=gpu)
+        ctx.rescale_box(box)
+        ctx.sample_k(step)
+        ctx.forces_pressure(x, y, z, *f, virial6=vir, energy=en)
+        torch.cuda.synchronize()
+        m = ctx.get_k().astype(np.int64)
+        m_o = osamp.sample_k(s["alpha"], box, p, seed=77, system_id=3, step=step)
+        assert np.array_equal(m, m_o), step
+        sd = dict(s, pos=pos, box=box)
+        o = oracle_eval(sd, m_o)
+        W6 = vir.cpu().numpy()
+        W = np.array([[W6[0], W6[3], W6[4]], [W6[3], W6[1], W6[5]], [W6[4], W6[5], W6[2]]])
+        g = dict(rho=ctx.get_rho(), forces=np.stack([t.cpu().numpy() for t in f], 1),
+                 virial=W, energy=float(en.cpu()[0]))
+        e = errors(g, o, s["q"])
+        report("%s p=%d step %d %s" % (case, p, step, precision), e)
+        for key in ("force", "virial", "rho", "energy"):
+            assert e[key] < TOL[precision], (step, key, e)
