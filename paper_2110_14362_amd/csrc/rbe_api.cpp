@@ -47,6 +47,10 @@ struct rbe_ctx_s {
   FCoef32* d_fc32 = nullptr;     // p
   FCoef64* d_fc64 = nullptr;     // p
   uint32_t* d_cnt = nullptr;     // Y*NG + Y + 1
+  PreDraw* d_pre = nullptr;
+  int32_t* d_m_pre = nullptr;    // 3p
+  bool pre_valid = false;        // a batch for step pre_step was drawn ahead (device checks the cell)
+  uint64_t pre_step = 0;
   // kernel timing (rbe_timing_enable)
   static constexpr int kKinds = 4;
   int timing_cap = 0;
@@ -113,6 +117,15 @@ long env_long(const char* name, long dflt) {
   return dflt;
 }
 
+// 0/1 switch from the environment (anything else: the default)
+bool env_flag(const char* name, bool dflt) {
+  if (const char* e = std::getenv(name)) {
+    if (e[0] == '0' && e[1] == 0) return false;
+    if (e[0] == '1' && e[1] == 0) return true;
+  }
+  return dflt;
+}
+
 // Launch geometry.  Structure factors: 8-wave blocks, KB frequency groups of
 // 64 per block (a power of two), 8/KB particle sub-slices per group; X
 // particle chunks x Y frequency slices, about 2 blocks per CU.  Chunk
@@ -139,10 +152,15 @@ void plan_launch(rbe_ctx_s* c) {
   while ((long)GX * GX < X) ++GX;
   a.GX = GX;
   a.NG = (int)((X + GX - 1) / GX);
+  // small batches: the force kernel sums the group partials of rho itself
+  const long rows = a.NG > 1 ? a.NG : a.X;
+  a.k2reduce = (a.Y == 1 && rows * a.Ppad <= 4096 && env_flag("RBE_K2REDUCE", true)) ? 1 : 0;
   const long fblocks = (c->n + kWave - 1) / kWave;
   const long target_waves = env_long("RBE_FORCE_WAVES", 4096);
   int KS = 1;
-  while (KS < 16 && (long)(KS * 2) * fblocks <= target_waves && KS * 2 <= c->p) KS <<= 1;
+  while (KS < 8 && (long)(KS * 2) * fblocks <= target_waves && KS * 2 <= c->p) KS <<= 1;
+  if (a.k2reduce)
+    while (KS * kWave < a.Ppad) KS <<= 1;        // the block sums Ppad columns at once
   a.KS = KS;
 }
 
@@ -173,7 +191,8 @@ void destroy_events(rbe_ctx_s* c) {
 
 void free_all(rbe_ctx_s* c) {
   void* bufs[] = {c->d_q, c->d_qf, c->d_qsum, c->d_bs, c->d_tab, c->d_m, c->d_partial,
-                  c->d_gpart, c->d_rho, c->d_terms, c->d_fc32, c->d_fc64, c->d_cnt};
+                  c->d_gpart, c->d_rho, c->d_terms, c->d_fc32, c->d_fc64, c->d_cnt,
+                  c->d_pre, c->d_m_pre};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -186,6 +205,8 @@ StepArgs step_args(rbe_ctx_s* c) {
   a.box_ptr = c->pend_box_ptr;
   a.sample = c->pend_sample ? 1 : 0;
   a.step = c->pend_step;
+  a.use_pre = (c->pend_sample && c->pre_valid && c->pre_step == c->pend_step) ? 1 : 0;
+  a.predraw = 0;
   return a;
 }
 
@@ -276,6 +297,8 @@ rbe_status rbe_init(const rbe_config* cfg, const double* d_q, const double* box_
   ok = ok && hipMalloc(&c->d_fc32, p * sizeof(FCoef32)) == hipSuccess;
   ok = ok && hipMalloc(&c->d_fc64, p * sizeof(FCoef64)) == hipSuccess;
   ok = ok && hipMalloc(&c->d_cnt, ncnt * sizeof(uint32_t)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_pre, 2 * sizeof(PreDraw)) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_m_pre, 2 * 3 * p * sizeof(int32_t)) == hipSuccess;
   if (!ok) { free_all(c); delete c; return fail(RBE_ERR_ALLOC, "device allocation failed"); }
 
   A.q = c->d_q; A.qf = c->d_qf;
@@ -287,6 +310,7 @@ rbe_status rbe_init(const rbe_config* cfg, const double* d_q, const double* box_
   A.bs = c->d_bs; A.tab = c->d_tab; A.m = c->d_m;
   A.partial = c->d_partial; A.gpart = c->d_gpart; A.rho = c->d_rho; A.terms = c->d_terms;
   A.fc32 = c->d_fc32; A.fc64 = c->d_fc64; A.cnt = c->d_cnt;
+  A.pre = c->d_pre; A.m_pre = c->d_m_pre;
 
   rbe_status st = RBE_OK;
   double qs[3] = {0, 0, 0};
@@ -294,6 +318,7 @@ rbe_status rbe_init(const rbe_config* cfg, const double* d_q, const double* box_
     if ((e = hipMemsetAsync(c->d_bs, 0, sizeof(BoxState), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
     if ((e = hipMemsetAsync(c->d_cnt, 0, ncnt * sizeof(uint32_t), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
     if ((e = hipMemsetAsync(c->d_m, 0, 3 * p * sizeof(int32_t), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
+    if ((e = hipMemsetAsync(c->d_pre, 0, 2 * sizeof(PreDraw), c->stream)) != hipSuccess) { st = hip_fail(e, "hipMemsetAsync"); break; }
     if ((e = hipMemcpyAsync(c->d_q, d_q, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess) { st = hip_fail(e, "copy charges"); break; }
     if ((e = launch_qsum(c->d_q, c->d_qf, c->d_qsum, c->n, c->stream)) != hipSuccess) { st = hip_fail(e, "charge sums"); break; }
     if ((e = hipMemcpyAsync(qs, c->d_qsum, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) { st = hip_fail(e, "copy charge sums"); break; }
@@ -381,11 +406,14 @@ rbe_status rbe_forces_pressure(rbe_ctx c, const double* d_x, const double* d_y, 
   a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
   a.accumulate = accumulate ? 1 : 0;
   a.virial6 = d_virial6; a.energy = d_energy;
+  // a sampled step draws the next step's batch ahead, for its own cell
+  a.predraw = a.sample && env_flag("RBE_PREDRAW", true) ? 1 : 0;
   const int prec = c->cfg.precision;
   int ts = timed_begin(c, K_SFAC);
   hipError_t e = launch_sfac(prec, a, c->stream);
   timed_end(c, K_SFAC, ts);
   if (e != hipSuccess) return hip_fail(e, "structure-factor kernel");
+  if (a.predraw) { c->pre_valid = true; c->pre_step = a.step + 1; }
   clear_pending(c);
   ts = timed_begin(c, K_FORCE);
   e = launch_force(prec, a, c->stream);

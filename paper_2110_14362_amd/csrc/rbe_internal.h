@@ -43,6 +43,18 @@ struct alignas(64) FCoef64 {
 
 enum BoxSource : int32_t { BOX_COMMITTED = 0, BOX_ARGS = 1, BOX_PTR = 2 };
 
+// A batch drawn ahead of time by an extra block of the structure-factor
+// kernel: the draw of step `step` for the cell `bs` (that launch's cell).  The
+// next launch uses it instead of redrawing when its step and cell match
+// exactly, which gives the identical batch.  Two slots, by step parity, so a
+// launch reads one while its extra block fills the other.
+struct PreDraw {
+  BoxState bs;
+  uint64_t step;
+  int32_t valid;
+  int32_t pad;
+};
+
 // Everything one Fourier-space evaluation of one system needs (passed by value
 // as the kernel argument).
 struct StepArgs {
@@ -63,6 +75,9 @@ struct StepArgs {
   int32_t tab_stride;
   // launch plan
   int32_t X, Y, KB, GX, NG, chunk, Ppad, KS;
+  int32_t k2reduce;     // 1: the force kernel sums the NG group partials itself
+  int32_t predraw;      // 1: an extra k_sfac block draws the batch of step + 1 ahead
+  int32_t use_pre;      // 1: k_sfac may take the batch drawn ahead
   // context-owned state and scratch
   BoxState* bs; double* tab;
   int32_t* m;
@@ -72,6 +87,8 @@ struct StepArgs {
   double* terms;        // [p][8]
   FCoef32* fc32; FCoef64* fc64;
   uint32_t* cnt;        // [Y*NG] + [Y] + [1] arrival counters, zero between launches
+  PreDraw* pre;         // [2] batches drawn ahead: step and cell, by step parity
+  int32_t* m_pre;       // [2][3p]
 };
 
 size_t sfac_lds_bytes(const StepArgs& a);

@@ -339,15 +339,15 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, i
 }
 
 // dst[i] = sum over r = 0..R-1 of src[r*stride + i] for i < W, in a fixed
-// order, by the whole block (W a power of two <= the block size).  Thread t
-// owns column t % W and rows t / W + RG*j (RG = threads / W); its loads are
+// order, by the whole block (W a power of two dividing the block size).
+// Thread t owns column t % W and rows t / W + RG*j (RG = threads / W); its loads are
 // issued together, then the RG row-group sums are added in order through
 // LDS.  src is read with coherent loads; dst is written with coherent stores
 // when dst_coh, else with LDS/plain stores.  Reached by every thread.
 __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
                                bool dst_coh, double2* scratch) {
   const int t = threadIdx.x;
-  const int RG = kSfacThreads / W;
+  const int RG = blockDim.x / W;
   const int col = t % W, rg = t / W;
   double2 acc = make_double2(0.0, 0.0);
   int r = rg;
@@ -374,13 +374,72 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
   __syncthreads();
 }
 
+// Per-frequency constants from rho_l and m_l (eq. (appforce), eq. (apppress)
+// in tensor form, appendix C):
+//   k = 2 pi m / l,  c = C (S/p) 4 pi / (V |k|^2)  ->  force coefficients (c Re rho, c Im rho)
+//   tv = |rho|^2/|k|^2 [delta_ab - 2 (1/|k|^2 + 1/(4 alpha)) k_a k_b]  (xx yy zz xy xz yz) and
+//   tv[6] = |rho|^2/|k|^2, to be scaled by C (2 pi / V)(S/p) after the batch sum.
+__device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const BoxState& b,
+                                            double alpha, double coulomb, int p, FCoef64& f,
+                                            FCoef32& h, double tv[7]) {
+  double km[3], kk[3];
+  for (int c = 0; c < 3; ++c) {
+    km[c] = (double)mi[c];
+    kk[c] = 2.0 * M_PI * km[c] * b.inv_l[c];
+  }
+  const double k2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
+  const double ik2 = 1.0 / k2;
+  const double cl = coulomb * (b.S / (double)p) * 4.0 * M_PI / b.V * ik2;
+  const double fac = (r.x * r.x + r.y * r.y) * ik2;
+  const double beta = 2.0 * (ik2 + 0.25 / alpha);
+  tv[0] = fac * (1.0 - beta * kk[0] * kk[0]);
+  tv[1] = fac * (1.0 - beta * kk[1] * kk[1]);
+  tv[2] = fac * (1.0 - beta * kk[2] * kk[2]);
+  tv[3] = -fac * beta * kk[0] * kk[1];
+  tv[4] = -fac * beta * kk[0] * kk[2];
+  tv[5] = -fac * beta * kk[1] * kk[2];
+  tv[6] = fac;
+  for (int c = 0; c < 3; ++c) {
+    f.m[c] = km[c]; f.k[c] = kk[c];
+    h.m[c] = (float)km[c]; h.k[c] = (float)kk[c];
+  }
+  f.cA = cl * r.x; f.cB = cl * r.y;
+  h.cA = (float)f.cA; h.cB = (float)f.cB;
+}
+
+// Batch sum of the virial summands held one frequency per thread (tv, zero on
+// idle threads), in a fixed order: 7 x 8 strided partial sums over the
+// threads through LDS, then the 8 partials in order.  Writes the virial
+// tensor and the energy.  Reached by every thread; stv holds 7*blockDim.x.
+__device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8],
+                              const BoxState& b, double coulomb, int p, double self_energy,
+                              double* virial6, double* energy) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int c = 0; c < 7; ++c) stv[c * nt + tid] = tv[c];
+  __syncthreads();
+  if (tid < 56) {
+    const int c = tid / 8, part_i = tid % 8;
+    double v = 0.0;
+    for (int l = part_i; l < nt; l += 8) v += stv[c * nt + l];
+    sh_vs[c][part_i] = v;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double v = 0.0;
+    for (int w = 0; w < 8; ++w) v += sh_vs[tid][w];
+    const double pref = coulomb * (2.0 * M_PI / b.V) * (b.S / (double)p);
+    if (tid < 6) { if (virial6) virial6[tid] = pref * v; }
+    else if (energy) energy[0] = pref * v + self_energy;
+  }
+}
+
 template <bool F64>
 __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ BoxState sbs;
   __shared__ double sh_T[3];
   __shared__ int sh_flag;
-  __shared__ double sh_vs[7][kSfacWaves];
+  __shared__ double sh_vs[7][8];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int x = blockIdx.x, y = blockIdx.y;
   const int KB = a.KB, SUB = kSfacWaves / KB, PB = kWave * KB;
@@ -398,9 +457,54 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
     pq = F64 ? a.q[c0 + tid] : (double)a.qf[c0 + tid];
   }
 
+  // ---- the extra block: draw the batch of step + 1 for this launch's cell
+  if (x == a.X) {
+    if (y != 0) return;
+    double l[3];
+    box_source(a, l);
+    build_tables(l, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    const uint64_t next = a.step + 1;
+    const int slot = (int)(next & 1);
+    int32_t* mp = a.m_pre + (int64_t)slot * 3 * a.p;
+    for (int l2 = tid; l2 < a.p; l2 += kSfacThreads) {
+      int mv[3];
+      draw_frequency(sbs, tabs, a.seed, a.sysid, next, l2, mv);
+      mp[3 * l2] = mv[0]; mp[3 * l2 + 1] = mv[1]; mp[3 * l2 + 2] = mv[2];
+    }
+    if (tid == 0) {
+      a.pre[slot].bs = sbs;
+      a.pre[slot].step = next;
+      a.pre[slot].valid = 1;
+    }
+    return;
+  }
+
+  // ---- batch drawn ahead: usable when its step and cell equal this call's
+  const int pslot = (int)(a.step & 1);
+  if (tid == 0) {
+    int ok = 0;
+    if (a.sample && a.use_pre && a.pre[pslot].valid && a.pre[pslot].step == a.step) {
+      double l[3];
+      box_source(a, l);
+      const PreDraw& pd = a.pre[pslot];
+      ok = (l[0] == pd.bs.l[0] && l[1] == pd.bs.l[1] && l[2] == pd.bs.l[2]) ? 1 : 0;
+      if (ok) sbs = pd.bs;
+    }
+    sh_flag = ok;
+  }
+  __syncthreads();
+  const bool pre = sh_flag != 0;
+  const int32_t* m_pre = a.m_pre + (int64_t)pslot * 3 * a.p;
+
   // ---- cell values and tables
-  const bool need_tables = a.sample || a.box_src != BOX_COMMITTED;
-  if (need_tables) {
+  const bool need_tables = !pre && (a.sample || a.box_src != BOX_COMMITTED);
+  if (pre) {
+    if (x == 0 && y == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
+      BoxState b = sbs;
+      b.err |= a.bs->err;
+      *a.bs = b;
+    }
+  } else if (need_tables) {
     double l[3];
     box_source(a, l);
     build_tables(l, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
@@ -419,7 +523,10 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
     const int l = y * PB + tid;
     int mv[3] = {0, 0, 0};
     if (l < a.p) {
-      if (a.sample) {
+      if (pre) {
+        mv[0] = m_pre[3 * l]; mv[1] = m_pre[3 * l + 1]; mv[2] = m_pre[3 * l + 2];
+        if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
+      } else if (a.sample) {
         draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, l, mv);
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else {
@@ -449,11 +556,11 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
         float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j < cnt) {
           const int64_t i = t0 + j;
-          const bool pre = (t0 == c0);       // j == tid here: prefetched above
-          split_coord(pre ? px : a.x[i], ix, u.x, v.x);
-          split_coord(pre ? py : a.y[i], iy, u.y, v.y);
-          split_coord(pre ? pz : a.z[i], iz, u.z, v.z);
-          u.w = pre ? (float)pq : a.qf[i];
+          const bool first = (t0 == c0);     // j == tid here: prefetched above
+          split_coord(first ? px : a.x[i], ix, u.x, v.x);
+          split_coord(first ? py : a.y[i], iy, u.y, v.y);
+          split_coord(first ? pz : a.z[i], iz, u.z, v.z);
+          u.w = first ? (float)pq : a.qf[i];
         }
         tA[j] = u; tB[j] = v;
       }
@@ -488,12 +595,12 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
         double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
         if (j < cnt) {
           const int64_t i = t0 + j;
-          const bool pre = (t0 == c0);       // j == tid here: prefetched above
-          double sx = (pre ? px : a.x[i]) * ix, sy = (pre ? py : a.y[i]) * iy;
-          double sz = (pre ? pz : a.z[i]) * iz;
+          const bool first = (t0 == c0);     // j == tid here: prefetched above
+          double sx = (first ? px : a.x[i]) * ix, sy = (first ? py : a.y[i]) * iy;
+          double sz = (first ? pz : a.z[i]) * iz;
           sx -= floor(sx); sy -= floor(sy); sz -= floor(sz);
           u = make_double2(sx, sy);
-          v = make_double2(sz, pre ? pq : a.q[i]);
+          v = make_double2(sz, first ? pq : a.q[i]);
         }
         tA[j] = u; tB[j] = v;
       }
@@ -535,6 +642,10 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
     if (tid == 0) a.cnt[y * a.NG + g] = 0u;
   }
 
+  // the force kernel takes it from here (small batches: every force block
+  // sums the NG group partials itself)
+  if (a.k2reduce) return;
+
   // ---- level 2: the last group of the slice forms rho, the force
   // coefficients and the per-frequency virial summands
   if (!arrive_last(&a.cnt[a.Y * a.NG + y], (uint32_t)a.NG, &sh_flag)) return;
@@ -548,35 +659,14 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
     const int l = (int)(slice + tid);
     const double2 r = srho[tid];
     a.rho[l] = r;
-    double km[3], kk[3];
-    for (int c = 0; c < 3; ++c) {
-      km[c] = (double)sm[3 * tid + c];
-      kk[c] = 2.0 * M_PI * km[c] * sbs.inv_l[c];
-    }
-    const double k2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
-    const double ik2 = 1.0 / k2;
-    const double cl = a.coulomb * (sbs.S / (double)a.p) * 4.0 * M_PI / sbs.V * ik2;
-    const double fac = (r.x * r.x + r.y * r.y) * ik2;
-    const double beta = 2.0 * (ik2 + 0.25 / a.alpha);
-    tv[0] = fac * (1.0 - beta * kk[0] * kk[0]);
-    tv[1] = fac * (1.0 - beta * kk[1] * kk[1]);
-    tv[2] = fac * (1.0 - beta * kk[2] * kk[2]);
-    tv[3] = -fac * beta * kk[0] * kk[1];
-    tv[4] = -fac * beta * kk[0] * kk[2];
-    tv[5] = -fac * beta * kk[1] * kk[2];
-    tv[6] = fac;
+    const int mi[3] = {sm[3 * tid], sm[3 * tid + 1], sm[3 * tid + 2]};
+    FCoef64 f;
+    FCoef32 h;
+    freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tv);
     if (a.Y > 1) {
       double* tr = a.terms + (int64_t)l * 8;
       for (int c = 0; c < 7; ++c) st_coh(tr + c, tv[c]);
     }
-    FCoef64 f;
-    FCoef32 h;
-    for (int c = 0; c < 3; ++c) {
-      f.m[c] = km[c]; f.k[c] = kk[c];
-      h.m[c] = (float)km[c]; h.k[c] = (float)kk[c];
-    }
-    f.cA = cl * r.x; f.cB = cl * r.y;
-    h.cA = (float)f.cA; h.cB = (float)f.cB;
     a.fc64[l] = f;
     a.fc32[l] = h;
   }
@@ -584,35 +674,19 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
 
   // ---- level 3: the batch sum -> virial tensor and energy.  With one slice
   // the level-2 block holds every summand; otherwise the last slice loads
-  // them back, thread t taking frequencies t, t + kSfacThreads, ...  Then a
-  // fixed-order reduction over the threads through LDS.
+  // them back, thread t taking frequencies t, t + kSfacThreads, ...
   if (a.Y > 1) {
     if (!arrive_last(&a.cnt[a.Y * a.NG + a.Y], (uint32_t)a.Y, &sh_flag)) return;
     for (int c = 0; c < 7; ++c) tv[c] = 0.0;
     for (int l = tid; l < a.p; l += kSfacThreads)
       for (int c = 0; c < 7; ++c) tv[c] += ld_coh(a.terms + (int64_t)l * 8 + c);
   }
-  for (int c = 0; c < 7; ++c) stv[c * kSfacThreads + tid] = tv[c];
-  __syncthreads();
-  if (tid < 7 * kSfacWaves) {
-    const int c = tid / kSfacWaves, part_i = tid % kSfacWaves;
-    double v = 0.0;
-    for (int l = part_i; l < kSfacThreads; l += kSfacWaves) v += stv[c * kSfacThreads + l];
-    sh_vs[c][part_i] = v;
-  }
-  __syncthreads();
-  if (tid < 7) {
-    double v = 0.0;
-    for (int w = 0; w < kSfacWaves; ++w) v += sh_vs[tid][w];
-    const double pref = a.coulomb * (2.0 * M_PI / sbs.V) * (sbs.S / (double)a.p);
-    if (tid < 6) { if (a.virial6) a.virial6[tid] = pref * v; }
-    else if (a.energy) a.energy[0] = pref * v + a.self_energy;
-  }
+  virial_energy(tv, stv, sh_vs, sbs, a.coulomb, a.p, a.self_energy, a.virial6, a.energy);
   if (tid == 0 && a.Y > 1) a.cnt[a.Y * a.NG + a.Y] = 0u;
 }
 
 hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
-  const dim3 grid(a.X, a.Y);
+  const dim3 grid(a.X + (a.predraw ? 1 : 0), a.Y);
   const size_t lds = sfac_lds_bytes(a);
   if (precision == RBE_PREC_FP32)
     hipLaunchKernelGGL(k_sfac<false>, grid, dim3(kSfacThreads), lds, s, a);
@@ -625,30 +699,82 @@ hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
 // k_force: 64 particles per block, the batch split over KS waves.  The
 // frequency constants are staged in LDS (read by every lane at the same
 // address) when they fit, else read from global memory with scalar loads.
+// Small batches (k2reduce): every block first sums the group partials of
+// rho itself, in one fixed order, and forms the constants in LDS.
+// In that mode one extra block (the last) does the batch-wide work instead
+// of forces: rho, the virial tensor and the energy.
 
 constexpr int kForceStageBytes = 32768;
 
 template <bool F64>
 __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
   using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
-  __shared__ double red[16][kWave][3];
+  __shared__ __align__(16) double red[16][kWave][3];
   __shared__ __align__(16) uint4 scoef[kForceStageBytes / 16];
+  __shared__ BoxState sbs;
+  __shared__ double sh_T[3];
+  __shared__ double sh_vs[7][8];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int KS = blockDim.x / kWave;
+  const bool extra = a.k2reduce && blockIdx.x == gridDim.x - 1;
+  // rows of rho partials left by k_sfac in k2reduce mode
+  const double2* rows = a.NG > 1 ? a.gpart : a.partial;
+  const int R = a.NG > 1 ? a.NG : a.X;
+  double2* scratch = reinterpret_cast<double2*>(&red[0][0][0]);     // blockDim.x entries
+  double2* srho = scratch + 1024;                                   // Ppad <= 512 entries
+
+  if (extra) {
+    if (tid == 0) sbs = *a.bs;
+    __syncthreads();
+    if (a.k2reduce) {
+      block_sum_rows(rows, a.Ppad, R, a.Ppad, srho, false, scratch);
+      double tv[7] = {0, 0, 0, 0, 0, 0, 0};
+      if (tid < a.p) {
+        const int mi[3] = {a.m[3 * tid], a.m[3 * tid + 1], a.m[3 * tid + 2]};
+        const double2 r = srho[tid];
+        a.rho[tid] = r;
+        FCoef64 f;
+        FCoef32 h;
+        freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tv);
+      }
+      virial_energy(tv, reinterpret_cast<double*>(scoef), sh_vs, sbs, a.coulomb, a.p,
+                    a.self_energy, a.virial6, a.energy);
+    }
+    return;
+  }
+
   const int64_t i = (int64_t)blockIdx.x * kWave + lane;
   const bool valid = i < a.n;
   double xi = 0.0, yi = 0.0, zi = 0.0;
   if (valid) { xi = a.x[i]; yi = a.y[i]; zi = a.z[i]; }
-  const double ix = a.bs->inv_l[0], iy = a.bs->inv_l[1], iz = a.bs->inv_l[2];
   const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)
                           : reinterpret_cast<const Coef*>(a.fc32);
-  const bool staged = (size_t)a.p * sizeof(Coef) <= kForceStageBytes;
-  if (staged) {
-    const int nvec = (int)((size_t)a.p * sizeof(Coef) / 16);
-    const uint4* src = reinterpret_cast<const uint4*>(gcoef);
-    for (int v = tid; v < nvec; v += blockDim.x) scoef[v] = src[v];
+  bool staged;
+  if (a.k2reduce) {
+    if (tid == 0) sbs = *a.bs;
+    block_sum_rows(rows, a.Ppad, R, a.Ppad, srho, false, scratch);
+    Coef* sc = reinterpret_cast<Coef*>(scoef);
+    for (int l = tid; l < a.p; l += blockDim.x) {
+      const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
+      FCoef64 f;
+      FCoef32 h;
+      double tv[7];
+      freq_consts(mi, srho[l], sbs, a.alpha, a.coulomb, a.p, f, h, tv);
+      if (F64) reinterpret_cast<FCoef64*>(sc)[l] = f;
+      else reinterpret_cast<FCoef32*>(sc)[l] = h;
+    }
+    staged = true;
+  } else {
+    staged = (size_t)a.p * sizeof(Coef) <= kForceStageBytes;
+    if (staged) {
+      const int nvec = (int)((size_t)a.p * sizeof(Coef) / 16);
+      const uint4* src = reinterpret_cast<const uint4*>(gcoef);
+      for (int v = tid; v < nvec; v += blockDim.x) scoef[v] = src[v];
+    }
+    if (tid == 0) sbs = *a.bs;
   }
   __syncthreads();
+  const double ix = sbs.inv_l[0], iy = sbs.inv_l[1], iz = sbs.inv_l[2];
   const Coef* fc = staged ? reinterpret_cast<const Coef*>(scoef) : gcoef;
   const int per = (a.p + KS - 1) / KS;
   const int l0 = min(a.p, wave * per), l1 = min(a.p, l0 + per);
@@ -687,6 +813,7 @@ __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
       gz = fma(gg, c.k[2], gz);
     }
   }
+  __syncthreads();                          // the scratch in `red` is dead
   red[wave][lane][0] = gx; red[wave][lane][1] = gy; red[wave][lane][2] = gz;
   __syncthreads();
   if (wave == 0 && valid) {
@@ -699,7 +826,7 @@ __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
 }
 
 hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.n + kWave - 1) / kWave;
+  const int64_t blocks = (a.n + kWave - 1) / kWave + (a.k2reduce ? 1 : 0);
   const dim3 block(a.KS * kWave);
   if (precision == RBE_PREC_FP32)
     hipLaunchKernelGGL(k_force<false>, dim3((unsigned)blocks), block, 0, s, a);
@@ -707,5 +834,4 @@ hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_force<true>, dim3((unsigned)blocks), block, 0, s, a);
   return hipGetLastError();
 }
-
 }  // namespace rbe

@@ -254,11 +254,13 @@ def test_error_paths(gpu):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case,p", [("water_30k", 100), ("water_3k", 700)])
-def test_consecutive_steps_with_changing_cell(gpu, case, precision, p):
-    # several steps on one context: new cell, new draw and new positions each
-    # step, every step checked against the oracle (no state may leak between
-    # launches: counters, partial sums, tables)
+@pytest.mark.parametrize("fixed_cell", [False, True])
+@pytest.mark.parametrize("case,p", [("water_30k", 100), ("water_30k", 500), ("water_3k", 700)])
+def test_consecutive_steps(gpu, case, precision, p, fixed_cell):
+    # several steps on one context: new draw and new positions each step, and
+    # a new cell each step unless fixed_cell (then the batch drawn ahead by
+    # the previous step is used); every step checked against the oracle (no
+    # state may leak between launches: counters, partial sums, tables)
     import torch
     from paper_2110_14362_amd.rbe import RBE
     s = workloads.make("water_30k") if case == "water_30k" else small_water()
@@ -267,8 +269,9 @@ def test_consecutive_steps_with_changing_cell(gpu, case, precision, p):
     ctx = RBE(q, s["box"], p, s["alpha"], coulomb=s["coulomb"], precision=precision,
               seed=77, system_id=3)
     rng = np.random.default_rng(5)
-    for step in range(5):
-        scale = 1.0 + 0.002 * (step - 2)
+    steps = [0, 1, 2, 3, 7, 8]          # a gap: the batch drawn ahead is not for step 7
+    for step in steps:
+        scale = 1.0 if fixed_cell else 1.0 + 0.002 * (step - 2)
         box = s["box"] * scale
         pos = np.mod(s["pos"] * scale + rng.normal(0, 0.05, s["pos"].shape), box)
         x, y, z = (torch.tensor(pos[:, a], dtype=torch.float64, device=gpu) for a in range(3))
