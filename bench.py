@@ -39,7 +39,21 @@ def parse():
     ap.add_argument("--p", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes 10 times (for scaling "
+                         "the HBM byte counters of a profiler run) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mb):
+    import torch
+    n = int(mb * 1e6) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 10}))
 
 
 def make_step(ctx, box, x, y, z, fx, fy, fz, vir, en):
@@ -86,6 +100,9 @@ def cpu_baseline(sysd, seconds):
 
 def main():
     args = parse()
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the multi-GPU "
               "sharding of the Fourier-space step is described, not built.", file=sys.stderr)

@@ -126,19 +126,25 @@ bool env_flag(const char* name, bool dflt) {
   return dflt;
 }
 
-// Launch geometry.  Structure factors: 8-wave blocks, KB frequency groups of
-// 64 per block (a power of two), 8/KB particle sub-slices per group; X
-// particle chunks x Y frequency slices, about 2 blocks per CU.  Chunk
-// partials are summed in groups of GX.  Forces: 64 particles per block, the
-// batch split over KS waves so that about 16 waves per CU are resident.
+// Launch geometry.  Structure factors: 8-wave blocks; a lane owns R
+// frequencies (FP32: more per lane for larger batches, so each particle read
+// from LDS serves more pairs), KB waves cover distinct frequency groups
+// (FB = KB*64*R per block, a power of two), 8/KB waves split the particles;
+// X particle chunks x Y frequency slices, about one block per CU.  Chunk
+// partials are summed in groups of GX.  Forces: lanes hold 2 particles
+// (FP32) or 1 (FP64); KS waves split the batch, PW particle waves share the
+// staged constants; about 16 waves per CU.
 void plan_launch(rbe_ctx_s* c) {
   StepArgs& a = c->a;
-  const int kgroups = (c->p + kWave - 1) / kWave;
+  const bool f64 = c->cfg.precision == RBE_PREC_FP64;
+  a.R = f64 ? 1 : (c->p <= 64 ? 1 : (c->p <= 256 ? 2 : 4));
+  const int per_wave = kWave * a.R;
+  const int kgroups = (c->p + per_wave - 1) / per_wave;
   int KB = 1;
   while (KB < kgroups && KB < kSfacWaves) KB <<= 1;
   a.KB = KB;
   a.Y = (kgroups + KB - 1) / KB;
-  a.Ppad = a.Y * KB * kWave;
+  a.Ppad = a.Y * KB * per_wave;
   const long target_blocks = env_long("RBE_SFAC_BLOCKS", 256);
   long X = (target_blocks + a.Y - 1) / a.Y;
   const long max_x = (c->n + 15) / 16;          // at least 16 particles per chunk
@@ -154,14 +160,15 @@ void plan_launch(rbe_ctx_s* c) {
   a.NG = (int)((X + GX - 1) / GX);
   // small batches: the force kernel sums the group partials of rho itself
   const long rows = a.NG > 1 ? a.NG : a.X;
-  a.k2reduce = (a.Y == 1 && rows * a.Ppad <= 4096 && env_flag("RBE_K2REDUCE", true)) ? 1 : 0;
-  const long fblocks = (c->n + kWave - 1) / kWave;
+  a.k2reduce = (a.Y == 1 && a.Ppad <= 512 && rows * a.Ppad <= 4096 &&
+                env_flag("RBE_K2REDUCE", true)) ? 1 : 0;
+  const int RP = f64 ? 1 : 2;
+  const long groups = (c->n + (long)kWave * RP - 1) / ((long)kWave * RP);
   const long target_waves = env_long("RBE_FORCE_WAVES", 4096);
   int KS = 1;
-  while (KS < 8 && (long)(KS * 2) * fblocks <= target_waves && KS * 2 <= c->p) KS <<= 1;
-  if (a.k2reduce)
-    while (KS * kWave < a.Ppad) KS <<= 1;        // the block sums Ppad columns at once
+  while (KS < 8 && (long)(KS * 2) * groups <= target_waves && KS * 2 <= c->p) KS <<= 1;
   a.KS = KS;
+  a.PW = (KS == 1 && groups >= 1024) ? 4 : 1;
 }
 
 enum Kind { K_TABLES = 0, K_SAMPLE, K_SFAC, K_FORCE };

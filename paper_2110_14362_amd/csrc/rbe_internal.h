@@ -75,6 +75,8 @@ struct StepArgs {
   int32_t tab_stride;
   // launch plan
   int32_t X, Y, KB, GX, NG, chunk, Ppad, KS;
+  int32_t R;            // frequencies per lane in k_sfac (FP32: 1, 2 or 4)
+  int32_t PW;           // particle waves per k_force block
   int32_t k2reduce;     // 1: the force kernel sums the NG group partials itself
   int32_t predraw;      // 1: an extra k_sfac block draws the batch of step + 1 ahead
   int32_t use_pre;      // 1: k_sfac may take the batch drawn ahead

@@ -149,6 +149,7 @@ __device__ __forceinline__ void draw_frequency(const BoxState& b, const double* 
   uint64_t c[4] = {step, (uint64_t)l, kTagKSample, 0ull};
   philox4x64_10(c, seed, sysid);
   double u[4];
+#pragma unroll
   for (int j = 0; j < 4; ++j) u[j] = (double)(c[j] >> 11) * 0x1.0p-53;
   const double t = u[0] * b.S;
   const int pivot = (t < b.case_w[0]) ? 0 : ((t < b.case_w[0] + b.case_w[1]) ? 1 : 2);
@@ -156,6 +157,7 @@ __device__ __forceinline__ void draw_frequency(const BoxState& b, const double* 
   int lo[3], hi[3];
   double tgt[3];
   int nmax = 1;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int mc = b.mcut[a];
     const bool nz = (a == pivot);
@@ -176,6 +178,7 @@ __device__ __forceinline__ void draw_frequency(const BoxState& b, const double* 
       }
     }
   }
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int mc = b.mcut[a];
     if (a < pivot) m[a] = 0;
@@ -291,20 +294,31 @@ hipError_t launch_sample(const StepArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // k_sfac: tables, draw, structure factors, fixed-order reduction, virial
+//
+// Block = 8 waves.  A wave owns 64*R frequencies (R per lane: slot r*64 +
+// lane), KB waves cover distinct frequency groups (FB = KB*64*R frequencies
+// per block), SUB = 8/KB waves split the chunk's particles.  Several
+// frequencies per lane amortise the LDS broadcast of each particle, whose
+// return costs LDS bandwidth like any other read.
 
 // Dynamic LDS of k_sfac, three regions:
-//   R0 particle tiles (kTile x 32 B); after the main loop: wave partials and rho
+//   R0 particle tiles (kTile x 32 B); after the main loop: reduction scratch
 //   R1 the block's slice of the batch (3 ints per frequency)
-//   R2 the sampler tables; after the draw: the 7 x kSfacThreads virial summands
+//   R2 the sampler tables; after the draw: rho of the slice, then the 7 x
+//      kSfacThreads virial summands
 constexpr size_t kR0 = (size_t)kTile * 32;
-constexpr size_t kR1 = (size_t)kSfacThreads * 3 * sizeof(int);
-constexpr size_t kR2min = (size_t)7 * kSfacThreads * sizeof(double);
 
-size_t sfac_lds_bytes(const StepArgs& a) {
+__host__ __device__ static size_t sfac_r1(const StepArgs& a) { return (size_t)a.KB * kWave * a.R * 3 * sizeof(int); }
+static size_t sfac_r2(const StepArgs& a) {
   const int cap = a.mcap[0] + a.mcap[1] + a.mcap[2];
-  const size_t tabs = (size_t)(4 * cap + 3) * sizeof(double);
-  return kR0 + kR1 + (tabs > kR2min ? tabs : kR2min);
+  size_t r2 = (size_t)(4 * cap + 3) * sizeof(double);
+  const size_t rho = (size_t)a.KB * kWave * a.R * sizeof(double2);
+  const size_t vir = (size_t)7 * kSfacThreads * sizeof(double);
+  if (rho > r2) r2 = rho;
+  if (vir > r2) r2 = vir;
+  return r2;
 }
+size_t sfac_lds_bytes(const StepArgs& a) { return kR0 + sfac_r1(a) + sfac_r2(a); }
 
 // Data handed from block to block within a launch is stored and loaded with
 // agent-scope atomic accesses (coherent across the XCDs' separate L2 caches)
@@ -339,15 +353,38 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, i
 }
 
 // dst[i] = sum over r = 0..R-1 of src[r*stride + i] for i < W, in a fixed
-// order, by the whole block (W a power of two dividing the block size).
-// Thread t owns column t % W and rows t / W + RG*j (RG = threads / W); its loads are
-// issued together, then the RG row-group sums are added in order through
-// LDS.  src is read with coherent loads; dst is written with coherent stores
-// when dst_coh, else with LDS/plain stores.  Reached by every thread.
+// order, by the whole block (W and the block size powers of two).  If W <
+// threads: thread t owns column t % W and rows t / W + RG*j (RG = threads /
+// W), then the RG row-group sums are added in order through LDS.  Otherwise
+// thread t owns columns t + threads*j and all rows.  Loads are issued four at
+// a time.  src is read with coherent loads; dst is written with coherent
+// stores when dst_coh, else plainly (LDS).  Reached by every thread;
+// scratch holds blockDim.x entries.
 __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
                                bool dst_coh, double2* scratch) {
-  const int t = threadIdx.x;
-  const int RG = blockDim.x / W;
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (W >= nt) {
+    for (int col = t; col < W; col += nt) {
+      double2 acc = make_double2(0.0, 0.0);
+      int r = 0;
+      for (; r + 3 < R; r += 4) {
+        const double2 v0 = ld_coh2(src + (int64_t)r * stride + col);
+        const double2 v1 = ld_coh2(src + (int64_t)(r + 1) * stride + col);
+        const double2 v2 = ld_coh2(src + (int64_t)(r + 2) * stride + col);
+        const double2 v3 = ld_coh2(src + (int64_t)(r + 3) * stride + col);
+        acc.x += v0.x; acc.y += v0.y; acc.x += v1.x; acc.y += v1.y;
+        acc.x += v2.x; acc.y += v2.y; acc.x += v3.x; acc.y += v3.y;
+      }
+      for (; r < R; ++r) {
+        const double2 v = ld_coh2(src + (int64_t)r * stride + col);
+        acc.x += v.x; acc.y += v.y;
+      }
+      if (dst_coh) st_coh2(dst + col, acc); else dst[col] = acc;
+    }
+    __syncthreads();
+    return;
+  }
+  const int RG = nt / W;
   const int col = t % W, rg = t / W;
   double2 acc = make_double2(0.0, 0.0);
   int r = rg;
@@ -407,14 +444,16 @@ __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const Bo
   h.cA = (float)f.cA; h.cB = (float)f.cB;
 }
 
-// Batch sum of the virial summands held one frequency per thread (tv, zero on
-// idle threads), in a fixed order: 7 x 8 strided partial sums over the
-// threads through LDS, then the 8 partials in order.  Writes the virial
-// tensor and the energy.  Reached by every thread; stv holds 7*blockDim.x.
+// Batch sum of the virial summands held per thread (tv: the thread's own
+// frequencies already summed in a fixed order, zero on idle threads), in a
+// fixed order: 7 x 8 strided partial sums over the threads through LDS, then
+// the 8 partials in order.  Writes the virial tensor and the energy.  Reached
+// by every thread; stv holds 7*blockDim.x doubles.
 __device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8],
                               const BoxState& b, double coulomb, int p, double self_energy,
                               double* virial6, double* energy) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  __syncthreads();
   for (int c = 0; c < 7; ++c) stv[c * nt + tid] = tv[c];
   __syncthreads();
   if (tid < 56) {
@@ -433,7 +472,7 @@ __device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8
   }
 }
 
-template <bool F64>
+template <bool F64, int R>
 __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ BoxState sbs;
@@ -442,20 +481,10 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   __shared__ double sh_vs[7][8];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int x = blockIdx.x, y = blockIdx.y;
-  const int KB = a.KB, SUB = kSfacWaves / KB, PB = kWave * KB;
+  const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;
   unsigned char* base = lds_raw;
   int* sm = reinterpret_cast<int*>(base + kR0);                     // batch slice, 3 ints each
-  double* tabs = reinterpret_cast<double*>(base + kR0 + kR1);
-
-  // ---- first tile of particles: loads issued now, consumed after the tables
-  const int64_t c0 = (int64_t)x * a.chunk;
-  const int64_t c1 = min(a.n, c0 + (int64_t)a.chunk);
-  const int first_cnt = (int)min((int64_t)kTile, c1 - c0);
-  double px = 0.0, py = 0.0, pz = 0.0, pq = 0.0;
-  if (tid < first_cnt) {
-    px = a.x[c0 + tid]; py = a.y[c0 + tid]; pz = a.z[c0 + tid];
-    pq = F64 ? a.q[c0 + tid] : (double)a.qf[c0 + tid];
-  }
+  double* tabs = reinterpret_cast<double*>(base + kR0 + sfac_r1(a));  // R2
 
   // ---- the extra block: draw the batch of step + 1 for this launch's cell
   if (x == a.X) {
@@ -477,6 +506,16 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
       a.pre[slot].valid = 1;
     }
     return;
+  }
+
+  // ---- first tile of particles: loads issued now, consumed after the tables
+  const int64_t c0 = (int64_t)x * a.chunk;
+  const int64_t c1 = min(a.n, c0 + (int64_t)a.chunk);
+  const int first_cnt = (int)min((int64_t)kTile, c1 - c0);
+  double px = 0.0, py = 0.0, pz = 0.0, pq = 0.0;
+  if (tid < first_cnt) {
+    px = a.x[c0 + tid]; py = a.y[c0 + tid]; pz = a.z[c0 + tid];
+    pq = F64 ? a.q[c0 + tid] : (double)a.qf[c0 + tid];
   }
 
   // ---- batch drawn ahead: usable when its step and cell equal this call's
@@ -519,35 +558,42 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   }
 
   // ---- this block's slice of the batch
-  if (tid < PB) {
-    const int l = y * PB + tid;
+  const int64_t slice = (int64_t)y * FB;
+  for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
+    const int64_t l = slice + s2;
     int mv[3] = {0, 0, 0};
     if (l < a.p) {
       if (pre) {
         mv[0] = m_pre[3 * l]; mv[1] = m_pre[3 * l + 1]; mv[2] = m_pre[3 * l + 2];
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else if (a.sample) {
-        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, l, mv);
+        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv);
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else {
         mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
       }
     }
-    sm[3 * tid] = mv[0]; sm[3 * tid + 1] = mv[1]; sm[3 * tid + 2] = mv[2];
+    sm[3 * s2] = mv[0]; sm[3 * s2 + 1] = mv[1]; sm[3 * s2 + 2] = mv[2];
   }
   __syncthreads();
 
-  // ---- structure factors over the chunk: lane = frequency, wave = (group, sub)
+  // ---- structure factors over the chunk: lane owns frequencies
+  // kg*64R + r*64 + lane (r < R); wave = sub*KB + kg
   const int kg = wave % KB, sub = wave / KB;
-  const int lk = kg * kWave + lane;
   const double ix = sbs.inv_l[0], iy = sbs.inv_l[1], iz = sbs.inv_l[2];
-  const int runlen = SUB * kKahan;
-  double2 part;
+  double2 part[R];
   if (!F64) {
+    constexpr int kRun = (R >= 4) ? 8 : kKahan;   // plain FP32 run between compensated folds
+    const int runlen = SUB * kRun;
     float4* tA = reinterpret_cast<float4*>(base);           // sh.x sh.y sh.z q
     float4* tB = tA + kTile;                                // sl.x sl.y sl.z 0
-    const float mx = (float)sm[3 * lk], my = (float)sm[3 * lk + 1], mz = (float)sm[3 * lk + 2];
-    float SA = 0.f, CA = 0.f, SB = 0.f, CB = 0.f;
+    float mx[R], my[R], mz[R], SA[R], CA[R], SB[R], CB[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = kg * kWave * R + r * kWave + lane;
+      mx[r] = (float)sm[3 * sl]; my[r] = (float)sm[3 * sl + 1]; mz[r] = (float)sm[3 * sl + 2];
+      SA[r] = CA[r] = SB[r] = CB[r] = 0.f;
+    }
     for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
       const int cnt = (int)min((int64_t)kTile, c1 - t0);
       const int cntp = (cnt + runlen - 1) / runlen * runlen;
@@ -566,27 +612,42 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
       }
       __syncthreads();
       for (int j0 = sub; j0 < cntp; j0 += runlen) {
-        float ra = 0.f, rb = 0.f;
+        float ra[R], rb[R];
 #pragma unroll
-        for (int u = 0; u < kKahan; ++u) {
+        for (int r = 0; r < R; ++r) { ra[r] = 0.f; rb[r] = 0.f; }
+#pragma unroll
+        for (int u = 0; u < kRun; ++u) {
           const int j = j0 + u * SUB;
           const float4 pa = tA[j], pb = tB[j];
-          const float f = phase_rev(mx, my, mz, pa.x, pa.y, pa.z, pb.x, pb.y, pb.z);
-          const float cs = __builtin_amdgcn_cosf(f);
-          const float sn = __builtin_amdgcn_sinf(f);
-          ra = fmaf(pa.w, cs, ra);
-          rb = fmaf(pa.w, sn, rb);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const float f = phase_rev(mx[r], my[r], mz[r], pa.x, pa.y, pa.z, pb.x, pb.y, pb.z);
+            const float cs = __builtin_amdgcn_cosf(f);
+            const float sn = __builtin_amdgcn_sinf(f);
+            ra[r] = fmaf(pa.w, cs, ra[r]);
+            rb[r] = fmaf(pa.w, sn, rb[r]);
+          }
         }
-        kahan_add(SA, CA, ra);
-        kahan_add(SB, CB, rb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          kahan_add(SA[r], CA[r], ra[r]);
+          kahan_add(SB[r], CB[r], rb[r]);
+        }
       }
     }
-    part = make_double2((double)SA - (double)CA, (double)SB - (double)CB);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      part[r] = make_double2((double)SA[r] - (double)CA[r], (double)SB[r] - (double)CB[r]);
   } else {
     double2* tA = reinterpret_cast<double2*>(base);         // s.x s.y
     double2* tB = tA + kTile;                               // s.z q
-    const double mx = (double)sm[3 * lk], my = (double)sm[3 * lk + 1], mz = (double)sm[3 * lk + 2];
-    double A = 0.0, B = 0.0;
+    double mx[R], my[R], mz[R], A[R], B[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = kg * kWave * R + r * kWave + lane;
+      mx[r] = (double)sm[3 * sl]; my[r] = (double)sm[3 * sl + 1]; mz[r] = (double)sm[3 * sl + 2];
+      A[r] = B[r] = 0.0;
+    }
     for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
       const int cnt = (int)min((int64_t)kTile, c1 - t0);
       const int cntp = (cnt + SUB - 1) / SUB * SUB;
@@ -607,29 +668,37 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
       __syncthreads();
       for (int j = sub; j < cntp; j += SUB) {
         const double2 pa = tA[j], pb = tB[j];
-        const double t = mx * pa.x + my * pa.y + mz * pb.x;
-        const double f = t - rint(t);
-        double sn, cs;
-        sincospi(2.0 * f, &sn, &cs);
-        A = fma(pb.y, cs, A);
-        B = fma(pb.y, sn, B);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double t = mx[r] * pa.x + my[r] * pa.y + mz[r] * pb.x;
+          const double f = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * f, &sn, &cs);
+          A[r] = fma(pb.y, cs, A[r]);
+          B[r] = fma(pb.y, sn, B[r]);
+        }
       }
     }
-    part = make_double2(A, B);
+#pragma unroll
+    for (int r = 0; r < R; ++r) part[r] = make_double2(A[r], B[r]);
   }
-  __syncthreads();                          // tiles are dead from here on
-  double2* red = reinterpret_cast<double2*>(base);                     // kSfacThreads entries
-  double2* srho = red + kSfacThreads;                                  // PB entries
-  red[tid] = part;
-  __syncthreads();
-  const int64_t slice = (int64_t)y * PB;
-  if (tid < PB) {
-    double2 s2 = make_double2(0.0, 0.0);
-    for (int sb = 0; sb < SUB; ++sb) {     // wave = sb*KB + kg  ->  index sb*PB + tid
-      const double2 v = red[sb * PB + tid];
-      s2.x += v.x; s2.y += v.y;
+
+  // ---- block partial: sum the SUB particle sub-slices, in order, per slot
+  double2* red = reinterpret_cast<double2*>(base);          // kSfacThreads entries (R0)
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    __syncthreads();
+    red[tid] = part[r];
+    __syncthreads();
+    if (tid < KB * kWave) {                // (kg', lane') = (tid / 64, tid % 64)
+      double2 s2 = make_double2(0.0, 0.0);
+      for (int sb = 0; sb < SUB; ++sb) {   // wave = sb*KB + kg'  ->  index sb*KB*64 + tid
+        const double2 v = red[sb * KB * kWave + tid];
+        s2.x += v.x; s2.y += v.y;
+      }
+      const int sl = (tid / kWave) * kWave * R + r * kWave + (tid % kWave);
+      st_coh2(a.partial + (int64_t)x * a.Ppad + slice + sl, s2);
     }
-    st_coh2(a.partial + (int64_t)x * a.Ppad + slice + tid, s2);
   }
 
   // ---- level 1: the last block of each chunk group sums the group's partials
@@ -637,7 +706,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   const int gsize = min(a.GX, a.X - g * a.GX);
   if (a.NG > 1) {
     if (!arrive_last(&a.cnt[y * a.NG + g], (uint32_t)gsize, &sh_flag)) return;
-    block_sum_rows(a.partial + (int64_t)g * a.GX * a.Ppad + slice, a.Ppad, gsize, PB,
+    block_sum_rows(a.partial + (int64_t)g * a.GX * a.Ppad + slice, a.Ppad, gsize, FB,
                    a.gpart + (int64_t)g * a.Ppad + slice, true, red);
     if (tid == 0) a.cnt[y * a.NG + g] = 0u;
   }
@@ -649,24 +718,27 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   // ---- level 2: the last group of the slice forms rho, the force
   // coefficients and the per-frequency virial summands
   if (!arrive_last(&a.cnt[a.Y * a.NG + y], (uint32_t)a.NG, &sh_flag)) return;
+  double2* srho = reinterpret_cast<double2*>(tabs);          // R2 (tables are dead)
   if (a.NG > 1)
-    block_sum_rows(a.gpart + slice, a.Ppad, a.NG, PB, srho, false, red);
+    block_sum_rows(a.gpart + slice, a.Ppad, a.NG, FB, srho, false, red);
   else
-    block_sum_rows(a.partial + slice, a.Ppad, a.X, PB, srho, false, red);
-  double* stv = tabs;                       // R2: 7 x kSfacThreads summands (tables are dead)
+    block_sum_rows(a.partial + slice, a.Ppad, a.X, FB, srho, false, red);
   double tv[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (tid < PB && slice + tid < a.p) {
-    const int l = (int)(slice + tid);
-    const double2 r = srho[tid];
+  for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
+    if (slice + s2 >= a.p) break;
+    const int l = (int)(slice + s2);
+    const double2 r = srho[s2];
     a.rho[l] = r;
-    const int mi[3] = {sm[3 * tid], sm[3 * tid + 1], sm[3 * tid + 2]};
+    const int mi[3] = {sm[3 * s2], sm[3 * s2 + 1], sm[3 * s2 + 2]};
     FCoef64 f;
     FCoef32 h;
-    freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tv);
+    double tl[7];
+    freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tl);
     if (a.Y > 1) {
       double* tr = a.terms + (int64_t)l * 8;
-      for (int c = 0; c < 7; ++c) st_coh(tr + c, tv[c]);
+      for (int c = 0; c < 7; ++c) st_coh(tr + c, tl[c]);
     }
+    for (int c = 0; c < 7; ++c) tv[c] += tl[c];
     a.fc64[l] = f;
     a.fc32[l] = h;
   }
@@ -681,157 +753,216 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
     for (int l = tid; l < a.p; l += kSfacThreads)
       for (int c = 0; c < 7; ++c) tv[c] += ld_coh(a.terms + (int64_t)l * 8 + c);
   }
-  virial_energy(tv, stv, sh_vs, sbs, a.coulomb, a.p, a.self_energy, a.virial6, a.energy);
+  virial_energy(tv, tabs, sh_vs, sbs, a.coulomb, a.p, a.self_energy, a.virial6, a.energy);
   if (tid == 0 && a.Y > 1) a.cnt[a.Y * a.NG + a.Y] = 0u;
 }
 
 hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.X + (a.predraw ? 1 : 0), a.Y);
   const size_t lds = sfac_lds_bytes(a);
-  if (precision == RBE_PREC_FP32)
-    hipLaunchKernelGGL(k_sfac<false>, grid, dim3(kSfacThreads), lds, s, a);
+  if (precision == RBE_PREC_FP64)
+    hipLaunchKernelGGL((k_sfac<true, 1>), grid, dim3(kSfacThreads), lds, s, a);
+  else if (a.R == 4)
+    hipLaunchKernelGGL((k_sfac<false, 4>), grid, dim3(kSfacThreads), lds, s, a);
+  else if (a.R == 2)
+    hipLaunchKernelGGL((k_sfac<false, 2>), grid, dim3(kSfacThreads), lds, s, a);
   else
-    hipLaunchKernelGGL(k_sfac<true>, grid, dim3(kSfacThreads), lds, s, a);
+    hipLaunchKernelGGL((k_sfac<false, 1>), grid, dim3(kSfacThreads), lds, s, a);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// k_force: 64 particles per block, the batch split over KS waves.  The
-// frequency constants are staged in LDS (read by every lane at the same
-// address) when they fit, else read from global memory with scalar loads.
-// Small batches (k2reduce): every block first sums the group partials of
-// rho itself, in one fixed order, and forms the constants in LDS.
-// In that mode one extra block (the last) does the batch-wide work instead
-// of forces: rho, the virial tensor and the energy.
+// k_force: the batch split over KS waves; PW particle waves per block, each
+// lane holding RP particles, so every frequency's constants (read by all
+// lanes at one LDS address) serve RP particles.  Constants are staged in LDS
+// in chunks of up to 32 KB.  Small batches (k2reduce): every block first sums
+// the group partials of rho itself, in one fixed order, and forms the
+// constants in LDS; one extra block (the last) then does the batch-wide work
+// instead of forces: rho, the virial tensor and the energy.
 
 constexpr int kForceStageBytes = 32768;
+constexpr int kForceRedBytes = 24576;
 
-template <bool F64>
+template <bool F64, int RP>
 __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
   using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
-  __shared__ __align__(16) double red[16][kWave][3];
-  __shared__ __align__(16) uint4 scoef[kForceStageBytes / 16];
+  constexpr int kChunk = kForceStageBytes / (int)sizeof(Coef);
+  __shared__ __align__(16) unsigned char red_raw[kForceRedBytes];
+  __shared__ __align__(16) Coef scoef[kChunk];
   __shared__ BoxState sbs;
-  __shared__ double sh_T[3];
   __shared__ double sh_vs[7][8];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  const int KS = blockDim.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int PW = a.PW, KS = nw / PW;
   const bool extra = a.k2reduce && blockIdx.x == gridDim.x - 1;
   // rows of rho partials left by k_sfac in k2reduce mode
   const double2* rows = a.NG > 1 ? a.gpart : a.partial;
-  const int R = a.NG > 1 ? a.NG : a.X;
-  double2* scratch = reinterpret_cast<double2*>(&red[0][0][0]);     // blockDim.x entries
-  double2* srho = scratch + 1024;                                   // Ppad <= 512 entries
+  const int Rr = a.NG > 1 ? a.NG : a.X;
+  double2* scratch = reinterpret_cast<double2*>(red_raw);   // blockDim.x entries
+  double2* srho = scratch + blockDim.x;                       // Ppad <= 512 entries
 
   if (extra) {
     if (tid == 0) sbs = *a.bs;
     __syncthreads();
-    if (a.k2reduce) {
-      block_sum_rows(rows, a.Ppad, R, a.Ppad, srho, false, scratch);
-      double tv[7] = {0, 0, 0, 0, 0, 0, 0};
-      if (tid < a.p) {
-        const int mi[3] = {a.m[3 * tid], a.m[3 * tid + 1], a.m[3 * tid + 2]};
-        const double2 r = srho[tid];
-        a.rho[tid] = r;
-        FCoef64 f;
-        FCoef32 h;
-        freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tv);
-      }
-      virial_energy(tv, reinterpret_cast<double*>(scoef), sh_vs, sbs, a.coulomb, a.p,
-                    a.self_energy, a.virial6, a.energy);
+    block_sum_rows(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
+    double tv[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int l = tid; l < a.p; l += blockDim.x) {
+      const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
+      const double2 r = srho[l];
+      a.rho[l] = r;
+      FCoef64 f;
+      FCoef32 h;
+      double tl[7];
+      freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tl);
+      for (int c = 0; c < 7; ++c) tv[c] += tl[c];
     }
+    virial_energy(tv, reinterpret_cast<double*>(scoef), sh_vs, sbs, a.coulomb, a.p,
+                  a.self_energy, a.virial6, a.energy);
     return;
   }
 
-  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
-  const bool valid = i < a.n;
-  double xi = 0.0, yi = 0.0, zi = 0.0;
-  if (valid) { xi = a.x[i]; yi = a.y[i]; zi = a.z[i]; }
-  const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)
-                          : reinterpret_cast<const Coef*>(a.fc32);
-  bool staged;
+  const int pw = wave % PW, ks = wave / PW;
+  const int64_t pbase = (int64_t)blockIdx.x * (kWave * RP * PW) + pw * kWave * RP + lane;
+  double xi[RP], yi[RP], zi[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int64_t i = pbase + r * kWave;
+    xi[r] = yi[r] = zi[r] = 0.0;
+    if (i < a.n) { xi[r] = a.x[i]; yi[r] = a.y[i]; zi[r] = a.z[i]; }
+  }
   if (a.k2reduce) {
     if (tid == 0) sbs = *a.bs;
-    block_sum_rows(rows, a.Ppad, R, a.Ppad, srho, false, scratch);
-    Coef* sc = reinterpret_cast<Coef*>(scoef);
+    block_sum_rows(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
     for (int l = tid; l < a.p; l += blockDim.x) {
       const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
       FCoef64 f;
       FCoef32 h;
-      double tv[7];
-      freq_consts(mi, srho[l], sbs, a.alpha, a.coulomb, a.p, f, h, tv);
-      if (F64) reinterpret_cast<FCoef64*>(sc)[l] = f;
-      else reinterpret_cast<FCoef32*>(sc)[l] = h;
+      double tl[7];
+      freq_consts(mi, srho[l], sbs, a.alpha, a.coulomb, a.p, f, h, tl);
+      if (F64) reinterpret_cast<FCoef64*>(scoef)[l] = f;
+      else reinterpret_cast<FCoef32*>(scoef)[l] = h;
     }
-    staged = true;
   } else {
-    staged = (size_t)a.p * sizeof(Coef) <= kForceStageBytes;
-    if (staged) {
-      const int nvec = (int)((size_t)a.p * sizeof(Coef) / 16);
-      const uint4* src = reinterpret_cast<const uint4*>(gcoef);
-      for (int v = tid; v < nvec; v += blockDim.x) scoef[v] = src[v];
-    }
     if (tid == 0) sbs = *a.bs;
   }
   __syncthreads();
   const double ix = sbs.inv_l[0], iy = sbs.inv_l[1], iz = sbs.inv_l[2];
-  const Coef* fc = staged ? reinterpret_cast<const Coef*>(scoef) : gcoef;
-  const int per = (a.p + KS - 1) / KS;
-  const int l0 = min(a.p, wave * per), l1 = min(a.p, l0 + per);
-  double gx, gy, gz;
-  if (!F64) {
-    float shx, shy, shz, slx, sly, slz;
-    split_coord(xi, ix, shx, slx);
-    split_coord(yi, iy, shy, sly);
-    split_coord(zi, iz, shz, slz);
-    float hx = 0.f, hy = 0.f, hz = 0.f;
-#pragma unroll 4
-    for (int l = l0; l < l1; ++l) {
-      const FCoef32 c = reinterpret_cast<const FCoef32*>(fc)[l];
-      const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx, shy, shz, slx, sly, slz);
-      const float cs = __builtin_amdgcn_cosf(f);
-      const float sn = __builtin_amdgcn_sinf(f);
-      const float gg = fmaf(cs, c.cB, -sn * c.cA);
-      hx = fmaf(gg, c.k[0], hx);
-      hy = fmaf(gg, c.k[1], hy);
-      hz = fmaf(gg, c.k[2], hz);
-    }
-    gx = hx; gy = hy; gz = hz;
-  } else {
-    double sx = xi * ix, sy = yi * iy, sz = zi * iz;
-    sx -= floor(sx); sy -= floor(sy); sz -= floor(sz);
-    gx = gy = gz = 0.0;
-    for (int l = l0; l < l1; ++l) {
-      const FCoef64 c = reinterpret_cast<const FCoef64*>(fc)[l];
-      const double t = c.m[0] * sx + c.m[1] * sy + c.m[2] * sz;
-      const double f = t - rint(t);
-      double sn, cs;
-      sincospi(2.0 * f, &sn, &cs);
-      const double gg = cs * c.cB - sn * c.cA;
-      gx = fma(gg, c.k[0], gx);
-      gy = fma(gg, c.k[1], gy);
-      gz = fma(gg, c.k[2], gz);
+  const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)
+                          : reinterpret_cast<const Coef*>(a.fc32);
+  double gx[RP], gy[RP], gz[RP];
+  float shx[RP], shy[RP], shz[RP], slx[RP], sly[RP], slz[RP];
+  double sx[RP], sy[RP], sz[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    gx[r] = gy[r] = gz[r] = 0.0;
+    if (!F64) {
+      split_coord(xi[r], ix, shx[r], slx[r]);
+      split_coord(yi[r], iy, shy[r], sly[r]);
+      split_coord(zi[r], iz, shz[r], slz[r]);
+    } else {
+      sx[r] = xi[r] * ix; sy[r] = yi[r] * iy; sz[r] = zi[r] * iz;
+      sx[r] -= floor(sx[r]); sy[r] -= floor(sy[r]); sz[r] -= floor(sz[r]);
     }
   }
-  __syncthreads();                          // the scratch in `red` is dead
-  red[wave][lane][0] = gx; red[wave][lane][1] = gy; red[wave][lane][2] = gz;
+  float hx[RP], hy[RP], hz[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) hx[r] = hy[r] = hz[r] = 0.f;
+  const int nchunk = a.k2reduce ? 1 : (a.p + kChunk - 1) / kChunk;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int cb = ch * kChunk;
+    const int cnt = min(kChunk, a.p - cb);
+    if (!a.k2reduce) {
+      __syncthreads();
+      const int nvec = (int)((size_t)cnt * sizeof(Coef) / 16);
+      const uint4* src = reinterpret_cast<const uint4*>(gcoef + cb);
+      uint4* dst = reinterpret_cast<uint4*>(scoef);
+      for (int v = tid; v < nvec; v += blockDim.x) dst[v] = src[v];
+      __syncthreads();
+    }
+    const int per = (cnt + KS - 1) / KS;
+    const int l0 = min(cnt, ks * per), l1 = min(cnt, l0 + per);
+    if (!F64) {
+      const FCoef32* sc = reinterpret_cast<const FCoef32*>(scoef);
+#pragma unroll 2
+      for (int l = l0; l < l1; ++l) {
+        const FCoef32 c = sc[l];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx[r], shy[r], shz[r], slx[r],
+                                    sly[r], slz[r]);
+          const float cs = __builtin_amdgcn_cosf(f);
+          const float sn = __builtin_amdgcn_sinf(f);
+          const float gg = fmaf(cs, c.cB, -sn * c.cA);
+          hx[r] = fmaf(gg, c.k[0], hx[r]);
+          hy[r] = fmaf(gg, c.k[1], hy[r]);
+          hz[r] = fmaf(gg, c.k[2], hz[r]);
+        }
+      }
+    } else {
+      const FCoef64* sc = reinterpret_cast<const FCoef64*>(scoef);
+      for (int l = l0; l < l1; ++l) {
+        const FCoef64 c = sc[l];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const double t = c.m[0] * sx[r] + c.m[1] * sy[r] + c.m[2] * sz[r];
+          const double f = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * f, &sn, &cs);
+          const double gg = cs * c.cB - sn * c.cA;
+          gx[r] = fma(gg, c.k[0], gx[r]);
+          gy[r] = fma(gg, c.k[1], gy[r]);
+          gz[r] = fma(gg, c.k[2], gz[r]);
+        }
+      }
+    }
+    if (!F64) {
+      // fold the chunk's FP32 sums into FP64 (chunks of up to 1024 terms)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        gx[r] += (double)hx[r]; gy[r] += (double)hy[r]; gz[r] += (double)hz[r];
+        hx[r] = hy[r] = hz[r] = 0.f;
+      }
+    }
+  }
+  // cross-wave (k-slice) sums, fixed order, then -q_i times the sum
+  __syncthreads();                          // scratch / srho in red_raw are dead
+  float* redf = reinterpret_cast<float*>(red_raw);
+  double* redd = reinterpret_cast<double*>(red_raw);
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int idx = (wave * RP + r) * kWave + lane;
+    if (F64) { redd[3 * idx] = gx[r]; redd[3 * idx + 1] = gy[r]; redd[3 * idx + 2] = gz[r]; }
+    else { redf[3 * idx] = (float)gx[r]; redf[3 * idx + 1] = (float)gy[r]; redf[3 * idx + 2] = (float)gz[r]; }
+  }
   __syncthreads();
-  if (wave == 0 && valid) {
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int w = 0; w < KS; ++w) { sx += red[w][lane][0]; sy += red[w][lane][1]; sz += red[w][lane][2]; }
-    const double qi = -a.q[i];
-    if (a.accumulate) { a.fx[i] += qi * sx; a.fy[i] += qi * sy; a.fz[i] += qi * sz; }
-    else { a.fx[i] = qi * sx; a.fy[i] = qi * sy; a.fz[i] = qi * sz; }
+  if (ks == 0) {
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int64_t i = pbase + r * kWave;
+      if (i >= a.n) continue;
+      double sx2 = 0.0, sy2 = 0.0, sz2 = 0.0;
+      for (int k2 = 0; k2 < KS; ++k2) {
+        const int idx = ((k2 * PW + pw) * RP + r) * kWave + lane;
+        if (F64) { sx2 += redd[3 * idx]; sy2 += redd[3 * idx + 1]; sz2 += redd[3 * idx + 2]; }
+        else { sx2 += redf[3 * idx]; sy2 += redf[3 * idx + 1]; sz2 += redf[3 * idx + 2]; }
+      }
+      const double qi = -a.q[i];
+      if (a.accumulate) { a.fx[i] += qi * sx2; a.fy[i] += qi * sy2; a.fz[i] += qi * sz2; }
+      else { a.fx[i] = qi * sx2; a.fy[i] = qi * sy2; a.fz[i] = qi * sz2; }
+    }
   }
 }
 
 hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.n + kWave - 1) / kWave + (a.k2reduce ? 1 : 0);
-  const dim3 block(a.KS * kWave);
-  if (precision == RBE_PREC_FP32)
-    hipLaunchKernelGGL(k_force<false>, dim3((unsigned)blocks), block, 0, s, a);
+  const int RP = precision == RBE_PREC_FP64 ? 1 : 2;
+  const int64_t per_block = (int64_t)kWave * RP * a.PW;
+  const int64_t blocks = (a.n + per_block - 1) / per_block + (a.k2reduce ? 1 : 0);
+  const dim3 block(a.KS * a.PW * kWave);
+  if (precision == RBE_PREC_FP64)
+    hipLaunchKernelGGL((k_force<true, 1>), dim3((unsigned)blocks), block, 0, s, a);
   else
-    hipLaunchKernelGGL(k_force<true>, dim3((unsigned)blocks), block, 0, s, a);
+    hipLaunchKernelGGL((k_force<false, 2>), dim3((unsigned)blocks), block, 0, s, a);
   return hipGetLastError();
 }
+
 }  // namespace rbe
