@@ -185,6 +185,68 @@ rbe_status rbe_timing_read(rbe_ctx ctx, double* h_ms, int32_t* h_count);
 /* Release the context and its device memory (waits for the stream). */
 void rbe_destroy(rbe_ctx ctx);
 
+/* ---------------------------------------------------------------------------
+ * Real-space part of the Ewald split (section 4.1 eq. (U2), eq. (force) second
+ * term; section 4.2: computed with the nearest image only, for pairs closer
+ * than a cutoff), FP64.  For x = r_j - r_i (nearest image) and |x| < rc:
+ *   U2  = (C/2) sum_{i != j} q_i q_j erfc(sqrt(alpha)|x|)/|x|
+ *   F_i = -C q_i sum_j q_j G(|x|) x/|x|,
+ *         G(r) = erfc(sqrt(alpha) r)/r^2 + 2 sqrt(alpha/pi) exp(-alpha r^2)/r
+ *   W   = +(C/2) sum_{i != j} q_i q_j G(|x|) x x^T/|x|   (energy units)
+ * The paper prints the virial term with the opposite sign; the sign here is
+ * the derivative of U2 in the cell at fixed reduced coordinates.
+ * Optionally a truncated Lennard-Jones term per type pair (not part of the
+ * paper's method; the water- and membrane-shaped systems need a short-range
+ * repulsion): U = c12/r^12 - c6/r^6 for r < rc, added to U2, F and W.
+ * Cells are at least rc wide and there must be >= 3 per axis (rc <= l/3).
+ * Within each cell the members are ordered by index, so every sum has a fixed
+ * order and results are bitwise reproducible. */
+typedef struct rbe_real_ctx_s* rbe_real_ctx;
+
+typedef struct {
+  int64_t n;          /* particles, >= 1                                       */
+  int32_t ntypes;     /* Lennard-Jones types, 0..64; 0 = Coulomb only          */
+  int32_t reserved;   /* must be 0                                             */
+  double  alpha;      /* splitting parameter (the same alpha as rbe_config)    */
+  double  rc;         /* cutoff, > 0                                           */
+  double  coulomb;    /* Coulomb constant C, > 0                               */
+} rbe_real_config;
+
+/* Create a real-space context.
+ *   d_q      : DEVICE, n charges (copied).
+ *   d_type   : DEVICE, n int32 types in 0..ntypes-1 (copied), or NULL if ntypes = 0.
+ *   h_lj     : HOST, ntypes*ntypes pairs (c12, c6), row-major over (t_i, t_j),
+ *              symmetric, or NULL if ntypes = 0.
+ *   box_host : HOST (lx, ly, lz); each >= 3 rc.  Cell storage is sized for
+ *              sides up to 2x these values (at most 64 cells per axis).
+ * Waits for the stream. */
+rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const int32_t* d_type,
+                         const double* h_lj, const double* box_host, void* stream,
+                         rbe_real_ctx* out);
+
+/* Set the cell from host values (read now) for later evaluations. */
+rbe_status rbe_real_set_box(rbe_real_ctx ctx, const double* box_host);
+
+/* Read the cell from DEVICE memory (3 doubles) at every later evaluation.
+ * A cell with a side below 3 rc, or beyond the capacity, is flagged on the
+ * device (the grid is clamped) and reported by rbe_real_check. */
+rbe_status rbe_real_set_box_dev(rbe_real_ctx ctx, const double* d_box);
+
+/* Forces (written, or added when accumulate != 0), virial tensor (6 doubles,
+ * xx yy zz xy xz yz; NULL to skip) and energy (1 double; NULL to skip) of the
+ * real-space sum.  All arrays are DEVICE memory; positions may lie outside
+ * the cell.  Asynchronous (five kernels on the context's stream). */
+rbe_status rbe_real_forces(rbe_real_ctx ctx, const double* d_x, const double* d_y,
+                           const double* d_z, double* d_fx, double* d_fy, double* d_fz,
+                           int accumulate, double* d_virial6, double* d_energy);
+
+/* Wait and report device-side flags: a cell below 3 rc or over capacity, or a
+ * cell with more than 2048 members (its evaluation is then incomplete). */
+rbe_status rbe_real_check(rbe_real_ctx ctx);
+
+/* Release the context (waits for the stream). */
+void rbe_real_destroy(rbe_real_ctx ctx);
+
 /* Text of the last error reported to the calling thread ("" if none). */
 const char* rbe_last_error(void);
 

@@ -62,6 +62,17 @@ namespace {
 
 thread_local std::string g_err;
 
+}  // namespace
+
+namespace rbe {
+rbe_status set_error(rbe_status st, const char* msg) {
+  g_err = msg;
+  return st;
+}
+}  // namespace rbe
+
+namespace {
+
 rbe_status fail(rbe_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 rbe_status fail(rbe_status st, const char* fmt, ...) {
   char buf[512];

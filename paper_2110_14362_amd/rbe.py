@@ -23,7 +23,9 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev",
            "rbe_sample_k", "rbe_set_k", "rbe_get_k", "rbe_forces_pressure", "rbe_get_rho",
            "rbe_get_box_info", "rbe_check", "rbe_timing_enable", "rbe_timing_read",
-           "rbe_destroy", "rbe_last_error", "rbe_version"]
+           "rbe_destroy", "rbe_last_error", "rbe_version",
+           "rbe_real_init", "rbe_real_set_box", "rbe_real_set_box_dev", "rbe_real_forces",
+           "rbe_real_check", "rbe_real_destroy"]
 KERNEL_KINDS = ["tables", "sample", "sfac", "force"]
 
 
@@ -38,6 +40,11 @@ class Config(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("coulomb", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64)]
+
+
+class RealConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ntypes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("rc", ctypes.c_double), ("coulomb", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +75,11 @@ def load_library(path=LIB_PATH):
         "rbe_check": [vp],
         "rbe_timing_enable": [vp, i32],
         "rbe_timing_read": [vp, dp, ctypes.POINTER(i32)],
+        "rbe_real_init": [ctypes.POINTER(RealConfig), vp, vp, dp, dp, vp, ctypes.POINTER(vp)],
+        "rbe_real_set_box": [vp, dp],
+        "rbe_real_set_box_dev": [vp, vp],
+        "rbe_real_forces": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
+        "rbe_real_check": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -75,6 +87,8 @@ def load_library(path=LIB_PATH):
         fn.restype = ctypes.c_int
     lib.rbe_destroy.argtypes = [vp]
     lib.rbe_destroy.restype = None
+    lib.rbe_real_destroy.argtypes = [vp]
+    lib.rbe_real_destroy.restype = None
     lib.rbe_last_error.argtypes = []
     lib.rbe_last_error.restype = ctypes.c_char_p
     lib.rbe_version.argtypes = []
@@ -193,3 +207,55 @@ class RBE:
         _check(_lib.rbe_timing_read(self._ctx, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+class RealSpace:
+    """Real-space Ewald pair sum (rbe_real_init ... rbe_real_destroy)."""
+
+    def __init__(self, q, box, alpha, rc, coulomb=1.0, types=None, lj=None, stream=None):
+        lib = load_library()
+        n = int(q.numel())
+        ntypes = 0 if lj is None else int(np.asarray(lj).shape[0])
+        cfg = RealConfig(n=n, ntypes=ntypes, reserved=0, alpha=float(alpha), rc=float(rc),
+                         coulomb=float(coulomb))
+        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        ljarr = None
+        if ntypes:
+            lj = np.ascontiguousarray(np.asarray(lj, dtype=np.float64).reshape(ntypes, ntypes, 2))
+            self._lj = lj
+            ljarr = lj.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        tptr = _dptr(types, "types", n, "int32") if ntypes else None
+        ctx = ctypes.c_void_p()
+        _check(lib.rbe_real_init(ctypes.byref(cfg), _dptr(q, "q", n), tptr, ljarr, boxarr,
+                                 _stream_handle(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.rbe_real_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_box(self, box):
+        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        _check(_lib.rbe_real_set_box(self._ctx, boxarr))
+
+    def set_box_dev(self, d_box):
+        _check(_lib.rbe_real_set_box_dev(self._ctx, _dptr(d_box, "box", 3)))
+
+    def forces(self, x, y, z, fx, fy, fz, accumulate=False, virial6=None, energy=None):
+        n = self.n
+        _check(_lib.rbe_real_forces(
+            self._ctx, _dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n),
+            _dptr(fx, "fx", n), _dptr(fy, "fy", n), _dptr(fz, "fz", n), int(bool(accumulate)),
+            _dptr(virial6, "virial6", 6) if virial6 is not None else None,
+            _dptr(energy, "energy", 1) if energy is not None else None))
+
+    def check(self):
+        _check(_lib.rbe_real_check(self._ctx))

@@ -1,0 +1,123 @@
+"""Real-space pair kernels vs the FP64 brute-force oracle (nearest image,
+cutoff), with and without the Lennard-Jones term.  Tolerance 1e-10 relative
+(both sides FP64; differences are rounding order only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import realspace as orsp
+from paper_2110_14362_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+# SPC/E oxygen-oxygen Lennard-Jones (sigma 3.166 A, epsilon 0.1553 kcal/mol)
+SIG_O, EPS_O = 3.166, 0.1553
+
+
+def lj_table_water():
+    c12 = np.zeros((2, 2)); c6 = np.zeros((2, 2))
+    c12[0, 0] = 4 * EPS_O * SIG_O ** 12
+    c6[0, 0] = 4 * EPS_O * SIG_O ** 6
+    return c12, c6
+
+
+def water_types(n):
+    return (np.arange(n) % 3 != 0).astype(np.int32)      # O = 0, H = 1
+
+
+def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=None):
+    import torch
+    from paper_2110_14362_amd.rbe import RealSpace
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    pos = s["pos"] if shift is None else s["pos"] + shift
+    lj_arr = None if lj is None else np.stack(lj, axis=-1)
+    tt = None if types is None else torch.tensor(types, dtype=torch.int32, device=dev)
+    ctx = RealSpace(t(s["q"]), s["box"], s["alpha"], rc, coulomb=s.get("coulomb", 1.0),
+                    types=tt, lj=lj_arr)
+    x, y, z = (t(pos[:, a]) for a in range(3))
+    f = [t(f0[:, a]) if f0 is not None else torch.zeros_like(x) for a in range(3)]
+    vir = torch.zeros(6, dtype=torch.float64, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.forces(x, y, z, *f, accumulate=accumulate, virial6=vir, energy=en)
+    ctx.check()
+    W6 = vir.cpu().numpy()
+    W = np.array([[W6[0], W6[3], W6[4]], [W6[3], W6[1], W6[5]], [W6[4], W6[5], W6[2]]])
+    out = dict(forces=np.stack([a.cpu().numpy() for a in f], 1), virial=W,
+               energy=float(en.cpu()[0]))
+    ctx.close()
+    return out
+
+
+def oracle(s, rc, lj=None, types=None, rows=None):
+    o = orsp.realspace_nearest(s["pos"], s["q"], s["box"], s["alpha"], rc,
+                               coulomb=s.get("coulomb", 1.0), rows=rows)
+    if lj is not None:
+        l = orsp.lj_nearest(s["pos"], types, s["box"], lj[0], lj[1], rc, rows=rows)
+        o["forces"] = o["forces"] + l["forces"]
+        if rows is None:
+            o["energy"] += l["energy"]
+            o["virial"] = o["virial"] + l["virial"]
+    return o
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def test_electrolyte_coulomb(gpu):
+    s = workloads.make("electrolyte_1k")
+    g = run_gpu(s, gpu, 6.0)
+    o = oracle(s, 6.0)
+    print("electrolyte real space: force %.2e virial %.2e energy %.2e" %
+          (rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
+           abs(g["energy"] - o["energy"]) / abs(o["energy"])))
+    assert rel(g["forces"], o["forces"]) < 1e-10
+    assert rel(g["virial"], o["virial"]) < 1e-10
+    assert abs(g["energy"] - o["energy"]) < 1e-10 * abs(o["energy"])
+
+
+def test_water_with_lj(gpu):
+    s = workloads.water(1000, seed=7)
+    s.update(alpha=0.09, coulomb=332.0637)
+    types = water_types(len(s["q"]))
+    lj = lj_table_water()
+    g = run_gpu(s, gpu, 10.0, lj=lj, types=types)
+    o = oracle(s, 10.0, lj=lj, types=types)
+    assert rel(g["forces"], o["forces"]) < 1e-10
+    assert rel(g["virial"], o["virial"]) < 1e-10
+    assert abs(g["energy"] - o["energy"]) < 1e-10 * abs(o["energy"])
+
+
+def test_water_30k_sampled_rows(gpu):
+    s = workloads.make("water_30k")
+    types = water_types(len(s["q"]))
+    lj = lj_table_water()
+    g = run_gpu(s, gpu, 10.0, lj=lj, types=types)
+    rows = np.random.default_rng(1).choice(len(s["q"]), 3000, replace=False)
+    o = oracle(s, 10.0, lj=lj, types=types, rows=rows)
+    assert rel(g["forces"][rows], o["forces"]) < 1e-10
+    # Newton's third law over the whole system
+    assert np.abs(g["forces"].sum(0)).max() < 1e-9 * np.sqrt((g["forces"] ** 2).sum())
+
+
+def test_unwrapped_accumulate_and_reproducible(gpu):
+    s = workloads.make("electrolyte_1k")
+    base = run_gpu(s, gpu, 6.0)
+    shift = np.random.default_rng(2).integers(-2, 3, size=s["pos"].shape) * s["box"]
+    moved = run_gpu(s, gpu, 6.0, shift=shift)
+    assert rel(moved["forces"], base["forces"]) < 1e-12
+    again = run_gpu(s, gpu, 6.0)
+    assert np.array_equal(again["forces"], base["forces"])
+    assert np.array_equal(again["virial"], base["virial"])
+    f0 = np.random.default_rng(3).standard_normal(s["pos"].shape)
+    acc = run_gpu(s, gpu, 6.0, accumulate=True, f0=f0)
+    assert np.allclose(acc["forces"] - f0, base["forces"], rtol=1e-12, atol=1e-12)
+
+
+def test_rejects_cutoff_above_third_of_box(gpu):
+    import torch
+    from paper_2110_14362_amd.rbe import RealSpace, RBEError
+    q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
+    with pytest.raises(RBEError):
+        RealSpace(q, (10.0, 10.0, 10.0), 0.3, 4.0)

@@ -325,3 +325,27 @@ def test_rbe_unbiased_and_prop1_variance():
     assert abs(emp.sum() / var_f.sum() - 1.0) < 0.08
     empp = ((Ps - P2) ** 2).mean()
     assert abs(empp / var_p - 1.0) < 0.15
+
+
+def test_lennard_jones_oracle_gradients_and_virial():
+    # pair sum of c12/r^12 - c6/r^6: forces are -grad U (finite differences),
+    # the virial is -dU/deps for l -> (1+eps) l at fixed reduced coordinates
+    s = workloads.random_neutral(24, (7.0, 7.5, 8.0), seed=13)
+    types = np.arange(24) % 3
+    c12 = np.array([[1.0, 1.5, 2.0], [1.5, 2.5, 1.2], [2.0, 1.2, 3.0]]) * 2e-3
+    c6 = np.array([[1.0, 0.8, 0.6], [0.8, 1.2, 0.7], [0.6, 0.7, 0.9]]) * 2e-2
+    rc = 3.4
+    base = realspace.lj_nearest(s["pos"], types, s["box"], c12, c6, rc)
+    eps = 1e-6
+    for i, c in ((0, 0), (7, 1), (19, 2)):
+        rp = s["pos"].copy(); rp[i, c] += eps
+        rm = s["pos"].copy(); rm[i, c] -= eps
+        fd = -(realspace.lj_nearest(rp, types, s["box"], c12, c6, rc)["energy"]
+               - realspace.lj_nearest(rm, types, s["box"], c12, c6, rc)["energy"]) / (2 * eps)
+        assert abs(fd - base["forces"][i, c]) < 1e-6 * max(1.0, np.abs(base["forces"]).max())
+    for a in range(3):
+        sc = np.ones(3); sc[a] += eps
+        up = realspace.lj_nearest(s["pos"] * sc, types, s["box"] * sc, c12, c6, rc)["energy"]
+        sc[a] -= 2 * eps
+        dn = realspace.lj_nearest(s["pos"] * sc, types, s["box"] * sc, c12, c6, rc)["energy"]
+        assert abs(-(up - dn) / (2 * eps) - base["virial"][a, a]) < 1e-6 * max(1.0, np.abs(base["virial"]).max())
