@@ -247,6 +247,82 @@ rbe_status rbe_real_check(rbe_real_ctx ctx);
 /* Release the context (waits for the stream). */
 void rbe_real_destroy(rbe_real_ctx ctx);
 
+/* ---------------------------------------------------------------------------
+ * Langevin NPT integrator (section 3.2 eq. (24), cubic cell; appendix A eq.
+ * (99999), semi-isotropic cell with gamma0 = 0), FP64, split as in section
+ * 3.3:   B_V(h) B_R(h) A_V(h) A_R(h) O^p(dt) O(dt) A_R(h) A_V(h) | F, P | B_R(h) B_V(h)
+ * with h = dt/2, every sub-flow solved exactly with the other variables
+ * frozen:  A_R  r <- r e^{a h} + (p/m)(e^{a h} - 1)/a,
+ *          B_R  p <- p e^{-a h} + F (1 - e^{-a h})/a,
+ * a the per-axis scaling rate (V'/3V; or A'/2A, A'/2A, L'/L), the OU steps
+ * exact (section 3.3), B_V driven by the instantaneous pressure tensor
+ * (sum_i p_i p_i^T/m_i + W)/V of appendix C (iso: its trace/3; semi: (xx+yy)/2
+ * against L, zz against A).  The B_V opening a step uses the pressure formed
+ * at the end of the previous step (or by rbe_md_pressure before the first).
+ * Noise: Philox4x64-10 keyed (seed, system_id), counter (step, i, 'nois', 0)
+ * for particle i and (step, 0, 'cell', 0) for the cell; Box-Muller normals.
+ * Units: forces and virials are multiplied by ftm to give mass x length /
+ * time^2 (1 in reduced units; 4.184e-4 for kcal/mol/A with g/mol and fs);
+ * kT and p_ext are in the force's energy units.  Momenta p = m v.
+ * Positions, momenta and forces are caller-owned DEVICE arrays (SoA FP64). */
+typedef struct rbe_md_ctx_s* rbe_md_ctx;
+
+typedef struct {
+  int64_t  n;            /* particles                                           */
+  int32_t  box_mode;     /* RBE_BOX_ISO or RBE_BOX_SEMIISO                       */
+  int32_t  reserved;     /* must be 0                                           */
+  double   dt;           /* time step                                           */
+  double   kT;           /* k_B T (energy units)                                */
+  double   p_ext;        /* external pressure (energy / length^3)               */
+  double   gamma_p;      /* particle friction (1/time), >= 0                     */
+  double   gamma_cell;   /* cell friction (1/time), >= 0                         */
+  double   mass_cell;    /* iso: mass M of V; semi: mass M_A of A                */
+  double   mass_cell_z;  /* semi: mass M_L of L (ignored for iso)                */
+  double   ftm;          /* force units -> mass x length / time^2                */
+  uint64_t seed;
+  uint64_t system_id;
+} rbe_md_config;
+
+/* d_mass: DEVICE, n masses (copied).  box_host: initial cell (cubic for iso,
+ * lx == ly for semi), momenta of the cell start at 0.  Waits. */
+rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const double* box_host,
+                       void* stream, rbe_md_ctx* out);
+
+/* Instantaneous pressure from the current momenta and the virial tensors
+ * (6 doubles each, DEVICE, either may be NULL), without moving anything: call
+ * once before the first step.  Asynchronous. */
+rbe_status rbe_md_pressure(rbe_md_ctx ctx, const double* d_px, const double* d_py,
+                           const double* d_pz, const double* d_virial_k,
+                           const double* d_virial_r);
+
+/* B_V B_R A_V A_R O^p O A_R A_V of step `step` on positions and momenta with
+ * the forces of the previous evaluation.  Afterwards rbe_md_box_dev() holds
+ * the cell for this step's force evaluation.  Asynchronous. */
+rbe_status rbe_md_first_half(rbe_md_ctx ctx, uint64_t step, double* d_x, double* d_y,
+                             double* d_z, double* d_px, double* d_py, double* d_pz,
+                             const double* d_fx, const double* d_fy, const double* d_fz);
+
+/* B_R with the new forces, the pressure tensor from the momenta and the
+ * virial tensors (DEVICE, 6 doubles each, either may be NULL), then B_V.
+ * Asynchronous. */
+rbe_status rbe_md_second_half(rbe_md_ctx ctx, double* d_px, double* d_py, double* d_pz,
+                              const double* d_fx, const double* d_fy, const double* d_fz,
+                              const double* d_virial_k, const double* d_virial_r);
+
+/* DEVICE pointer to the 3 side lengths of the current step's cell (valid
+ * after rbe_md_first_half; feed it to rbe_rescale_box_dev / rbe_real_set_box_dev). */
+const double* rbe_md_box_dev(rbe_md_ctx ctx);
+
+/* Waits; h_state[24] = lx ly lz, volume, pV, pA, pL, pressure tensor (6,
+ * energy/length^3), kinetic tensor sum p p^T/m (6, energy), error flags,
+ * step, A, L, V. */
+rbe_status rbe_md_get_state(rbe_md_ctx ctx, double* h_state);
+
+/* Waits; RBE_ERR_STATE if the cell collapsed or became non-finite. */
+rbe_status rbe_md_check(rbe_md_ctx ctx);
+
+void rbe_md_destroy(rbe_md_ctx ctx);
+
 /* Text of the last error reported to the calling thread ("" if none). */
 const char* rbe_last_error(void);
 

@@ -1,0 +1,181 @@
+"""Langevin NPT integrator in FP64 (reference).
+
+TEST INFRASTRUCTURE ONLY (FP64 CPU oracle; imported by tests, the smoke check
+and the benchmark's CPU-baseline leg, never by the product path).
+
+Equations of motion: section 3.2 eq. (24) for a cubic cell (V, p^V) and
+appendix A eq. (99999) for the semi-isotropic cell (A, p^A, L, p^L):
+
+    r' = p/m + D r,         p' = F - D p - gamma p + sqrt(2 kT m gamma) W'
+    iso:  D = (V'/3V) I,    V' = p^V/M,  p^V' = P_ins - P - gamma_c p^V + noise
+    semi: D = diag(A'/2A, A'/2A, L'/L),
+          p^A' = L (P_A - P) - ...,  P_A = (P_xx + P_yy)/2 + gamma0/L (gamma0 = 0),
+          p^L' = A (P_zz - P) - ...
+
+Time step (section 3.3): the palindromic Trotter order
+    B_V(h) B_R(h) A_V(h) A_R(h) O^p(dt) O(dt) A_R(h) A_V(h) [forces, pressure] B_R(h) B_V(h),
+h = dt/2.  Sub-flows, each solved exactly with the other variables frozen
+(reading of the cited exact solutions): with the per-axis rate a = D_aa,
+    A_R:  r <- r e^{a h} + (p/m) (e^{a h} - 1)/a
+    B_R:  p <- p e^{-a h} + F (1 - e^{-a h})/a
+    A_V:  V <- V + h p^V/M   (A, L likewise)
+    B_V:  p^V <- p^V + h (P_ins - P)   (semi: h L (P_A - P), h A (P_zz - P))
+    O:    p <- e^{-g dt} p + sqrt(kT m (1 - e^{-2 g dt})) R   (exact OU, section 3.3)
+The instantaneous pressure tensor is (sum_i p_i p_i^T/m_i + W)/V, W the
+virial tensor of the forces (eq. pressuretensorflexible); its trace/3 is the
+scalar P_ins of eq. (pressurecubic).  The B_V that opens a step uses the
+pressure from the end of the previous step (same momenta and virial).
+
+Units: forces and virials enter multiplied by `ftm` (force unit -> mass x
+length / time^2); kT and P are given in energy units and multiplied by ftm.
+
+Noise: Philox4x64-10 keyed (seed, system_id); particle i at step s uses
+counter (s, i, TAG_NOISE, 0): uniforms u0..u3 give three normals by Box-Muller,
+z0 = sqrt(-2 ln(1-u0)) cos(2 pi u1), z1 = ... sin(2 pi u1),
+z2 = sqrt(-2 ln(1-u2)) cos(2 pi u3).  The cell uses counter (s, 0, TAG_CELL, 0):
+z0 for V (or A), z1 for L.
+"""
+
+import math
+import numpy as np
+
+from .philox import philox4x64, u01
+
+TAG_NOISE = 0x6E6F6973   # 'nois'
+TAG_CELL = 0x63656C6C    # 'cell'
+
+
+def normals3(seed, system_id, step, index, tag):
+    r = philox4x64((step, index, tag, 0), (seed, system_id))
+    u = [u01(x) for x in r]
+    a = math.sqrt(-2.0 * math.log(1.0 - u[0]))
+    b = math.sqrt(-2.0 * math.log(1.0 - u[2]))
+    return (a * math.cos(2.0 * math.pi * u[1]), a * math.sin(2.0 * math.pi * u[1]),
+            b * math.cos(2.0 * math.pi * u[3]))
+
+
+def particle_noise(seed, system_id, step, n):
+    return np.array([normals3(seed, system_id, step, i, TAG_NOISE) for i in range(n)])
+
+
+def _expm1_over(a, h):
+    """(e^{a h} - 1)/a, with its limit h at a = 0."""
+    return h if a == 0.0 else math.expm1(a * h) / a
+
+
+class NPTState:
+    """Cell and barostat state.  mode 'iso': V, pV, M; 'semi': A, pA, MA, L, pL, ML."""
+
+    def __init__(self, mode, box, masses):
+        self.mode = mode
+        box = [float(b) for b in box]
+        if mode == "iso":
+            self.V = box[0] * box[1] * box[2]
+            self.pV = 0.0
+            self.M = float(masses[0])
+        else:
+            self.A = box[0] * box[1]
+            self.L = box[2]
+            self.pA = 0.0
+            self.pL = 0.0
+            self.MA = float(masses[0])
+            self.ML = float(masses[1])
+        self.P_ins = np.zeros((3, 3))
+
+    def box(self):
+        if self.mode == "iso":
+            L = self.V ** (1.0 / 3.0)
+            return np.array([L, L, L])
+        s = math.sqrt(self.A)
+        return np.array([s, s, self.L])
+
+    def volume(self):
+        return self.V if self.mode == "iso" else self.A * self.L
+
+    def rates(self):
+        """Per-axis scaling rate D_aa of eq. (24) / eq. (99999)."""
+        if self.mode == "iso":
+            a = self.pV / (3.0 * self.M * self.V)
+            return np.array([a, a, a])
+        axy = self.pA / (2.0 * self.MA * self.A)
+        return np.array([axy, axy, self.pL / (self.ML * self.L)])
+
+
+class LangevinNPT:
+    """One BAOAB step of the Langevin NPT equations (see the module docstring)."""
+
+    def __init__(self, mode, masses_cell, dt, kT, P, gamma_p, gamma_c, ftm, seed, system_id):
+        self.mode = mode
+        self.masses_cell = masses_cell
+        self.dt, self.kT, self.P = dt, kT, P
+        self.gp, self.gc, self.ftm = gamma_p, gamma_c, ftm
+        self.seed, self.sysid = seed, system_id
+
+    def pressure(self, st, p, m, W):
+        """Instantaneous pressure tensor (internal units): (sum p p^T/m + ftm W)/V."""
+        K = np.einsum("ia,ib->ab", p, p / m[:, None])
+        return (K + self.ftm * np.asarray(W)) / st.volume()
+
+    def B_V(self, st, h):
+        P = self.ftm * self.P
+        Pt = st.P_ins
+        if st.mode == "iso":
+            st.pV += h * (np.trace(Pt) / 3.0 - P)
+        else:
+            st.pA += h * st.L * (0.5 * (Pt[0, 0] + Pt[1, 1]) - P)
+            st.pL += h * st.A * (Pt[2, 2] - P)
+
+    def A_V(self, st, h):
+        if st.mode == "iso":
+            st.V += h * st.pV / st.M
+        else:
+            st.A += h * st.pA / st.MA
+            st.L += h * st.pL / st.ML
+
+    def B_R(self, st, p, F, h):
+        a = st.rates()
+        out = p.copy()
+        for ax in range(3):
+            e = math.exp(-a[ax] * h)
+            out[:, ax] = p[:, ax] * e + self.ftm * F[:, ax] * _expm1_over(-a[ax], h)
+        return out
+
+    def A_R(self, st, r, p, m, h):
+        a = st.rates()
+        out = r.copy()
+        for ax in range(3):
+            out[:, ax] = r[:, ax] * math.exp(a[ax] * h) + (p[:, ax] / m) * _expm1_over(a[ax], h)
+        return out
+
+    def O_cell(self, st, step):
+        z = normals3(self.seed, self.sysid, step, 0, TAG_CELL)
+        c1 = math.exp(-self.gc * self.dt)
+        if st.mode == "iso":
+            st.pV = c1 * st.pV + math.sqrt(self.ftm * self.kT * st.M * (1.0 - c1 * c1)) * z[0]
+        else:
+            st.pA = c1 * st.pA + math.sqrt(self.ftm * self.kT * st.MA * (1.0 - c1 * c1)) * z[0]
+            st.pL = c1 * st.pL + math.sqrt(self.ftm * self.kT * st.ML * (1.0 - c1 * c1)) * z[1]
+
+    def O_particles(self, p, m, step):
+        z = particle_noise(self.seed, self.sysid, step, p.shape[0])
+        c1 = math.exp(-self.gp * self.dt)
+        return c1 * p + np.sqrt(self.ftm * self.kT * m * (1.0 - c1 * c1))[:, None] * z
+
+    def first_half(self, st, r, p, m, F, step):
+        h = 0.5 * self.dt
+        self.B_V(st, h)
+        p = self.B_R(st, p, F, h)
+        self.A_V(st, h)
+        r = self.A_R(st, r, p, m, h)
+        self.O_cell(st, step)
+        p = self.O_particles(p, m, step)
+        r = self.A_R(st, r, p, m, h)
+        self.A_V(st, h)
+        return r, p
+
+    def second_half(self, st, p, m, F, W):
+        h = 0.5 * self.dt
+        p = self.B_R(st, p, F, h)
+        st.P_ins = self.pressure(st, p, m, W)
+        self.B_V(st, h)
+        return p

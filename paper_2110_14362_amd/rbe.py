@@ -25,7 +25,9 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_get_box_info", "rbe_check", "rbe_timing_enable", "rbe_timing_read",
            "rbe_destroy", "rbe_last_error", "rbe_version",
            "rbe_real_init", "rbe_real_set_box", "rbe_real_set_box_dev", "rbe_real_forces",
-           "rbe_real_check", "rbe_real_destroy"]
+           "rbe_real_check", "rbe_real_destroy",
+           "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
+           "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy"]
 KERNEL_KINDS = ["tables", "sample", "sfac", "force"]
 
 
@@ -45,6 +47,14 @@ class Config(ctypes.Structure):
 class RealConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ntypes", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("rc", ctypes.c_double), ("coulomb", ctypes.c_double)]
+
+
+class MDConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("box_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("kT", ctypes.c_double), ("p_ext", ctypes.c_double),
+                ("gamma_p", ctypes.c_double), ("gamma_cell", ctypes.c_double),
+                ("mass_cell", ctypes.c_double), ("mass_cell_z", ctypes.c_double),
+                ("ftm", ctypes.c_double), ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64)]
 
 
 _lib = None
@@ -80,6 +90,12 @@ def load_library(path=LIB_PATH):
         "rbe_real_set_box_dev": [vp, vp],
         "rbe_real_forces": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "rbe_real_check": [vp],
+        "rbe_md_init": [ctypes.POINTER(MDConfig), vp, dp, vp, ctypes.POINTER(vp)],
+        "rbe_md_pressure": [vp, vp, vp, vp, vp, vp],
+        "rbe_md_first_half": [vp, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "rbe_md_second_half": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "rbe_md_get_state": [vp, dp],
+        "rbe_md_check": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -89,6 +105,10 @@ def load_library(path=LIB_PATH):
     lib.rbe_destroy.restype = None
     lib.rbe_real_destroy.argtypes = [vp]
     lib.rbe_real_destroy.restype = None
+    lib.rbe_md_destroy.argtypes = [vp]
+    lib.rbe_md_destroy.restype = None
+    lib.rbe_md_box_dev.argtypes = [vp]
+    lib.rbe_md_box_dev.restype = ctypes.c_void_p
     lib.rbe_last_error.argtypes = []
     lib.rbe_last_error.restype = ctypes.c_char_p
     lib.rbe_version.argtypes = []
@@ -161,6 +181,10 @@ class RBE:
 
     def rescale_box_dev(self, d_box):
         _check(_lib.rbe_rescale_box_dev(self._ctx, _dptr(d_box, "box", 3)))
+
+    def rescale_box_dev_ptr(self, ptr):
+        """Like rescale_box_dev with a raw device address (e.g. Integrator.box_dev_ptr())."""
+        _check(_lib.rbe_rescale_box_dev(self._ctx, ctypes.c_void_p(int(ptr))))
 
     def sample_k(self, step):
         _check(_lib.rbe_sample_k(self._ctx, ctypes.c_uint64(int(step) & (2**64 - 1))))
@@ -249,6 +273,10 @@ class RealSpace:
     def set_box_dev(self, d_box):
         _check(_lib.rbe_real_set_box_dev(self._ctx, _dptr(d_box, "box", 3)))
 
+    def set_box_dev_ptr(self, ptr):
+        """Like set_box_dev with a raw device address."""
+        _check(_lib.rbe_real_set_box_dev(self._ctx, ctypes.c_void_p(int(ptr))))
+
     def forces(self, x, y, z, fx, fy, fz, accumulate=False, virial6=None, energy=None):
         n = self.n
         _check(_lib.rbe_real_forces(
@@ -259,3 +287,69 @@ class RealSpace:
 
     def check(self):
         _check(_lib.rbe_real_check(self._ctx))
+
+
+class Integrator:
+    """Langevin NPT integrator (rbe_md_init ... rbe_md_destroy)."""
+
+    def __init__(self, mass, box, dt, kT, p_ext, gamma_p, gamma_cell, mass_cell,
+                 mass_cell_z=0.0, box_mode="iso", ftm=1.0, seed=0, system_id=0, stream=None):
+        lib = load_library()
+        n = int(mass.numel())
+        cfg = MDConfig(n=n, box_mode=BOX_MODES[box_mode], reserved=0, dt=float(dt), kT=float(kT),
+                       p_ext=float(p_ext), gamma_p=float(gamma_p), gamma_cell=float(gamma_cell),
+                       mass_cell=float(mass_cell), mass_cell_z=float(mass_cell_z), ftm=float(ftm),
+                       seed=int(seed) & (2**64 - 1), system_id=int(system_id) & (2**64 - 1))
+        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        ctx = ctypes.c_void_p()
+        _check(lib.rbe_md_init(ctypes.byref(cfg), _dptr(mass, "mass", n), boxarr,
+                               _stream_handle(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.rbe_md_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pressure(self, px, py, pz, virial_k=None, virial_r=None):
+        n = self.n
+        _check(_lib.rbe_md_pressure(self._ctx, _dptr(px, "px", n), _dptr(py, "py", n),
+                                    _dptr(pz, "pz", n),
+                                    _dptr(virial_k, "virial_k", 6) if virial_k is not None else None,
+                                    _dptr(virial_r, "virial_r", 6) if virial_r is not None else None))
+
+    def first_half(self, step, x, y, z, px, py, pz, fx, fy, fz):
+        n = self.n
+        _check(_lib.rbe_md_first_half(self._ctx, ctypes.c_uint64(int(step)),
+                                      *[_dptr(t, nm, n) for t, nm in
+                                        ((x, "x"), (y, "y"), (z, "z"), (px, "px"), (py, "py"),
+                                         (pz, "pz"), (fx, "fx"), (fy, "fy"), (fz, "fz"))]))
+
+    def second_half(self, px, py, pz, fx, fy, fz, virial_k=None, virial_r=None):
+        n = self.n
+        _check(_lib.rbe_md_second_half(
+            self._ctx, *[_dptr(t, nm, n) for t, nm in
+                         ((px, "px"), (py, "py"), (pz, "pz"), (fx, "fx"), (fy, "fy"), (fz, "fz"))],
+            _dptr(virial_k, "virial_k", 6) if virial_k is not None else None,
+            _dptr(virial_r, "virial_r", 6) if virial_r is not None else None))
+
+    def box_dev_ptr(self):
+        return _lib.rbe_md_box_dev(self._ctx)
+
+    def state(self):
+        h = np.zeros(24, dtype=np.float64)
+        _check(_lib.rbe_md_get_state(self._ctx, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        t6 = lambda v: np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+        return dict(box=h[0:3].copy(), volume=h[3], pV=h[4], pA=h[5], pL=h[6],
+                    pressure=t6(h[7:13]), kinetic=t6(h[13:19]), err=int(h[19]), step=int(h[20]),
+                    A=h[21], L=h[22], V=h[23])
+
+    def check(self):
+        _check(_lib.rbe_md_check(self._ctx))

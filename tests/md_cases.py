@@ -1,0 +1,42 @@
+"""Oracle-side NPT trajectories matching paper_2110_14362_amd.md.NPTSystem
+(same step order, same noise and batch streams)."""
+import numpy as np
+
+from oracle import integrator as oint
+from oracle import rbe as orbe
+from oracle import realspace as orsp
+from oracle import sampler as osamp
+
+INIT_STEP = 2 ** 63       # batch stream step used for the forces before step 0
+
+
+def oracle_forces(sysd, md, pos, box, step, seed, system_id):
+    m = osamp.sample_k(sysd["alpha"], box, sysd["p"], seed=seed, system_id=system_id, step=step)
+    S = osamp.box_tables(sysd["alpha"], box)["S"]
+    k = orbe.rbe_kspace(pos, sysd["q"], box, sysd["alpha"], m, S, coulomb=sysd["coulomb"])
+    r = orsp.realspace_nearest(pos, sysd["q"], box, sysd["alpha"], md["rc"], coulomb=sysd["coulomb"])
+    F = k["forces"] + r["forces"]
+    W = k["virial"] + r["virial"]
+    if md.get("lj") is not None:
+        lj = np.asarray(md["lj"])
+        l = orsp.lj_nearest(pos, md["types"], box, lj[..., 0], lj[..., 1], md["rc"])
+        F = F + l["forces"]
+        W = W + l["virial"]
+    return F, W
+
+
+def oracle_trajectory(sysd, md, momenta, steps, seed, system_id):
+    mode = "iso" if md.get("box_mode", "iso") == "iso" else "semi"
+    st = oint.NPTState(mode, sysd["box"], (md["mass_cell"], md.get("mass_cell_z", 0.0)))
+    integ = oint.LangevinNPT(mode, None, md["dt"], md["kT"], md["p_ext"], md["gamma_p"],
+                             md["gamma_cell"], md["ftm"], seed, system_id)
+    m = np.asarray(sysd["mass"], dtype=np.float64)
+    r = np.asarray(sysd["pos"], dtype=np.float64).copy()
+    p = np.asarray(momenta, dtype=np.float64).copy()
+    F, W = oracle_forces(sysd, md, r, st.box(), INIT_STEP, seed, system_id)
+    st.P_ins = integ.pressure(st, p, m, W)
+    for s in range(steps):
+        r, p = integ.first_half(st, r, p, m, F, s)
+        F, W = oracle_forces(sysd, md, r, st.box(), s, seed, system_id)
+        p = integ.second_half(st, p, m, F, W)
+    return dict(pos=r, mom=p, box=st.box(), state=st)
