@@ -56,6 +56,24 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 10}))
 
 
+def profiled_traffic(kernel, workload):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2110_14362_amd", "csrc", "rbe_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if not line.startswith("traffic: "):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if (kv.get("kernel") == kernel and kv.get("workload") == workload
+                    and kv.get("source_sha256") == sha):
+                return int(kv["read_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def make_step(ctx, box, x, y, z, fx, fy, fz, vir, en):
     def step(i):
         ctx.rescale_box(box)
@@ -138,7 +156,7 @@ def main():
         kt = ctx.timing_read()
         ctx.timing_enable(0)
         ctx.check()
-        results[prec] = dict(seconds=el, steps=K, kernels=kt)
+        results[prec] = dict(seconds=el, steps=K, kernels=kt, plan=ctx.plan())
         ctx.close()
 
     main_r = results[args.precision]
@@ -150,11 +168,18 @@ def main():
     t_dom = kern[dom]["avg_us"] * 1e-6
     achieved = TRANS_PER_PAIR * N * P / t_dom
     step_dev = sum((v["avg_us"] or 0.0) for v in kern.values()) * 1e-6
-    roof = {"bound": "alu", "kernel": "k_%s_%s" % (dom, args.precision),
+    plan = main_r["plan"]
+    f64 = args.precision == "fp64"
+    kname = ("k_sfac<%s,%d>" % ("true" if f64 else "false", 1 if f64 else plan["R"]) if dom == "sfac"
+             else "k_force<%s,%d>" % ("true" if f64 else "false", 1 if f64 else 2))
+    roof = {"bound": "alu", "kernel": kname,
             "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
-            "frac": achieved / TRANS_PEAK, "traffic": None,
+            "frac": achieved / TRANS_PEAK, "traffic": profiled_traffic(kname, args.workload + (
+                "_p%d" % args.p if args.p else "")),
             "per_unit": "2 transcendentals (sin, cos) per (particle, frequency) pair; "
-                        "%d x %d pairs per launch" % (N, P)}
+                        "%d x %d pairs per launch" % (N, P),
+            "timing": "HIP events on the library stream around each launch, over %d steps"
+                      % main_r["steps"]}
     out = {
         "metric": METRIC, "value": value, "unit": "(N*P)/s", "n_gpus": 1,
         "steps": main_r["steps"], "warmup": args.warmup, "ms_per_step": ms,
@@ -170,6 +195,7 @@ def main():
                           "note": "one complex exponential per pair over the summed device "
                                   "time of all kernels of a step"},
         "kernels_us": kern,
+        "plan": plan,
     }
     for prec, r in results.items():
         if prec != args.precision:

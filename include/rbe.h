@@ -165,6 +165,14 @@ rbe_status rbe_get_rho(rbe_ctx ctx, double* h_rho);
  * h_info[10] = mcut_z; h_info[11] = device error flags (0 = none). */
 rbe_status rbe_get_box_info(rbe_ctx ctx, double* h_info);
 
+/* Launch geometry chosen at rbe_init (no device work): h_plan[12] = X
+ * (particle chunks), Y (frequency slices), KB (frequency groups per block),
+ * R (frequencies per lane), GX (chunks per reduction group), NG (groups),
+ * chunk (particles per chunk), Ppad, KS (force waves per particle group),
+ * PW (particle waves per force block), k2reduce (1: the force kernel sums
+ * the rho partials), 0. */
+rbe_status rbe_get_plan(rbe_ctx ctx, int32_t* h_plan);
+
 /* Wait for the stream and report device-side errors (capacity overflow of a
  * device rescale) as a status.  Clears the device error flags. */
 rbe_status rbe_check(rbe_ctx ctx);

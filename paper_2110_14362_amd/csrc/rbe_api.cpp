@@ -462,6 +462,14 @@ rbe_status rbe_get_box_info(rbe_ctx c, double* h_info) {
   return RBE_OK;
 }
 
+rbe_status rbe_get_plan(rbe_ctx c, int32_t* h) {
+  if (!c || !h) return fail(RBE_ERR_ARG, "NULL argument");
+  const StepArgs& a = c->a;
+  const int32_t v[12] = {a.X, a.Y, a.KB, a.R, a.GX, a.NG, a.chunk, a.Ppad, a.KS, a.PW, a.k2reduce, 0};
+  for (int i = 0; i < 12; ++i) h[i] = v[i];
+  return RBE_OK;
+}
+
 rbe_status rbe_check(rbe_ctx c) {
   if (!c) return fail(RBE_ERR_ARG, "NULL context");
   rbe_status st = flush(c);

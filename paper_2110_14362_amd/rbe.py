@@ -22,7 +22,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 # every symbol include/rbe.h declares
 EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev",
            "rbe_sample_k", "rbe_set_k", "rbe_get_k", "rbe_forces_pressure", "rbe_get_rho",
-           "rbe_get_box_info", "rbe_check", "rbe_timing_enable", "rbe_timing_read",
+           "rbe_get_box_info", "rbe_get_plan", "rbe_check", "rbe_timing_enable", "rbe_timing_read",
            "rbe_destroy", "rbe_last_error", "rbe_version",
            "rbe_real_init", "rbe_real_set_box", "rbe_real_set_box_dev", "rbe_real_forces",
            "rbe_real_check", "rbe_real_destroy",
@@ -83,6 +83,7 @@ def load_library(path=LIB_PATH):
         "rbe_get_rho": [vp, dp],
         "rbe_get_box_info": [vp, dp],
         "rbe_check": [vp],
+        "rbe_get_plan": [vp, ctypes.POINTER(i32)],
         "rbe_timing_enable": [vp, i32],
         "rbe_timing_read": [vp, dp, ctypes.POINTER(i32)],
         "rbe_real_init": [ctypes.POINTER(RealConfig), vp, vp, dp, dp, vp, ctypes.POINTER(vp)],
@@ -220,6 +221,12 @@ class RBE:
 
     def check(self):
         _check(_lib.rbe_check(self._ctx))
+
+    def plan(self):
+        h = np.zeros(12, dtype=np.int32)
+        _check(_lib.rbe_get_plan(self._ctx, h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        keys = ["X", "Y", "KB", "R", "GX", "NG", "chunk", "Ppad", "KS", "PW", "k2reduce"]
+        return {k: int(h[i]) for i, k in enumerate(keys)}
 
     def timing_enable(self, max_launches):
         _check(_lib.rbe_timing_enable(self._ctx, int(max_launches)))
