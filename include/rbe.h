@@ -256,7 +256,8 @@ rbe_status rbe_real_check(rbe_real_ctx ctx);
 void rbe_real_destroy(rbe_real_ctx ctx);
 
 /* ---------------------------------------------------------------------------
- * Langevin NPT integrator (section 3.2 eq. (24), cubic cell; appendix A eq.
+ * Langevin NPT integrator (section 3.2 eq. (24), isotropic scaling of a
+ * rectangular cell at its initial aspect ratio; appendix A eq.
  * (99999), semi-isotropic cell with gamma0 = 0), FP64, split as in section
  * 3.3:   B_V(h) B_R(h) A_V(h) A_R(h) O^p(dt) O(dt) A_R(h) A_V(h) | F, P | B_R(h) B_V(h)
  * with h = dt/2, every sub-flow solved exactly with the other variables
@@ -291,8 +292,9 @@ typedef struct {
   uint64_t system_id;
 } rbe_md_config;
 
-/* d_mass: DEVICE, n masses (copied).  box_host: initial cell (cubic for iso,
- * lx == ly for semi), momenta of the cell start at 0.  Waits. */
+/* d_mass: DEVICE, n masses (copied).  box_host: initial cell (any aspect
+ * ratio for iso, which keeps it; lx == ly for semi), momenta of the cell
+ * start at 0.  Waits. */
 rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const double* box_host,
                        void* stream, rbe_md_ctx* out);
 
@@ -330,6 +332,89 @@ rbe_status rbe_md_get_state(rbe_md_ctx ctx, double* h_state);
 rbe_status rbe_md_check(rbe_md_ctx ctx);
 
 void rbe_md_destroy(rbe_md_ctx ctx);
+
+/* ---------------------------------------------------------------------------
+ * Served batching: many independent NPT systems, each the full step above
+ * (Fourier part, real-space pairs, integrator) with its own state kept on
+ * the device between steps, advanced together.  Admission is bounded by a
+ * device-memory budget and a slot count.  A fused step launches each kernel
+ * of the step once for all admitted systems (a system's blocks are its own
+ * launch plan's blocks, so its arithmetic and reduction order are those it
+ * has alone: results do not depend on which other systems share the step).
+ * All calls on one batch must come from one host thread. */
+typedef struct rbe_batch_s* rbe_batch;
+
+typedef struct {
+  int32_t  precision;    /* rbe_precision of the Fourier part, every system  */
+  int32_t  max_systems;  /* slots, 1..4096                                     */
+  int64_t  hbm_budget;   /* device bytes the admitted systems may hold (> 0)    */
+} rbe_batch_config;
+
+typedef struct {
+  int64_t  n;            /* particles                                          */
+  int32_t  p;            /* frequencies per step (batch size P)                */
+  int32_t  ntypes;       /* Lennard-Jones types (0: none)                      */
+  int32_t  box_mode;     /* RBE_BOX_ISO (any aspect ratio, kept) or RBE_BOX_SEMIISO */
+  int32_t  reserved;     /* must be 0                                          */
+  double   alpha;        /* Ewald splitting parameter (length^-2)              */
+  double   coulomb;      /* Coulomb constant in the force units                */
+  double   rc;           /* real-space cutoff                                  */
+  double   dt, kT, p_ext, gamma_p, gamma_cell, mass_cell, mass_cell_z, ftm;
+                         /* integrator parameters, as in rbe_md_config         */
+  uint64_t seed;         /* Philox key word 0                                  */
+  uint64_t system_id;    /* Philox key word 1 (e.g. the request id)            */
+} rbe_system_desc;
+
+/* stream: hipStream_t for every launch and copy of the batch (NULL: the null
+ * stream).  Allocates two pinned argument-table buffers. */
+rbe_status rbe_batch_create(const rbe_batch_config* cfg, void* stream, rbe_batch* out);
+
+/* Device bytes a system holds while admitted (its state arrays and the
+ * buffers of its three contexts, each rounded up to 256 bytes): the figure
+ * admission charges against the budget. */
+rbe_status rbe_batch_footprint(const rbe_system_desc* desc, const double* box_host,
+                               int64_t* bytes);
+
+/* Admit one system.  HOST arrays: h_pos [n][3], h_mom [n][3] (NULL: zero
+ * momenta), h_q [n] (neutral), h_mass [n], h_type [n] and h_lj
+ * [ntypes][ntypes][2] = (c12, c6) when ntypes > 0; box_host [3].  Copies
+ * everything to the device, evaluates the opening forces and pressure (the
+ * Fourier batch of step 2^63) and waits.  RBE_ERR_CAPACITY, with nothing
+ * allocated, when no slot is free or the footprint would take the batch
+ * over its budget; *slot gets the slot index (>= 0) on success. */
+rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* desc, const double* h_pos,
+                           const double* h_mom, const double* h_q, const double* h_mass,
+                           const int32_t* h_type, const double* h_lj, const double* box_host,
+                           int32_t* slot);
+
+/* One NPT step of every admitted system (each at its own step index, which
+ * then advances).  fused = 1: every kernel launched once for all systems,
+ * the argument tables copied in one transfer; fused = 0: each system's
+ * kernels launched on their own, one system after another (the same
+ * arithmetic).  Asynchronous. */
+rbe_status rbe_batch_step(rbe_batch b, int32_t fused);
+
+/* Waits for the batch's stream. */
+rbe_status rbe_batch_sync(rbe_batch b);
+
+/* Waits; h_pos, h_mom [n][3] (either may be NULL), h_state [24] as
+ * rbe_md_get_state (may be NULL). */
+rbe_status rbe_batch_read(rbe_batch b, int32_t slot, double* h_pos, double* h_mom,
+                          double* h_state);
+
+/* Waits; the device-side error flags of the slot's three contexts. */
+rbe_status rbe_batch_check(rbe_batch b, int32_t slot);
+
+/* Steps the slot's system has taken since admission. */
+rbe_status rbe_batch_slot_step(rbe_batch b, int32_t slot, int64_t* step);
+
+/* Waits for launched work, frees the slot and returns its bytes to the budget. */
+rbe_status rbe_batch_release(rbe_batch b, int32_t slot);
+
+/* h[4] = admitted systems, bytes held, budget, steps launched. */
+rbe_status rbe_batch_info(rbe_batch b, int64_t* h);
+
+void rbe_batch_destroy(rbe_batch b);
 
 /* Text of the last error reported to the calling thread ("" if none). */
 const char* rbe_last_error(void);

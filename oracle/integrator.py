@@ -73,6 +73,12 @@ class NPTState:
             self.V = box[0] * box[1] * box[2]
             self.pV = 0.0
             self.M = float(masses[0])
+            # D = (V'/3V) I scales every side by the same factor, so the
+            # initial aspect ratio is kept (1:1:1 for a cube)
+            if box[0] == box[1] == box[2]:
+                self.asp = np.ones(3)
+            else:
+                self.asp = np.array(box) / self.V ** (1.0 / 3.0)
         else:
             self.A = box[0] * box[1]
             self.L = box[2]
@@ -84,8 +90,7 @@ class NPTState:
 
     def box(self):
         if self.mode == "iso":
-            L = self.V ** (1.0 / 3.0)
-            return np.array([L, L, L])
+            return self.asp * self.V ** (1.0 / 3.0)
         s = math.sqrt(self.A)
         return np.array([s, s, self.L])
 

@@ -254,6 +254,49 @@ rbe_status flush(rbe_ctx_s* c) {
 
 }  // namespace
 
+namespace rbe {
+
+rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                            double* d_fx, double* d_fy, double* d_fz, int accumulate,
+                            double* d_virial6, double* d_energy, StepArgs* out) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return fail(RBE_ERR_ARG, "NULL particle array");
+  if (!c->have_k) return fail(RBE_ERR_STATE, "rbe_forces_pressure before rbe_sample_k / rbe_set_k");
+  StepArgs a = step_args(c);
+  a.x = d_x; a.y = d_y; a.z = d_z;
+  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
+  a.accumulate = accumulate ? 1 : 0;
+  a.virial6 = d_virial6; a.energy = d_energy;
+  // a sampled step draws the next step's batch ahead, for its own cell
+  a.predraw = a.sample && env_flag("RBE_PREDRAW", true) ? 1 : 0;
+  if (a.predraw) { c->pre_valid = true; c->pre_step = a.step + 1; }
+  clear_pending(c);
+  *out = a;
+  return RBE_OK;
+}
+
+int kspace_precision(rbe_ctx c) { return c->cfg.precision; }
+
+int64_t kspace_footprint(const rbe_config* cfg, const double* box) {
+  rbe_ctx_s c;
+  c.cfg = *cfg;
+  c.n = cfg->n;
+  c.p = cfg->p;
+  c.tail_ln = 53.0 * std::log(2.0);
+  for (int k = 0; k < 3; ++k) c.mcap[k] = (int)axis_mcut(c.tail_ln, cfg->alpha, 2.0 * box[k]);
+  c.tab_stride = 4 * (c.mcap[0] + c.mcap[1] + c.mcap[2]) + 3;
+  plan_launch(&c);
+  const StepArgs& A = c.a;
+  const int64_t n = c.n, p = c.p;
+  auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
+  return r(n * 8) + r(n * 4) + r(24) + r(sizeof(BoxState)) + r((int64_t)c.tab_stride * 8) + r(12 * p) +
+         r((int64_t)A.X * A.Ppad * 16) + r((int64_t)A.NG * A.Ppad * 16) + r(16 * p) + r(64 * p) +
+         r(p * (int64_t)sizeof(FCoef32)) + r(p * (int64_t)sizeof(FCoef64)) +
+         r(4 * ((int64_t)A.Y * A.NG + A.Y + 1)) + r(2 * sizeof(PreDraw)) + r(24 * p);
+}
+
+}  // namespace rbe
+
 extern "C" {
 
 const char* rbe_last_error(void) { return g_err.c_str(); }
@@ -416,23 +459,15 @@ rbe_status rbe_get_k(rbe_ctx c, int32_t* h_m) {
 rbe_status rbe_forces_pressure(rbe_ctx c, const double* d_x, const double* d_y, const double* d_z,
                                double* d_fx, double* d_fy, double* d_fz, int accumulate,
                                double* d_virial6, double* d_energy) {
-  if (!c) return fail(RBE_ERR_ARG, "NULL context");
-  if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return fail(RBE_ERR_ARG, "NULL particle array");
-  if (!c->have_k) return fail(RBE_ERR_STATE, "rbe_forces_pressure before rbe_sample_k / rbe_set_k");
-  StepArgs a = step_args(c);
-  a.x = d_x; a.y = d_y; a.z = d_z;
-  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
-  a.accumulate = accumulate ? 1 : 0;
-  a.virial6 = d_virial6; a.energy = d_energy;
-  // a sampled step draws the next step's batch ahead, for its own cell
-  a.predraw = a.sample && env_flag("RBE_PREDRAW", true) ? 1 : 0;
+  StepArgs a;
+  rbe_status st = rbe::kspace_step_args(c, d_x, d_y, d_z, d_fx, d_fy, d_fz, accumulate, d_virial6,
+                                        d_energy, &a);
+  if (st != RBE_OK) return st;
   const int prec = c->cfg.precision;
   int ts = timed_begin(c, K_SFAC);
   hipError_t e = launch_sfac(prec, a, c->stream);
   timed_end(c, K_SFAC, ts);
   if (e != hipSuccess) return hip_fail(e, "structure-factor kernel");
-  if (a.predraw) { c->pre_valid = true; c->pre_step = a.step + 1; }
-  clear_pending(c);
   ts = timed_begin(c, K_FORCE);
   e = launch_force(prec, a, c->stream);
   timed_end(c, K_FORCE, ts);

@@ -103,5 +103,23 @@ hipError_t launch_sample(const StepArgs& a, hipStream_t s);
 // the two kernels of a step
 hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s);
 hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s);
+// many systems per launch (served batching)
+int sfac_blocks(const StepArgs& a);
+int force_blocks(int precision, const StepArgs& a);
+hipError_t launch_sfac_multi(int precision, int R, const StepArgs* d_tab, const int* d_bstart,
+                             int nsys, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_force_multi(int precision, int threads, const StepArgs* d_tab,
+                              const int* d_bstart, int nsys, int total_blocks, hipStream_t s);
+
+// host side of rbe_forces_pressure without the launches: the arguments of
+// the two kernels, with the pending cell and draw folded in (the context's
+// pending state is consumed as by a launch)
+rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                            double* d_fx, double* d_fy, double* d_fz, int accumulate,
+                            double* d_virial6, double* d_energy, StepArgs* out);
+int kspace_precision(rbe_ctx c);
+// device bytes rbe_init allocates for this configuration (each buffer rounded
+// up to 256 bytes)
+int64_t kspace_footprint(const rbe_config* cfg, const double* box);
 
 }  // namespace rbe

@@ -473,14 +473,13 @@ __device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8
 }
 
 template <bool F64, int R>
-__global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+__device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const int y,
+                                          unsigned char* lds_raw) {
   __shared__ BoxState sbs;
   __shared__ double sh_T[3];
   __shared__ int sh_flag;
   __shared__ double sh_vs[7][8];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  const int x = blockIdx.x, y = blockIdx.y;
   const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;
   unsigned char* base = lds_raw;
   int* sm = reinterpret_cast<int*>(base + kR0);                     // batch slice, 3 ints each
@@ -757,6 +756,38 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   if (tid == 0 && a.Y > 1) a.cnt[a.Y * a.NG + a.Y] = 0u;
 }
 
+template <bool F64, int R>
+__global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  sfac_body<F64, R>(a, blockIdx.x, blockIdx.y, lds_raw);
+}
+
+// Many systems in one launch: block b belongs to system s with
+// bstart[s] <= b < bstart[s+1]; its local index runs over that system's
+// (X + predraw) x Y grid.  The system's arguments are copied to LDS.
+__device__ __forceinline__ int find_system(const int* bstart, int nsys, int b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {                          // last s with bstart[s] <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool F64, int R>
+__global__ void __launch_bounds__(kSfacThreads) k_sfac_multi(const StepArgs* tab, const int* bstart,
+                                                             int nsys) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ StepArgs sa;
+  const int b = blockIdx.x;
+  const int sys = find_system(bstart, nsys, b);
+  if (threadIdx.x == 0) sa = tab[sys];
+  __syncthreads();
+  const int local = b - bstart[sys];
+  const int xs = sa.X + (sa.predraw ? 1 : 0);
+  sfac_body<F64, R>(sa, local % xs, local / xs, lds_raw);
+}
+
 hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.X + (a.predraw ? 1 : 0), a.Y);
   const size_t lds = sfac_lds_bytes(a);
@@ -768,6 +799,22 @@ hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_sfac<false, 2>), grid, dim3(kSfacThreads), lds, s, a);
   else
     hipLaunchKernelGGL((k_sfac<false, 1>), grid, dim3(kSfacThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+int sfac_blocks(const StepArgs& a) { return (a.X + (a.predraw ? 1 : 0)) * a.Y; }
+
+hipError_t launch_sfac_multi(int precision, int R, const StepArgs* d_tab, const int* d_bstart,
+                             int nsys, int total_blocks, size_t lds, hipStream_t s) {
+  const dim3 grid(total_blocks), block(kSfacThreads);
+  if (precision == RBE_PREC_FP64)
+    hipLaunchKernelGGL((k_sfac_multi<true, 1>), grid, block, lds, s, d_tab, d_bstart, nsys);
+  else if (R == 4)
+    hipLaunchKernelGGL((k_sfac_multi<false, 4>), grid, block, lds, s, d_tab, d_bstart, nsys);
+  else if (R == 2)
+    hipLaunchKernelGGL((k_sfac_multi<false, 2>), grid, block, lds, s, d_tab, d_bstart, nsys);
+  else
+    hipLaunchKernelGGL((k_sfac_multi<false, 1>), grid, block, lds, s, d_tab, d_bstart, nsys);
   return hipGetLastError();
 }
 
@@ -784,7 +831,7 @@ constexpr int kForceStageBytes = 32768;
 constexpr int kForceRedBytes = 24576;
 
 template <bool F64, int RP>
-__global__ void __launch_bounds__(1024) k_force(StepArgs a) {
+__device__ __forceinline__ void force_body(const StepArgs& a, const int bx, const int nbx) {
   using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
   constexpr int kChunk = kForceStageBytes / (int)sizeof(Coef);
   __shared__ __align__(16) unsigned char red_raw[kForceRedBytes];
@@ -794,7 +841,7 @@ __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int nw = blockDim.x / kWave;
   const int PW = a.PW, KS = nw / PW;
-  const bool extra = a.k2reduce && blockIdx.x == gridDim.x - 1;
+  const bool extra = a.k2reduce && bx == nbx - 1;
   // rows of rho partials left by k_sfac in k2reduce mode
   const double2* rows = a.NG > 1 ? a.gpart : a.partial;
   const int Rr = a.NG > 1 ? a.NG : a.X;
@@ -822,7 +869,7 @@ __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
   }
 
   const int pw = wave % PW, ks = wave / PW;
-  const int64_t pbase = (int64_t)blockIdx.x * (kWave * RP * PW) + pw * kWave * RP + lane;
+  const int64_t pbase = (int64_t)bx * (kWave * RP * PW) + pw * kWave * RP + lane;
   double xi[RP], yi[RP], zi[RP];
 #pragma unroll
   for (int r = 0; r < RP; ++r) {
@@ -953,15 +1000,46 @@ __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
   }
 }
 
-hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
+template <bool F64, int RP>
+__global__ void __launch_bounds__(1024) k_force(StepArgs a) {
+  force_body<F64, RP>(a, blockIdx.x, gridDim.x);
+}
+
+template <bool F64, int RP>
+__global__ void __launch_bounds__(1024) k_force_multi(const StepArgs* tab, const int* bstart,
+                                                      int nsys) {
+  __shared__ StepArgs sa;
+  const int b = blockIdx.x;
+  const int sys = find_system(bstart, nsys, b);
+  if (threadIdx.x == 0) sa = tab[sys];
+  __syncthreads();
+  force_body<F64, RP>(sa, b - bstart[sys], bstart[sys + 1] - bstart[sys]);
+}
+
+int force_blocks(int precision, const StepArgs& a) {
   const int RP = precision == RBE_PREC_FP64 ? 1 : 2;
   const int64_t per_block = (int64_t)kWave * RP * a.PW;
-  const int64_t blocks = (a.n + per_block - 1) / per_block + (a.k2reduce ? 1 : 0);
+  return (int)((a.n + per_block - 1) / per_block + (a.k2reduce ? 1 : 0));
+}
+
+hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
   const dim3 block(a.KS * a.PW * kWave);
+  const dim3 grid((unsigned)force_blocks(precision, a));
   if (precision == RBE_PREC_FP64)
-    hipLaunchKernelGGL((k_force<true, 1>), dim3((unsigned)blocks), block, 0, s, a);
+    hipLaunchKernelGGL((k_force<true, 1>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((k_force<false, 2>), dim3((unsigned)blocks), block, 0, s, a);
+    hipLaunchKernelGGL((k_force<false, 2>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+// every system of a multi launch must use the same force block shape (KS, PW)
+hipError_t launch_force_multi(int precision, int threads, const StepArgs* d_tab,
+                              const int* d_bstart, int nsys, int total_blocks, hipStream_t s) {
+  const dim3 grid(total_blocks), block(threads);
+  if (precision == RBE_PREC_FP64)
+    hipLaunchKernelGGL((k_force_multi<true, 1>), grid, block, 0, s, d_tab, d_bstart, nsys);
+  else
+    hipLaunchKernelGGL((k_force_multi<false, 2>), grid, block, 0, s, d_tab, d_bstart, nsys);
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ void cell_rates(const MDCell& c, double a[3]) {
 __device__ __forceinline__ void cell_lengths(MDCell& c) {
   if (c.mode == 0) {
     const double L = cbrt(c.V);
-    c.l[0] = c.l[1] = c.l[2] = L;
+    c.l[0] = c.asp[0] * L; c.l[1] = c.asp[1] * L; c.l[2] = c.asp[2] * L;
   } else {
     const double s = sqrt(c.A);
     c.l[0] = c.l[1] = s;
@@ -93,7 +93,7 @@ __device__ __forceinline__ void A_V(MDCell& c, double h) {
   else { c.A += h * c.pA / c.MA; c.L += h * c.pL / c.ML; }
 }
 
-__global__ void __launch_bounds__(256) k_md_first(MDArgs a) {
+__device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   __shared__ MDCell sc;
   __shared__ double rate[3][3];
   const double h = 0.5 * a.dt;
@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(256) k_md_first(MDArgs a) {
     sc = c;
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cell_out = sc;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bx == 0 && threadIdx.x == 0) *a.cell_out = sc;
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const double m = a.mass[i], im = 1.0 / m;
   double r[3] = {a.x[i], a.y[i], a.z[i]};
@@ -148,7 +148,7 @@ __device__ __forceinline__ double wsum_md(double v) {
 }
 
 // mode 0: closing half step (B_R, pressure, B_V); mode 1: pressure only
-__global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
+__device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int bx, int nbx) {
   __shared__ MDCell sc;
   __shared__ double sh[4][6];
   __shared__ int sh_last;
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
   __syncthreads();
   double rate[3];
   cell_rates(sc, rate);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   double k6[6] = {0, 0, 0, 0, 0, 0};
   if (i < a.n) {
     double p[3] = {a.px[i], a.py[i], a.pz[i]};
@@ -180,18 +180,18 @@ __global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
   __syncthreads();
   if (threadIdx.x < 6) {
     const double s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
-    __hip_atomic_store(&a.part[blockIdx.x * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.part[bx * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0)
-    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1u;
+    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
   __syncthreads();
   if (!sh_last) return;
   __shared__ double ksum[6];
   if (threadIdx.x < 6) {
     double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b)
+    for (int b = 0; b < nbx; ++b)
       s += __hip_atomic_load(&a.part[b * 8 + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ksum[threadIdx.x] = s;
   }
@@ -212,6 +212,11 @@ __global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_md_first(MDArgs a) { md_first_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
+  md_second_body(a, prime, blockIdx.x, gridDim.x);
+}
+
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s) {
   const unsigned blocks = (unsigned)((a.n + 255) / 256);
   hipLaunchKernelGGL(k_md_first, dim3(blocks), dim3(256), 0, s, a);
@@ -221,6 +226,45 @@ hipError_t launch_md_first(const MDArgs& a, hipStream_t s) {
 hipError_t launch_md_second(const MDArgs& a, int prime, hipStream_t s) {
   const unsigned blocks = (unsigned)((a.n + 255) / 256);
   hipLaunchKernelGGL(k_md_second, dim3(blocks), dim3(256), 0, s, a, prime);
+  return hipGetLastError();
+}
+
+// many systems per launch (block b -> system s with bstart[s] <= b < bstart[s+1])
+__device__ __forceinline__ int find_sys_m(const int* bstart, int nsys, int b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_md_first_m(const MDArgs* tab, const int* bstart, int nsys) {
+  __shared__ MDArgs sa;
+  const int sys = find_sys_m(bstart, nsys, blockIdx.x);
+  if (threadIdx.x == 0) sa = tab[sys];
+  __syncthreads();
+  md_first_body(sa, blockIdx.x - bstart[sys]);
+}
+
+__global__ void __launch_bounds__(256) k_md_second_m(const MDArgs* tab, const int* bstart, int nsys,
+                                                     int prime) {
+  __shared__ MDArgs sa;
+  const int sys = find_sys_m(bstart, nsys, blockIdx.x);
+  if (threadIdx.x == 0) sa = tab[sys];
+  __syncthreads();
+  md_second_body(sa, prime, blockIdx.x - bstart[sys], bstart[sys + 1] - bstart[sys]);
+}
+
+hipError_t launch_md_first_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_md_first_m, dim3(total), dim3(256), 0, s, d_tab, d_bstart, nsys);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_second_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
+                                  int prime, hipStream_t s) {
+  hipLaunchKernelGGL(k_md_second_m, dim3(total), dim3(256), 0, s, d_tab, d_bstart, nsys, prime);
   return hipGetLastError();
 }
 

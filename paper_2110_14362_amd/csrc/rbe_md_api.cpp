@@ -43,6 +43,42 @@ void mfree(rbe_md_ctx_s* c) {
 
 }  // namespace
 
+namespace rbe {
+
+rbe_status md_first_args(rbe_md_ctx c, uint64_t step, double* d_x, double* d_y, double* d_z,
+                         double* d_px, double* d_py, double* d_pz, const double* d_fx,
+                         const double* d_fy, const double* d_fz, MDArgs* out) {
+  if (!c || !d_x || !d_y || !d_z || !d_px || !d_py || !d_pz || !d_fx || !d_fy || !d_fz)
+    return mfail(RBE_ERR_ARG, "NULL argument");
+  MDArgs a = c->a;
+  a.x = d_x; a.y = d_y; a.z = d_z; a.px = d_px; a.py = d_py; a.pz = d_pz;
+  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
+  a.step = step;
+  a.cell_in = c->d_cell; a.cell_out = c->d_cell + 1;
+  *out = a;
+  return RBE_OK;
+}
+
+rbe_status md_second_args(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz,
+                          const double* d_fx, const double* d_fy, const double* d_fz,
+                          const double* d_virial_k, const double* d_virial_r, MDArgs* out) {
+  if (!c || !d_px || !d_py || !d_pz || !d_fx || !d_fy || !d_fz) return mfail(RBE_ERR_ARG, "NULL argument");
+  MDArgs a = c->a;
+  a.px = d_px; a.py = d_py; a.pz = d_pz;
+  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
+  a.virial_k = d_virial_k; a.virial_r = d_virial_r;
+  a.cell_in = c->d_cell + 1; a.cell_out = c->d_cell;
+  *out = a;
+  return RBE_OK;
+}
+
+int64_t md_footprint(int64_t n) {
+  auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
+  return r(2 * sizeof(MDCell)) + r(8 * n) + r(64 * ((n + 255) / 256)) + r(4);
+}
+
+}  // namespace rbe
+
 extern "C" {
 
 rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const double* box_host,
@@ -61,8 +97,6 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   for (int d = 0; d < 3; ++d)
     if (!pos_fin(box_host[d])) return mfail(RBE_ERR_ARG, "box[%d] must be positive", d);
   const double tol = 1e-12 * box_host[0];
-  if (cfg->box_mode == RBE_BOX_ISO && (std::fabs(box_host[1] - box_host[0]) > tol || std::fabs(box_host[2] - box_host[0]) > tol))
-    return mfail(RBE_ERR_ARG, "isotropic mode needs a cubic box");
   if (cfg->box_mode == RBE_BOX_SEMIISO && std::fabs(box_host[1] - box_host[0]) > tol)
     return mfail(RBE_ERR_ARG, "semi-isotropic mode needs lx == ly");
   rbe_md_ctx_s* c = new (std::nothrow) rbe_md_ctx_s();
@@ -85,6 +119,10 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   cell.MA = cfg->mass_cell;
   cell.ML = cfg->mass_cell_z;
   for (int d = 0; d < 3; ++d) cell.l[d] = box_host[d];
+  // isotropic coupling keeps the initial aspect ratio (exactly 1:1:1 for a cubic cell)
+  const bool cubic = box_host[1] == box_host[0] && box_host[2] == box_host[0];
+  const double L0 = std::cbrt(cell.V);
+  for (int d = 0; d < 3; ++d) cell.asp[d] = cubic ? 1.0 : box_host[d] / L0;
   MDCell cells[2] = {cell, cell};
   hipError_t e = hipSuccess;
   do {
@@ -118,13 +156,9 @@ rbe_status rbe_md_pressure(rbe_md_ctx c, const double* d_px, const double* d_py,
 rbe_status rbe_md_first_half(rbe_md_ctx c, uint64_t step, double* d_x, double* d_y, double* d_z,
                              double* d_px, double* d_py, double* d_pz, const double* d_fx,
                              const double* d_fy, const double* d_fz) {
-  if (!c || !d_x || !d_y || !d_z || !d_px || !d_py || !d_pz || !d_fx || !d_fy || !d_fz)
-    return mfail(RBE_ERR_ARG, "NULL argument");
-  MDArgs a = c->a;
-  a.x = d_x; a.y = d_y; a.z = d_z; a.px = d_px; a.py = d_py; a.pz = d_pz;
-  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
-  a.step = step;
-  a.cell_in = c->d_cell; a.cell_out = c->d_cell + 1;
+  MDArgs a;
+  rbe_status st = rbe::md_first_args(c, step, d_x, d_y, d_z, d_px, d_py, d_pz, d_fx, d_fy, d_fz, &a);
+  if (st != RBE_OK) return st;
   hipError_t e = launch_md_first(a, c->stream);
   if (e != hipSuccess) return mfail(RBE_ERR_DEVICE, "first half kernel: %s", hipGetErrorString(e));
   return RBE_OK;
@@ -133,12 +167,9 @@ rbe_status rbe_md_first_half(rbe_md_ctx c, uint64_t step, double* d_x, double* d
 rbe_status rbe_md_second_half(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz,
                               const double* d_fx, const double* d_fy, const double* d_fz,
                               const double* d_virial_k, const double* d_virial_r) {
-  if (!c || !d_px || !d_py || !d_pz || !d_fx || !d_fy || !d_fz) return mfail(RBE_ERR_ARG, "NULL argument");
-  MDArgs a = c->a;
-  a.px = d_px; a.py = d_py; a.pz = d_pz;
-  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
-  a.virial_k = d_virial_k; a.virial_r = d_virial_r;
-  a.cell_in = c->d_cell + 1; a.cell_out = c->d_cell;
+  MDArgs a;
+  rbe_status st = rbe::md_second_args(c, d_px, d_py, d_pz, d_fx, d_fy, d_fz, d_virial_k, d_virial_r, &a);
+  if (st != RBE_OK) return st;
   hipError_t e = launch_md_second(a, 0, c->stream);
   if (e != hipSuccess) return mfail(RBE_ERR_DEVICE, "second half kernel: %s", hipGetErrorString(e));
   return RBE_OK;

@@ -13,6 +13,7 @@ struct MDCell {
   double V, pV, M;
   double A, pA, MA, L, pL, ML;
   double l[3];       // side lengths
+  double asp[3];     // isotropic mode: l = asp * V^(1/3), asp fixed (product 1)
   double P_ins[6];   // pressure tensor xx yy zz xy xz yz (internal units)
   double K[6];       // kinetic tensor sum p p^T / m
   uint64_t step;
@@ -35,5 +36,19 @@ struct MDArgs {
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s);
 hipError_t launch_md_second(const MDArgs& a, int prime, hipStream_t s);
+hipError_t launch_md_first_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
+                                 hipStream_t s);
+hipError_t launch_md_second_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
+                                  int prime, hipStream_t s);
+
+// host side of rbe_md_first_half / rbe_md_second_half without the launches
+rbe_status md_first_args(rbe_md_ctx c, uint64_t step, double* d_x, double* d_y, double* d_z,
+                         double* d_px, double* d_py, double* d_pz, const double* d_fx,
+                         const double* d_fy, const double* d_fz, MDArgs* out);
+rbe_status md_second_args(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz,
+                          const double* d_fx, const double* d_fy, const double* d_fz,
+                          const double* d_virial_k, const double* d_virial_r, MDArgs* out);
+// device bytes rbe_md_init allocates (each buffer rounded up to 256 bytes)
+int64_t md_footprint(int64_t n);
 
 }  // namespace rbe

@@ -39,8 +39,8 @@ __device__ __forceinline__ void cell_grid(const RealArgs& a, const double l[3], 
   }
 }
 
-__global__ void __launch_bounds__(256) k_bin(RealArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void bin_body(const RealArgs& a, int bx) {
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   double l[3];
   real_box(a, l);
@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) k_bin(RealArgs a) {
   if (i == 0 && err) atomicOr(a.err, err);
 }
 
-__global__ void __launch_bounds__(1024) k_scan(RealArgs a) {
+__device__ __forceinline__ void scan_body(const RealArgs& a) {
   __shared__ int sh[1024];
   double l[3];
   real_box(a, l);
@@ -89,17 +89,16 @@ __global__ void __launch_bounds__(1024) k_scan(RealArgs a) {
   if (t == 0) a.grid[0] = nc[0], a.grid[1] = nc[1], a.grid[2] = nc[2];
 }
 
-__global__ void __launch_bounds__(256) k_fill(RealArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fill_body(const RealArgs& a, int bx) {
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int pos = atomicAdd(&a.cursor[a.cellof[i]], 1);
   a.list[pos] = (int)i;
 }
 
 // one block per cell: sort member indices, then gather in that order
-__global__ void __launch_bounds__(1024) k_csort(RealArgs a) {
+__device__ __forceinline__ void csort_body(const RealArgs& a, int c) {
   __shared__ int key[kCellMax];
-  const int c = blockIdx.x;
   const int ncell = a.grid[0] * a.grid[1] * a.grid[2];
   if (c >= ncell) return;
   const int s0 = a.start[c], cnt = min(a.start[c + 1] - s0, kCellMax);
@@ -137,10 +136,10 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-__global__ void __launch_bounds__(256) k_pairs(RealArgs a) {
+__device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   __shared__ double sh[4][8];
   __shared__ int sh_last;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   double l[3];
   real_box(a, l);
@@ -204,24 +203,30 @@ __global__ void __launch_bounds__(256) k_pairs(RealArgs a) {
   __syncthreads();
   if (threadIdx.x < 7) {
     const double s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
-    __hip_atomic_store(&a.part[blockIdx.x * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.part[bx * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0)
-    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1u;
+    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
   __syncthreads();
   if (!sh_last) return;
   // the last block: sum the block partials in block order (thread k: component k)
   if (threadIdx.x < 7) {
     double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b)
+    for (int b = 0; b < nbx; ++b)
       s += __hip_atomic_load(&a.part[b * 8 + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) { if (a.energy) a.energy[0] = 0.5 * s; }
     else if (a.virial6) a.virial6[threadIdx.x - 1] = 0.5 * s;
   }
   if (threadIdx.x == 0) *a.cnt = 0u;
 }
+
+__global__ void __launch_bounds__(256) k_bin(RealArgs a) { bin_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(1024) k_scan(RealArgs a) { scan_body(a); }
+__global__ void __launch_bounds__(256) k_fill(RealArgs a) { fill_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_csort(RealArgs a) { csort_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_pairs(RealArgs a) { pairs_body(a, blockIdx.x, gridDim.x); }
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   const unsigned pb = (unsigned)((a.n + 255) / 256);
@@ -230,6 +235,66 @@ hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_pairs, dim3(pb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// many systems per launch: block b of a launch belongs to system s with
+// bstart[s] <= b < bstart[s+1] (one table per kernel shape); the system's
+// arguments are copied to LDS.
+
+__device__ __forceinline__ int find_sys_r(const int* bstart, int nsys, int b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+#define REAL_MULTI_PROLOGUE                                \
+  __shared__ RealArgs sa;                                  \
+  const int b = blockIdx.x;                                \
+  const int sys = find_sys_r(bstart, nsys, b);             \
+  if (threadIdx.x == 0) sa = tab[sys];                     \
+  __syncthreads();                                         \
+  const int lb = b - bstart[sys], nb = bstart[sys + 1] - bstart[sys];
+
+__global__ void __launch_bounds__(256) k_bin_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  (void)nb;
+  bin_body(sa, lb);
+}
+__global__ void __launch_bounds__(1024) k_scan_m(const RealArgs* tab, int nsys) {
+  __shared__ RealArgs sa;
+  if (threadIdx.x == 0) sa = tab[blockIdx.x];
+  __syncthreads();
+  (void)nsys;
+  scan_body(sa);
+}
+__global__ void __launch_bounds__(256) k_fill_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  (void)nb;
+  fill_body(sa, lb);
+}
+__global__ void __launch_bounds__(256) k_csort_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  (void)nb;
+  csort_body(sa, lb);
+}
+__global__ void __launch_bounds__(256) k_pairs_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  pairs_body(sa, lb, nb);
+}
+
+// bstart_p: per-particle blocks (256 particles each); bstart_c: cell blocks
+hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
+                             const int* d_bstart_c, int total_c, int nsys, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
+  hipLaunchKernelGGL(k_scan_m, dim3(nsys), dim3(1024), 0, s, d_tab, nsys);
+  hipLaunchKernelGGL(k_fill_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
+  hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
+  hipLaunchKernelGGL(k_pairs_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   return hipGetLastError();
 }
 

@@ -61,6 +61,42 @@ rbe_status check_real_box(const rbe_real_ctx_s* c, const double* box) {
 
 }  // namespace
 
+namespace rbe {
+
+rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                          double* d_fx, double* d_fy, double* d_fz, int accumulate,
+                          double* d_virial6, double* d_energy, RealArgs* out, int* ncell_cap) {
+  if (!c) return rfail(RBE_ERR_ARG, "NULL context");
+  if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return rfail(RBE_ERR_ARG, "NULL particle array");
+  RealArgs a = c->a;
+  a.x = d_x; a.y = d_y; a.z = d_z;
+  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
+  a.accumulate = accumulate ? 1 : 0;
+  a.virial6 = d_virial6; a.energy = d_energy;
+  *out = a;
+  *ncell_cap = c->ncell_cap;
+  return RBE_OK;
+}
+
+int64_t real_footprint(const rbe_real_config* cfg, const double* box) {
+  int64_t cap = 1;
+  for (int d = 0; d < 3; ++d) {
+    long v = (long)std::floor(2.0 * box[d] / cfg->rc);
+    if (v > kCellAxisMax) v = kCellAxisMax;
+    if (v < 3) v = 3;
+    cap *= v;
+  }
+  const int64_t n = cfg->n, blocks = (n + 255) / 256;
+  auto r = [](int64_t b) { return (b + 16 + 255) / 256 * 256; };
+  int64_t t = r(8 * n);
+  if (cfg->ntypes > 0) t += r(4 * n) + r(16 * (int64_t)cfg->ntypes * cfg->ntypes);
+  t += r(4 * n) + r(4 * cap) + r(4 * (cap + 1)) + r(4 * cap) + r(4 * n) + 4 * r(8 * n) + 2 * r(4 * n) +
+       r(16) + r(64 * blocks) + r(4) + r(4);
+  return t;
+}
+
+}  // namespace rbe
+
 extern "C" {
 
 rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const int32_t* d_type,
@@ -150,14 +186,12 @@ rbe_status rbe_real_set_box_dev(rbe_real_ctx c, const double* d_box) {
 rbe_status rbe_real_forces(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,
                            double* d_fx, double* d_fy, double* d_fz, int accumulate,
                            double* d_virial6, double* d_energy) {
-  if (!c) return rfail(RBE_ERR_ARG, "NULL context");
-  if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return rfail(RBE_ERR_ARG, "NULL particle array");
-  RealArgs a = c->a;
-  a.x = d_x; a.y = d_y; a.z = d_z;
-  a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
-  a.accumulate = accumulate ? 1 : 0;
-  a.virial6 = d_virial6; a.energy = d_energy;
-  hipError_t e = launch_real(a, c->ncell_cap, c->stream);
+  RealArgs a;
+  int ncell_cap = 0;
+  rbe_status st = rbe::real_step_args(c, d_x, d_y, d_z, d_fx, d_fy, d_fz, accumulate, d_virial6,
+                                      d_energy, &a, &ncell_cap);
+  if (st != RBE_OK) return st;
+  hipError_t e = launch_real(a, ncell_cap, c->stream);
   if (e != hipSuccess) return rfail(RBE_ERR_DEVICE, "real-space kernels: %s", hipGetErrorString(e));
   return RBE_OK;
 }

@@ -31,5 +31,14 @@ struct RealArgs {
 };
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
+hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
+                             const int* d_bstart_c, int total_c, int nsys, hipStream_t s);
+
+// host side of rbe_real_forces without the launches
+rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                          double* d_fx, double* d_fy, double* d_fz, int accumulate,
+                          double* d_virial6, double* d_energy, RealArgs* out, int* ncell_cap);
+// device bytes rbe_real_init allocates (each buffer rounded up to 256 bytes)
+int64_t real_footprint(const rbe_real_config* cfg, const double* box);
 
 }  // namespace rbe

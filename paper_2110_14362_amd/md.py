@@ -39,8 +39,12 @@ class NPTSystem:
         self.er = torch.zeros(1, dtype=torch.float64, device=dev)
         q = t(sysd["q"])
         mode = md.get("box_mode", "iso")
+        b = [float(v) for v in sysd["box"]]
+        # the Fourier part only checks the cell's shape: a non-cubic cell under
+        # isotropic coupling is a general rectangular one there
+        kmode = "aniso" if mode == "iso" and not (b[0] == b[1] == b[2]) else mode
         self.kspace = RBE(q, sysd["box"], sysd["p"], sysd["alpha"], coulomb=sysd["coulomb"],
-                          precision=precision, box_mode=mode, seed=seed, system_id=system_id,
+                          precision=precision, box_mode=kmode, seed=seed, system_id=system_id,
                           stream=stream)
         types = None
         if md.get("lj") is not None:

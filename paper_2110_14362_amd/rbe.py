@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librbe.so")
 
 RBE_OK = 0
+RBE_ERR_CAPACITY = 6
 STATUS_NAMES = {0: "RBE_OK", 1: "RBE_ERR_ARG", 2: "RBE_ERR_ALLOC", 3: "RBE_ERR_DEVICE",
                 4: "RBE_ERR_STATE", 5: "RBE_ERR_NONNEUTRAL", 6: "RBE_ERR_CAPACITY"}
 BOX_MODES = {"iso": 0, "semiiso": 1, "aniso": 2}
@@ -27,7 +28,10 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_real_init", "rbe_real_set_box", "rbe_real_set_box_dev", "rbe_real_forces",
            "rbe_real_check", "rbe_real_destroy",
            "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
-           "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy"]
+           "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy",
+           "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
+           "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
+           "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy"]
 KERNEL_KINDS = ["tables", "sample", "sfac", "force"]
 
 
@@ -51,6 +55,21 @@ class RealConfig(ctypes.Structure):
 
 class MDConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("box_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("kT", ctypes.c_double), ("p_ext", ctypes.c_double),
+                ("gamma_p", ctypes.c_double), ("gamma_cell", ctypes.c_double),
+                ("mass_cell", ctypes.c_double), ("mass_cell_z", ctypes.c_double),
+                ("ftm", ctypes.c_double), ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_systems", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64)]
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("ntypes", ctypes.c_int32),
+                ("box_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("coulomb", ctypes.c_double), ("rc", ctypes.c_double),
                 ("dt", ctypes.c_double), ("kT", ctypes.c_double), ("p_ext", ctypes.c_double),
                 ("gamma_p", ctypes.c_double), ("gamma_cell", ctypes.c_double),
                 ("mass_cell", ctypes.c_double), ("mass_cell_z", ctypes.c_double),
@@ -97,6 +116,17 @@ def load_library(path=LIB_PATH):
         "rbe_md_second_half": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "rbe_md_get_state": [vp, dp],
         "rbe_md_check": [vp],
+        "rbe_batch_create": [ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(vp)],
+        "rbe_batch_footprint": [ctypes.POINTER(SystemDesc), dp, ctypes.POINTER(i64)],
+        "rbe_batch_admit": [vp, ctypes.POINTER(SystemDesc), dp, dp, dp, dp, ctypes.POINTER(i32), dp,
+                            dp, ctypes.POINTER(i32)],
+        "rbe_batch_step": [vp, i32],
+        "rbe_batch_sync": [vp],
+        "rbe_batch_read": [vp, i32, dp, dp, dp],
+        "rbe_batch_check": [vp, i32],
+        "rbe_batch_slot_step": [vp, i32, ctypes.POINTER(i64)],
+        "rbe_batch_release": [vp, i32],
+        "rbe_batch_info": [vp, ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -108,6 +138,8 @@ def load_library(path=LIB_PATH):
     lib.rbe_real_destroy.restype = None
     lib.rbe_md_destroy.argtypes = [vp]
     lib.rbe_md_destroy.restype = None
+    lib.rbe_batch_destroy.argtypes = [vp]
+    lib.rbe_batch_destroy.restype = None
     lib.rbe_md_box_dev.argtypes = [vp]
     lib.rbe_md_box_dev.restype = ctypes.c_void_p
     lib.rbe_last_error.argtypes = []
@@ -360,3 +392,115 @@ class Integrator:
 
     def check(self):
         _check(_lib.rbe_md_check(self._ctx))
+
+
+def _hp(a, dtype=np.float64):
+    """Host pointer of a contiguous numpy array (None passes NULL)."""
+    if a is None:
+        return None
+    ctype = ctypes.c_double if dtype == np.float64 else ctypes.c_int32
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def system_desc(n, p, alpha, coulomb, rc, md, ntypes=0, seed=0, system_id=0):
+    """rbe_system_desc from the integrator parameter dict used by NPTSystem."""
+    return SystemDesc(n=int(n), p=int(p), ntypes=int(ntypes),
+                      box_mode=BOX_MODES[md.get("box_mode", "iso")], reserved=0,
+                      alpha=float(alpha), coulomb=float(coulomb), rc=float(rc),
+                      dt=float(md["dt"]), kT=float(md["kT"]), p_ext=float(md["p_ext"]),
+                      gamma_p=float(md["gamma_p"]), gamma_cell=float(md["gamma_cell"]),
+                      mass_cell=float(md["mass_cell"]), mass_cell_z=float(md.get("mass_cell_z", 0.0)),
+                      ftm=float(md["ftm"]), seed=int(seed) & (2**64 - 1),
+                      system_id=int(system_id) & (2**64 - 1))
+
+
+class Batch:
+    """Many NPT systems served together (rbe_batch_create ... rbe_batch_destroy).
+
+    Host arrays in, host arrays out; every step of every system runs in the
+    library's kernels.
+    """
+
+    def __init__(self, hbm_budget, max_systems=256, precision="fp32", stream=None):
+        lib = load_library()
+        cfg = BatchConfig(precision=PRECISIONS[precision], max_systems=int(max_systems),
+                          hbm_budget=int(hbm_budget))
+        ctx = ctypes.c_void_p()
+        _check(lib.rbe_batch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.n_of = {}
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.rbe_batch_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def footprint(desc, box):
+        lib = load_library()
+        out = ctypes.c_int64()
+        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        _check(lib.rbe_batch_footprint(ctypes.byref(desc), boxarr, ctypes.byref(out)))
+        return out.value
+
+    def admit(self, desc, pos, q, mass, box, mom=None, types=None, lj=None):
+        """Admit one system; returns its slot, or None when the budget or the
+        slots are exhausted (RBE_ERR_CAPACITY)."""
+        n = int(desc.n)
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(n, 3)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        if mom is not None:
+            mom = np.ascontiguousarray(mom, dtype=np.float64).reshape(n, 3)
+        if types is not None:
+            types = np.ascontiguousarray(types, dtype=np.int32)
+        if lj is not None:
+            lj = np.ascontiguousarray(lj, dtype=np.float64)
+        boxarr = np.ascontiguousarray(box, dtype=np.float64)
+        slot = ctypes.c_int32(-1)
+        st = _lib.rbe_batch_admit(self._ctx, ctypes.byref(desc), _hp(pos), _hp(mom), _hp(q),
+                                  _hp(mass), _hp(types, np.int32), _hp(lj), _hp(boxarr),
+                                  ctypes.byref(slot))
+        if st == RBE_ERR_CAPACITY:
+            return None
+        _check(st)
+        self.n_of[slot.value] = n
+        return slot.value
+
+    def step(self, fused=True):
+        _check(_lib.rbe_batch_step(self._ctx, 1 if fused else 0))
+
+    def sync(self):
+        _check(_lib.rbe_batch_sync(self._ctx))
+
+    def read(self, slot):
+        n = self.n_of[slot]
+        pos = np.zeros((n, 3))
+        mom = np.zeros((n, 3))
+        h = np.zeros(24)
+        _check(_lib.rbe_batch_read(self._ctx, int(slot), _hp(pos), _hp(mom), _hp(h)))
+        return dict(pos=pos, mom=mom, box=h[0:3].copy(), volume=h[3], err=int(h[19]),
+                    step=int(h[20]), state=h)
+
+    def check(self, slot):
+        _check(_lib.rbe_batch_check(self._ctx, int(slot)))
+
+    def slot_step(self, slot):
+        out = ctypes.c_int64()
+        _check(_lib.rbe_batch_slot_step(self._ctx, int(slot), ctypes.byref(out)))
+        return out.value
+
+    def release(self, slot):
+        _check(_lib.rbe_batch_release(self._ctx, int(slot)))
+        self.n_of.pop(slot, None)
+
+    def info(self):
+        h = (ctypes.c_int64 * 4)()
+        _check(_lib.rbe_batch_info(self._ctx, h))
+        return dict(active=h[0], bytes=h[1], budget=h[2], steps=h[3])

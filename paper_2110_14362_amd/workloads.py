@@ -206,3 +206,104 @@ def make(name, **over):
     s.update(alpha=c["g"] ** 2, g=c["g"], rc=c["rc"], p=c["p"], coulomb=c["coulomb"],
              config=name)
     return s
+
+
+# ---------------------------------------------------------------------------
+# NPT parameters in real units (A, fs, kcal/mol, g/mol, e)
+
+KB_KCAL = 0.0019872043              # kcal/mol/K
+FTM_REAL = 4.184e-4                 # kcal/mol/A -> (g/mol) A / fs^2
+ATM_KCAL_A3 = 101325.0 / 6.9477e9   # 1 atm in kcal/mol/A^3
+KBAR_PER_KCAL_A3 = 69.477           # 1 kcal/mol/A^3 in kbar
+COULOMB_REAL = 332.0637             # kcal A / (mol e^2)
+
+
+def npt_real(box, T=300.0, p_atm=1.0, dt=1.0, tau_p=100.0, tau_cell=500.0, beta_kbar=4.5e-2,
+             rc=10.0, box_mode="iso"):
+    """Langevin NPT parameters for a real-unit system: particle friction
+    1/tau_p, cell friction 1/tau_cell, barostat mass M = tau_cell^2 / (beta_T V0)
+    (beta_T the isothermal compressibility in the integrator's pressure units),
+    so that gamma_cell M = tau_cell / (beta_T V0)."""
+    V0 = float(np.prod(box))
+    beta = beta_kbar * KBAR_PER_KCAL_A3 / FTM_REAL          # (A fs^2 mol/g)
+    M = tau_cell ** 2 / (beta * V0)
+    d = dict(dt=dt, kT=KB_KCAL * T, p_ext=p_atm * ATM_KCAL_A3, gamma_p=1.0 / tau_p,
+             gamma_cell=1.0 / tau_cell, mass_cell=M, mass_cell_z=0.0, ftm=FTM_REAL,
+             box_mode=box_mode, rc=rc)
+    if box_mode == "semiiso":
+        A0 = box[0] * box[1]
+        d["mass_cell"] = tau_cell ** 2 / (beta * V0) * box[2] ** 2
+        d["mass_cell_z"] = tau_cell ** 2 / (beta * V0) * A0 ** 2
+    return d
+
+
+# ---------------------------------------------------------------------------
+# served mixed-size stream
+
+CHARGES_PER_A3 = 3.0 * WATER_PER_A3  # 0.100284 charges per A^3 (water at 1 g/cm^3)
+ION_MASSES = (22.99, 35.45)          # cation, anion (g/mol)
+ION_SIGMA, ION_EPS = 2.0, 1.0        # repulsive core 4 eps (sigma/r)^12 (A, kcal/mol)
+
+
+def splitmix64(x):
+    """SplitMix64 output for state x (sub-seed derivation)."""
+    m = (1 << 64) - 1
+    z = (x + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def ions(n, box, seed, jitter=0.15):
+    """Primitive electrolyte with a repulsive core: n ions (n/2 at +1, n/2 at
+    -1, in random order) on a jittered lattice filling the rectangular box
+    (so no two start closer than the lattice spacing minus 2 jitter)."""
+    g = _rng(seed)
+    box = np.asarray(box, dtype=np.float64)
+    # lattice with about n sites, spacing about equal on the three axes
+    a = (np.prod(box) / n) ** (1.0 / 3.0)
+    dims = np.maximum(1, np.ceil(box / a).astype(int))
+    while np.prod(dims) < n:
+        dims[np.argmax(box / dims)] += 1
+    idx = np.stack(np.meshgrid(*[np.arange(d) for d in dims], indexing="ij"), -1).reshape(-1, 3)
+    pick = g.permutation(idx.shape[0])[:n]
+    spacing = box / dims
+    pos = np.mod((idx[pick] + 0.5) * spacing + g.uniform(-jitter, jitter, (n, 3)), box)
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    g.shuffle(q)
+    mass = np.where(q > 0, ION_MASSES[0], ION_MASSES[1])
+    c12 = 4.0 * ION_EPS * ION_SIGMA ** 12
+    lj = np.array([[[c12, 0.0]]])
+    return dict(pos=pos, q=q, mass=mass, box=box, types=np.zeros(n, dtype=np.int32), lj=lj,
+                name="ions N=%d" % n)
+
+
+def serving_request(i, seed=2110143625, nmin=1000, nmax=200000, p=100, steps=20, g_ewald=0.3,
+                    rc=10.0, kinds=("ions", "water")):
+    """Request i of the served stream: N log-uniform in [nmin, nmax], kind
+    drawn from `kinds` (ions or rigid 3-site water), cubic or 1:1:1.25 box
+    (fair coin) at 0.100284 charges per A^3, P frequencies, `steps` NPT steps.
+    Boxes shorter than 3.3 rc get a cutoff of a third of their shortest side
+    less 10 % and a splitting parameter g = g_ewald rc / rc' that keeps
+    erfc(g rc) (the real-space truncation error) unchanged."""
+    sub = splitmix64((seed + i) & ((1 << 64) - 1))
+    g = _rng(sub)
+    n = int(round(math.exp(g.uniform(math.log(nmin), math.log(nmax)))))
+    kind = kinds[int(g.integers(len(kinds)))]
+    aspect = np.array([1.0, 1.0, 1.25]) if g.integers(2) else np.ones(3)
+    if kind == "water":
+        n_mol = max(n // 3, 1)
+        n = 3 * n_mol
+    else:
+        n += n % 2
+    L = (n / CHARGES_PER_A3 / np.prod(aspect)) ** (1.0 / 3.0)
+    box = aspect * L
+    if kind == "water":
+        s = water(n_mol, box=box, seed=sub)
+    else:
+        s = ions(n, box, seed=sub)
+    rc_i = min(rc, float(box.min()) / 3.3)
+    g_i = g_ewald * rc / rc_i
+    s.update(alpha=g_i ** 2, g=g_i, rc=rc_i, p=p, coulomb=COULOMB_REAL, kind=kind, steps=steps,
+             request=i, seed=sub)
+    return s

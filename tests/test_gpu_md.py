@@ -27,7 +27,17 @@ def slab_setup():
     return s, md, mom
 
 
-@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup])
+def aspect_setup():
+    # isotropic coupling of a 1:1:1.25 cell (the aspect ratio is kept)
+    s = workloads.random_neutral(500, (13.0, 13.0, 16.25), seed=29)
+    s.update(alpha=0.5 ** 2, p=48, coulomb=1.0)
+    md = dict(dt=0.004, kT=1.0, p_ext=0.3, gamma_p=1.0, gamma_cell=1.5,
+              mass_cell=3e-3, ftm=1.0, box_mode="iso", rc=4.2)
+    mom = np.random.default_rng(19).normal(0.0, 1.0, s["pos"].shape)
+    return s, md, mom
+
+
+@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup])
 def test_npt_trajectory_matches_oracle(gpu, setup):
     from paper_2110_14362_amd.md import NPTSystem
     s, md, mom = setup()
@@ -47,3 +57,6 @@ def test_npt_trajectory_matches_oracle(gpu, setup):
     assert np.abs(o["box"] - np.asarray(s["box"])).max() > 1e-8
     if md["box_mode"] == "semiiso":
         assert g["box"][0] == g["box"][1]
+    else:
+        b0 = np.asarray(s["box"], dtype=np.float64)
+        np.testing.assert_allclose(g["box"] / g["box"][0], b0 / b0[0], rtol=1e-14)

@@ -1,0 +1,122 @@
+"""Served batching (rbe_batch_*): a system's trajectory is the same alone and
+in a mix of other systems admitted at different times, fused or with
+per-system launches, and equal to the one-system API's; the served path
+matches the oracle's trajectory; admission respects the memory budget."""
+import numpy as np
+import pytest
+
+from paper_2110_14362_amd import serve, workloads
+from paper_2110_14362_amd.rbe import Batch
+from tests.md_cases import oracle_trajectory
+
+pytestmark = pytest.mark.gpu
+
+BUDGET = 4 << 30
+
+
+def request(i, n, **kw):
+    r = serve.make_requests(1, seed=7000 + i, nmin=n, nmax=n, steps=kw.pop("steps", 4), **kw)[0]
+    r.rid = i
+    r.desc.system_id = i
+    return r
+
+
+def run_alone(r, steps, fused=True, precision="fp32"):
+    b = Batch(BUDGET, max_systems=2, precision=precision)
+    slot = serve._admit(b, r)
+    for _ in range(steps):
+        b.step(fused=fused)
+    b.sync()
+    b.check(slot)
+    out = b.read(slot)
+    b.close()
+    return out
+
+
+def test_alone_equals_mix_bitwise(gpu):
+    reqs = [request(0, 1500), request(1, 4000), request(2, 9000)]
+    print("sizes", [r.n for r in reqs], "boxes", [r.sysd["box"].round(2).tolist() for r in reqs],
+          flush=True)
+    b = Batch(BUDGET, max_systems=8, precision="fp32")
+    s0 = serve._admit(b, reqs[0])
+    s1 = serve._admit(b, reqs[1])
+    b.step()
+    b.step()
+    s2 = serve._admit(b, reqs[2])         # joins while the others run
+    for _ in range(3):
+        b.step()
+    b.sync()
+    mix = {}
+    for r, s in ((reqs[0], s0), (reqs[1], s1), (reqs[2], s2)):
+        b.check(s)
+        mix[r.rid] = (b.read(s), b.slot_step(s))
+    b.close()
+    assert mix[0][1] == 5 and mix[2][1] == 3
+    for r in reqs:
+        got, steps = mix[r.rid]
+        for fused in (True, False):
+            ref = run_alone(r, steps, fused=fused)
+            np.testing.assert_array_equal(got["pos"], ref["pos"])
+            np.testing.assert_array_equal(got["mom"], ref["mom"])
+            np.testing.assert_array_equal(got["box"], ref["box"])
+        print("request %d (N=%d, %d steps): box %s, identical alone and in the mix"
+              % (r.rid, r.n, steps, got["box"]), flush=True)
+
+
+def test_served_equals_one_system_api(gpu):
+    from paper_2110_14362_amd.md import NPTSystem
+    r = request(3, 2500)
+    steps = 4
+    ref = run_alone(r, steps)
+    md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"])
+    sysg = NPTSystem(r.sysd, md, precision="fp32", seed=r.desc.seed, system_id=r.desc.system_id)
+    sysg.step(steps)
+    g = sysg.state()
+    np.testing.assert_array_equal(g["pos"], ref["pos"])
+    np.testing.assert_array_equal(g["mom"], ref["mom"])
+
+
+def test_served_trajectory_matches_oracle(gpu):
+    r = request(4, 1000)
+    steps = 3
+    got = run_alone(r, steps, precision="fp64")
+    md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"])
+    o = oracle_trajectory(r.sysd, md, np.zeros((r.n, 3)), steps, seed=r.desc.seed,
+                          system_id=r.desc.system_id)
+    dpos = np.abs(got["pos"] - o["pos"]).max()
+    dmom = np.abs(got["mom"] - o["mom"]).max() / np.abs(o["mom"]).max()
+    dbox = np.abs(got["box"] - o["box"]).max() / o["box"].max()
+    print("served N=%d: max |dr| %.2e, rel |dp| %.2e, rel |dl| %.2e" % (r.n, dpos, dmom, dbox),
+          flush=True)
+    assert dpos < 1e-9 and dmom < 1e-9 and dbox < 1e-11
+
+
+def test_admission_respects_budget(gpu):
+    a, c = request(5, 3000), request(6, 3000)
+    budget = a.bytes + c.bytes // 2
+    b = Batch(budget, max_systems=4, precision="fp32")
+    sa = serve._admit(b, a)
+    assert sa is not None
+    assert serve._admit(b, c) is None            # over budget: refused, nothing held
+    assert b.info()["bytes"] == a.bytes
+    b.step()
+    b.release(sa)
+    assert b.info()["bytes"] == 0
+    sc = serve._admit(b, c)
+    assert sc is not None
+    b.step()
+    b.sync()
+    b.check(sc)
+    b.close()
+
+
+def test_served_stream_runs(gpu):
+    reqs = serve.make_requests(12, seed=9100, nmin=1000, nmax=20000, steps=5)
+    for r, t in zip(reqs, serve.poisson_arrivals(len(reqs), rate=400.0)):
+        r.arrival = float(t)
+    b = Batch(BUDGET, max_systems=16, precision="fp32")
+    st = serve.serve(b, reqs, fused=True)
+    b.close()
+    print(st, flush=True)
+    assert st["steps"] == 60 and all(len(r.lat) == 5 for r in reqs)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
