@@ -298,12 +298,30 @@ typedef struct {
 rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const double* box_host,
                        void* stream, rbe_md_ctx* out);
 
-/* Instantaneous pressure from the current momenta and the virial tensors
- * (6 doubles each, DEVICE, either may be NULL), without moving anything: call
- * once before the first step.  Asynchronous. */
-rbe_status rbe_md_pressure(rbe_md_ctx ctx, const double* d_px, const double* d_py,
-                           const double* d_pz, const double* d_virial_k,
-                           const double* d_virial_r);
+/* Rigid 3-site molecules: atoms first + 3k (O), first + 3k + 1 and
+ * first + 3k + 2 (H) for k < count, bonds O-H = d_oh and H-H = d_hh (the
+ * positions must satisfy them, molecules whole, i.e. not split across the
+ * periodic boundary); every molecule must have the masses of the first
+ * (equal H masses).  Each position sub-flow is then followed by the
+ * position constraint, solved in closed form per molecule (the result of
+ * SHAKE: constraint forces along the old bonds), with the momentum change
+ * the sub-flow's map gives it, and each momentum sub-flow by the projection
+ * of the molecule's momenta onto rigid-body motions (the velocity stage of
+ * RATTLE).  The pressure takes the molecular form
+ *     P V = sum_free p p^T/m + sum_mol P P^T/M + W - sum_mol sum_a sym((r_a - R) F_a),
+ * R, P the molecule's centre of mass and momentum.  count = 0 removes the
+ * constraints.  Call before rbe_md_pressure; reads the masses (waits). */
+rbe_status rbe_md_set_rigid(rbe_md_ctx ctx, int64_t first, int64_t count, double d_oh,
+                            double d_hh);
+
+/* Instantaneous pressure from the current state and the virial tensors (6
+ * doubles each, DEVICE, either may be NULL), without moving anything: call
+ * once before the first step.  With rigid molecules it also projects their
+ * momenta (stored back) and needs positions and forces.  Asynchronous. */
+rbe_status rbe_md_pressure(rbe_md_ctx ctx, const double* d_x, const double* d_y,
+                           const double* d_z, double* d_px, double* d_py, double* d_pz,
+                           const double* d_fx, const double* d_fy, const double* d_fz,
+                           const double* d_virial_k, const double* d_virial_r);
 
 /* B_V B_R A_V A_R O^p O A_R A_V of step `step` on positions and momenta with
  * the forces of the previous evaluation.  Afterwards rbe_md_box_dev() holds
@@ -312,10 +330,12 @@ rbe_status rbe_md_first_half(rbe_md_ctx ctx, uint64_t step, double* d_x, double*
                              double* d_z, double* d_px, double* d_py, double* d_pz,
                              const double* d_fx, const double* d_fy, const double* d_fz);
 
-/* B_R with the new forces, the pressure tensor from the momenta and the
+/* B_R with the new forces (and the momentum projection of rigid molecules,
+ * which needs the positions), the pressure tensor from the momenta and the
  * virial tensors (DEVICE, 6 doubles each, either may be NULL), then B_V.
  * Asynchronous. */
-rbe_status rbe_md_second_half(rbe_md_ctx ctx, double* d_px, double* d_py, double* d_pz,
+rbe_status rbe_md_second_half(rbe_md_ctx ctx, const double* d_x, const double* d_y,
+                              const double* d_z, double* d_px, double* d_py, double* d_pz,
                               const double* d_fx, const double* d_fy, const double* d_fz,
                               const double* d_virial_k, const double* d_virial_r);
 
@@ -323,12 +343,14 @@ rbe_status rbe_md_second_half(rbe_md_ctx ctx, double* d_px, double* d_py, double
  * after rbe_md_first_half; feed it to rbe_rescale_box_dev / rbe_real_set_box_dev). */
 const double* rbe_md_box_dev(rbe_md_ctx ctx);
 
-/* Waits; h_state[24] = lx ly lz, volume, pV, pA, pL, pressure tensor (6,
- * energy/length^3), kinetic tensor sum p p^T/m (6, energy), error flags,
- * step, A, L, V. */
+/* Waits; h_state[32] = lx ly lz, volume, pV, pA, pL, pressure tensor (6,
+ * energy/length^3), kinetic tensor sum p p^T/m (6, energy; rigid molecules
+ * contribute P P^T/M), error flags, step, A, L, V, the rigid-molecule
+ * correction sum sym((r - R) F) (6, energy), rigid molecules, 0. */
 rbe_status rbe_md_get_state(rbe_md_ctx ctx, double* h_state);
 
-/* Waits; RBE_ERR_STATE if the cell collapsed or became non-finite. */
+/* Waits; RBE_ERR_STATE if the cell collapsed or became non-finite, or a
+ * rigid-molecule position constraint had no solution (flags cleared). */
 rbe_status rbe_md_check(rbe_md_ctx ctx);
 
 void rbe_md_destroy(rbe_md_ctx ctx);
@@ -363,6 +385,9 @@ typedef struct {
                          /* integrator parameters, as in rbe_md_config         */
   uint64_t seed;         /* Philox key word 0                                  */
   uint64_t system_id;    /* Philox key word 1 (e.g. the request id)            */
+  int64_t  rigid_first;  /* rigid 3-site molecules as rbe_md_set_rigid         */
+  int64_t  rigid_count;  /* (0: none)                                          */
+  double   d_oh, d_hh;   /* their bond lengths                                 */
 } rbe_system_desc;
 
 /* stream: hipStream_t for every launch and copy of the batch (NULL: the null
@@ -397,10 +422,11 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused);
 /* Waits for the batch's stream. */
 rbe_status rbe_batch_sync(rbe_batch b);
 
-/* Waits; h_pos, h_mom [n][3] (either may be NULL), h_state [24] as
- * rbe_md_get_state (may be NULL). */
+/* Waits; h_pos, h_mom, h_frc [n][3]: positions, momenta and the forces of
+ * the last evaluation (each may be NULL); h_state [32] as rbe_md_get_state
+ * (may be NULL). */
 rbe_status rbe_batch_read(rbe_batch b, int32_t slot, double* h_pos, double* h_mom,
-                          double* h_state);
+                          double* h_frc, double* h_state);
 
 /* Waits; the device-side error flags of the slot's three contexts. */
 rbe_status rbe_batch_check(rbe_batch b, int32_t slot);

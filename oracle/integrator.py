@@ -29,6 +29,13 @@ pressure from the end of the previous step (same momenta and virial).
 Units: forces and virials enter multiplied by `ftm` (force unit -> mass x
 length / time^2); kT and P are given in energy units and multiplied by ftm.
 
+Rigid molecules (optional; constraints.py): every sub-flow that moves
+positions (A_R) is followed by SHAKE against the positions before it, with
+the momentum change that the A_R map gives the position change,
+    p <- p + m (r_shake - r_unconstrained) a / (e^{a h} - 1)   (per axis),
+and every sub-flow that changes momenta (B_R, O) by the RATTLE velocity
+stage.  The pressure then takes the molecular form of constraints.py.
+
 Noise: Philox4x64-10 keyed (seed, system_id); particle i at step s uses
 counter (s, i, TAG_NOISE, 0): uniforms u0..u3 give three normals by Box-Muller,
 z0 = sqrt(-2 ln(1-u0)) cos(2 pi u1), z1 = ... sin(2 pi u1),
@@ -39,6 +46,7 @@ z0 for V (or A), z1 for L.
 import math
 import numpy as np
 
+from . import constraints as cons
 from .philox import philox4x64, u01
 
 TAG_NOISE = 0x6E6F6973   # 'nois'
@@ -109,17 +117,45 @@ class NPTState:
 class LangevinNPT:
     """One BAOAB step of the Langevin NPT equations (see the module docstring)."""
 
-    def __init__(self, mode, masses_cell, dt, kT, P, gamma_p, gamma_c, ftm, seed, system_id):
+    def __init__(self, mode, masses_cell, dt, kT, P, gamma_p, gamma_c, ftm, seed, system_id,
+                 rigid=None):
+        """rigid: None or dict(first, count, d_oh, d_hh) (rigid 3-site molecules)."""
         self.mode = mode
+        self.rigid = rigid
+        self.mol = cons.molecules(rigid["first"], rigid["count"]) if rigid else None
         self.masses_cell = masses_cell
         self.dt, self.kT, self.P = dt, kT, P
         self.gp, self.gc, self.ftm = gamma_p, gamma_c, ftm
         self.seed, self.sysid = seed, system_id
 
-    def pressure(self, st, p, m, W):
-        """Instantaneous pressure tensor (internal units): (sum p p^T/m + ftm W)/V."""
-        K = np.einsum("ia,ib->ab", p, p / m[:, None])
-        return (K + self.ftm * np.asarray(W)) / st.volume()
+    def pressure(self, st, p, m, W, r=None, F=None):
+        """Instantaneous pressure tensor (internal units): (sum p p^T/m + ftm W)/V,
+        or with rigid molecules (K_mol + ftm (W - C))/V (constraints.py)."""
+        if self.rigid is None:
+            K = np.einsum("ia,ib->ab", p, p / m[:, None])
+            return (K + self.ftm * np.asarray(W)) / st.volume()
+        K = cons.molecular_kinetic(p, m, self.mol)
+        C = cons.molecular_correction(r, np.asarray(F), m, self.mol)
+        return (K + self.ftm * (np.asarray(W) - C)) / st.volume()
+
+    def project(self, r, p, m):
+        """RATTLE velocity stage (identity without rigid molecules)."""
+        if self.rigid is None:
+            return p
+        rg = self.rigid
+        return cons.rattle_momenta(r, p, m, self.mol, rg["d_oh"], rg["d_hh"])
+
+    def drift(self, st, r, p, m, h):
+        """A_R, then SHAKE and the matching momentum change (rigid molecules)."""
+        r1 = self.A_R(st, r, p, m, h)
+        if self.rigid is None:
+            return r1, p
+        rg = self.rigid
+        rs = cons.shake(r, r1, m, self.mol, rg["d_oh"], rg["d_hh"])
+        a = st.rates()
+        phi = np.array([_expm1_over(a[ax], h) for ax in range(3)])
+        p = p + m[:, None] * (rs - r1) / phi[None, :]
+        return rs, p
 
     def B_V(self, st, h):
         P = self.ftm * self.P
@@ -169,18 +205,18 @@ class LangevinNPT:
     def first_half(self, st, r, p, m, F, step):
         h = 0.5 * self.dt
         self.B_V(st, h)
-        p = self.B_R(st, p, F, h)
+        p = self.project(r, self.B_R(st, p, F, h), m)
         self.A_V(st, h)
-        r = self.A_R(st, r, p, m, h)
+        r, p = self.drift(st, r, p, m, h)
         self.O_cell(st, step)
-        p = self.O_particles(p, m, step)
-        r = self.A_R(st, r, p, m, h)
+        p = self.project(r, self.O_particles(p, m, step), m)
+        r, p = self.drift(st, r, p, m, h)
         self.A_V(st, h)
         return r, p
 
-    def second_half(self, st, p, m, F, W):
+    def second_half(self, st, p, m, F, W, r=None):
         h = 0.5 * self.dt
-        p = self.B_R(st, p, F, h)
-        st.P_ins = self.pressure(st, p, m, W)
+        p = self.project(r, self.B_R(st, p, F, h), m)
+        st.P_ins = self.pressure(st, p, m, W, r, F)
         self.B_V(st, h)
         return p

@@ -171,7 +171,7 @@ const T* put(rbe_batch_s* b, const T* src, size_t count) {
 }
 
 size_t stage_bytes_per_system() {
-  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 6 * sizeof(int) + 6 * 64;
+  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 7 * sizeof(int) + 7 * 64;
 }
 
 }  // namespace
@@ -194,15 +194,16 @@ rbe_status rbe_batch_create(const rbe_batch_config* cfg, void* stream, rbe_batch
   // tables of one step: every system once per kernel family, plus one
   // 64-byte alignment per group (at most 3 lane widths + 4 block shapes)
   b->stage_cap = (size_t)cfg->max_systems * stage_bytes_per_system() + 64 * 1024;
-  bool ok = true;
   for (Stage& st : b->stage) {
-    ok = ok && hipHostMalloc((void**)&st.host, b->stage_cap, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipMalloc((void**)&st.dev, b->stage_cap) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess;
-  }
-  if (!ok) {
-    rbe_batch_destroy(b);
-    return bfail(RBE_ERR_ALLOC, "staging allocation failed");
+    hipError_t e = hipHostMalloc((void**)&st.host, b->stage_cap, hipHostMallocDefault);
+    const char* what = "hipHostMalloc";
+    if (e == hipSuccess) { what = "hipMalloc"; e = hipMalloc((void**)&st.dev, b->stage_cap); }
+    if (e == hipSuccess) { what = "hipEventCreate"; e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming); }
+    if (e != hipSuccess) {
+      const size_t cap = b->stage_cap;
+      rbe_batch_destroy(b);
+      return bfail(RBE_ERR_ALLOC, "staging (%zu bytes): %s: %s", cap, what, hipGetErrorString(e));
+    }
   }
   *out = b;
   return RBE_OK;
@@ -271,12 +272,15 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* d, const double* 
   st = rbe_init(&kc, s.q, box_host, b->stream, &s.k);
   if (st == RBE_OK) st = rbe_real_init(&rc, s.q, d->ntypes > 0 ? s.type : nullptr, h_lj, box_host, b->stream, &s.r);
   if (st == RBE_OK) st = rbe_md_init(&mc, s.mass, box_host, b->stream, &s.m);
+  if (st == RBE_OK && d->rigid_count > 0)
+    st = rbe_md_set_rigid(s.m, d->rigid_first, d->rigid_count, d->d_oh, d->d_hh);
   // initial forces and pressure (the batch of the opening evaluation uses
   // step 2^63, outside the range of step indices)
   if (st == RBE_OK) st = rbe_sample_k(s.k, 1ull << 63);
   if (st == RBE_OK) st = rbe_forces_pressure(s.k, s.x, s.y, s.z, s.fx, s.fy, s.fz, 0, s.vk, s.ek);
   if (st == RBE_OK) st = rbe_real_forces(s.r, s.x, s.y, s.z, s.fx, s.fy, s.fz, 1, s.vr, s.er);
-  if (st == RBE_OK) st = rbe_md_pressure(s.m, s.px, s.py, s.pz, s.vk, s.vr);
+  if (st == RBE_OK)
+    st = rbe_md_pressure(s.m, s.x, s.y, s.z, s.px, s.py, s.pz, s.fx, s.fy, s.fz, s.vk, s.vr);
   if (st == RBE_OK) {
     // the integrator's mid-step cell drives both force evaluations
     s.box_dev = rbe_md_box_dev(s.m);
@@ -314,7 +318,8 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
     if (st == RBE_OK) st = rbe_sample_k(s.k, s.step);
     if (st == RBE_OK) st = kspace_step_args(s.k, s.x, s.y, s.z, s.fx, s.fy, s.fz, 0, s.vk, s.ek, &ka[j]);
     if (st == RBE_OK) st = real_step_args(s.r, s.x, s.y, s.z, s.fx, s.fy, s.fz, 1, s.vr, s.er, &ra[j], &ncap[j]);
-    if (st == RBE_OK) st = md_second_args(s.m, s.px, s.py, s.pz, s.fx, s.fy, s.fz, s.vk, s.vr, &md2[j]);
+    if (st == RBE_OK)
+      st = md_second_args(s.m, s.x, s.y, s.z, s.px, s.py, s.pz, s.fx, s.fy, s.fz, s.vk, s.vr, &md2[j]);
     if (st != RBE_OK) return st;
     s.step++;
   }
@@ -345,18 +350,21 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
     for (size_t i = 0; i < cnt.size(); ++i) o[i + 1] = o[i] + cnt[i];
     return o;
   };
-  // integrator and pair kernels: 256 particles per block; cell sort: one
-  // block per cell of the capacity
-  std::vector<int> pb(nsys), cb(nsys);
+  // pair kernels: 256 particles per block; integrator: 256 units (rigid
+  // molecules or free atoms) per block; cell sort: one block per cell of
+  // the capacity
+  std::vector<int> pb(nsys), ub(nsys), cb(nsys);
   for (int j = 0; j < nsys; ++j) {
     pb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
+    ub[j] = (int)((md_units(md1[j]) + 255) / 256);
     cb[j] = ncap[j];
   }
-  const std::vector<int> pstart = prefix(pb), cstart = prefix(cb);
+  const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb);
   const MDArgs* d_md1 = put(b, md1.data(), nsys);
   const MDArgs* d_md2 = put(b, md2.data(), nsys);
   const RealArgs* d_ra = put(b, ra.data(), nsys);
   const int* d_pstart = put(b, pstart.data(), nsys + 1);
+  const int* d_ustart = put(b, ustart.data(), nsys + 1);
   const int* d_cstart = put(b, cstart.data(), nsys + 1);
   // structure factors grouped by lane width, forces by block shape
   struct Group { std::vector<int> idx; const StepArgs* tab; const int* start; int total; size_t lds; };
@@ -386,7 +394,7 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   if (stg.overflow) return bfail(RBE_ERR_STATE, "argument table overflow");
   e = hipMemcpyAsync(stg.dev, stg.host, stg.used, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipEventRecord(stg.done, b->stream);
-  if (e == hipSuccess) e = launch_md_first_multi(d_md1, d_pstart, nsys, pstart.back(), b->stream);
+  if (e == hipSuccess) e = launch_md_first_multi(d_md1, d_ustart, nsys, ustart.back(), b->stream);
   for (auto& kv : sg)
     if (e == hipSuccess)
       e = launch_sfac_multi(prec, kv.first, kv.second.tab, kv.second.start, (int)kv.second.idx.size(),
@@ -397,7 +405,7 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
                              kv.second.total, b->stream);
   if (e == hipSuccess)
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), nsys, b->stream);
-  if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_pstart, nsys, pstart.back(), 0, b->stream);
+  if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
   b->cur ^= 1;
   b->steps_launched++;
   if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "fused step launches: %s", hipGetErrorString(e));
@@ -411,13 +419,14 @@ rbe_status rbe_batch_sync(rbe_batch b) {
   return RBE_OK;
 }
 
-rbe_status rbe_batch_read(rbe_batch b, int32_t slot, double* h_pos, double* h_mom, double* h_state) {
+rbe_status rbe_batch_read(rbe_batch b, int32_t slot, double* h_pos, double* h_mom, double* h_frc,
+                          double* h_state) {
   if (!b) return bfail(RBE_ERR_ARG, "NULL batch");
   if (slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot].active)
     return bfail(RBE_ERR_ARG, "slot %d is not admitted", slot);
   Slot& s = b->slots[slot];
   const int64_t n = s.desc.n;
-  std::vector<double> h((size_t)6 * n);
+  std::vector<double> h((size_t)9 * n);
   hipError_t e = hipMemcpyAsync(h.data(), s.mem, h.size() * 8, hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "read state: %s", hipGetErrorString(e));
@@ -425,6 +434,7 @@ rbe_status rbe_batch_read(rbe_batch b, int32_t slot, double* h_pos, double* h_mo
     for (int a = 0; a < 3; ++a) {
       if (h_pos) h_pos[3 * i + a] = h[(size_t)a * n + i];
       if (h_mom) h_mom[3 * i + a] = h[(size_t)(3 + a) * n + i];
+      if (h_frc) h_frc[3 * i + a] = h[(size_t)(6 + a) * n + i];
     }
   if (h_state) return rbe_md_get_state(s.m, h_state);
   return RBE_OK;

@@ -9,8 +9,21 @@
 //                tensor and applies the closing B_V
 // The start-of-step and mid-step cells live in two buffers, so no block reads
 // a cell another block of the same launch writes.
+//
+// Rigid 3-site molecules: a thread owns a whole molecule.  Each position
+// sub-flow (A_R) is followed by the position constraint solved in closed
+// form (rigid_positions), with the momentum change the A_R map gives the
+// position change, and each momentum sub-flow (B_R, O) by the projection of
+// the molecule's momenta onto rigid-body motions (rigid_momenta).  The
+// pressure takes the molecular form: centre-of-mass kinetic tensor and the
+// atomic virial less sum sym((r - R_mol) F).
 #include "rbe_md_internal.h"
 #include <math.h>
+
+// Multiply-adds are fused only where one source expression holds both, so the
+// one-system and many-system kernels (the same code inlined in different
+// surroundings) round identically.
+#pragma clang fp contract(on)
 
 namespace rbe {
 
@@ -93,6 +106,160 @@ __device__ __forceinline__ void A_V(MDCell& c, double h) {
   else { c.A += h * c.pA / c.MA; c.L += h * c.pL / c.ML; }
 }
 
+
+// ---------------------------------------------------------------------------
+// rigid 3-site molecules
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Mass-weighted orthogonal projection of the three momenta onto rigid-body
+// motions, p_k <- m_k (P/M + w x rho_k), w = I^-1 L: the velocity stage of
+// RATTLE for a rigid triangle in closed form (the part removed carries no
+// linear or angular momentum, and no bond has a relative velocity along it
+// afterwards).
+__device__ void rigid_momenta(const double r[3][3], double p[3][3], const double m[3]) {
+  const double M = m[0] + m[1] + m[2];
+  double R[3], P[3], rho[3][3], L[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    R[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) / M;
+    P[d] = p[0][d] + p[1][d] + p[2][d];
+  }
+  double I[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int k = 0; k < 3; ++k) {
+    for (int d = 0; d < 3; ++d) rho[k][d] = r[k][d] - R[d];
+    double lk[3];
+    cross3(rho[k], p[k], lk);
+    const double r2 = dot3(rho[k], rho[k]);
+    for (int d = 0; d < 3; ++d) {
+      L[d] += lk[d];
+      for (int e = 0; e < 3; ++e) I[d][e] += m[k] * ((d == e ? r2 : 0.0) - rho[k][d] * rho[k][e]);
+    }
+  }
+  // w = I^-1 L by the adjugate (I symmetric positive definite for a triangle)
+  const double c00 = I[1][1] * I[2][2] - I[1][2] * I[2][1];
+  const double c01 = I[1][2] * I[2][0] - I[1][0] * I[2][2];
+  const double c02 = I[1][0] * I[2][1] - I[1][1] * I[2][0];
+  const double c11 = I[0][0] * I[2][2] - I[0][2] * I[2][0];
+  const double c12 = I[0][1] * I[2][0] - I[0][0] * I[2][1];
+  const double c22 = I[0][0] * I[1][1] - I[0][1] * I[1][0];
+  const double det = I[0][0] * c00 + I[0][1] * c01 + I[0][2] * c02;
+  const double w[3] = {(c00 * L[0] + c01 * L[1] + c02 * L[2]) / det,
+                       (c01 * L[0] + c11 * L[1] + c12 * L[2]) / det,
+                       (c02 * L[0] + c12 * L[1] + c22 * L[2]) / det};
+  for (int k = 0; k < 3; ++k) {
+    double v[3];
+    cross3(w, rho[k], v);
+    for (int d = 0; d < 3; ++d) p[k][d] = m[k] * (P[d] / M + v[d]);
+  }
+}
+
+// Position constraint in closed form.  r0: positions before the drift (a
+// rigid molecule); r: unconstrained positions after it, replaced by the
+// constrained ones.  The corrections of SHAKE (constraint forces along the
+// old bonds) keep the centre of mass, lie in the old molecular plane (so each
+// atom's coordinate along that plane's normal n is kept) and exert no torque
+// about n with the old positions as lever arms.  The molecule's shape is
+// fixed, so the result is a rotation of the reference triangle about the new
+// centre of mass: its tilt follows from the three kept normal coordinates and
+// its turn about n from the torque condition.  Returns false if no tilt
+// matches (a drift far too long for the step).
+__device__ bool rigid_positions(const double r0[3][3], double r[3][3], const double m[3],
+                                double ra, double rb, double rc) {
+  const double M = m[0] + m[1] + m[2];
+  double b0[3], c0[3], Z[3], X[3], Y[3];
+  for (int d = 0; d < 3; ++d) {
+    b0[d] = r0[1][d] - r0[0][d];
+    c0[d] = r0[2][d] - r0[0][d];
+    X[d] = r0[2][d] - r0[1][d];
+  }
+  cross3(b0, c0, Z);
+  const double zn = sqrt(dot3(Z, Z)), xn = sqrt(dot3(X, X));
+  for (int d = 0; d < 3; ++d) { Z[d] /= zn; X[d] /= xn; }
+  cross3(Z, X, Y);
+  double D[3], C0[3];
+  for (int d = 0; d < 3; ++d) {
+    D[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) / M;
+    C0[d] = (m[0] * r0[0][d] + m[1] * r0[1][d] + m[2] * r0[2][d]) / M;
+  }
+  double an[3][3], on[3][2];     // new (x, y, z) and old (x, y) in the frame
+  for (int k = 0; k < 3; ++k) {
+    double u[3], v[3];
+    for (int d = 0; d < 3; ++d) { u[d] = r[k][d] - D[d]; v[d] = r0[k][d] - C0[d]; }
+    an[k][0] = dot3(u, X); an[k][1] = dot3(u, Y); an[k][2] = dot3(u, Z);
+    on[k][0] = dot3(v, X); on[k][1] = dot3(v, Y);
+  }
+  // tilt: the unit vector t (reference frame) with t . c_k = normal coordinate
+  const double ty = an[0][2] / ra;
+  const double tx = (an[2][2] - an[1][2]) / (2.0 * rc);
+  const double s2 = tx * tx + ty * ty;
+  if (!(s2 < 1.0)) return false;
+  const double tz = sqrt(1.0 - s2), sb = sqrt(s2);
+  const double cref[3][2] = {{0.0, ra}, {-rc, -rb}, {rc, -rb}};
+  double q[3][3];
+  for (int k = 0; k < 3; ++k) {
+    const double cx = cref[k][0], cy = cref[k][1];
+    if (sb > 0.0) {
+      // rotation taking t to the normal, about the axis (ty, -tx, 0)/sb
+      const double kx = ty / sb, ky = -tx / sb;
+      const double kc = kx * cx + ky * cy;
+      q[k][0] = cx * tz + kx * kc * (1.0 - tz);
+      q[k][1] = cy * tz + ky * kc * (1.0 - tz);
+      q[k][2] = (kx * cy - ky * cx) * sb;
+    } else {
+      q[k][0] = cx; q[k][1] = cy; q[k][2] = 0.0;
+    }
+  }
+  // turn about the normal: sum_k m_k (o_k x p_k).n equals sum_k m_k (o_k x a_k).n
+  double A = 0.0, B = 0.0, Lt = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    A += m[k] * (on[k][0] * q[k][0] + on[k][1] * q[k][1]);
+    B += m[k] * (on[k][0] * q[k][1] - on[k][1] * q[k][0]);
+    Lt += m[k] * (on[k][0] * an[k][1] - on[k][1] * an[k][0]);
+  }
+  const double sarg = Lt / sqrt(A * A + B * B);
+  if (!(fabs(sarg) <= 1.0)) return false;
+  const double th = asin(sarg) - atan2(B, A);
+  double sn, cs;
+  sincos(th, &sn, &cs);
+  for (int k = 0; k < 3; ++k) {
+    const double px = q[k][0] * cs - q[k][1] * sn;
+    const double py = q[k][0] * sn + q[k][1] * cs;
+    const double pz = q[k][2];
+    for (int d = 0; d < 3; ++d) r[k][d] = D[d] + px * X[d] + py * Y[d] + pz * Z[d];
+  }
+  return true;
+}
+
+// A_R on a molecule, then the position constraint and the momentum change
+// p += m (r_constrained - r_unconstrained) a / (e^{a h} - 1) per axis
+__device__ __forceinline__ bool rigid_drift(const MDArgs& a, double r[3][3], double p[3][3],
+                                            const double m[3], const double rate[3], double h) {
+  double r0[3][3], ru[3][3], e[3], f[3];
+  for (int d = 0; d < 3; ++d) { e[d] = exp(rate[d] * h); f[d] = expm1_over(rate[d], h); }
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) {
+      r0[k][d] = r[k][d];
+      ru[k][d] = r[k][d] * e[d] + p[k][d] / m[k] * f[d];
+      r[k][d] = ru[k][d];
+    }
+  const bool ok = rigid_positions(r0, r, m, a.ra, a.rb, a.rc);
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) p[k][d] += m[k] * (r[k][d] - ru[k][d]) / f[d];
+  return ok;
+}
+
+// atom index of free unit j (atoms outside the rigid block)
+__device__ __forceinline__ int64_t free_atom(const MDArgs& a, int64_t j) {
+  return j < a.rig_first ? j : j + 3 * a.rig_count;
+}
+
 __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   __shared__ MDCell sc;
   __shared__ double rate[3][3];
@@ -120,15 +287,46 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   }
   __syncthreads();
   if (bx == 0 && threadIdx.x == 0) *a.cell_out = sc;
-  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  const int64_t u = (int64_t)bx * blockDim.x + threadIdx.x;
+  if (u >= md_units(a)) return;
+  const double c1 = exp(-a.gp * a.dt);
+  if (u < a.rig_count) {
+    const int64_t i0 = a.rig_first + 3 * u;
+    double r[3][3], p[3][3], F[3][3], m[3], z[3][3];
+    for (int k = 0; k < 3; ++k) {
+      const int64_t i = i0 + k;
+      m[k] = a.mass[i];
+      r[k][0] = a.x[i]; r[k][1] = a.y[i]; r[k][2] = a.z[i];
+      p[k][0] = a.px[i]; p[k][1] = a.py[i]; p[k][2] = a.pz[i];
+      F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
+      normals3(a.seed, a.sysid, a.step, (uint64_t)i, kTagNoise, z[k]);
+    }
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d)
+        p[k][d] = p[k][d] * exp(-rate[0][d] * h) + a.ftm * F[k][d] * expm1_over(-rate[0][d], h);  // B_R
+    rigid_momenta(r, p, m);
+    bool ok = rigid_drift(a, r, p, m, rate[1], h);                                              // A_R
+    for (int k = 0; k < 3; ++k) {
+      const double amp = sqrt(a.ftm * a.kT * m[k] * (1.0 - c1 * c1));
+      for (int d = 0; d < 3; ++d) p[k][d] = c1 * p[k][d] + amp * z[k][d];                      // O
+    }
+    rigid_momenta(r, p, m);
+    ok = rigid_drift(a, r, p, m, rate[2], h) && ok;                                             // A_R
+    if (!ok) atomicOr(a.flags, 1);
+    for (int k = 0; k < 3; ++k) {
+      const int64_t i = i0 + k;
+      a.x[i] = r[k][0]; a.y[i] = r[k][1]; a.z[i] = r[k][2];
+      a.px[i] = p[k][0]; a.py[i] = p[k][1]; a.pz[i] = p[k][2];
+    }
+    return;
+  }
+  const int64_t i = free_atom(a, u - a.rig_count);
   const double m = a.mass[i], im = 1.0 / m;
   double r[3] = {a.x[i], a.y[i], a.z[i]};
   double p[3] = {a.px[i], a.py[i], a.pz[i]};
   const double F[3] = {a.fx[i], a.fy[i], a.fz[i]};
   double z[3];
   normals3(a.seed, a.sysid, a.step, (uint64_t)i, kTagNoise, z);
-  const double c1 = exp(-a.gp * a.dt);
   const double amp = sqrt(a.ftm * a.kT * m * (1.0 - c1 * c1));
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -150,7 +348,7 @@ __device__ __forceinline__ double wsum_md(double v) {
 // mode 0: closing half step (B_R, pressure, B_V); mode 1: pressure only
 __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int bx, int nbx) {
   __shared__ MDCell sc;
-  __shared__ double sh[4][6];
+  __shared__ double sh[4][12];
   __shared__ int sh_last;
   const double h = 0.5 * a.dt;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -158,9 +356,43 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   __syncthreads();
   double rate[3];
   cell_rates(sc, rate);
-  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  double k6[6] = {0, 0, 0, 0, 0, 0};
-  if (i < a.n) {
+  const int64_t u = (int64_t)bx * blockDim.x + threadIdx.x;
+  double k6[6] = {0, 0, 0, 0, 0, 0};   // kinetic tensor
+  double c6[6] = {0, 0, 0, 0, 0, 0};   // molecular correction sum sym((r - R) F)
+  if (u < md_units(a) && u < a.rig_count) {
+    const int64_t i0 = a.rig_first + 3 * u;
+    double r[3][3], p[3][3], F[3][3], m[3];
+    for (int k = 0; k < 3; ++k) {
+      const int64_t i = i0 + k;
+      m[k] = a.mass[i];
+      r[k][0] = a.x[i]; r[k][1] = a.y[i]; r[k][2] = a.z[i];
+      p[k][0] = a.px[i]; p[k][1] = a.py[i]; p[k][2] = a.pz[i];
+      F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
+    }
+    if (!prime)
+      for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d)
+          p[k][d] = p[k][d] * exp(-rate[d] * h) + a.ftm * F[k][d] * expm1_over(-rate[d], h);
+    rigid_momenta(r, p, m);
+    const double M = m[0] + m[1] + m[2];
+    double P[3], R[3];
+    for (int d = 0; d < 3; ++d) {
+      P[d] = p[0][d] + p[1][d] + p[2][d];
+      R[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) / M;
+    }
+    k6[0] = P[0] * P[0] / M; k6[1] = P[1] * P[1] / M; k6[2] = P[2] * P[2] / M;
+    k6[3] = P[0] * P[1] / M; k6[4] = P[0] * P[2] / M; k6[5] = P[1] * P[2] / M;
+    for (int k = 0; k < 3; ++k) {
+      const double x0 = r[k][0] - R[0], x1 = r[k][1] - R[1], x2 = r[k][2] - R[2];
+      c6[0] += x0 * F[k][0]; c6[1] += x1 * F[k][1]; c6[2] += x2 * F[k][2];
+      c6[3] += 0.5 * (x0 * F[k][1] + x1 * F[k][0]);
+      c6[4] += 0.5 * (x0 * F[k][2] + x2 * F[k][0]);
+      c6[5] += 0.5 * (x1 * F[k][2] + x2 * F[k][1]);
+      const int64_t i = i0 + k;
+      a.px[i] = p[k][0]; a.py[i] = p[k][1]; a.pz[i] = p[k][2];
+    }
+  } else if (u < md_units(a)) {
+    const int64_t i = free_atom(a, u - a.rig_count);
     double p[3] = {a.px[i], a.py[i], a.pz[i]};
     if (!prime) {
       const double F[3] = {a.fx[i], a.fy[i], a.fz[i]};
@@ -175,12 +407,13 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   }
   for (int k = 0; k < 6; ++k) {
     const double s = wsum_md(k6[k]);
-    if (lane == 0) sh[wave][k] = s;
+    const double t = wsum_md(c6[k]);
+    if (lane == 0) { sh[wave][k] = s; sh[wave][6 + k] = t; }
   }
   __syncthreads();
-  if (threadIdx.x < 6) {
+  if (threadIdx.x < 12) {
     const double s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
-    __hip_atomic_store(&a.part[bx * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.part[bx * 16 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -188,11 +421,11 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
     sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
   __syncthreads();
   if (!sh_last) return;
-  __shared__ double ksum[6];
-  if (threadIdx.x < 6) {
+  __shared__ double ksum[12];
+  if (threadIdx.x < 12) {
     double s = 0.0;
     for (int b = 0; b < nbx; ++b)
-      s += __hip_atomic_load(&a.part[b * 8 + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s += __hip_atomic_load(&a.part[b * 16 + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ksum[threadIdx.x] = s;
   }
   __syncthreads();
@@ -204,7 +437,8 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
       if (a.virial_k) w += a.virial_k[k];
       if (a.virial_r) w += a.virial_r[k];
       c.K[k] = ksum[k];
-      c.P_ins[k] = (ksum[k] + a.ftm * w) / V;
+      c.C[k] = ksum[6 + k];
+      c.P_ins[k] = (ksum[k] + a.ftm * (w - ksum[6 + k])) / V;
     }
     if (!prime) B_V(a, c, h);
     *a.cell_out = c;
@@ -218,13 +452,13 @@ __global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
 }
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.n + 255) / 256);
+  const unsigned blocks = (unsigned)((md_units(a) + 255) / 256);
   hipLaunchKernelGGL(k_md_first, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_md_second(const MDArgs& a, int prime, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.n + 255) / 256);
+  const unsigned blocks = (unsigned)((md_units(a) + 255) / 256);
   hipLaunchKernelGGL(k_md_second, dim3(blocks), dim3(256), 0, s, a, prime);
   return hipGetLastError();
 }

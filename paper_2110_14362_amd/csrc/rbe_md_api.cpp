@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <new>
+#include <vector>
 
 using namespace rbe;
 
@@ -20,6 +21,7 @@ struct rbe_md_ctx_s {
   double* d_mass = nullptr;
   double* d_part = nullptr;
   uint32_t* d_cnt = nullptr;
+  int32_t* d_flags = nullptr;
 };
 
 namespace {
@@ -36,7 +38,7 @@ rbe_status mfail(rbe_status st, const char* fmt, ...) {
 bool pos_fin(double v) { return std::isfinite(v) && v > 0.0; }
 
 void mfree(rbe_md_ctx_s* c) {
-  void* b[] = {c->d_cell, c->d_mass, c->d_part, c->d_cnt};
+  void* b[] = {c->d_cell, c->d_mass, c->d_part, c->d_cnt, c->d_flags};
   for (void* p : b)
     if (p) (void)hipFree(p);
 }
@@ -59,11 +61,14 @@ rbe_status md_first_args(rbe_md_ctx c, uint64_t step, double* d_x, double* d_y, 
   return RBE_OK;
 }
 
-rbe_status md_second_args(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz,
+rbe_status md_second_args(rbe_md_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                          double* d_px, double* d_py, double* d_pz,
                           const double* d_fx, const double* d_fy, const double* d_fz,
                           const double* d_virial_k, const double* d_virial_r, MDArgs* out) {
-  if (!c || !d_px || !d_py || !d_pz || !d_fx || !d_fy || !d_fz) return mfail(RBE_ERR_ARG, "NULL argument");
+  if (!c || !d_x || !d_y || !d_z || !d_px || !d_py || !d_pz || !d_fx || !d_fy || !d_fz)
+    return mfail(RBE_ERR_ARG, "NULL argument");
   MDArgs a = c->a;
+  a.x = const_cast<double*>(d_x); a.y = const_cast<double*>(d_y); a.z = const_cast<double*>(d_z);
   a.px = d_px; a.py = d_py; a.pz = d_pz;
   a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
   a.virial_k = d_virial_k; a.virial_r = d_virial_r;
@@ -74,7 +79,7 @@ rbe_status md_second_args(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz
 
 int64_t md_footprint(int64_t n) {
   auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
-  return r(2 * sizeof(MDCell)) + r(8 * n) + r(64 * ((n + 255) / 256)) + r(4);
+  return r(2 * sizeof(MDCell)) + r(8 * n) + r(128 * ((n + 255) / 256)) + r(4) + r(4);
 }
 
 }  // namespace rbe
@@ -107,8 +112,9 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   const size_t blocks = (n + 255) / 256;
   bool ok = hipMalloc(&c->d_cell, 2 * sizeof(MDCell)) == hipSuccess &&
             hipMalloc(&c->d_mass, n * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->d_part, blocks * 8 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->d_cnt, sizeof(uint32_t)) == hipSuccess;
+            hipMalloc(&c->d_part, blocks * 16 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_cnt, sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(&c->d_flags, sizeof(int32_t)) == hipSuccess;
   if (!ok) { mfree(c); delete c; return mfail(RBE_ERR_ALLOC, "device allocation failed"); }
   MDCell cell{};
   cell.mode = cfg->box_mode == RBE_BOX_ISO ? 0 : 1;
@@ -129,6 +135,7 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
     if ((e = hipMemcpyAsync(c->d_mass, d_mass, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess) break;
     if ((e = hipMemcpyAsync(c->d_cell, cells, sizeof cells, hipMemcpyHostToDevice, c->stream)) != hipSuccess) break;
     if ((e = hipMemsetAsync(c->d_cnt, 0, sizeof(uint32_t), c->stream)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(c->d_flags, 0, sizeof(int32_t), c->stream)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (0);
   if (e != hipSuccess) { mfree(c); delete c; return mfail(RBE_ERR_DEVICE, "init: %s", hipGetErrorString(e)); }
@@ -136,17 +143,54 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   a.mass = c->d_mass; a.n = cfg->n;
   a.dt = cfg->dt; a.kT = cfg->kT; a.P = cfg->p_ext; a.gp = cfg->gamma_p; a.gc = cfg->gamma_cell;
   a.ftm = cfg->ftm; a.seed = cfg->seed; a.sysid = cfg->system_id;
-  a.part = c->d_part; a.cnt = c->d_cnt;
+  a.part = c->d_part; a.cnt = c->d_cnt; a.flags = c->d_flags;
+  a.rig_first = 0; a.rig_count = 0;
   *out = c;
   return RBE_OK;
 }
 
-rbe_status rbe_md_pressure(rbe_md_ctx c, const double* d_px, const double* d_py, const double* d_pz,
-                           const double* d_virial_k, const double* d_virial_r) {
-  if (!c || !d_px || !d_py || !d_pz) return mfail(RBE_ERR_ARG, "NULL argument");
-  MDArgs a = c->a;
-  a.px = const_cast<double*>(d_px); a.py = const_cast<double*>(d_py); a.pz = const_cast<double*>(d_pz);
-  a.virial_k = d_virial_k; a.virial_r = d_virial_r;
+rbe_status rbe_md_set_rigid(rbe_md_ctx c, int64_t first, int64_t count, double d_oh, double d_hh) {
+  if (!c) return mfail(RBE_ERR_ARG, "NULL context");
+  if (count == 0) {
+    c->a.rig_first = 0;
+    c->a.rig_count = 0;
+    return RBE_OK;
+  }
+  if (first < 0 || count < 0 || first + 3 * count > c->a.n)
+    return mfail(RBE_ERR_ARG, "rigid block [%lld, %lld + 3 x %lld) is outside the %lld atoms",
+                 (long long)first, (long long)first, (long long)count, (long long)c->a.n);
+  if (!(d_oh > 0.0 && std::isfinite(d_oh)) || !(d_hh > 0.0 && d_hh < 2.0 * d_oh))
+    return mfail(RBE_ERR_ARG, "bond lengths d_oh = %g, d_hh = %g do not form a triangle", d_oh, d_hh);
+  std::vector<double> m((size_t)(3 * count));
+  hipError_t e = hipMemcpyAsync(m.data(), c->d_mass + first, m.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return mfail(RBE_ERR_DEVICE, "read masses: %s", hipGetErrorString(e));
+  const double mo = m[0], mh = m[1];
+  for (int64_t k = 0; k < count; ++k)
+    if (m[3 * k] != mo || m[3 * k + 1] != mh || m[3 * k + 2] != mh)
+      return mfail(RBE_ERR_ARG, "rigid molecule %lld: masses differ from the first molecule's (O, H, H)",
+                   (long long)k);
+  if (!(mo > 0.0 && mh > 0.0)) return mfail(RBE_ERR_ARG, "masses must be positive");
+  const double M = mo + 2.0 * mh;
+  const double rc = 0.5 * d_hh;
+  const double hgt = std::sqrt(d_oh * d_oh - rc * rc);
+  c->a.rig_first = first;
+  c->a.rig_count = count;
+  c->a.rc = rc;
+  c->a.ra = 2.0 * mh * hgt / M;
+  c->a.rb = hgt - c->a.ra;
+  return RBE_OK;
+}
+
+rbe_status rbe_md_pressure(rbe_md_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                           double* d_px, double* d_py, double* d_pz, const double* d_fx,
+                           const double* d_fy, const double* d_fz, const double* d_virial_k,
+                           const double* d_virial_r) {
+  MDArgs a;
+  rbe_status st = rbe::md_second_args(c, d_x, d_y, d_z, d_px, d_py, d_pz, d_fx, d_fy, d_fz,
+                                      d_virial_k, d_virial_r, &a);
+  if (st != RBE_OK) return st;
   a.cell_in = c->d_cell; a.cell_out = c->d_cell;
   hipError_t e = launch_md_second(a, 1, c->stream);
   if (e != hipSuccess) return mfail(RBE_ERR_DEVICE, "pressure kernel: %s", hipGetErrorString(e));
@@ -164,11 +208,13 @@ rbe_status rbe_md_first_half(rbe_md_ctx c, uint64_t step, double* d_x, double* d
   return RBE_OK;
 }
 
-rbe_status rbe_md_second_half(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz,
+rbe_status rbe_md_second_half(rbe_md_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                              double* d_px, double* d_py, double* d_pz,
                               const double* d_fx, const double* d_fy, const double* d_fz,
                               const double* d_virial_k, const double* d_virial_r) {
   MDArgs a;
-  rbe_status st = rbe::md_second_args(c, d_px, d_py, d_pz, d_fx, d_fy, d_fz, d_virial_k, d_virial_r, &a);
+  rbe_status st = rbe::md_second_args(c, d_x, d_y, d_z, d_px, d_py, d_pz, d_fx, d_fy, d_fz,
+                                      d_virial_k, d_virial_r, &a);
   if (st != RBE_OK) return st;
   hipError_t e = launch_md_second(a, 0, c->stream);
   if (e != hipSuccess) return mfail(RBE_ERR_DEVICE, "second half kernel: %s", hipGetErrorString(e));
@@ -191,14 +237,25 @@ rbe_status rbe_md_get_state(rbe_md_ctx c, double* h) {
   h[19] = (double)cell.err;
   h[20] = (double)cell.step;
   h[21] = cell.A; h[22] = cell.L; h[23] = cell.V;
+  for (int k = 0; k < 6; ++k) h[24 + k] = cell.C[k];
+  h[30] = (double)c->a.rig_count;
+  h[31] = 0.0;
   return RBE_OK;
 }
 
 rbe_status rbe_md_check(rbe_md_ctx c) {
-  double h[24];
+  double h[32];
   rbe_status st = rbe_md_get_state(c, h);
   if (st != RBE_OK) return st;
   if (h[19] != 0.0) return mfail(RBE_ERR_STATE, "the cell collapsed or became non-finite");
+  int32_t flags = 0;
+  if (hipMemcpy(&flags, c->d_flags, sizeof flags, hipMemcpyDeviceToHost) != hipSuccess)
+    return mfail(RBE_ERR_DEVICE, "read constraint flags");
+  if (flags) {
+    const int32_t zero = 0;
+    (void)hipMemcpy(c->d_flags, &zero, sizeof zero, hipMemcpyHostToDevice);
+    return mfail(RBE_ERR_STATE, "a rigid-molecule position constraint had no solution (step too long)");
+  }
   return RBE_OK;
 }
 

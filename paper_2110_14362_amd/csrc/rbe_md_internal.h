@@ -15,7 +15,8 @@ struct MDCell {
   double l[3];       // side lengths
   double asp[3];     // isotropic mode: l = asp * V^(1/3), asp fixed (product 1)
   double P_ins[6];   // pressure tensor xx yy zz xy xz yz (internal units)
-  double K[6];       // kinetic tensor sum p p^T / m
+  double K[6];       // kinetic tensor sum p p^T / m (rigid molecules: P P^T / M)
+  double C[6];       // rigid molecules: sum sym((r - R_mol) F), force x length units
   uint64_t step;
 };
 
@@ -30,9 +31,18 @@ struct MDArgs {
   uint64_t seed, sysid, step;
   const MDCell* cell_in;
   MDCell* cell_out;
-  double* part;      // [blocks][8]
+  double* part;      // [blocks][16]
   uint32_t* cnt;
+  // rigid 3-site molecules: atoms rig_first + 3k (O), +1, +2 (H) for
+  // k < rig_count; one thread per molecule, one per remaining atom
+  int64_t rig_first, rig_count;
+  double ra, rb, rc;   // the molecule in its centre-of-mass frame: O at (0, ra),
+                       // H at (-rc, -rb) and (rc, -rb)
+  int32_t* flags;      // bit 0: a position constraint had no solution
 };
+
+// threads (units) of the integrator kernels: molecules plus free atoms
+__host__ __device__ inline int64_t md_units(const MDArgs& a) { return a.n - 2 * a.rig_count; }
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s);
 hipError_t launch_md_second(const MDArgs& a, int prime, hipStream_t s);
@@ -45,7 +55,8 @@ hipError_t launch_md_second_multi(const MDArgs* d_tab, const int* d_bstart, int 
 rbe_status md_first_args(rbe_md_ctx c, uint64_t step, double* d_x, double* d_y, double* d_z,
                          double* d_px, double* d_py, double* d_pz, const double* d_fx,
                          const double* d_fy, const double* d_fz, MDArgs* out);
-rbe_status md_second_args(rbe_md_ctx c, double* d_px, double* d_py, double* d_pz,
+rbe_status md_second_args(rbe_md_ctx c, const double* d_x, const double* d_y, const double* d_z,
+                          double* d_px, double* d_py, double* d_pz,
                           const double* d_fx, const double* d_fy, const double* d_fz,
                           const double* d_virial_k, const double* d_virial_r, MDArgs* out);
 // device bytes rbe_md_init allocates (each buffer rounded up to 256 bytes)

@@ -16,7 +16,9 @@ class NPTSystem:
     sysd: dict with pos (N,3), q, mass, box; alpha, p, coulomb;
     md: dict with dt, kT, p_ext, gamma_p, gamma_cell, mass_cell, mass_cell_z,
         ftm, box_mode ('iso' or 'semiiso'), rc; optional types + lj for the
-        real-space Lennard-Jones term.
+        real-space Lennard-Jones term; optional rigid = dict(first, count,
+        d_oh, d_hh) for rigid 3-site molecules (whole, not split by the
+        periodic boundary).
     """
 
     def __init__(self, sysd, md, precision="fp32", seed=0, system_id=0, momenta=None,
@@ -55,10 +57,14 @@ class NPTSystem:
                                 md["gamma_p"], md["gamma_cell"], md["mass_cell"],
                                 md.get("mass_cell_z", 0.0), box_mode=mode, ftm=md["ftm"],
                                 seed=seed, system_id=system_id, stream=stream)
+        rg = md.get("rigid")
+        if rg:
+            self.integ.set_rigid(rg["first"], rg["count"], rg["d_oh"], rg["d_hh"])
         self.step_index = 0
         self._box_ptr = None
         self._forces(sample_step=2**63, first=True)
-        self.integ.pressure(self.px, self.py, self.pz, self.vk, self.vr)
+        self.integ.pressure(self.x, self.y, self.z, self.px, self.py, self.pz, *self.f,
+                            self.vk, self.vr)
 
     def _forces(self, sample_step, first=False):
         self.kspace.sample_k(sample_step)
@@ -80,7 +86,8 @@ class NPTSystem:
             self.integ.first_half(s, self.x, self.y, self.z, self.px, self.py, self.pz, *self.f)
             self._bind_device_box()
             self._forces(sample_step=s)
-            self.integ.second_half(self.px, self.py, self.pz, *self.f, self.vk, self.vr)
+            self.integ.second_half(self.x, self.y, self.z, self.px, self.py, self.pz, *self.f,
+                                   self.vk, self.vr)
             self.step_index += 1
 
     def state(self):

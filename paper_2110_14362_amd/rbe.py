@@ -29,6 +29,7 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_real_check", "rbe_real_destroy",
            "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
            "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy",
+           "rbe_md_set_rigid",
            "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
            "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy"]
@@ -73,7 +74,9 @@ class SystemDesc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("kT", ctypes.c_double), ("p_ext", ctypes.c_double),
                 ("gamma_p", ctypes.c_double), ("gamma_cell", ctypes.c_double),
                 ("mass_cell", ctypes.c_double), ("mass_cell_z", ctypes.c_double),
-                ("ftm", ctypes.c_double), ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64)]
+                ("ftm", ctypes.c_double), ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64),
+                ("rigid_first", ctypes.c_int64), ("rigid_count", ctypes.c_int64),
+                ("d_oh", ctypes.c_double), ("d_hh", ctypes.c_double)]
 
 
 _lib = None
@@ -111,9 +114,10 @@ def load_library(path=LIB_PATH):
         "rbe_real_forces": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "rbe_real_check": [vp],
         "rbe_md_init": [ctypes.POINTER(MDConfig), vp, dp, vp, ctypes.POINTER(vp)],
-        "rbe_md_pressure": [vp, vp, vp, vp, vp, vp],
+        "rbe_md_pressure": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "rbe_md_set_rigid": [vp, i64, i64, ctypes.c_double, ctypes.c_double],
         "rbe_md_first_half": [vp, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp],
-        "rbe_md_second_half": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "rbe_md_second_half": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "rbe_md_get_state": [vp, dp],
         "rbe_md_check": [vp],
         "rbe_batch_create": [ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(vp)],
@@ -122,7 +126,7 @@ def load_library(path=LIB_PATH):
                             dp, ctypes.POINTER(i32)],
         "rbe_batch_step": [vp, i32],
         "rbe_batch_sync": [vp],
-        "rbe_batch_read": [vp, i32, dp, dp, dp],
+        "rbe_batch_read": [vp, i32, dp, dp, dp, dp],
         "rbe_batch_check": [vp, i32],
         "rbe_batch_slot_step": [vp, i32, ctypes.POINTER(i64)],
         "rbe_batch_release": [vp, i32],
@@ -357,12 +361,17 @@ class Integrator:
         except Exception:
             pass
 
-    def pressure(self, px, py, pz, virial_k=None, virial_r=None):
+    def set_rigid(self, first, count, d_oh, d_hh):
+        _check(_lib.rbe_md_set_rigid(self._ctx, int(first), int(count), float(d_oh), float(d_hh)))
+
+    def pressure(self, x, y, z, px, py, pz, fx, fy, fz, virial_k=None, virial_r=None):
         n = self.n
-        _check(_lib.rbe_md_pressure(self._ctx, _dptr(px, "px", n), _dptr(py, "py", n),
-                                    _dptr(pz, "pz", n),
-                                    _dptr(virial_k, "virial_k", 6) if virial_k is not None else None,
-                                    _dptr(virial_r, "virial_r", 6) if virial_r is not None else None))
+        _check(_lib.rbe_md_pressure(
+            self._ctx, *[_dptr(t, nm, n) for t, nm in
+                         ((x, "x"), (y, "y"), (z, "z"), (px, "px"), (py, "py"), (pz, "pz"),
+                          (fx, "fx"), (fy, "fy"), (fz, "fz"))],
+            _dptr(virial_k, "virial_k", 6) if virial_k is not None else None,
+            _dptr(virial_r, "virial_r", 6) if virial_r is not None else None))
 
     def first_half(self, step, x, y, z, px, py, pz, fx, fy, fz):
         n = self.n
@@ -371,11 +380,12 @@ class Integrator:
                                         ((x, "x"), (y, "y"), (z, "z"), (px, "px"), (py, "py"),
                                          (pz, "pz"), (fx, "fx"), (fy, "fy"), (fz, "fz"))]))
 
-    def second_half(self, px, py, pz, fx, fy, fz, virial_k=None, virial_r=None):
+    def second_half(self, x, y, z, px, py, pz, fx, fy, fz, virial_k=None, virial_r=None):
         n = self.n
         _check(_lib.rbe_md_second_half(
             self._ctx, *[_dptr(t, nm, n) for t, nm in
-                         ((px, "px"), (py, "py"), (pz, "pz"), (fx, "fx"), (fy, "fy"), (fz, "fz"))],
+                         ((x, "x"), (y, "y"), (z, "z"), (px, "px"), (py, "py"), (pz, "pz"),
+                          (fx, "fx"), (fy, "fy"), (fz, "fz"))],
             _dptr(virial_k, "virial_k", 6) if virial_k is not None else None,
             _dptr(virial_r, "virial_r", 6) if virial_r is not None else None))
 
@@ -383,15 +393,24 @@ class Integrator:
         return _lib.rbe_md_box_dev(self._ctx)
 
     def state(self):
-        h = np.zeros(24, dtype=np.float64)
+        h = np.zeros(32, dtype=np.float64)
         _check(_lib.rbe_md_get_state(self._ctx, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        t6 = lambda v: np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
-        return dict(box=h[0:3].copy(), volume=h[3], pV=h[4], pA=h[5], pL=h[6],
-                    pressure=t6(h[7:13]), kinetic=t6(h[13:19]), err=int(h[19]), step=int(h[20]),
-                    A=h[21], L=h[22], V=h[23])
+        return state_dict(h)
 
     def check(self):
         _check(_lib.rbe_md_check(self._ctx))
+
+
+def _t6(v):
+    return np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+
+
+def state_dict(h):
+    """The 32 doubles of rbe_md_get_state as a dict."""
+    return dict(box=h[0:3].copy(), volume=h[3], pV=h[4], pA=h[5], pL=h[6],
+                pressure=_t6(h[7:13]), kinetic=_t6(h[13:19]), err=int(h[19]), step=int(h[20]),
+                A=h[21], L=h[22], V=h[23], rigid_correction=_t6(h[24:30]),
+                rigid_count=int(h[30]))
 
 
 def _hp(a, dtype=np.float64):
@@ -403,8 +422,12 @@ def _hp(a, dtype=np.float64):
 
 
 def system_desc(n, p, alpha, coulomb, rc, md, ntypes=0, seed=0, system_id=0):
-    """rbe_system_desc from the integrator parameter dict used by NPTSystem."""
-    return SystemDesc(n=int(n), p=int(p), ntypes=int(ntypes),
+    """rbe_system_desc from the integrator parameter dict used by NPTSystem
+    (md["rigid"]: optional dict(first, count, d_oh, d_hh))."""
+    rg = md.get("rigid") or dict(first=0, count=0, d_oh=0.0, d_hh=0.0)
+    return SystemDesc(rigid_first=int(rg["first"]), rigid_count=int(rg["count"]),
+                      d_oh=float(rg["d_oh"]), d_hh=float(rg["d_hh"]),
+                      n=int(n), p=int(p), ntypes=int(ntypes),
                       box_mode=BOX_MODES[md.get("box_mode", "iso")], reserved=0,
                       alpha=float(alpha), coulomb=float(coulomb), rc=float(rc),
                       dt=float(md["dt"]), kT=float(md["kT"]), p_ext=float(md["p_ext"]),
@@ -483,10 +506,12 @@ class Batch:
         n = self.n_of[slot]
         pos = np.zeros((n, 3))
         mom = np.zeros((n, 3))
-        h = np.zeros(24)
-        _check(_lib.rbe_batch_read(self._ctx, int(slot), _hp(pos), _hp(mom), _hp(h)))
-        return dict(pos=pos, mom=mom, box=h[0:3].copy(), volume=h[3], err=int(h[19]),
-                    step=int(h[20]), state=h)
+        frc = np.zeros((n, 3))
+        h = np.zeros(32)
+        _check(_lib.rbe_batch_read(self._ctx, int(slot), _hp(pos), _hp(mom), _hp(frc), _hp(h)))
+        out = state_dict(h)
+        out.update(pos=pos, mom=mom, forces=frc)
+        return out
 
     def check(self, slot):
         _check(_lib.rbe_batch_check(self._ctx, int(slot)))

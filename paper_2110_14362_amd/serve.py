@@ -61,6 +61,8 @@ def make_requests(count, seed=2110143625, kinds=("ions",), nmin=1000, nmax=20000
         s = workloads.serving_request(i, seed=seed, nmin=nmin, nmax=nmax, p=p, steps=steps,
                                       kinds=kinds)
         md = workloads.npt_real(s["box"], rc=s["rc"])
+        if s.get("rigid"):
+            md["rigid"] = s["rigid"]
         reqs.append(Request(i, 0.0, s, md, steps))
     return reqs
 

@@ -299,11 +299,52 @@ def serving_request(i, seed=2110143625, nmin=1000, nmax=200000, p=100, steps=20,
     L = (n / CHARGES_PER_A3 / np.prod(aspect)) ** (1.0 / 3.0)
     box = aspect * L
     if kind == "water":
-        s = water(n_mol, box=box, seed=sub)
+        s = rigid_water(n_mol, box, seed=sub)
     else:
         s = ions(n, box, seed=sub)
     rc_i = min(rc, float(box.min()) / 3.3)
     g_i = g_ewald * rc / rc_i
     s.update(alpha=g_i ** 2, g=g_i, rc=rc_i, p=p, coulomb=COULOMB_REAL, kind=kind, steps=steps,
              request=i, seed=sub)
+    return s
+
+
+# SPC/E oxygen-oxygen Lennard-Jones (sigma 3.166 A, epsilon 0.650 kJ/mol)
+SPCE_SIGMA, SPCE_EPS = 3.166, 0.1553   # A, kcal/mol
+D_OH = R_OH
+D_HH = 2.0 * R_OH * math.sin(0.5 * THETA_HOH)
+
+
+def water_lj(n_atoms, first=0, n_mol=None):
+    """Types (O = 0, H = 1, anything before `first` = 2) and the LJ table
+    lj[ti][tj] = (c12, c6) with only the O-O pair non-zero."""
+    if n_mol is None:
+        n_mol = (n_atoms - first) // 3
+    types = np.full(n_atoms, 2, dtype=np.int32)
+    types[first:first + 3 * n_mol] = np.tile([0, 1, 1], n_mol)
+    lj = np.zeros((3, 3, 2))
+    lj[0, 0] = (4.0 * SPCE_EPS * SPCE_SIGMA ** 12, 4.0 * SPCE_EPS * SPCE_SIGMA ** 6)
+    return types, lj
+
+
+def whole_molecules(pos, box, first, n_mol):
+    """Positions with every rigid molecule's H atoms moved to the image
+    nearest its O (the constraint solvers need whole molecules)."""
+    pos = np.array(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    o = pos[first:first + 3 * n_mol:3]
+    for j in (1, 2):
+        h = pos[first + j:first + 3 * n_mol:3]
+        d = h - o
+        pos[first + j:first + 3 * n_mol:3] = o + d - box * np.rint(d / box)
+    return pos
+
+
+def rigid_water(n_mol, box=None, seed=2):
+    """water() with whole molecules (H atoms beside their O, not wrapped),
+    SPC/E O-O Lennard-Jones types and the rigid-molecule description."""
+    s = water(n_mol, box=box, seed=seed)
+    s["pos"] = whole_molecules(s["pos"], s["box"], 0, n_mol)
+    types, lj = water_lj(3 * n_mol)
+    s.update(types=types, lj=lj, rigid=dict(first=0, count=n_mol, d_oh=D_OH, d_hh=D_HH))
     return s

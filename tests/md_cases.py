@@ -29,14 +29,16 @@ def oracle_trajectory(sysd, md, momenta, steps, seed, system_id):
     mode = "iso" if md.get("box_mode", "iso") == "iso" else "semi"
     st = oint.NPTState(mode, sysd["box"], (md["mass_cell"], md.get("mass_cell_z", 0.0)))
     integ = oint.LangevinNPT(mode, None, md["dt"], md["kT"], md["p_ext"], md["gamma_p"],
-                             md["gamma_cell"], md["ftm"], seed, system_id)
+                             md["gamma_cell"], md["ftm"], seed, system_id,
+                             rigid=md.get("rigid"))
     m = np.asarray(sysd["mass"], dtype=np.float64)
     r = np.asarray(sysd["pos"], dtype=np.float64).copy()
     p = np.asarray(momenta, dtype=np.float64).copy()
     F, W = oracle_forces(sysd, md, r, st.box(), INIT_STEP, seed, system_id)
-    st.P_ins = integ.pressure(st, p, m, W)
+    p = integ.project(r, p, m)
+    st.P_ins = integ.pressure(st, p, m, W, r, F)
     for s in range(steps):
         r, p = integ.first_half(st, r, p, m, F, s)
         F, W = oracle_forces(sysd, md, r, st.box(), s, seed, system_id)
-        p = integ.second_half(st, p, m, F, W)
+        p = integ.second_half(st, p, m, F, W, r)
     return dict(pos=r, mom=p, box=st.box(), state=st)

@@ -10,6 +10,14 @@ from tests.md_cases import oracle_trajectory
 pytestmark = pytest.mark.gpu
 
 
+def o_kin(o_state, mom, md, s):
+    # molecular kinetic tensor of the device momenta (centre-of-mass part)
+    from oracle import constraints as cons
+    rg = md["rigid"]
+    mol = cons.molecules(rg["first"], rg["count"])
+    return cons.molecular_kinetic(mom, np.asarray(s["mass"]), mol) / md["ftm"]
+
+
 def electrolyte_setup():
     s = workloads.make("electrolyte_1k")
     md = dict(dt=0.005, kT=1.0, p_ext=0.1, gamma_p=1.0, gamma_cell=1.0,
@@ -37,10 +45,24 @@ def aspect_setup():
     return s, md, mom
 
 
-@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup])
+def rigid_water_setup():
+    # rigid SPC/E-shaped water (150 molecules), O-O Lennard-Jones, real units
+    s = workloads.rigid_water(150, seed=31)
+    rc = float(s["box"].min()) / 3.2
+    g = 3.0 / rc
+    s.update(alpha=g * g, p=100, coulomb=workloads.COULOMB_REAL)
+    md = workloads.npt_real(s["box"], rc=rc)
+    md.update(types=s["types"], lj=s["lj"], rigid=s["rigid"])
+    mom = None
+    return s, md, mom
+
+
+@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup, rigid_water_setup])
 def test_npt_trajectory_matches_oracle(gpu, setup):
     from paper_2110_14362_amd.md import NPTSystem
     s, md, mom = setup()
+    if mom is None:
+        mom = np.zeros_like(s["pos"])
     steps = 10
     sysg = NPTSystem(s, md, precision="fp64", seed=99, system_id=5, momenta=mom)
     sysg.step(steps)
@@ -55,6 +77,14 @@ def test_npt_trajectory_matches_oracle(gpu, setup):
     assert dpos < 1e-8 and dmom < 1e-8 and dbox < 1e-10
     # the cell moved: the barostat is live
     assert np.abs(o["box"] - np.asarray(s["box"])).max() > 1e-8
+    if md.get("rigid"):
+        x = g["pos"]
+        rg = md["rigid"]
+        o, h1, h2 = x[0::3], x[1::3], x[2::3]
+        for a, b, d in ((o, h1, rg["d_oh"]), (o, h2, rg["d_oh"]), (h1, h2, rg["d_hh"])):
+            assert np.abs(np.linalg.norm(a - b, axis=1) - d).max() < 1e-12
+        np.testing.assert_allclose(g["kinetic"], o_kin(o_state=o, mom=g["mom"], md=md, s=s),
+                                   rtol=1e-8, atol=1e-12)
     if md["box_mode"] == "semiiso":
         assert g["box"][0] == g["box"][1]
     else:

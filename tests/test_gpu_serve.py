@@ -15,7 +15,8 @@ BUDGET = 4 << 30
 
 
 def request(i, n, **kw):
-    r = serve.make_requests(1, seed=7000 + i, nmin=n, nmax=n, steps=kw.pop("steps", 4), **kw)[0]
+    r = serve.make_requests(1, seed=7000 + i, nmin=n, nmax=n, steps=kw.pop("steps", 4),
+                            kinds=kw.pop("kinds", ("ions",)), **kw)[0]
     r.rid = i
     r.desc.system_id = i
     return r
@@ -34,7 +35,7 @@ def run_alone(r, steps, fused=True, precision="fp32"):
 
 
 def test_alone_equals_mix_bitwise(gpu):
-    reqs = [request(0, 1500), request(1, 4000), request(2, 9000)]
+    reqs = [request(0, 1500), request(1, 4000, kinds=("water",)), request(2, 9000)]
     print("sizes", [r.n for r in reqs], "boxes", [r.sysd["box"].round(2).tolist() for r in reqs],
           flush=True)
     b = Batch(BUDGET, max_systems=8, precision="fp32")
@@ -52,6 +53,7 @@ def test_alone_equals_mix_bitwise(gpu):
         mix[r.rid] = (b.read(s), b.slot_step(s))
     b.close()
     assert mix[0][1] == 5 and mix[2][1] == 3
+    assert mix[1][0]["rigid_count"] == reqs[1].n // 3
     for r in reqs:
         got, steps = mix[r.rid]
         for fused in (True, False):
@@ -76,18 +78,19 @@ def test_served_equals_one_system_api(gpu):
     np.testing.assert_array_equal(g["mom"], ref["mom"])
 
 
-def test_served_trajectory_matches_oracle(gpu):
-    r = request(4, 1000)
+@pytest.mark.parametrize("kind", ["ions", "water"])
+def test_served_trajectory_matches_oracle(gpu, kind):
+    r = request(4, 1000, kinds=(kind,))
     steps = 3
     got = run_alone(r, steps, precision="fp64")
-    md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"])
+    md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"], rigid=r.sysd.get("rigid"))
     o = oracle_trajectory(r.sysd, md, np.zeros((r.n, 3)), steps, seed=r.desc.seed,
                           system_id=r.desc.system_id)
     dpos = np.abs(got["pos"] - o["pos"]).max()
     dmom = np.abs(got["mom"] - o["mom"]).max() / np.abs(o["mom"]).max()
     dbox = np.abs(got["box"] - o["box"]).max() / o["box"].max()
-    print("served N=%d: max |dr| %.2e, rel |dp| %.2e, rel |dl| %.2e" % (r.n, dpos, dmom, dbox),
-          flush=True)
+    print("served %s N=%d: max |dr| %.2e, rel |dp| %.2e, rel |dl| %.2e"
+          % (kind, r.n, dpos, dmom, dbox), flush=True)
     assert dpos < 1e-9 and dmom < 1e-9 and dbox < 1e-11
 
 
@@ -111,7 +114,8 @@ def test_admission_respects_budget(gpu):
 
 
 def test_served_stream_runs(gpu):
-    reqs = serve.make_requests(12, seed=9100, nmin=1000, nmax=20000, steps=5)
+    reqs = serve.make_requests(12, seed=9100, nmin=1000, nmax=20000, steps=5,
+                               kinds=("ions", "water"))
     for r, t in zip(reqs, serve.poisson_arrivals(len(reqs), rate=400.0)):
         r.arrival = float(t)
     b = Batch(BUDGET, max_systems=16, precision="fp32")
