@@ -171,7 +171,7 @@ const T* put(rbe_batch_s* b, const T* src, size_t count) {
 }
 
 size_t stage_bytes_per_system() {
-  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 7 * sizeof(int) + 7 * 64;
+  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 8 * sizeof(int) + 8 * 64;
 }
 
 }  // namespace
@@ -353,18 +353,21 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   // pair kernels: 256 particles per block; integrator: 256 units (rigid
   // molecules or free atoms) per block; cell sort: one block per cell of
   // the capacity
-  std::vector<int> pb(nsys), ub(nsys), cb(nsys);
+  std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys);
   for (int j = 0; j < nsys; ++j) {
     pb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
     ub[j] = (int)((md_units(md1[j]) + 255) / 256);
     cb[j] = ncap[j];
+    qb[j] = (int)pair_blocks(b->slots[act[j]].desc.n);
   }
-  const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb);
+  const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb),
+                         qstart = prefix(qb);
   const MDArgs* d_md1 = put(b, md1.data(), nsys);
   const MDArgs* d_md2 = put(b, md2.data(), nsys);
   const RealArgs* d_ra = put(b, ra.data(), nsys);
   const int* d_pstart = put(b, pstart.data(), nsys + 1);
   const int* d_ustart = put(b, ustart.data(), nsys + 1);
+  const int* d_qstart = put(b, qstart.data(), nsys + 1);
   const int* d_cstart = put(b, cstart.data(), nsys + 1);
   // structure factors grouped by lane width, forces by block shape
   struct Group { std::vector<int> idx; const StepArgs* tab; const int* start; int total; size_t lds; };
@@ -404,7 +407,8 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
       e = launch_force_multi(prec, kv.first, kv.second.tab, kv.second.start, (int)kv.second.idx.size(),
                              kv.second.total, b->stream);
   if (e == hipSuccess)
-    e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), nsys, b->stream);
+    e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
+                          qstart.back(), nsys, b->stream);
   if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
   b->cur ^= 1;
   b->steps_launched++;

@@ -7,21 +7,34 @@
 //   k_scan    exclusive scan of the cell counts (one block), counts cleared
 //   k_fill    scatter particle indices into their cells
 //   k_csort   per cell: sort the member indices (bitonic, LDS) so every sum
-//             below has a fixed order, and gather positions/charges/types
-//             into cell order
-//   k_pairs   one lane per particle (in cell order): the 27 neighbour cells,
-//             forces, and per-block energy/virial partials summed in a
-//             fixed order by the last-arriving block
+//             below has a fixed order, and gather positions (wrapped into
+//             the cell, consistently with the binning)/charges/types into
+//             cell order
+//   k_pairs   a wave per particle i at a time (in cell order): its lanes
+//             test 64 candidates j of the 27 neighbour cells at once (each
+//             neighbour cell's periodic shift applied to i once), append the
+//             pairs inside the cutoff to a wave-private LDS queue, and
+//             evaluate the queue 64 pairs at a time with every lane busy;
+//             the force on i is a fixed-order wave sum per batch, energy and
+//             virial are per-lane sums reduced in a fixed order by the
+//             last-arriving block
 #include "rbe_real_internal.h"
+#include "erfcx_cheb.h"
 #include <math.h>
 
 namespace rbe {
 
-__device__ __forceinline__ int cell_coord(double x, double inv_l, int nc) {
-  double s = x * inv_l;
-  s -= floor(s);
-  int c = (int)(s * nc);
+// fractional coordinate in [0, 1] (1 only by rounding) and its cell
+__device__ __forceinline__ double frac_coord(double x, double inv_l) {
+  const double s = x * inv_l;
+  return s - floor(s);
+}
+__device__ __forceinline__ int cell_of(double s, int nc) {
+  const int c = (int)(s * nc);
   return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+__device__ __forceinline__ int cell_coord(double x, double inv_l, int nc) {
+  return cell_of(frac_coord(x, inv_l), nc);
 }
 
 __device__ __forceinline__ void real_box(const RealArgs& a, double l[3]) {
@@ -119,12 +132,21 @@ __device__ __forceinline__ void csort_body(const RealArgs& a, int c) {
       __syncthreads();
     }
   }
+  double l[3];
+  real_box(a, l);
   for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
     const int i = key[k];
     const int d = s0 + k;
     a.list[d] = i;
-    a.xs[d] = a.x[i]; a.ys[d] = a.y[i]; a.zs[d] = a.z[i];
-    a.qs[d] = a.q[i];
+    // wrapped with the binning's own fractional coordinate, so a particle
+    // lies in (or on the boundary of) the cell it was binned into
+    double4 v;
+    v.x = frac_coord(a.x[i], 1.0 / l[0]) * l[0];
+    v.y = frac_coord(a.y[i], 1.0 / l[1]) * l[1];
+    v.z = frac_coord(a.z[i], 1.0 / l[2]) * l[2];
+    v.w = a.q[i];
+    a.xq[d] = v;
+    a.xf[d] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
     a.ts[d] = a.type ? a.type[i] : 0;
     a.cs[d] = c;
   }
@@ -136,63 +158,217 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Accepted pairs of one wave: cell-ordered index of j and the periodic shift
+// it was seen through (3 trits); the erfcx coefficients (a copy per wave).
+struct PairQueue {
+  int j[kPairQueue];
+  int s[kPairQueue];
+  double cheb[kErfcxTerms];
+};
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0 from its Chebyshev series in
+// t = (x - K)/(x + K) (Clenshaw); erfc(x) = exp(-x^2) erfcx(x) then shares
+// exp(-x^2) with the force term.  The coefficients are read from LDS, which
+// keeps them out of the scalar registers.
+__device__ __forceinline__ double erfcx_pos(double x, const double* cheb) {
+  const double t = (x - kErfcxK) / (x + kErfcxK), t2 = 2.0 * t;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = kErfcxTerms - 1; k >= 1; --k) {
+    const double b0 = fma(t2, b1, cheb[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(t, b1, cheb[0] - b2);
+}
+
+// A queued pair as loaded for evaluation: j's position and charge, its
+// type, and the shift code.
+struct PairLoad {
+  double4 v;
+  int tj, code;
+};
+
+__device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue& Q, int e) {
+  PairLoad p;
+  const int j = Q.j[e];
+  p.code = Q.s[e];
+  p.v = a.xq[j];
+  p.tj = a.ntypes > 0 ? a.ts[j] : 0;
+  return p;
+}
+
+// Evaluate one loaded pair per lane (lanes with valid = false add nothing):
+// the force on i is added as a wave sum (the same value in every lane, summed
+// in a fixed order); energy and virial accumulate per lane.
+__device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
+                                          const double4& vi, int ti, const double l[3], double sa,
+                                          double two_sa_pi, const double* cheb, double f[3],
+                                          double& u, double w[6]) {
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  if (valid) {
+    const double4 v = p.v;
+    const int code = p.code;
+    // the same arithmetic as the candidate test
+    const double ex = v.x - (vi.x - l[0] * (double)(code % 3 - 1));
+    const double ey = v.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1));
+    const double ez = v.z - (vi.z - l[2] * (double)(code / 9 - 1));
+    const double r2 = ex * ex + ey * ey + ez * ez;
+    const double r = sqrt(r2), ir = 1.0 / r;
+    // Coulomb: phi = C qi qj erfc(sa r)/r,  -phi' = C qi qj G(r)
+    const double qq = a.coulomb * vi.w * v.w;
+    const double g2 = exp(-a.alpha * r2);
+    const double er = g2 * erfcx_pos(sa * r, cheb);
+    double dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
+    u += qq * er * ir;
+    if (a.ntypes > 0) {
+      const int k = ti * a.ntypes + p.tj;
+      const double c12 = a.lj[2 * k], c6 = a.lj[2 * k + 1];
+      const double i2 = ir * ir, i6 = i2 * i2 * i2;
+      u += c12 * i6 * i6 - c6 * i6;
+      dU += (-12.0 * c12 * i6 * i6 + 6.0 * c6 * i6) * ir;
+    }
+    // force on i: U'(r) x/r;  virial: (1/2) (-U'(r)) x x^T / r per ordered pair
+    const double g = dU * ir;
+    gx = g * ex; gy = g * ey; gz = g * ez;
+    w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
+    w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
+  }
+  f[0] += wsum(gx);
+  f[1] += wsum(gy);
+  f[2] += wsum(gz);
+}
+
+// The 27 neighbour cells of cell (cx, cy, cz) as 9 rows of three cells along
+// x; a row is one contiguous range of the cell-ordered arrays unless it
+// wraps in x, then two.  Segment `seg` (0..17) of that list: the cell range
+// [c0, c1] and the periodic shift code; false if the segment is empty.
+__device__ __forceinline__ bool neighbour_segment(int seg, int cx, int cy, int cz, int nx, int ny,
+                                                  int nz, int& c0, int& c1, int& code) {
+  const int row = seg >> 1, half = seg & 1;
+  const int dz = row / 3 - 1, dy = row % 3 - 1;
+  int zz = cz + dz, yy = cy + dy, kz = 1, ky = 1, kx = 1;
+  if (zz < 0) { zz += nz; kz = 0; } else if (zz >= nz) { zz -= nz; kz = 2; }
+  if (yy < 0) { yy += ny; ky = 0; } else if (yy >= ny) { yy -= ny; ky = 2; }
+  int x0, x1;
+  if (cx == 0) {
+    if (half == 0) { x0 = x1 = nx - 1; kx = 0; } else { x0 = 0; x1 = 1; }
+  } else if (cx == nx - 1) {
+    if (half == 0) { x0 = nx - 2; x1 = nx - 1; } else { x0 = x1 = 0; kx = 2; }
+  } else {
+    if (half == 1) return false;
+    x0 = cx - 1; x1 = cx + 1;
+  }
+  const int rbase = (zz * ny + yy) * nx;
+  c0 = rbase + x0;
+  c1 = rbase + x1;
+  code = (kz * 3 + ky) * 3 + kx;
+  return true;
+}
+
 __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
-  __shared__ double sh[4][8];
+  __shared__ PairQueue queue[kPairWaves];
+  __shared__ double sh[kPairWaves][8];
   __shared__ int sh_last;
-  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  PairQueue& Q = queue[wave];
+  if (lane < kErfcxTerms) Q.cheb[lane] = kErfcxCheb[lane];
+  wave_sync();
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   double l[3];
   real_box(a, l);
   const int nx = a.grid[0], ny = a.grid[1], nz = a.grid[2];
   const double rc2 = a.rc * a.rc, sa = sqrt(a.alpha);
   const double two_sa_pi = 2.0 * sa / sqrt(M_PI);
-  double fx = 0, fy = 0, fz = 0, u = 0, w[6] = {0, 0, 0, 0, 0, 0};
-  if (t < a.n) {
-    const double xi = a.xs[t], yi = a.ys[t], zi = a.zs[t], qi = a.qs[t];
-    const int ti = a.ts[t];
-    const int c = a.cs[t];
+  // FP32 positions in [0, l] carry an error below 2^-24 l each; a squared
+  // separation below rc then errs by less than 8 rc 2^-24 lmax + O(2^-48):
+  // outside [rc2_lo, rc2_hi] the FP32 test decides as FP64 would
+  const double lmax = fmax(l[0], fmax(l[1], l[2]));
+  const double band = 16.0 * a.rc * lmax * 0x1.0p-24 + 8.0 * lmax * lmax * 0x1.0p-48;
+  const float rc2_lo = (float)(rc2 - band), rc2_hi = (float)(rc2 + band);
+  double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < kPairPerWave; ++k) {
+    const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);   // the wave's i
+    if (t >= a.n) break;
+    const double4 vi = a.xq[t];
+    const int ti = uniform(a.ts[t]);
+    const int c = uniform(a.cs[t]);
     const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int zz = (cz + dz + nz) % nz;
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = (cy + dy + ny) % ny;
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = (cx + dx + nx) % nx;
-          const int cc = (zz * ny + yy) * nx + xx;
-          const int j0 = a.start[cc], j1 = a.start[cc + 1];
-          for (int j = j0; j < j1; ++j) {
-            if (j == t) continue;
-            double ex = a.xs[j] - xi, ey = a.ys[j] - yi, ez = a.zs[j] - zi;
-            ex -= l[0] * rint(ex / l[0]);
-            ey -= l[1] * rint(ey / l[1]);
-            ez -= l[2] * rint(ez / l[2]);
-            const double r2 = ex * ex + ey * ey + ez * ez;
-            if (r2 >= rc2) continue;
-            const double r = sqrt(r2), ir = 1.0 / r;
-            // Coulomb: phi = C qi qj erfc(sa r)/r,  -phi' = C qi qj G(r)
-            const double qq = a.coulomb * qi * a.qs[j];
-            const double er = erfc(sa * r);
-            double dU = -qq * (er * ir * ir + two_sa_pi * exp(-a.alpha * r2) * ir);   // U'(r)
-            u += qq * er * ir;
-            if (a.ntypes > 0) {
-              const int k = ti * a.ntypes + a.ts[j];
-              const double c12 = a.lj[2 * k], c6 = a.lj[2 * k + 1];
-              const double i2 = ir * ir, i6 = i2 * i2 * i2;
-              u += c12 * i6 * i6 - c6 * i6;
-              dU += (-12.0 * c12 * i6 * i6 + 6.0 * c6 * i6) * ir;
-            }
-            // force on i: U'(r) x/r;  virial: (1/2) (-U'(r)) x x^T / r per ordered pair
-            const double g = dU * ir;
-            fx += g * ex; fy += g * ey; fz += g * ez;
-            w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
-            w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
+    double f[3] = {0.0, 0.0, 0.0};
+    int qn = 0;                                   // queued pairs (wave-uniform)
+    // Alternate between testing candidates into the queue until it is
+    // nearly full (or the candidates are exhausted) and evaluating the
+    // queue, so the two phases' registers are never live together.
+    int seg = -1, jb = 0, j1 = 0, code = 0;       // resume point of the test phase
+    double xo = 0.0, yo = 0.0, zo = 0.0;          // i seen from the segment's image
+    float xf = 0.0f, yf = 0.0f, zf = 0.0f;        // the same in FP32
+    bool done = false;
+    while (!done) {
+      while (qn <= kPairQueue - 64) {
+        if (jb >= j1) {                           // next non-empty segment
+          int c0 = 0, c1 = -1;
+          do {
+            ++seg;
+          } while (seg < 18 && !neighbour_segment(seg, cx, cy, cz, nx, ny, nz, c0, c1, code));
+          if (seg >= 18) { done = true; break; }
+          jb = uniform(a.start[c0]);
+          j1 = uniform(a.start[c1 + 1]);
+          xo = vi.x - l[0] * (double)(code % 3 - 1);
+          yo = vi.y - l[1] * (double)((code / 3) % 3 - 1);
+          zo = vi.z - l[2] * (double)(code / 9 - 1);
+          xf = (float)xo; yf = (float)yo; zf = (float)zo;
+          continue;
+        }
+        const int j = jb + lane;
+        bool acc = false;
+        if (j < j1 && j != t) {
+          // FP32 test; pairs within the FP32 error band of the cutoff are
+          // decided in FP64, so the accepted set is the FP64 one
+          const float4 v = a.xf[j];
+          const float ex = v.x - xf, ey = v.y - yf, ez = v.z - zf;
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          if (r2 < rc2_lo) acc = true;
+          else if (r2 <= rc2_hi) {
+            const double4 d = a.xq[j];
+            const double dx = d.x - xo, dy = d.y - yo, dz = d.z - zo;
+            acc = dx * dx + dy * dy + dz * dz < rc2;
           }
         }
+        const uint64_t bal = __ballot(acc);
+        if (acc) {
+          const int pos = qn + __popcll(bal & below);
+          Q.j[pos] = j;
+          Q.s[pos] = code;
+        }
+        qn += __popcll(bal);
+        jb += 64;
       }
+      // evaluate: every full batch, and the last partial one when done
+      wave_sync();
+      const int m = done ? qn : (qn & ~63);
+      for (int from = 0; from < m; from += 64) {
+        PairLoad cur;
+        if (from + lane < m) cur = pair_load(a, Q, from + lane);
+        pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.cheb, f, u, w);
+      }
+      wave_sync();
+      if (lane < qn - m) { Q.j[lane] = Q.j[m + lane]; Q.s[lane] = Q.s[m + lane]; }
+      wave_sync();
+      qn -= m;
     }
-    const int i = a.list[t];
-    if (a.accumulate) { a.fx[i] += fx; a.fy[i] += fy; a.fz[i] += fz; }
-    else { a.fx[i] = fx; a.fy[i] = fy; a.fz[i] = fz; }
+    if (lane == 0) {
+      const int i = a.list[t];
+      if (a.accumulate) { a.fx[i] += f[0]; a.fy[i] += f[1]; a.fz[i] += f[2]; }
+      else { a.fx[i] = f[0]; a.fy[i] = f[1]; a.fz[i] = f[2]; }
+    }
   }
   // block partial of (U, W), fixed order: wave sums, then waves in order
   double v[7] = {u, w[0], w[1], w[2], w[3], w[4], w[5]};
@@ -202,7 +378,8 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   }
   __syncthreads();
   if (threadIdx.x < 7) {
-    const double s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+    double s = 0.0;
+    for (int q = 0; q < kPairWaves; ++q) s += sh[q][threadIdx.x];
     __hip_atomic_store(&a.part[bx * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0);
@@ -211,11 +388,20 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
     sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
   __syncthreads();
   if (!sh_last) return;
-  // the last block: sum the block partials in block order (thread k: component k)
+  // the last block: sum the block partials in a fixed order, 32 strided
+  // chunks per component in parallel, then the chunks in order
+  __shared__ double red[7][33];
+  if (threadIdx.x < 7 * 32) {
+    const int k = threadIdx.x / 32, ch = threadIdx.x % 32;
+    double s = 0.0;
+    for (int b = ch; b < nbx; b += 32)
+      s += __hip_atomic_load(&a.part[b * 8 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    red[k][ch] = s;
+  }
+  __syncthreads();
   if (threadIdx.x < 7) {
     double s = 0.0;
-    for (int b = 0; b < nbx; ++b)
-      s += __hip_atomic_load(&a.part[b * 8 + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int ch = 0; ch < 32; ++ch) s += red[threadIdx.x][ch];
     if (threadIdx.x == 0) { if (a.energy) a.energy[0] = 0.5 * s; }
     else if (a.virial6) a.virial6[threadIdx.x - 1] = 0.5 * s;
   }
@@ -226,7 +412,9 @@ __global__ void __launch_bounds__(256) k_bin(RealArgs a) { bin_body(a, blockIdx.
 __global__ void __launch_bounds__(1024) k_scan(RealArgs a) { scan_body(a); }
 __global__ void __launch_bounds__(256) k_fill(RealArgs a) { fill_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(256) k_csort(RealArgs a) { csort_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_pairs(RealArgs a) { pairs_body(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(kPairWaves * 64) k_pairs(RealArgs a) {
+  pairs_body(a, blockIdx.x, gridDim.x);
+}
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   const unsigned pb = (unsigned)((a.n + 255) / 256);
@@ -234,7 +422,7 @@ hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_pairs, dim3(pb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_pairs, dim3((unsigned)pair_blocks(a.n)), dim3(kPairWaves * 64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -282,19 +470,22 @@ __global__ void __launch_bounds__(256) k_csort_m(const RealArgs* tab, const int*
   (void)nb;
   csort_body(sa, lb);
 }
-__global__ void __launch_bounds__(256) k_pairs_m(const RealArgs* tab, const int* bstart, int nsys) {
+__global__ void __launch_bounds__(kPairWaves * 64) k_pairs_m(const RealArgs* tab, const int* bstart,
+                                                             int nsys) {
   REAL_MULTI_PROLOGUE
   pairs_body(sa, lb, nb);
 }
 
-// bstart_p: per-particle blocks (256 particles each); bstart_c: cell blocks
+// bstart_p: per-particle blocks (256 particles each); bstart_c: cell blocks;
+// bstart_q: pair blocks (pair_blocks(n) each)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
-                             const int* d_bstart_c, int total_c, int nsys, hipStream_t s) {
+                             const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
+                             int nsys, hipStream_t s) {
   hipLaunchKernelGGL(k_bin_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_scan_m, dim3(nsys), dim3(1024), 0, s, d_tab, nsys);
   hipLaunchKernelGGL(k_fill_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
-  hipLaunchKernelGGL(k_pairs_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
+  hipLaunchKernelGGL(k_pairs_m, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
   return hipGetLastError();
 }
 

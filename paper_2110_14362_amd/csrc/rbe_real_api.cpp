@@ -86,11 +86,11 @@ int64_t real_footprint(const rbe_real_config* cfg, const double* box) {
     if (v < 3) v = 3;
     cap *= v;
   }
-  const int64_t n = cfg->n, blocks = (n + 255) / 256;
+  const int64_t n = cfg->n, blocks = pair_blocks(n);
   auto r = [](int64_t b) { return (b + 16 + 255) / 256 * 256; };
   int64_t t = r(8 * n);
   if (cfg->ntypes > 0) t += r(4 * n) + r(16 * (int64_t)cfg->ntypes * cfg->ntypes);
-  t += r(4 * n) + r(4 * cap) + r(4 * (cap + 1)) + r(4 * cap) + r(4 * n) + 4 * r(8 * n) + 2 * r(4 * n) +
+  t += r(4 * n) + r(4 * cap) + r(4 * (cap + 1)) + r(4 * cap) + r(4 * n) + r(32 * n) + r(16 * n) + 2 * r(4 * n) +
        r(16) + r(64 * blocks) + r(4) + r(4);
   return t;
 }
@@ -132,7 +132,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
     if (st != RBE_OK) { delete c; return st; }
   }
   c->ncell_cap = (int)cap;
-  c->nblocks = (int)((cfg->n + 255) / 256);
+  c->nblocks = (int)pair_blocks(cfg->n);
   const size_t n = (size_t)cfg->n;
   bool ok = true;
   double* dq = nullptr; int32_t* dt = nullptr; double* dlj = nullptr;
@@ -143,8 +143,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
   }
   ok = ok && ralloc(c, &a.cellof, n) && ralloc(c, &a.count, (size_t)cap) &&
        ralloc(c, &a.start, (size_t)cap + 1) && ralloc(c, &a.cursor, (size_t)cap) &&
-       ralloc(c, &a.list, n) && ralloc(c, &a.xs, n) && ralloc(c, &a.ys, n) && ralloc(c, &a.zs, n) &&
-       ralloc(c, &a.qs, n) && ralloc(c, &a.ts, n) && ralloc(c, &a.cs, n) &&
+       ralloc(c, &a.list, n) && ralloc(c, &a.xq, n) && ralloc(c, &a.xf, n) && ralloc(c, &a.ts, n) && ralloc(c, &a.cs, n) &&
        ralloc(c, &a.grid, 4) && ralloc(c, &a.part, (size_t)c->nblocks * 8) &&
        ralloc(c, &a.cnt, 1) && ralloc(c, &a.err, 1);
   if (!ok) { rfree(c); delete c; return rfail(RBE_ERR_ALLOC, "device allocation failed"); }

@@ -8,6 +8,14 @@ namespace rbe {
 
 constexpr int kCellMax = 2048;     // members of one cell the sort kernel can order
 constexpr int kCellAxisMax = 64;   // cells per axis
+constexpr int kPairWaves = 4;      // pair kernel: waves per block
+constexpr int kPairPerWave = 1;    // particles i a wave takes in turn
+constexpr int kPairPerBlock = kPairWaves * kPairPerWave;
+constexpr int kPairQueue = 512;    // accepted-pair queue of a wave
+
+__host__ __device__ inline int64_t pair_blocks(int64_t n) {
+  return (n + kPairPerBlock - 1) / kPairPerBlock;
+}
 
 struct RealArgs {
   const double* x; const double* y; const double* z;
@@ -23,16 +31,19 @@ struct RealArgs {
   int32_t nc_cap[3];
   // scratch (context-owned)
   int32_t* cellof; int32_t* count; int32_t* start; int32_t* cursor; int32_t* list;
-  double* xs; double* ys; double* zs; double* qs; int32_t* ts; int32_t* cs;
+  double4* xq;                             // cell order: wrapped x, y, z and q
+  float4* xf;                              // the same positions in FP32 (candidate tests)
+  int32_t* ts; int32_t* cs;
   int32_t* grid;                           // cells per axis of the last binning
-  double* part;                            // [blocks][8]
+  double* part;                            // [pair_blocks(n)][8]
   uint32_t* cnt;
   int32_t* err;                            // bit 1: rc > l/3 or cell cap; bit 2: cell overflow
 };
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
-                             const int* d_bstart_c, int total_c, int nsys, hipStream_t s);
+                             const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
+                             int nsys, hipStream_t s);
 
 // host side of rbe_real_forces without the launches
 rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,
