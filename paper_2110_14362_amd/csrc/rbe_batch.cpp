@@ -350,12 +350,12 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
     for (size_t i = 0; i < cnt.size(); ++i) o[i + 1] = o[i] + cnt[i];
     return o;
   };
-  // pair kernels: 256 particles per block; integrator: 256 units (rigid
+  // binning kernels: bin_blocks(n); pairs: pair_blocks(n); integrator: 256 units (rigid
   // molecules or free atoms) per block; cell sort: one block per cell of
   // the capacity
   std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys);
   for (int j = 0; j < nsys; ++j) {
-    pb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
+    pb[j] = (int)bin_blocks(b->slots[act[j]].desc.n);
     ub[j] = (int)((md_units(md1[j]) + 255) / 256);
     cb[j] = ncap[j];
     qb[j] = (int)pair_blocks(b->slots[act[j]].desc.n);

@@ -52,20 +52,39 @@ __device__ __forceinline__ void cell_grid(const RealArgs& a, const double l[3], 
   }
 }
 
+// A block bins kBinPer particles; with at most kBinLds cells it counts them
+// in LDS first and adds one total per cell to the global counts (far fewer
+// contended global atomics).
 __device__ __forceinline__ void bin_body(const RealArgs& a, int bx) {
-  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  __shared__ int hist[kBinLds];
   double l[3];
   real_box(a, l);
   int nc[3], err = 0;
   cell_grid(a, l, nc, err);
-  const int cx = cell_coord(a.x[i], 1.0 / l[0], nc[0]);
-  const int cy = cell_coord(a.y[i], 1.0 / l[1], nc[1]);
-  const int cz = cell_coord(a.z[i], 1.0 / l[2], nc[2]);
-  const int c = (cz * nc[1] + cy) * nc[0] + cx;
-  a.cellof[i] = c;
-  atomicAdd(&a.count[c], 1);
-  if (i == 0 && err) atomicOr(a.err, err);
+  const int ncell = nc[0] * nc[1] * nc[2];
+  const bool lds = ncell <= kBinLds;
+  if (lds) {
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+  }
+  const double il[3] = {1.0 / l[0], 1.0 / l[1], 1.0 / l[2]};
+  for (int k = 0; k < kBinPer; k += blockDim.x) {
+    const int64_t i = (int64_t)bx * kBinPer + k + threadIdx.x;
+    if (i >= a.n) break;
+    const int cx = cell_coord(a.x[i], il[0], nc[0]);
+    const int cy = cell_coord(a.y[i], il[1], nc[1]);
+    const int cz = cell_coord(a.z[i], il[2], nc[2]);
+    const int c = (cz * nc[1] + cy) * nc[0] + cx;
+    a.cellof[i] = c;
+    if (lds) atomicAdd(&hist[c], 1);
+    else atomicAdd(&a.count[c], 1);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x)
+      if (hist[c]) atomicAdd(&a.count[c], hist[c]);
+  }
+  if (bx == 0 && threadIdx.x == 0 && err) atomicOr(a.err, err);
 }
 
 __device__ __forceinline__ void scan_body(const RealArgs& a) {
@@ -102,11 +121,39 @@ __device__ __forceinline__ void scan_body(const RealArgs& a) {
   if (t == 0) a.grid[0] = nc[0], a.grid[1] = nc[1], a.grid[2] = nc[2];
 }
 
+// Scatter particle indices into their cells' ranges: with at most kBinLds
+// cells, ranks within the block come from LDS atomics and each cell's range
+// for the block from one global atomic.
 __device__ __forceinline__ void fill_body(const RealArgs& a, int bx) {
-  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int pos = atomicAdd(&a.cursor[a.cellof[i]], 1);
-  a.list[pos] = (int)i;
+  __shared__ int hist[kBinLds];
+  const int ncell = a.grid[0] * a.grid[1] * a.grid[2];
+  const bool lds = ncell <= kBinLds;
+  constexpr int kPer = kBinPer / 256;
+  int cell[kPer], rank[kPer];
+  if (lds) {
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t i = (int64_t)bx * kBinPer + k * 256 + threadIdx.x;
+    cell[k] = -1;
+    if (i < a.n) {
+      cell[k] = a.cellof[i];
+      rank[k] = lds ? atomicAdd(&hist[cell[k]], 1) : atomicAdd(&a.cursor[cell[k]], 1);
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x)
+      if (hist[c]) hist[c] = atomicAdd(&a.cursor[c], hist[c]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t i = (int64_t)bx * kBinPer + k * 256 + threadIdx.x;
+    if (cell[k] >= 0) a.list[(lds ? hist[cell[k]] : 0) + rank[k]] = (int)i;
+  }
 }
 
 // one block per cell: sort member indices, then gather in that order
@@ -417,7 +464,7 @@ __global__ void __launch_bounds__(kPairWaves * 64) k_pairs(RealArgs a) {
 }
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
-  const unsigned pb = (unsigned)((a.n + 255) / 256);
+  const unsigned pb = (unsigned)bin_blocks(a.n);
   hipLaunchKernelGGL(k_bin, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
@@ -476,7 +523,7 @@ __global__ void __launch_bounds__(kPairWaves * 64) k_pairs_m(const RealArgs* tab
   pairs_body(sa, lb, nb);
 }
 
-// bstart_p: per-particle blocks (256 particles each); bstart_c: cell blocks;
+// bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
 // bstart_q: pair blocks (pair_blocks(n) each)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,

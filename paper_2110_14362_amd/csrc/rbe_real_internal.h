@@ -13,6 +13,11 @@ constexpr int kPairPerWave = 1;    // particles i a wave takes in turn
 constexpr int kPairPerBlock = kPairWaves * kPairPerWave;
 constexpr int kPairQueue = 512;    // accepted-pair queue of a wave
 
+constexpr int kBinPer = 2048;      // particles a binning block takes (256 threads)
+constexpr int kBinLds = 8192;      // cells counted in LDS by the binning kernels
+
+__host__ __device__ inline int64_t bin_blocks(int64_t n) { return (n + kBinPer - 1) / kBinPer; }
+
 __host__ __device__ inline int64_t pair_blocks(int64_t n) {
   return (n + kPairPerBlock - 1) / kPairPerBlock;
 }
