@@ -6,7 +6,13 @@ One step = the whole Fourier-space hot path on one batch: cell update
 factors, their fixed-order reduction, virial tensor and energy, and forces
 (rbe_forces_pressure).  Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line (metric, value, ..., roofline, cpu_baseline).
+Beside it (default workload): ns/day of the full NPT step of the 30k-charge
+rigid water (Fourier part, real-space pairs, Langevin integrator with the
+rigid-molecule constraints), and a served mixed-size stream of NPT systems
+(p50/p99 step latency, aggregate (N*P)/s, fused vs one system at a time).
+
+Prints ONE JSON line (metric, value, ..., roofline, cpu_baseline, ns_per_day,
+served); progress notes go to stderr.
 """
 import argparse
 import json
@@ -39,6 +45,11 @@ def parse():
     ap.add_argument("--p", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--md-steps", type=int, default=300,
+                    help="timed full NPT steps for ns/day (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests of the served stream (0: skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 10 times (for scaling "
                          "the HBM byte counters of a profiler run) and exit")
@@ -114,6 +125,94 @@ def cpu_baseline(sysd, seconds):
             "sample": "%d full steps of %s (N=%d, P=%d): tables, draw, rho, virial, forces in "
                       "FP64 numpy, BLAS limited to 1 thread" % (reps, sysd["config"], N, P),
             "seconds": el}
+
+
+def note(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def md_ns_per_day(steps, precision, torch):
+    """Full NPT step of the 30k-charge rigid water (10,000 molecules at 1 g/cm^3,
+    L = 66.88 A, g = 0.3/A, r_c = 10 A, P = 100, 1 fs, 300 K, 1 atm): every
+    kernel of the step, one system, per-system launches."""
+    from paper_2110_14362_amd import workloads
+    from paper_2110_14362_amd.rbe import Batch, system_desc
+    c = workloads.CONFIGS["water_30k"]
+    s = workloads.rigid_water(c["n_mol"], seed=c["seed"])
+    g, rc = c["g"], c["rc"]
+    md = workloads.npt_real(s["box"], rc=rc)
+    md["rigid"] = s["rigid"]
+    n = len(s["q"])
+    desc = system_desc(n, c["p"], g * g, workloads.COULOMB_REAL, rc, md, ntypes=3, seed=1,
+                       system_id=1)
+    b = Batch(1 << 32, max_systems=1, precision=precision)
+    slot = b.admit(desc, s["pos"], s["q"], s["mass"], s["box"], types=s["types"], lj=s["lj"])
+    for _ in range(20):
+        b.step(fused=False)
+    b.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.step(fused=False)
+    b.sync()
+    el = time.perf_counter() - t0
+    b.check(slot)
+    st = b.read(slot)
+    b.close()
+    t_step = el / steps
+    return {"value": md["dt"] * 1e-6 * 86400.0 / t_step, "unit": "ns/day",
+            "ms_per_step": t_step * 1e3, "steps": steps, "dt_fs": md["dt"],
+            "workload": "rigid 3-site water, %d molecules, N = %d, box %.2f A, g = %.2f/A, "
+                        "r_c = %.0f A, P = %d, NPT 300 K / 1 atm" % (c["n_mol"], n, s["box"][0],
+                                                                   g, rc, c["p"]),
+            "step": "integrator first half | Fourier part (%s) | cell list + pairs (FP64) | "
+                    "integrator second half" % precision,
+            "final_box_A": float(st["box"][0])}
+
+
+def served_stream(nreq, budget_gib, precision):
+    """Served mixed-size NPT stream: requests of N log-uniform in [1e3, 2e5]
+    (half ions, half rigid water), cubic or 1:1:1.25 cells at 0.100284
+    charges/A^3, P = 100, 20 NPT steps each.  One system at a time, back to
+    back, first (the serial capacity); then Poisson arrivals at 0.8 of it,
+    served one system at a time (first come, first served) and with
+    continuous batching (fused launches); then all requests at once
+    (saturated, fused)."""
+    from paper_2110_14362_amd import serve
+    from paper_2110_14362_amd.rbe import Batch
+    reqs = serve.make_requests(nreq, kinds=("ions", "water"))
+    budget = int(budget_gib * (1 << 30))
+    b = Batch(budget, max_systems=1024, precision=precision)
+    warm = serve.make_requests(3, seed=77, kinds=("ions", "water"), nmin=2000, nmax=20000,
+                               steps=3)
+    serve.serve_serial(b, warm)
+    ser = serve.serve_serial(b, reqs)
+    note("served: serial %.2f s" % ser["wall_s"])
+    rate = 0.8 * nreq / ser["wall_s"]
+    arrivals = serve.poisson_arrivals(nreq, rate)
+    for r, t in zip(reqs, arrivals):
+        r.arrival, r.lat, r.done = float(t), [], 0
+    fifo = serve.serve(b, reqs, fused=False, max_active=1)
+    note("served: one at a time, Poisson %.2f s" % fifo["wall_s"])
+    for r, t in zip(reqs, arrivals):
+        r.arrival, r.lat, r.done = float(t), [], 0
+    fused = serve.serve(b, reqs, fused=True)
+    note("served: fused Poisson %.2f s" % fused["wall_s"])
+    for r in reqs:
+        r.arrival, r.lat, r.done = 0.0, [], 0
+    sat = serve.serve(b, reqs, fused=True)
+    note("served: fused saturated %.2f s" % sat["wall_s"])
+    b.close()
+    keep = ("wall_s", "np_per_s", "p50_ms", "p99_ms")
+    return {"requests": nreq, "steps_per_request": reqs[0].steps,
+            "mean_n": ser["mean_n"], "budget_bytes": budget, "arrival_rate_per_s": rate,
+            "serial_capacity": {k: ser[k] for k in keep},
+            "one_at_a_time_poisson": {k: fifo[k] for k in keep},
+            "fused_poisson": {k: fused[k] for k in keep + ("max_active", "ticks")},
+            "fused_saturated": {k: sat[k] for k in keep + ("max_active", "ticks")},
+            "throughput_gain_saturated": sat["np_per_s"] / ser["np_per_s"],
+            "note": "latency = time between a request's consecutive step completions, the "
+                    "first from its arrival (queueing included); (N*P)/s counts the "
+                    "Fourier-space pairs of all steps over the wall time, admission included"}
 
 
 def main():
@@ -204,7 +303,14 @@ def main():
                          "kernels_us": {k: (v[0] / v[1] * 1e3) if v[1] else None
                                         for k, v in r["kernels"].items()}}
     if not args.no_cpu_baseline:
+        note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    if args.workload == "water_30k" and args.md_steps > 0:
+        note("full NPT step")
+        out["ns_per_day"] = md_ns_per_day(args.md_steps, args.precision, torch)
+    if args.workload == "water_30k" and args.serve_requests > 0:
+        note("served stream")
+        out["served"] = served_stream(args.serve_requests, args.serve_budget_gib, args.precision)
     print(json.dumps(out), flush=True)
 
 

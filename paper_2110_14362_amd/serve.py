@@ -79,18 +79,22 @@ def _admit(batch, r):
                        lj=s.get("lj"))
 
 
-def serve(batch, reqs, fused=True, keep_results=False, check=True, clock=time.perf_counter):
+def serve(batch, reqs, fused=True, max_active=None, keep_results=False, check=True,
+          clock=time.perf_counter):
     """Run the stream; reqs carry arrival times (s from the start).  Returns
-    summary statistics; per-request latencies stay in r.lat."""
+    summary statistics; per-request latencies stay in r.lat.  max_active = 1
+    with fused = False is the one-system-at-a-time server (first come, first
+    served, each system's kernels launched on their own)."""
     pending = collections.deque(sorted(reqs, key=lambda r: r.arrival))
     active = {}
     t0 = clock()
     ticks = 0
-    max_active = 0
+    peak_active = 0
     busy = 0.0
     while pending or active:
         now = clock() - t0
-        while pending and pending[0].arrival <= now:
+        while pending and pending[0].arrival <= now and (max_active is None
+                                                          or len(active) < max_active):
             r = pending[0]
             slot = _admit(batch, r)
             if slot is None:
@@ -107,7 +111,7 @@ def serve(batch, reqs, fused=True, keep_results=False, check=True, clock=time.pe
             if wait > 0:
                 time.sleep(wait)
             continue
-        max_active = max(max_active, len(active))
+        peak_active = max(peak_active, len(active))
         ts = clock()
         batch.step(fused=fused)
         batch.sync()
@@ -128,7 +132,7 @@ def serve(batch, reqs, fused=True, keep_results=False, check=True, clock=time.pe
                 batch.release(slot)
                 del active[slot]
     wall = clock() - t0
-    return summarize(reqs, wall, ticks=ticks, max_active=max_active, busy=busy)
+    return summarize(reqs, wall, ticks=ticks, max_active=peak_active, busy=busy)
 
 
 def serve_serial(batch, reqs, keep_results=False, check=True, clock=time.perf_counter):

@@ -242,7 +242,8 @@ def npt_real(box, T=300.0, p_atm=1.0, dt=1.0, tau_p=100.0, tau_cell=500.0, beta_
 
 CHARGES_PER_A3 = 3.0 * WATER_PER_A3  # 0.100284 charges per A^3 (water at 1 g/cm^3)
 ION_MASSES = (22.99, 35.45)          # cation, anion (g/mol)
-ION_SIGMA, ION_EPS = 2.0, 1.0        # repulsive core 4 eps (sigma/r)^12 (A, kcal/mol)
+ION_SIGMA, ION_EPS = 1.7, 1.0        # repulsive core 4 eps (sigma/r)^12 (A, kcal/mol)
+EPS_WATER = 78.5                     # primitive model: the solvent as a dielectric continuum
 
 
 def splitmix64(x):
@@ -257,7 +258,9 @@ def splitmix64(x):
 def ions(n, box, seed, jitter=0.15):
     """Primitive electrolyte with a repulsive core: n ions (n/2 at +1, n/2 at
     -1, in random order) on a jittered lattice filling the rectangular box
-    (so no two start closer than the lattice spacing minus 2 jitter)."""
+    (so no two start closer than the lattice spacing minus 2 jitter).  The
+    caller sets the Coulomb constant (the primitive model divides it by the
+    solvent's relative permittivity)."""
     g = _rng(seed)
     box = np.asarray(box, dtype=np.float64)
     # lattice with about n sites, spacing about equal on the three axes
@@ -304,7 +307,9 @@ def serving_request(i, seed=2110143625, nmin=1000, nmax=200000, p=100, steps=20,
         s = ions(n, box, seed=sub)
     rc_i = min(rc, float(box.min()) / 3.3)
     g_i = g_ewald * rc / rc_i
-    s.update(alpha=g_i ** 2, g=g_i, rc=rc_i, p=p, coulomb=COULOMB_REAL, kind=kind, steps=steps,
+    # the primitive electrolyte's ions interact through the solvent's dielectric
+    coul = COULOMB_REAL if kind == "water" else COULOMB_REAL / EPS_WATER
+    s.update(alpha=g_i ** 2, g=g_i, rc=rc_i, p=p, coulomb=coul, kind=kind, steps=steps,
              request=i, seed=sub)
     return s
 
