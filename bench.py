@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--p", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--large-steps", type=int, default=40,
+                    help="timed steps of the 10^6-charge, P = 2000 Fourier step (0: skip)")
     ap.add_argument("--md-steps", type=int, default=300,
                     help="timed full NPT steps for ns/day (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=120,
@@ -134,6 +136,45 @@ def note(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def large_roofline(steps, precision, torch):
+    """The Fourier step where the GPU is saturated: 10^6-charge water (333,333
+    molecules, L = 215.24 A, g = 0.3/A), P = 2000; per-kernel HIP-event times."""
+    from paper_2110_14362_amd import workloads
+    from paper_2110_14362_amd.rbe import RBE
+    dev = torch.device("cuda:0")
+    s = workloads.make("water_1m")
+    P = 2000
+    N = len(s["q"])
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    x, y, z, q = t(s["pos"][:, 0]), t(s["pos"][:, 1]), t(s["pos"][:, 2]), t(s["q"])
+    f = [torch.zeros(N, dtype=torch.float64, device=dev) for _ in range(3)]
+    vir = torch.zeros(6, dtype=torch.float64, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    box = [float(b) for b in s["box"]]
+    ctx = RBE(q, box, P, s["alpha"], coulomb=s["coulomb"], precision=precision, box_mode="iso",
+              seed=2110143620, system_id=0)
+    step = make_step(ctx, box, x, y, z, *f, vir, en)
+    el = time_steps(step, steps, 5, torch)
+    ctx.timing_enable(steps)
+    time_steps(step, steps, 0, torch)
+    kt = ctx.timing_read()
+    ctx.timing_enable(0)
+    ctx.check()
+    plan = ctx.plan()
+    ctx.close()
+    kern = {k: (v[0] / v[1] * 1e3) if v[1] else None for k, v in kt.items()}
+    out = {"workload": "water_1m: N = %d, P = %d, %s" % (N, P, precision),
+           "ms_per_step": el / steps * 1e3, "value": N * P / (el / steps), "unit": "(N*P)/s",
+           "kernels_us": kern}
+    for k in ("sfac", "force"):
+        if kern.get(k):
+            a = TRANS_PER_PAIR * N * P / (kern[k] * 1e-6)
+            out["roofline_" + k] = {"bound": "alu", "achieved": a / 1e12, "peak": TRANS_PEAK / 1e12,
+                                    "unit": "Ttrans/s", "frac": a / TRANS_PEAK}
+    out["plan"] = plan
+    return out
+
+
 def md_ns_per_day(steps, precision, torch):
     """Full NPT step of the 30k-charge rigid water (10,000 molecules at 1 g/cm^3,
     L = 66.88 A, g = 0.3/A, r_c = 10 A, P = 100, 1 fs, 300 K, 1 atm): every
@@ -202,9 +243,21 @@ def served_stream(nreq, budget_gib, precision):
     note("served: fused Poisson %.2f s" % fused["wall_s"])
     for r in reqs:
         r.arrival, r.lat, r.done = 0.0, [], 0
+    b.timing_enable(4 * reqs[0].steps)
     sat = serve.serve(b, reqs, fused=True)
+    kt = b.timing_read()
+    b.timing_enable(0)
     note("served: fused saturated %.2f s" % sat["wall_s"])
     b.close()
+    fourier = {}
+    for k in ("sfac", "force"):
+        if kt[k] > 0:
+            a = TRANS_PER_PAIR * kt["np"] / (kt[k] * 1e-3)
+            fourier["roofline_" + k] = {"bound": "alu", "achieved": a / 1e12,
+                                        "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
+                                        "frac": a / TRANS_PEAK}
+    fourier["device_ms_per_step"] = {k: kt[k] / max(kt["steps"], 1) for k in b.BATCH_KINDS}
+    fourier["timed_steps"] = kt["steps"]
     keep = ("wall_s", "np_per_s", "p50_ms", "p99_ms")
     return {"requests": nreq, "steps_per_request": reqs[0].steps,
             "mean_n": ser["mean_n"], "budget_bytes": budget, "arrival_rate_per_s": rate,
@@ -213,6 +266,7 @@ def served_stream(nreq, budget_gib, precision):
             "fused_poisson": {k: fused[k] for k in keep + ("max_active", "ticks")},
             "fused_saturated": {k: sat[k] for k in keep + ("max_active", "ticks")},
             "throughput_gain_saturated": sat["np_per_s"] / ser["np_per_s"],
+            "saturated_kernels": fourier,
             "note": "latency = time between a request's consecutive step completions, the "
                     "first from its arrival (queueing included); (N*P)/s counts the "
                     "Fourier-space pairs of all steps over the wall time, admission included"}
@@ -367,6 +421,9 @@ def main():
     if not args.no_cpu_baseline:
         note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    if args.workload == "water_30k" and args.large_steps > 0:
+        note("10^6-charge Fourier step")
+        out["saturated_1m_p2000"] = large_roofline(args.large_steps, args.precision, torch)
     if args.workload == "water_30k" and args.md_steps > 0:
         note("full NPT step")
         out["ns_per_day"] = md_ns_per_day(args.md_steps, args.precision, torch)

@@ -440,6 +440,16 @@ rbe_status rbe_batch_release(rbe_batch b, int32_t slot);
 /* h[4] = admitted systems, bytes held, budget, steps launched. */
 rbe_status rbe_batch_info(rbe_batch b, int64_t* h);
 
+/* Kernel timing of the next max_steps fused steps (0: off; waits): HIP events
+ * on the batch's stream before and after each kernel family. */
+rbe_status rbe_batch_timing_enable(rbe_batch b, int32_t max_steps);
+
+/* Waits; h_ms[5] = summed device time (ms) of the integrator's first half,
+ * the structure factors, the forces, the real-space kernels and the
+ * integrator's second half over the timed steps; *h_steps their number;
+ * *h_np the summed N p (Fourier pairs) of those steps.  Resets the count. */
+rbe_status rbe_batch_timing_read(rbe_batch b, double* h_ms, int32_t* h_steps, double* h_np);
+
 void rbe_batch_destroy(rbe_batch b);
 
 /* Text of the last error reported to the calling thread ("" if none). */

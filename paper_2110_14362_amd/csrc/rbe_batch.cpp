@@ -67,6 +67,11 @@ struct rbe_batch_s {
   size_t stage_cap = 0;
   Stage stage[2];
   int cur = 0;
+  // kernel timing of fused steps: events around each kernel family
+  static constexpr int kKinds = 5;   // md first half, structure factors, forces, real space, md second half
+  int timing_cap = 0, timed = 0;
+  std::vector<hipEvent_t> ev;        // [timing_cap][kKinds + 1]
+  double timed_np = 0.0;             // sum of N p over the timed steps
 };
 
 namespace {
@@ -397,19 +402,35 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   if (stg.overflow) return bfail(RBE_ERR_STATE, "argument table overflow");
   e = hipMemcpyAsync(stg.dev, stg.host, stg.used, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipEventRecord(stg.done, b->stream);
+  // timing: an event before each kernel family and one after the last
+  hipEvent_t* tev = nullptr;
+  if (b->timed < b->timing_cap) {
+    tev = &b->ev[(size_t)b->timed * (rbe_batch_s::kKinds + 1)];
+    b->timed++;
+    for (int j = 0; j < nsys; ++j) b->timed_np += (double)ka[j].n * (double)ka[j].p;
+  }
+  auto mark = [&](int k) {
+    if (tev && e == hipSuccess) e = hipEventRecord(tev[k], b->stream);
+  };
+  mark(0);
   if (e == hipSuccess) e = launch_md_first_multi(d_md1, d_ustart, nsys, ustart.back(), b->stream);
+  mark(1);
   for (auto& kv : sg)
     if (e == hipSuccess)
       e = launch_sfac_multi(prec, kv.first, kv.second.tab, kv.second.start, (int)kv.second.idx.size(),
                             kv.second.total, kv.second.lds, b->stream);
+  mark(2);
   for (auto& kv : fg)
     if (e == hipSuccess)
       e = launch_force_multi(prec, kv.first, kv.second.tab, kv.second.start, (int)kv.second.idx.size(),
                              kv.second.total, b->stream);
+  mark(3);
   if (e == hipSuccess)
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
                           qstart.back(), nsys, b->stream);
+  mark(4);
   if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
+  mark(5);
   b->cur ^= 1;
   b->steps_launched++;
   if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "fused step launches: %s", hipGetErrorString(e));
@@ -487,9 +508,52 @@ rbe_status rbe_batch_slot_step(rbe_batch b, int32_t slot, int64_t* step) {
   return RBE_OK;
 }
 
+rbe_status rbe_batch_timing_enable(rbe_batch b, int32_t max_steps) {
+  if (!b) return bfail(RBE_ERR_ARG, "NULL batch");
+  if (max_steps < 0) return bfail(RBE_ERR_ARG, "max_steps = %d must be >= 0", max_steps);
+  (void)hipStreamSynchronize(b->stream);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  b->ev.clear();
+  b->timing_cap = b->timed = 0;
+  b->timed_np = 0.0;
+  if (max_steps == 0) return RBE_OK;
+  b->ev.assign((size_t)max_steps * (rbe_batch_s::kKinds + 1), nullptr);
+  for (hipEvent_t& e : b->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      return bfail(RBE_ERR_DEVICE, "hipEventCreate failed");
+    }
+  b->timing_cap = max_steps;
+  return RBE_OK;
+}
+
+rbe_status rbe_batch_timing_read(rbe_batch b, double* h_ms, int32_t* h_steps, double* h_np) {
+  if (!b || !h_ms || !h_steps || !h_np) return bfail(RBE_ERR_ARG, "NULL argument");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  for (int k = 0; k < rbe_batch_s::kKinds; ++k) h_ms[k] = 0.0;
+  for (int s = 0; s < b->timed; ++s) {
+    const hipEvent_t* t = &b->ev[(size_t)s * (rbe_batch_s::kKinds + 1)];
+    for (int k = 0; k < rbe_batch_s::kKinds; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, t[k], t[k + 1]);
+      if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "hipEventElapsedTime: %s", hipGetErrorString(e));
+      h_ms[k] += ms;
+    }
+  }
+  *h_steps = b->timed;
+  *h_np = b->timed_np;
+  b->timed = 0;
+  b->timed_np = 0.0;
+  return RBE_OK;
+}
+
 void rbe_batch_destroy(rbe_batch b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
   for (Slot& s : b->slots)
     if (s.active || s.mem) release_slot(s);
   for (Stage& st : b->stage) {

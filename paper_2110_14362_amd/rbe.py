@@ -32,7 +32,8 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_md_set_rigid",
            "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
-           "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy"]
+           "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy",
+           "rbe_batch_timing_enable", "rbe_batch_timing_read"]
 KERNEL_KINDS = ["tables", "sample", "sfac", "force"]
 
 
@@ -131,6 +132,8 @@ def load_library(path=LIB_PATH):
         "rbe_batch_slot_step": [vp, i32, ctypes.POINTER(i64)],
         "rbe_batch_release": [vp, i32],
         "rbe_batch_info": [vp, ctypes.POINTER(i64)],
+        "rbe_batch_timing_enable": [vp, i32],
+        "rbe_batch_timing_read": [vp, dp, ctypes.POINTER(i32), dp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -529,3 +532,19 @@ class Batch:
         h = (ctypes.c_int64 * 4)()
         _check(_lib.rbe_batch_info(self._ctx, h))
         return dict(active=h[0], bytes=h[1], budget=h[2], steps=h[3])
+
+    BATCH_KINDS = ("md_first", "sfac", "force", "real", "md_second")
+
+    def timing_enable(self, max_steps):
+        _check(_lib.rbe_batch_timing_enable(self._ctx, int(max_steps)))
+
+    def timing_read(self):
+        """dict kind -> summed ms over the timed fused steps, plus steps and
+        the summed N p of those steps."""
+        ms = (ctypes.c_double * 5)()
+        steps = ctypes.c_int32()
+        npairs = ctypes.c_double()
+        _check(_lib.rbe_batch_timing_read(self._ctx, ms, ctypes.byref(steps), ctypes.byref(npairs)))
+        out = {k: ms[i] for i, k in enumerate(self.BATCH_KINDS)}
+        out.update(steps=steps.value, np=npairs.value)
+        return out
