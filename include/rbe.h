@@ -206,9 +206,10 @@ void rbe_destroy(rbe_ctx ctx);
  * Optionally a truncated Lennard-Jones term per type pair (not part of the
  * paper's method; the water- and membrane-shaped systems need a short-range
  * repulsion): U = c12/r^12 - c6/r^6 for r < rc, added to U2, F and W.
- * Cells are at least rc wide and there must be >= 3 per axis (rc <= l/3).
- * Within each cell the members are ordered by index, so every sum has a fixed
- * order and results are bitwise reproducible. */
+ * Cells are at least rc/2 wide and there must be >= 5 per axis (rc <= 2l/5);
+ * a particle's candidates are the 125 cells around its own.  Within each cell
+ * the members are ordered by index, so every sum has a fixed order and results
+ * are bitwise reproducible. */
 typedef struct rbe_real_ctx_s* rbe_real_ctx;
 
 typedef struct {
@@ -225,8 +226,8 @@ typedef struct {
  *   d_type   : DEVICE, n int32 types in 0..ntypes-1 (copied), or NULL if ntypes = 0.
  *   h_lj     : HOST, ntypes*ntypes pairs (c12, c6), row-major over (t_i, t_j),
  *              symmetric, or NULL if ntypes = 0.
- *   box_host : HOST (lx, ly, lz); each >= 3 rc.  Cell storage is sized for
- *              sides up to 2x these values (at most 64 cells per axis).
+ *   box_host : HOST (lx, ly, lz); each >= 2.5 rc.  Cell storage is sized for
+ *              sides up to 2x these values (at most 96 cells per axis).
  * Waits for the stream. */
 rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const int32_t* d_type,
                          const double* h_lj, const double* box_host, void* stream,
@@ -236,7 +237,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
 rbe_status rbe_real_set_box(rbe_real_ctx ctx, const double* box_host);
 
 /* Read the cell from DEVICE memory (3 doubles) at every later evaluation.
- * A cell with a side below 3 rc, or beyond the capacity, is flagged on the
+ * A cell with a side below 2.5 rc, or beyond the capacity, is flagged on the
  * device (the grid is clamped) and reported by rbe_real_check. */
 rbe_status rbe_real_set_box_dev(rbe_real_ctx ctx, const double* d_box);
 
@@ -248,7 +249,7 @@ rbe_status rbe_real_forces(rbe_real_ctx ctx, const double* d_x, const double* d_
                            const double* d_z, double* d_fx, double* d_fy, double* d_fz,
                            int accumulate, double* d_virial6, double* d_energy);
 
-/* Wait and report device-side flags: a cell below 3 rc or over capacity, or a
+/* Wait and report device-side flags: a cell below 2.5 rc or over capacity, or a
  * cell with more than 2048 members (its evaluation is then incomplete). */
 rbe_status rbe_real_check(rbe_real_ctx ctx);
 

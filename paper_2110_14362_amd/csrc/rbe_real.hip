@@ -1,19 +1,21 @@
 // Real-space part of the Ewald split on gfx950 (section 4.1 eq. (U2) and
 // eq. (force); section 4.2: nearest image, pairs closer than the cutoff),
-// with an optional Lennard-Jones 12-6 term per type pair.  FP64 throughout.
+// with an optional Lennard-Jones 12-6 term per type pair.  Pair arithmetic
+// in FP64 (the candidate test in FP32, with FP64 at the cutoff's edge).
 //
 // One evaluation is five launches:
-//   k_bin     cell of each particle (cells at least rc wide, >= 3 per axis)
+//   k_bin     cell of each particle (cells at least rc/2 wide, >= 5 per axis)
 //   k_scan    exclusive scan of the cell counts (one block), counts cleared
 //   k_fill    scatter particle indices into their cells
 //   k_csort   per cell: sort the member indices (bitonic, LDS) so every sum
 //             below has a fixed order, and gather positions (wrapped into
 //             the cell, consistently with the binning)/charges/types into
 //             cell order
-//   k_pairs   a wave per particle i at a time (in cell order): its lanes
-//             test 64 candidates j of the 27 neighbour cells at once (each
-//             neighbour cell's periodic shift applied to i once), append the
-//             pairs inside the cutoff to a wave-private LDS queue, and
+//   k_pairs   a wave per particle i at a time (in cell order): the 125
+//             neighbour cells form up to 50 contiguous segments, laid end
+//             to end as one candidate list that the lanes test 64 at a time
+//             (each lane applying its segment's periodic shift to i), append
+//             the pairs inside the cutoff to a wave-private LDS queue, and
 //             evaluate the queue 64 pairs at a time with every lane busy;
 //             the force on i is a fixed-order wave sum per batch, energy and
 //             virial are per-lane sums reduced in a fixed order by the
@@ -42,12 +44,13 @@ __device__ __forceinline__ void real_box(const RealArgs& a, double l[3]) {
   else { l[0] = a.box[0]; l[1] = a.box[1]; l[2] = a.box[2]; }
 }
 
-// cells per axis: floor(l / rc), clamped to [3, cap]; err bit 1 if clamped
+// cells per axis: floor(2 l / rc) (cells at least rc/2 wide), clamped to
+// [5, cap]; err bit 1 if clamped below (l < 2.5 rc)
 __device__ __forceinline__ void cell_grid(const RealArgs& a, const double l[3], int nc[3], int& err) {
   for (int d = 0; d < 3; ++d) {
-    const double f = floor(l[d] / a.rc);
-    int v = (f >= 3.0 && f <= (double)a.nc_cap[d]) ? (int)f : -1;
-    if (v < 0) { err |= (f < 3.0 || !(f == f)) ? 2 : 0; v = (f >= 3.0) ? a.nc_cap[d] : 3; }
+    const double f = floor(2.0 * l[d] / a.rc);
+    int v = (f >= 5.0 && f <= (double)a.nc_cap[d]) ? (int)f : -1;
+    if (v < 0) { err |= (f < 5.0 || !(f == f)) ? 2 : 0; v = (f >= 5.0) ? a.nc_cap[d] : 5; }
     nc[d] = v;
   }
 }
@@ -217,6 +220,9 @@ struct PairQueue {
   int j[kPairQueue];
   int s[kPairQueue];
   double cheb[kErfcxTerms];
+  int seg_off[kSegments + 1];   // candidate offset of each neighbour segment (exclusive scan)
+  int seg_j0[kSegments];        // its first cell-ordered index
+  int seg_code[kSegments];      // its periodic shift
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -294,25 +300,26 @@ __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, 
   f[2] += wsum(gz);
 }
 
-// The 27 neighbour cells of cell (cx, cy, cz) as 9 rows of three cells along
+// The 125 neighbour cells of cell (cx, cy, cz) (cells at least rc/2 wide,
+// so every pair closer than rc is in them) as 25 rows of five cells along
 // x; a row is one contiguous range of the cell-ordered arrays unless it
-// wraps in x, then two.  Segment `seg` (0..17) of that list: the cell range
-// [c0, c1] and the periodic shift code; false if the segment is empty.
+// wraps in x, then two.  Segment `seg` (0..49) of that list: the cell range
+// [c0, c1] and the periodic shift code (3 trits); false if empty.
 __device__ __forceinline__ bool neighbour_segment(int seg, int cx, int cy, int cz, int nx, int ny,
                                                   int nz, int& c0, int& c1, int& code) {
   const int row = seg >> 1, half = seg & 1;
-  const int dz = row / 3 - 1, dy = row % 3 - 1;
+  const int dz = row / 5 - 2, dy = row % 5 - 2;
   int zz = cz + dz, yy = cy + dy, kz = 1, ky = 1, kx = 1;
   if (zz < 0) { zz += nz; kz = 0; } else if (zz >= nz) { zz -= nz; kz = 2; }
   if (yy < 0) { yy += ny; ky = 0; } else if (yy >= ny) { yy -= ny; ky = 2; }
   int x0, x1;
-  if (cx == 0) {
-    if (half == 0) { x0 = x1 = nx - 1; kx = 0; } else { x0 = 0; x1 = 1; }
-  } else if (cx == nx - 1) {
-    if (half == 0) { x0 = nx - 2; x1 = nx - 1; } else { x0 = x1 = 0; kx = 2; }
+  if (cx < 2) {                                   // cells cx-2 .. -1 wrap to the far end
+    if (half == 0) { x0 = nx + cx - 2; x1 = nx - 1; kx = 0; } else { x0 = 0; x1 = cx + 2; }
+  } else if (cx > nx - 3) {                       // cells nx .. cx+2 wrap to the start
+    if (half == 0) { x0 = cx - 2; x1 = nx - 1; } else { x0 = 0; x1 = cx + 2 - nx; kx = 2; }
   } else {
     if (half == 1) return false;
-    x0 = cx - 1; x1 = cx + 1;
+    x0 = cx - 2; x1 = cx + 2;
   }
   const int rbase = (zz * ny + yy) * nx;
   c0 = rbase + x0;
@@ -325,7 +332,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   __shared__ PairQueue queue[kPairWaves];
   __shared__ double sh[kPairWaves][8];
   __shared__ int sh_last;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
   if (lane < kErfcxTerms) Q.cheb[lane] = kErfcxCheb[lane];
   wave_sync();
@@ -351,42 +358,63 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
     const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
     double f[3] = {0.0, 0.0, 0.0};
     int qn = 0;                                   // queued pairs (wave-uniform)
+    // the neighbour segments, lane s describing segment s, and their
+    // candidate offsets (an exclusive scan): the candidates of the 125 cells
+    // become one flat list, tested 64 at a time with every lane in use
+    int len = 0;
+    {
+      int c0 = 0, c1 = -1, code = 0;
+      if (lane < kSegments && neighbour_segment(lane, cx, cy, cz, nx, ny, nz, c0, c1, code)) {
+        const int j0 = a.start[c0];
+        len = a.start[c1 + 1] - j0;
+        Q.seg_j0[lane] = j0;
+        Q.seg_code[lane] = code;
+      } else if (lane < kSegments) {
+        Q.seg_j0[lane] = 0;
+        Q.seg_code[lane] = 13;
+      }
+    }
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane < kSegments) Q.seg_off[lane] = incl - len;
+    const int total = uniform(__shfl(incl, kSegments - 1, 64));
+    if (lane == 0) Q.seg_off[kSegments] = total;
+    wave_sync();
     // Alternate between testing candidates into the queue until it is
     // nearly full (or the candidates are exhausted) and evaluating the
     // queue, so the two phases' registers are never live together.
-    int seg = -1, jb = 0, j1 = 0, code = 0;       // resume point of the test phase
-    double xo = 0.0, yo = 0.0, zo = 0.0;          // i seen from the segment's image
-    float xf = 0.0f, yf = 0.0f, zf = 0.0f;        // the same in FP32
+    int base = 0, sg = 0;                         // next batch; this lane's segment
     bool done = false;
     while (!done) {
       while (qn <= kPairQueue - 64) {
-        if (jb >= j1) {                           // next non-empty segment
-          int c0 = 0, c1 = -1;
-          do {
-            ++seg;
-          } while (seg < 18 && !neighbour_segment(seg, cx, cy, cz, nx, ny, nz, c0, c1, code));
-          if (seg >= 18) { done = true; break; }
-          jb = uniform(a.start[c0]);
-          j1 = uniform(a.start[c1 + 1]);
-          xo = vi.x - l[0] * (double)(code % 3 - 1);
-          yo = vi.y - l[1] * (double)((code / 3) % 3 - 1);
-          zo = vi.z - l[2] * (double)(code / 9 - 1);
-          xf = (float)xo; yf = (float)yo; zf = (float)zo;
-          continue;
-        }
-        const int j = jb + lane;
+        if (base >= total) { done = true; break; }
+        const int cf = base + lane;
         bool acc = false;
-        if (j < j1 && j != t) {
-          // FP32 test; pairs within the FP32 error band of the cutoff are
-          // decided in FP64, so the accepted set is the FP64 one
-          const float4 v = a.xf[j];
-          const float ex = v.x - xf, ey = v.y - yf, ez = v.z - zf;
-          const float r2 = ex * ex + ey * ey + ez * ez;
-          if (r2 < rc2_lo) acc = true;
-          else if (r2 <= rc2_hi) {
-            const double4 d = a.xq[j];
-            const double dx = d.x - xo, dy = d.y - yo, dz = d.z - zo;
-            acc = dx * dx + dy * dy + dz * dz < rc2;
+        int j = 0, code = 13;
+        if (cf < total) {
+          while (Q.seg_off[sg + 1] <= cf) ++sg;
+          j = Q.seg_j0[sg] + (cf - Q.seg_off[sg]);
+          code = Q.seg_code[sg];
+          if (j != t) {
+            // i seen from the segment's image
+            const double xo = vi.x - l[0] * (double)(code % 3 - 1);
+            const double yo = vi.y - l[1] * (double)((code / 3) % 3 - 1);
+            const double zo = vi.z - l[2] * (double)(code / 9 - 1);
+            // FP32 test; pairs within the FP32 error band of the cutoff are
+            // decided in FP64, so the accepted set is the FP64 one
+            const float4 v = a.xf[j];
+            const float ex = v.x - (float)xo, ey = v.y - (float)yo, ez = v.z - (float)zo;
+            const float r2 = ex * ex + ey * ey + ez * ez;
+            if (r2 < rc2_lo) acc = true;
+            else if (r2 <= rc2_hi) {
+              const double4 d = a.xq[j];
+              const double dx = d.x - xo, dy = d.y - yo, dz = d.z - zo;
+              acc = dx * dx + dy * dy + dz * dz < rc2;
+            }
           }
         }
         const uint64_t bal = __ballot(acc);
@@ -396,7 +424,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
           Q.s[pos] = code;
         }
         qn += __popcll(bal);
-        jb += 64;
+        base += 64;
       }
       // evaluate: every full batch, and the last partial one when done
       wave_sync();

@@ -53,8 +53,8 @@ rbe_status check_real_box(const rbe_real_ctx_s* c, const double* box) {
   if (!box) return rfail(RBE_ERR_ARG, "box pointer is NULL");
   for (int d = 0; d < 3; ++d) {
     if (!(std::isfinite(box[d]) && box[d] > 0.0)) return rfail(RBE_ERR_ARG, "box[%d] = %g is not a positive finite length", d, box[d]);
-    if (box[d] < 3.0 * c->cfg.rc) return rfail(RBE_ERR_ARG, "box[%d] = %g is below 3 rc = %g", d, box[d], 3.0 * c->cfg.rc);
-    if (std::floor(box[d] / c->cfg.rc) > c->a.nc_cap[d]) return rfail(RBE_ERR_CAPACITY, "box[%d] = %g exceeds the cell capacity", d, box[d]);
+    if (box[d] < 2.5 * c->cfg.rc) return rfail(RBE_ERR_ARG, "box[%d] = %g is below 2.5 rc = %g", d, box[d], 2.5 * c->cfg.rc);
+    if (std::floor(2.0 * box[d] / c->cfg.rc) > c->a.nc_cap[d]) return rfail(RBE_ERR_CAPACITY, "box[%d] = %g exceeds the cell capacity", d, box[d]);
   }
   return RBE_OK;
 }
@@ -81,9 +81,9 @@ rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, 
 int64_t real_footprint(const rbe_real_config* cfg, const double* box) {
   int64_t cap = 1;
   for (int d = 0; d < 3; ++d) {
-    long v = (long)std::floor(2.0 * box[d] / cfg->rc);
+    long v = (long)std::floor(4.0 * box[d] / cfg->rc);
     if (v > kCellAxisMax) v = kCellAxisMax;
-    if (v < 3) v = 3;
+    if (v < 5) v = 5;
     cap *= v;
   }
   const int64_t n = cfg->n, blocks = pair_blocks(n);
@@ -120,9 +120,9 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
   a.alpha = cfg->alpha; a.rc = cfg->rc; a.coulomb = cfg->coulomb;
   long cap = 1;
   for (int d = 0; d < 3; ++d) {
-    long v = (long)std::floor(2.0 * box_host[d] / cfg->rc);
+    long v = (long)std::floor(4.0 * box_host[d] / cfg->rc);   // cells at least rc/2 wide, box up to 2x
     if (v > kCellAxisMax) v = kCellAxisMax;
-    if (v < 3) v = 3;
+    if (v < 5) v = 5;
     a.nc_cap[d] = (int)v;
     cap *= v;
     c->box0[d] = box_host[d];

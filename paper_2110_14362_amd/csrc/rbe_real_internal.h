@@ -7,11 +7,12 @@
 namespace rbe {
 
 constexpr int kCellMax = 2048;     // members of one cell the sort kernel can order
-constexpr int kCellAxisMax = 64;   // cells per axis
+constexpr int kCellAxisMax = 96;   // cells per axis
 constexpr int kPairWaves = 4;      // pair kernel: waves per block
 constexpr int kPairPerWave = 1;    // particles i a wave takes in turn
 constexpr int kPairPerBlock = kPairWaves * kPairPerWave;
 constexpr int kPairQueue = 512;    // accepted-pair queue of a wave
+constexpr int kSegments = 50;      // neighbour segments: 25 rows of 5 cells, split at x wraps
 
 constexpr int kBinPer = 2048;      // particles a binning block takes (256 threads)
 constexpr int kBinLds = 8192;      // cells counted in LDS by the binning kernels
@@ -42,7 +43,7 @@ struct RealArgs {
   int32_t* grid;                           // cells per axis of the last binning
   double* part;                            // [pair_blocks(n)][8]
   uint32_t* cnt;
-  int32_t* err;                            // bit 1: rc > l/3 or cell cap; bit 2: cell overflow
+  int32_t* err;                            // bit 1: rc > 2l/5 or cell cap; bit 2: cell overflow
 };
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);

@@ -115,9 +115,10 @@ def test_unwrapped_accumulate_and_reproducible(gpu):
     assert np.allclose(acc["forces"] - f0, base["forces"], rtol=1e-12, atol=1e-12)
 
 
-def test_rejects_cutoff_above_third_of_box(gpu):
+def test_rejects_cutoff_above_two_fifths_of_box(gpu):
+    # the cell grid needs at least five cells of width >= rc/2 per axis
     import torch
     from paper_2110_14362_amd.rbe import RealSpace, RBEError
     q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
     with pytest.raises(RBEError):
-        RealSpace(q, (10.0, 10.0, 10.0), 0.3, 4.0)
+        RealSpace(q, (10.0, 10.0, 10.0), 0.3, 4.5)
