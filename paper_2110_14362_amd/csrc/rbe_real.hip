@@ -223,6 +223,7 @@ struct PairQueue {
   int seg_off[kSegments + 1];   // candidate offset of each neighbour segment (exclusive scan)
   int seg_j0[kSegments];        // its first cell-ordered index
   int seg_code[kSegments];      // its periodic shift
+  float4 seg_io[kSegments];     // i seen from the segment's image, FP32
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -369,9 +370,13 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
         len = a.start[c1 + 1] - j0;
         Q.seg_j0[lane] = j0;
         Q.seg_code[lane] = code;
+        Q.seg_io[lane] = make_float4((float)(vi.x - l[0] * (double)(code % 3 - 1)),
+                                     (float)(vi.y - l[1] * (double)((code / 3) % 3 - 1)),
+                                     (float)(vi.z - l[2] * (double)(code / 9 - 1)), 0.0f);
       } else if (lane < kSegments) {
         Q.seg_j0[lane] = 0;
         Q.seg_code[lane] = 13;
+        Q.seg_io[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       }
     }
     int incl = len;
@@ -387,34 +392,46 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
     // Alternate between testing candidates into the queue until it is
     // nearly full (or the candidates are exhausted) and evaluating the
     // queue, so the two phases' registers are never live together.
+    // candidate batches: the next batch's position load is issued before the
+    // current batch is tested (two register sets, alternating)
     int base = 0, sg = 0;                         // next batch; this lane's segment
+    int nj = -1, ncode = 13;                      // the loaded batch's j and shift
+    float4 nv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    auto fetch = [&](int b) {                     // candidate b + lane: j, shift, position
+      const int cf = b + lane;
+      nj = -1;
+      if (cf < total) {
+        while (Q.seg_off[sg + 1] <= cf) ++sg;
+        nj = Q.seg_j0[sg] + (cf - Q.seg_off[sg]);
+        ncode = sg;
+        nv = a.xf[nj];
+      }
+    };
+    fetch(0);
     bool done = false;
     while (!done) {
       while (qn <= kPairQueue - 64) {
         if (base >= total) { done = true; break; }
-        const int cf = base + lane;
+        const int j = nj, sj = ncode;
+        const float4 v = nv;
+        fetch(base + 64);
         bool acc = false;
-        int j = 0, code = 13;
-        if (cf < total) {
-          while (Q.seg_off[sg + 1] <= cf) ++sg;
-          j = Q.seg_j0[sg] + (cf - Q.seg_off[sg]);
-          code = Q.seg_code[sg];
-          if (j != t) {
-            // i seen from the segment's image
+        int code = 13;
+        if (j >= 0 && j != t) {
+          code = Q.seg_code[sj];
+          // FP32 test; pairs within the FP32 error band of the cutoff are
+          // decided in FP64, so the accepted set is the FP64 one
+          const float4 io = Q.seg_io[sj];
+          const float ex = v.x - io.x, ey = v.y - io.y, ez = v.z - io.z;
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          if (r2 < rc2_lo) acc = true;
+          else if (r2 <= rc2_hi) {
             const double xo = vi.x - l[0] * (double)(code % 3 - 1);
             const double yo = vi.y - l[1] * (double)((code / 3) % 3 - 1);
             const double zo = vi.z - l[2] * (double)(code / 9 - 1);
-            // FP32 test; pairs within the FP32 error band of the cutoff are
-            // decided in FP64, so the accepted set is the FP64 one
-            const float4 v = a.xf[j];
-            const float ex = v.x - (float)xo, ey = v.y - (float)yo, ez = v.z - (float)zo;
-            const float r2 = ex * ex + ey * ey + ez * ez;
-            if (r2 < rc2_lo) acc = true;
-            else if (r2 <= rc2_hi) {
-              const double4 d = a.xq[j];
-              const double dx = d.x - xo, dy = d.y - yo, dz = d.z - zo;
-              acc = dx * dx + dy * dy + dz * dz < rc2;
-            }
+            const double4 d = a.xq[j];
+            const double dx = d.x - xo, dy = d.y - yo, dz = d.z - zo;
+            acc = dx * dx + dy * dy + dz * dz < rc2;
           }
         }
         const uint64_t bal = __ballot(acc);
@@ -487,7 +504,10 @@ __global__ void __launch_bounds__(256) k_bin(RealArgs a) { bin_body(a, blockIdx.
 __global__ void __launch_bounds__(1024) k_scan(RealArgs a) { scan_body(a); }
 __global__ void __launch_bounds__(256) k_fill(RealArgs a) { fill_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(256) k_csort(RealArgs a) { csort_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(kPairWaves * 64) k_pairs(RealArgs a) {
+// four waves per SIMD: the register budget that keeps the pair evaluation
+// from spilling beyond a few registers
+__global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
+k_pairs(RealArgs a) {
   pairs_body(a, blockIdx.x, gridDim.x);
 }
 
@@ -545,8 +565,8 @@ __global__ void __launch_bounds__(256) k_csort_m(const RealArgs* tab, const int*
   (void)nb;
   csort_body(sa, lb);
 }
-__global__ void __launch_bounds__(kPairWaves * 64) k_pairs_m(const RealArgs* tab, const int* bstart,
-                                                             int nsys) {
+__global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
+k_pairs_m(const RealArgs* tab, const int* bstart, int nsys) {
   REAL_MULTI_PROLOGUE
   pairs_body(sa, lb, nb);
 }
