@@ -215,7 +215,8 @@ typedef struct rbe_real_ctx_s* rbe_real_ctx;
 typedef struct {
   int64_t n;          /* particles, >= 1                                       */
   int32_t ntypes;     /* Lennard-Jones types, 0..64; 0 = Coulomb only          */
-  int32_t reserved;   /* must be 0                                             */
+  int32_t precision;  /* RBE_PREC_FP64: pair arithmetic in FP64; RBE_PREC_FP32: */
+                      /* in FP32 (separations formed in FP64, sums in FP64)    */
   double  alpha;      /* splitting parameter (the same alpha as rbe_config)    */
   double  rc;         /* cutoff, > 0                                           */
   double  coulomb;    /* Coulomb constant C, > 0                               */
@@ -371,6 +372,8 @@ typedef struct {
   int32_t  precision;    /* rbe_precision of the Fourier part, every system  */
   int32_t  max_systems;  /* slots, 1..4096                                     */
   int64_t  hbm_budget;   /* device bytes the admitted systems may hold (> 0)    */
+  int32_t  real_precision; /* rbe_precision of the real-space pair arithmetic */
+  int32_t  reserved;     /* must be 0                                          */
 } rbe_batch_config;
 
 typedef struct {

@@ -119,9 +119,10 @@ rbe_config kspace_cfg(const rbe_batch_s* b, const rbe_system_desc* d, const doub
   return c;
 }
 
-rbe_real_config real_cfg(const rbe_system_desc* d) {
+rbe_real_config real_cfg(const rbe_batch_s* b, const rbe_system_desc* d) {
   rbe_real_config c{};
   c.n = d->n;
+  c.precision = b ? b->cfg.real_precision : RBE_PREC_FP64;
   c.ntypes = d->ntypes;
   c.alpha = d->alpha;
   c.rc = d->rc;
@@ -150,7 +151,7 @@ int64_t state_bytes(int64_t n) { return round256(11 * 8 * n + 14 * 8 + 4 * n); }
 
 int64_t footprint(const rbe_batch_s* b, const rbe_system_desc* d, const double* box) {
   const rbe_config kc = kspace_cfg(b, d, box);
-  const rbe_real_config rc = real_cfg(d);
+  const rbe_real_config rc = real_cfg(b, d);
   return state_bytes(d->n) + kspace_footprint(&kc, box) + real_footprint(&rc, box) + md_footprint(d->n);
 }
 
@@ -191,6 +192,9 @@ rbe_status rbe_batch_create(const rbe_batch_config* cfg, void* stream, rbe_batch
   if (cfg->max_systems < 1 || cfg->max_systems > 4096)
     return bfail(RBE_ERR_ARG, "max_systems = %d must be in 1..4096", cfg->max_systems);
   if (cfg->hbm_budget <= 0) return bfail(RBE_ERR_ARG, "hbm_budget must be positive");
+  if (cfg->real_precision != RBE_PREC_FP32 && cfg->real_precision != RBE_PREC_FP64)
+    return bfail(RBE_ERR_ARG, "unknown real_precision %d", cfg->real_precision);
+  if (cfg->reserved != 0) return bfail(RBE_ERR_ARG, "reserved field must be 0");
   rbe_batch_s* b = new (std::nothrow) rbe_batch_s();
   if (!b) return bfail(RBE_ERR_ALLOC, "host allocation failed");
   b->cfg = *cfg;
@@ -272,7 +276,7 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* d, const double* 
     return bfail(RBE_ERR_DEVICE, "admission copies: %s", hipGetErrorString(e));
   }
   const rbe_config kc = kspace_cfg(b, d, box_host);
-  const rbe_real_config rc = real_cfg(d);
+  const rbe_real_config rc = real_cfg(b, d);
   const rbe_md_config mc = md_cfg(d);
   st = rbe_init(&kc, s.q, box_host, b->stream, &s.k);
   if (st == RBE_OK) st = rbe_real_init(&rc, s.q, d->ntypes > 0 ? s.type : nullptr, h_lj, box_host, b->stream, &s.r);
@@ -427,7 +431,7 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   mark(3);
   if (e == hipSuccess)
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
-                          qstart.back(), nsys, b->stream);
+                          qstart.back(), nsys, b->cfg.real_precision == RBE_PREC_FP32, b->stream);
   mark(4);
   if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
   mark(5);

@@ -220,6 +220,7 @@ struct PairQueue {
   int j[kPairQueue];
   int s[kPairQueue];
   double cheb[kErfcxTerms];
+  float cheb32[kErfcxTerms32];
   int seg_off[kSegments + 1];   // candidate offset of each neighbour segment (exclusive scan)
   int seg_j0[kSegments];        // its first cell-ordered index
   int seg_code[kSegments];      // its periodic shift
@@ -301,6 +302,64 @@ __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, 
   f[2] += wsum(gz);
 }
 
+// Single-precision pair arithmetic (the FP32 real-space option): the
+// separation is formed in FP64 and rounded once; erfcx from the shorter
+// series, exp(-x^2) and 1/sqrt from the hardware approximations (a few ulp);
+// energy and virial summed per lane in FP32 over one particle's pairs, then
+// folded into FP64; the force's wave sum is formed in FP32 and added in FP64.
+__device__ __forceinline__ float erfcx_pos32(float x, const float* cheb) {
+  const float t = (x - (float)kErfcxK) * __builtin_amdgcn_rcpf(x + (float)kErfcxK), t2 = 2.0f * t;
+  float b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+  for (int k = kErfcxTerms32 - 1; k >= 1; --k) {
+    const float b0 = fmaf(t2, b1, cheb[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fmaf(t, b1, cheb[0] - b2);
+}
+
+__device__ __forceinline__ float wsumf(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p, bool valid,
+                                            const double4& vi, int ti, const double l[3], float sa,
+                                            float two_sa_pi, float alpha, const float* cheb,
+                                            double f[3], float& u, float w[6]) {
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  if (valid) {
+    const double4 v = p.v;
+    const int code = p.code;
+    const float ex = (float)(v.x - (vi.x - l[0] * (double)(code % 3 - 1)));
+    const float ey = (float)(v.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1)));
+    const float ez = (float)(v.z - (vi.z - l[2] * (double)(code / 9 - 1)));
+    const float r2 = ex * ex + ey * ey + ez * ez;
+    const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
+    const float qq = (float)(a.coulomb * vi.w * v.w);
+    const float g2 = __expf(-alpha * r2);
+    const float er = g2 * erfcx_pos32(sa * r, cheb);
+    float dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
+    u += qq * er * ir;
+    if (a.ntypes > 0) {
+      const int k = ti * a.ntypes + p.tj;
+      const float c12 = (float)a.lj[2 * k], c6 = (float)a.lj[2 * k + 1];
+      const float i2 = ir * ir, i6 = i2 * i2 * i2;
+      u += c12 * i6 * i6 - c6 * i6;
+      dU += (-12.0f * c12 * i6 * i6 + 6.0f * c6 * i6) * ir;
+    }
+    const float g = dU * ir;
+    gx = g * ex; gy = g * ey; gz = g * ez;
+    w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
+    w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
+  }
+  f[0] += (double)wsumf(gx);
+  f[1] += (double)wsumf(gy);
+  f[2] += (double)wsumf(gz);
+}
+
 // The 125 neighbour cells of cell (cx, cy, cz) (cells at least rc/2 wide,
 // so every pair closer than rc is in them) as 25 rows of five cells along
 // x; a row is one contiguous range of the cell-ordered arrays unless it
@@ -329,6 +388,7 @@ __device__ __forceinline__ bool neighbour_segment(int seg, int cx, int cy, int c
   return true;
 }
 
+template <bool P32>
 __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   __shared__ PairQueue queue[kPairWaves];
   __shared__ double sh[kPairWaves][8];
@@ -336,6 +396,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
   if (lane < kErfcxTerms) Q.cheb[lane] = kErfcxCheb[lane];
+  if (lane < kErfcxTerms32) Q.cheb32[lane] = kErfcxCheb32[lane];
   wave_sync();
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   double l[3];
@@ -350,6 +411,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   const double band = 16.0 * a.rc * lmax * 0x1.0p-24 + 8.0 * lmax * lmax * 0x1.0p-48;
   const float rc2_lo = (float)(rc2 - band), rc2_hi = (float)(rc2 + band);
   double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
+  float u32 = 0.0f, w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // FP32 option: one particle's sums
   for (int k = 0; k < kPairPerWave; ++k) {
     const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);   // the wave's i
     if (t >= a.n) break;
@@ -449,7 +511,11 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
       for (int from = 0; from < m; from += 64) {
         PairLoad cur;
         if (from + lane < m) cur = pair_load(a, Q, from + lane);
-        pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.cheb, f, u, w);
+        if (P32)
+          pair_eval32(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
+                      (float)a.alpha, Q.cheb32, f, u32, w32);
+        else
+          pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.cheb, f, u, w);
       }
       wave_sync();
       if (lane < qn - m) { Q.j[lane] = Q.j[m + lane]; Q.s[lane] = Q.s[m + lane]; }
@@ -460,6 +526,12 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
       const int i = a.list[t];
       if (a.accumulate) { a.fx[i] += f[0]; a.fy[i] += f[1]; a.fz[i] += f[2]; }
       else { a.fx[i] = f[0]; a.fy[i] = f[1]; a.fz[i] = f[2]; }
+    }
+    if (P32) {
+      u += (double)u32;
+      u32 = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) { w[q] += (double)w32[q]; w32[q] = 0.0f; }
     }
   }
   // block partial of (U, W), fixed order: wave sums, then waves in order
@@ -506,9 +578,10 @@ __global__ void __launch_bounds__(256) k_fill(RealArgs a) { fill_body(a, blockId
 __global__ void __launch_bounds__(256) k_csort(RealArgs a) { csort_body(a, blockIdx.x); }
 // four waves per SIMD: the register budget that keeps the pair evaluation
 // from spilling beyond a few registers
+template <bool P32>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_pairs(RealArgs a) {
-  pairs_body(a, blockIdx.x, gridDim.x);
+  pairs_body<P32>(a, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
@@ -517,7 +590,10 @@ hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_pairs, dim3((unsigned)pair_blocks(a.n)), dim3(kPairWaves * 64), 0, s, a);
+  if (a.prec32)
+    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)pair_blocks(a.n)), dim3(kPairWaves * 64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)pair_blocks(a.n)), dim3(kPairWaves * 64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -565,22 +641,26 @@ __global__ void __launch_bounds__(256) k_csort_m(const RealArgs* tab, const int*
   (void)nb;
   csort_body(sa, lb);
 }
+template <bool P32>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_pairs_m(const RealArgs* tab, const int* bstart, int nsys) {
   REAL_MULTI_PROLOGUE
-  pairs_body(sa, lb, nb);
+  pairs_body<P32>(sa, lb, nb);
 }
 
 // bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
 // bstart_q: pair blocks (pair_blocks(n) each)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
-                             int nsys, hipStream_t s) {
+                             int nsys, int prec32, hipStream_t s) {
   hipLaunchKernelGGL(k_bin_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_scan_m, dim3(nsys), dim3(1024), 0, s, d_tab, nsys);
   hipLaunchKernelGGL(k_fill_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
-  hipLaunchKernelGGL(k_pairs_m, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+  if (prec32)
+    hipLaunchKernelGGL(k_pairs_m<true>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+  else
+    hipLaunchKernelGGL(k_pairs_m<false>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
   return hipGetLastError();
 }
 

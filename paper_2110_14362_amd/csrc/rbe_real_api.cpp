@@ -107,7 +107,8 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
   if (cfg->n < 1) return rfail(RBE_ERR_ARG, "n = %lld must be >= 1", (long long)cfg->n);
   if (cfg->ntypes < 0 || cfg->ntypes > 64) return rfail(RBE_ERR_ARG, "ntypes = %d must be in 0..64", cfg->ntypes);
   if (cfg->ntypes > 0 && (!d_type || !h_lj)) return rfail(RBE_ERR_ARG, "ntypes > 0 needs types and LJ coefficients");
-  if (cfg->reserved != 0) return rfail(RBE_ERR_ARG, "reserved field must be 0");
+  if (cfg->precision != RBE_PREC_FP64 && cfg->precision != RBE_PREC_FP32)
+    return rfail(RBE_ERR_ARG, "unknown precision %d", cfg->precision);
   if (!(std::isfinite(cfg->alpha) && cfg->alpha > 0)) return rfail(RBE_ERR_ARG, "alpha must be positive");
   if (!(std::isfinite(cfg->rc) && cfg->rc > 0)) return rfail(RBE_ERR_ARG, "rc must be positive");
   if (!(std::isfinite(cfg->coulomb) && cfg->coulomb > 0)) return rfail(RBE_ERR_ARG, "coulomb must be positive");
@@ -117,6 +118,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
   c->stream = (hipStream_t)stream;
   RealArgs& a = c->a;
   a.n = cfg->n; a.ntypes = cfg->ntypes;
+  a.prec32 = cfg->precision == RBE_PREC_FP32 ? 1 : 0;
   a.alpha = cfg->alpha; a.rc = cfg->rc; a.coulomb = cfg->coulomb;
   long cap = 1;
   for (int d = 0; d < 3; ++d) {

@@ -30,6 +30,7 @@ struct RealArgs {
   const double* q; const int32_t* type;   // type may be NULL
   const double* lj;                        // [ntypes*ntypes][2] = (c12, c6)
   int32_t ntypes, accumulate;
+  int32_t prec32, pad;                     // 1: single-precision pair arithmetic
   int64_t n;
   double alpha, rc, coulomb;
   double box[3];                           // used when box_ptr is NULL
@@ -49,7 +50,7 @@ struct RealArgs {
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
-                             int nsys, hipStream_t s);
+                             int nsys, int prec32, hipStream_t s);
 
 // host side of rbe_real_forces without the launches
 rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,

@@ -22,7 +22,7 @@ class NPTSystem:
     """
 
     def __init__(self, sysd, md, precision="fp32", seed=0, system_id=0, momenta=None,
-                 stream=None, device="cuda:0"):
+                 stream=None, device="cuda:0", real_precision="fp64"):
         import torch
         self.torch = torch
         dev = torch.device(device)
@@ -52,7 +52,8 @@ class NPTSystem:
         if md.get("lj") is not None:
             types = torch.tensor(np.asarray(md["types"], dtype=np.int32), device=dev)
         self.real = RealSpace(q, sysd["box"], sysd["alpha"], md["rc"], coulomb=sysd["coulomb"],
-                              types=types, lj=md.get("lj"), stream=stream)
+                              types=types, lj=md.get("lj"), stream=stream,
+                              precision=real_precision)
         self.integ = Integrator(t(mass), sysd["box"], md["dt"], md["kT"], md["p_ext"],
                                 md["gamma_p"], md["gamma_cell"], md["mass_cell"],
                                 md.get("mass_cell_z", 0.0), box_mode=mode, ftm=md["ftm"],

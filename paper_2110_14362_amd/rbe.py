@@ -51,7 +51,7 @@ class Config(ctypes.Structure):
 
 
 class RealConfig(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int64), ("ntypes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("n", ctypes.c_int64), ("ntypes", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("rc", ctypes.c_double), ("coulomb", ctypes.c_double)]
 
 
@@ -65,7 +65,8 @@ class MDConfig(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_systems", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_int64)]
+                ("hbm_budget", ctypes.c_int64), ("real_precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SystemDesc(ctypes.Structure):
@@ -282,12 +283,13 @@ class RBE:
 class RealSpace:
     """Real-space Ewald pair sum (rbe_real_init ... rbe_real_destroy)."""
 
-    def __init__(self, q, box, alpha, rc, coulomb=1.0, types=None, lj=None, stream=None):
+    def __init__(self, q, box, alpha, rc, coulomb=1.0, types=None, lj=None, stream=None,
+                 precision="fp64"):
         lib = load_library()
         n = int(q.numel())
         ntypes = 0 if lj is None else int(np.asarray(lj).shape[0])
-        cfg = RealConfig(n=n, ntypes=ntypes, reserved=0, alpha=float(alpha), rc=float(rc),
-                         coulomb=float(coulomb))
+        cfg = RealConfig(n=n, ntypes=ntypes, precision=PRECISIONS[precision], alpha=float(alpha),
+                         rc=float(rc), coulomb=float(coulomb))
         boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
         ljarr = None
         if ntypes:
@@ -447,10 +449,12 @@ class Batch:
     library's kernels.
     """
 
-    def __init__(self, hbm_budget, max_systems=256, precision="fp32", stream=None):
+    def __init__(self, hbm_budget, max_systems=256, precision="fp32", stream=None,
+                 real_precision="fp64"):
         lib = load_library()
         cfg = BatchConfig(precision=PRECISIONS[precision], max_systems=int(max_systems),
-                          hbm_budget=int(hbm_budget))
+                          hbm_budget=int(hbm_budget), real_precision=PRECISIONS[real_precision],
+                          reserved=0)
         ctx = ctypes.c_void_p()
         _check(lib.rbe_batch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(ctx)))
         self._ctx = ctx

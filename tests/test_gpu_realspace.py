@@ -1,6 +1,8 @@
 """Real-space pair kernels vs the FP64 brute-force oracle (nearest image,
 cutoff), with and without the Lennard-Jones term.  Tolerance 1e-10 relative
-(both sides FP64; differences are rounding order only)."""
+for FP64 pair arithmetic (differences are rounding order only); 2e-5 for the
+FP32 option (single-precision erfc, exp and 1/sqrt, a few ulp each; FP32 sums
+over one particle's pairs)."""
 import math
 
 import numpy as np
@@ -26,7 +28,11 @@ def water_types(n):
     return (np.arange(n) % 3 != 0).astype(np.int32)      # O = 0, H = 1
 
 
-def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=None):
+TOLR = {"fp64": 1e-10, "fp32": 2e-5}
+
+
+def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=None,
+            precision="fp64"):
     import torch
     from paper_2110_14362_amd.rbe import RealSpace
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -34,7 +40,7 @@ def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=No
     lj_arr = None if lj is None else np.stack(lj, axis=-1)
     tt = None if types is None else torch.tensor(types, dtype=torch.int32, device=dev)
     ctx = RealSpace(t(s["q"]), s["box"], s["alpha"], rc, coulomb=s.get("coulomb", 1.0),
-                    types=tt, lj=lj_arr)
+                    types=tt, lj=lj_arr, precision=precision)
     x, y, z = (t(pos[:, a]) for a in range(3))
     f = [t(f0[:, a]) if f0 is not None else torch.zeros_like(x) for a in range(3)]
     vir = torch.zeros(6, dtype=torch.float64, device=dev)
@@ -65,40 +71,49 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
 
 
-def test_electrolyte_coulomb(gpu):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_electrolyte_coulomb(gpu, precision):
     s = workloads.make("electrolyte_1k")
-    g = run_gpu(s, gpu, 6.0)
+    g = run_gpu(s, gpu, 6.0, precision=precision)
     o = oracle(s, 6.0)
-    print("electrolyte real space: force %.2e virial %.2e energy %.2e" %
-          (rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
+    print("electrolyte real space %s: force %.2e virial %.2e energy %.2e" %
+          (precision, rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
            abs(g["energy"] - o["energy"]) / abs(o["energy"])))
-    assert rel(g["forces"], o["forces"]) < 1e-10
-    assert rel(g["virial"], o["virial"]) < 1e-10
-    assert abs(g["energy"] - o["energy"]) < 1e-10 * abs(o["energy"])
+    tol = TOLR[precision]
+    assert rel(g["forces"], o["forces"]) < tol
+    assert rel(g["virial"], o["virial"]) < tol
+    assert abs(g["energy"] - o["energy"]) < tol * abs(o["energy"])
 
 
-def test_water_with_lj(gpu):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_water_with_lj(gpu, precision):
     s = workloads.water(1000, seed=7)
     s.update(alpha=0.09, coulomb=332.0637)
     types = water_types(len(s["q"]))
     lj = lj_table_water()
-    g = run_gpu(s, gpu, 10.0, lj=lj, types=types)
+    g = run_gpu(s, gpu, 10.0, lj=lj, types=types, precision=precision)
     o = oracle(s, 10.0, lj=lj, types=types)
-    assert rel(g["forces"], o["forces"]) < 1e-10
-    assert rel(g["virial"], o["virial"]) < 1e-10
-    assert abs(g["energy"] - o["energy"]) < 1e-10 * abs(o["energy"])
+    print("water real space %s: force %.2e virial %.2e energy %.2e" %
+          (precision, rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
+           abs(g["energy"] - o["energy"]) / abs(o["energy"])))
+    tol = TOLR[precision]
+    assert rel(g["forces"], o["forces"]) < tol
+    assert rel(g["virial"], o["virial"]) < tol
+    assert abs(g["energy"] - o["energy"]) < tol * abs(o["energy"])
 
 
-def test_water_30k_sampled_rows(gpu):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_water_30k_sampled_rows(gpu, precision):
     s = workloads.make("water_30k")
     types = water_types(len(s["q"]))
     lj = lj_table_water()
-    g = run_gpu(s, gpu, 10.0, lj=lj, types=types)
+    g = run_gpu(s, gpu, 10.0, lj=lj, types=types, precision=precision)
     rows = np.random.default_rng(1).choice(len(s["q"]), 3000, replace=False)
     o = oracle(s, 10.0, lj=lj, types=types, rows=rows)
-    assert rel(g["forces"][rows], o["forces"]) < 1e-10
+    assert rel(g["forces"][rows], o["forces"]) < TOLR[precision]
     # Newton's third law over the whole system
-    assert np.abs(g["forces"].sum(0)).max() < 1e-9 * np.sqrt((g["forces"] ** 2).sum())
+    tol3 = 1e-9 if precision == "fp64" else 1e-5
+    assert np.abs(g["forces"].sum(0)).max() < tol3 * np.sqrt((g["forces"] ** 2).sum())
 
 
 def test_unwrapped_accumulate_and_reproducible(gpu):
