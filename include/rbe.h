@@ -250,8 +250,24 @@ rbe_status rbe_real_forces(rbe_real_ctx ctx, const double* d_x, const double* d_
                            const double* d_z, double* d_fx, double* d_fy, double* d_fz,
                            int accumulate, double* d_virial6, double* d_energy);
 
-/* Wait and report device-side flags: a cell below 2.5 rc or over capacity, or a
- * cell with more than 2048 members (its evaluation is then incomplete). */
+/* Neighbour lists (skin > 0; call once, before the first evaluation; waits):
+ * each particle keeps the pairs closer than rc + skin at the last build, and
+ * every evaluation tests them against rc with the minimum image; the lists
+ * (and the cell list, now with cells at least (rc + skin)/2 wide) are rebuilt
+ * on the device when 2 max|displacement since the build| + sqrt(3) max|cell
+ * side change| >= skin (first evaluation: always).  The same pairs as without
+ * lists, summed in the order of the list.  Needs every side >= 2.5 (rc +
+ * skin); a list holds 1.6 x the mean number of neighbours + 64 (a fuller one
+ * is flagged). */
+rbe_status rbe_real_set_skin(rbe_real_ctx ctx, double skin);
+
+/* Wait; h_stats[0] = evaluations launched on the context, h_stats[1] =
+ * neighbour-list builds among them (0 without a skin). */
+rbe_status rbe_real_list_stats(rbe_real_ctx ctx, int64_t* h_stats);
+
+/* Wait and report device-side flags: a cell below 2.5 x the search radius or
+ * over capacity, a cell with more than 2048 members, or a neighbour list over
+ * capacity (the evaluation is then incomplete). */
 rbe_status rbe_real_check(rbe_real_ctx ctx);
 
 /* Release the context (waits for the stream). */
@@ -392,6 +408,8 @@ typedef struct {
   int64_t  rigid_first;  /* rigid 3-site molecules as rbe_md_set_rigid         */
   int64_t  rigid_count;  /* (0: none)                                          */
   double   d_oh, d_hh;   /* their bond lengths                                 */
+  double   skin;         /* real-space neighbour-list skin (0: none), as       */
+                         /* rbe_real_set_skin                                  */
 } rbe_system_desc;
 
 /* stream: hipStream_t for every launch and copy of the batch (NULL: the null

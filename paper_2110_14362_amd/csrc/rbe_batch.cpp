@@ -96,6 +96,7 @@ rbe_status check_desc(const rbe_system_desc* d, const double* box) {
     return bfail(RBE_ERR_ARG, "box_mode must be RBE_BOX_ISO or RBE_BOX_SEMIISO");
   if (d->reserved != 0) return bfail(RBE_ERR_ARG, "reserved field must be 0");
   if (d->ntypes < 0 || d->ntypes > 64) return bfail(RBE_ERR_ARG, "ntypes = %d must be in 0..64", d->ntypes);
+  if (!(d->skin >= 0.0 && fin(d->skin))) return bfail(RBE_ERR_ARG, "skin = %g must be >= 0", d->skin);
   if (!(d->alpha > 0 && fin(d->alpha)) || !(d->rc > 0 && fin(d->rc)) || !(d->coulomb > 0 && fin(d->coulomb)))
     return bfail(RBE_ERR_ARG, "alpha, rc and coulomb must be positive and finite");
   for (int a = 0; a < 3; ++a)
@@ -152,7 +153,8 @@ int64_t state_bytes(int64_t n) { return round256(11 * 8 * n + 14 * 8 + 4 * n); }
 int64_t footprint(const rbe_batch_s* b, const rbe_system_desc* d, const double* box) {
   const rbe_config kc = kspace_cfg(b, d, box);
   const rbe_real_config rc = real_cfg(b, d);
-  return state_bytes(d->n) + kspace_footprint(&kc, box) + real_footprint(&rc, box) + md_footprint(d->n);
+  return state_bytes(d->n) + kspace_footprint(&kc, box) + real_footprint(&rc, box, d->skin) +
+         md_footprint(d->n);
 }
 
 void release_slot(Slot& s) {
@@ -177,7 +179,7 @@ const T* put(rbe_batch_s* b, const T* src, size_t count) {
 }
 
 size_t stage_bytes_per_system() {
-  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 8 * sizeof(int) + 8 * 64;
+  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 9 * sizeof(int) + 9 * 64;
 }
 
 }  // namespace
@@ -280,6 +282,7 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* d, const double* 
   const rbe_md_config mc = md_cfg(d);
   st = rbe_init(&kc, s.q, box_host, b->stream, &s.k);
   if (st == RBE_OK) st = rbe_real_init(&rc, s.q, d->ntypes > 0 ? s.type : nullptr, h_lj, box_host, b->stream, &s.r);
+  if (st == RBE_OK && d->skin > 0.0) st = rbe_real_set_skin(s.r, d->skin);
   if (st == RBE_OK) st = rbe_md_init(&mc, s.mass, box_host, b->stream, &s.m);
   if (st == RBE_OK && d->rigid_count > 0)
     st = rbe_md_set_rigid(s.m, d->rigid_first, d->rigid_count, d->d_oh, d->d_hh);
@@ -362,21 +365,26 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   // binning kernels: bin_blocks(n); pairs: pair_blocks(n); integrator: 256 units (rigid
   // molecules or free atoms) per block; cell sort: one block per cell of
   // the capacity
-  std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys);
+  std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys), vb(nsys);
+  int any_list = 0, any_cells = 0, max_types = 0;
   for (int j = 0; j < nsys; ++j) {
+    vb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
+    if (ra[j].skin > 0.0) any_list = 1; else any_cells = 1;
+    max_types = std::max(max_types, ra[j].ntypes);
     pb[j] = (int)bin_blocks(b->slots[act[j]].desc.n);
     ub[j] = (int)((md_units(md1[j]) + 255) / 256);
     cb[j] = ncap[j];
     qb[j] = (int)pair_blocks(b->slots[act[j]].desc.n);
   }
   const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb),
-                         qstart = prefix(qb);
+                         qstart = prefix(qb), vstart = prefix(vb);
   const MDArgs* d_md1 = put(b, md1.data(), nsys);
   const MDArgs* d_md2 = put(b, md2.data(), nsys);
   const RealArgs* d_ra = put(b, ra.data(), nsys);
   const int* d_pstart = put(b, pstart.data(), nsys + 1);
   const int* d_ustart = put(b, ustart.data(), nsys + 1);
   const int* d_qstart = put(b, qstart.data(), nsys + 1);
+  const int* d_vstart = put(b, vstart.data(), nsys + 1);
   const int* d_cstart = put(b, cstart.data(), nsys + 1);
   // structure factors grouped by lane width, forces by block shape
   struct Group { std::vector<int> idx; const StepArgs* tab; const int* start; int total; size_t lds; };
@@ -431,7 +439,8 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   mark(3);
   if (e == hipSuccess)
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
-                          qstart.back(), nsys, b->cfg.real_precision == RBE_PREC_FP32, b->stream);
+                          qstart.back(), d_vstart, vstart.back(), any_list, any_cells, max_types, nsys,
+                          b->cfg.real_precision == RBE_PREC_FP32, b->stream);
   mark(4);
   if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
   mark(5);

@@ -44,11 +44,11 @@ __device__ __forceinline__ void real_box(const RealArgs& a, double l[3]) {
   else { l[0] = a.box[0]; l[1] = a.box[1]; l[2] = a.box[2]; }
 }
 
-// cells per axis: floor(2 l / rc) (cells at least rc/2 wide), clamped to
-// [5, cap]; err bit 1 if clamped below (l < 2.5 rc)
+// cells per axis: floor(2 l / rs) (cells at least rs/2 wide, rs the search
+// radius), clamped to [5, cap]; err bit 1 if clamped below (l < 2.5 rs)
 __device__ __forceinline__ void cell_grid(const RealArgs& a, const double l[3], int nc[3], int& err) {
   for (int d = 0; d < 3; ++d) {
-    const double f = floor(2.0 * l[d] / a.rc);
+    const double f = floor(2.0 * l[d] / search_radius(a));
     int v = (f >= 5.0 && f <= (double)a.nc_cap[d]) ? (int)f : -1;
     if (v < 0) { err |= (f < 5.0 || !(f == f)) ? 2 : 0; v = (f >= 5.0) ? a.nc_cap[d] : 5; }
     nc[d] = v;
@@ -58,8 +58,14 @@ __device__ __forceinline__ void cell_grid(const RealArgs& a, const double l[3], 
 // A block bins kBinPer particles; with at most kBinLds cells it counts them
 // in LDS first and adds one total per cell to the global counts (far fewer
 // contended global atomics).
+// list mode: the cell list is rebuilt only with the neighbour lists
+__device__ __forceinline__ bool skip_cells(const RealArgs& a) {
+  return a.skin > 0.0 && __hip_atomic_load(&a.state[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
 __device__ __forceinline__ void bin_body(const RealArgs& a, int bx) {
   __shared__ int hist[kBinLds];
+  if (skip_cells(a)) return;
   double l[3];
   real_box(a, l);
   int nc[3], err = 0;
@@ -92,6 +98,7 @@ __device__ __forceinline__ void bin_body(const RealArgs& a, int bx) {
 
 __device__ __forceinline__ void scan_body(const RealArgs& a) {
   __shared__ int sh[1024];
+  if (skip_cells(a)) return;
   double l[3];
   real_box(a, l);
   int nc[3], err = 0;
@@ -129,6 +136,7 @@ __device__ __forceinline__ void scan_body(const RealArgs& a) {
 // for the block from one global atomic.
 __device__ __forceinline__ void fill_body(const RealArgs& a, int bx) {
   __shared__ int hist[kBinLds];
+  if (skip_cells(a)) return;
   const int ncell = a.grid[0] * a.grid[1] * a.grid[2];
   const bool lds = ncell <= kBinLds;
   constexpr int kPer = kBinPer / 256;
@@ -162,6 +170,7 @@ __device__ __forceinline__ void fill_body(const RealArgs& a, int bx) {
 // one block per cell: sort member indices, then gather in that order
 __device__ __forceinline__ void csort_body(const RealArgs& a, int c) {
   __shared__ int key[kCellMax];
+  if (skip_cells(a)) return;
   const int ncell = a.grid[0] * a.grid[1] * a.grid[2];
   if (c >= ncell) return;
   const int s0 = a.start[c], cnt = min(a.start[c + 1] - s0, kCellMax);
@@ -247,16 +256,23 @@ __device__ __forceinline__ double erfcx_pos(double x, const double* cheb) {
 
 // A queued pair as loaded for evaluation: j's position and charge, its
 // type, and the shift code.
+// A queued pair as loaded for evaluation: the separation x_j - x_i (the
+// image the candidate test chose), q_j and type_j.
 struct PairLoad {
-  double4 v;
-  int tj, code;
+  double ex, ey, ez, qj;
+  int tj;
 };
 
-__device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue& Q, int e) {
+// cell path: the queue holds (j, shift code); the same arithmetic as the test
+__device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue& Q, int e,
+                                              const double4& vi, const double l[3]) {
   PairLoad p;
-  const int j = Q.j[e];
-  p.code = Q.s[e];
-  p.v = a.xq[j];
+  const int j = Q.j[e], code = Q.s[e];
+  const double4 v = a.xq[j];
+  p.ex = v.x - (vi.x - l[0] * (double)(code % 3 - 1));
+  p.ey = v.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1));
+  p.ez = v.z - (vi.z - l[2] * (double)(code / 9 - 1));
+  p.qj = v.w;
   p.tj = a.ntypes > 0 ? a.ts[j] : 0;
   return p;
 }
@@ -264,29 +280,25 @@ __device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue
 // Evaluate one loaded pair per lane (lanes with valid = false add nothing):
 // the force on i is added as a wave sum (the same value in every lane, summed
 // in a fixed order); energy and virial accumulate per lane.
-__device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
-                                          const double4& vi, int ti, const double l[3], double sa,
-                                          double two_sa_pi, const double* cheb, double f[3],
-                                          double& u, double w[6]) {
-  double gx = 0.0, gy = 0.0, gz = 0.0;
+// one pair's force on i (g), energy and virial terms (FP64)
+__device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, bool valid,
+                                          const double4& vi, int ti, double sa, double two_sa_pi,
+                                          const double* cheb, const double* lj, double& gx,
+                                          double& gy, double& gz, double& u, double w[6]) {
+  gx = 0.0; gy = 0.0; gz = 0.0;
   if (valid) {
-    const double4 v = p.v;
-    const int code = p.code;
-    // the same arithmetic as the candidate test
-    const double ex = v.x - (vi.x - l[0] * (double)(code % 3 - 1));
-    const double ey = v.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1));
-    const double ez = v.z - (vi.z - l[2] * (double)(code / 9 - 1));
+    const double ex = p.ex, ey = p.ey, ez = p.ez;
     const double r2 = ex * ex + ey * ey + ez * ez;
     const double r = sqrt(r2), ir = 1.0 / r;
     // Coulomb: phi = C qi qj erfc(sa r)/r,  -phi' = C qi qj G(r)
-    const double qq = a.coulomb * vi.w * v.w;
+    const double qq = a.coulomb * vi.w * p.qj;
     const double g2 = exp(-a.alpha * r2);
     const double er = g2 * erfcx_pos(sa * r, cheb);
     double dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
     u += qq * er * ir;
     if (a.ntypes > 0) {
       const int k = ti * a.ntypes + p.tj;
-      const double c12 = a.lj[2 * k], c6 = a.lj[2 * k + 1];
+      const double c12 = lj[2 * k], c6 = lj[2 * k + 1];
       const double i2 = ir * ir, i6 = i2 * i2 * i2;
       u += c12 * i6 * i6 - c6 * i6;
       dU += (-12.0 * c12 * i6 * i6 + 6.0 * c6 * i6) * ir;
@@ -297,6 +309,14 @@ __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, 
     w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
     w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
   }
+}
+
+__device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
+                                          const double4& vi, int ti, const double l[3], double sa,
+                                          double two_sa_pi, const double* cheb, double f[3],
+                                          double& u, double w[6]) {
+  double gx, gy, gz;
+  pair_core(a, p, valid, vi, ti, sa, two_sa_pi, cheb, a.lj, gx, gy, gz, u, w);
   f[0] += wsum(gx);
   f[1] += wsum(gy);
   f[2] += wsum(gz);
@@ -325,27 +345,24 @@ __device__ __forceinline__ float wsumf(float v) {
   return v;
 }
 
-__device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p, bool valid,
-                                            const double4& vi, int ti, const double l[3], float sa,
-                                            float two_sa_pi, float alpha, const float* cheb,
-                                            double f[3], float& u, float w[6]) {
-  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+__device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p, bool valid,
+                                            const double4& vi, int ti, float sa, float two_sa_pi,
+                                            float alpha, const float* cheb, const double* lj,
+                                            float& gx, float& gy, float& gz, float& u,
+                                            float w[6]) {
+  gx = 0.0f; gy = 0.0f; gz = 0.0f;
   if (valid) {
-    const double4 v = p.v;
-    const int code = p.code;
-    const float ex = (float)(v.x - (vi.x - l[0] * (double)(code % 3 - 1)));
-    const float ey = (float)(v.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1)));
-    const float ez = (float)(v.z - (vi.z - l[2] * (double)(code / 9 - 1)));
+    const float ex = (float)p.ex, ey = (float)p.ey, ez = (float)p.ez;
     const float r2 = ex * ex + ey * ey + ez * ez;
     const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
-    const float qq = (float)(a.coulomb * vi.w * v.w);
+    const float qq = (float)(a.coulomb * vi.w * p.qj);
     const float g2 = __expf(-alpha * r2);
     const float er = g2 * erfcx_pos32(sa * r, cheb);
     float dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
     u += qq * er * ir;
     if (a.ntypes > 0) {
       const int k = ti * a.ntypes + p.tj;
-      const float c12 = (float)a.lj[2 * k], c6 = (float)a.lj[2 * k + 1];
+      const float c12 = (float)lj[2 * k], c6 = (float)lj[2 * k + 1];
       const float i2 = ir * ir, i6 = i2 * i2 * i2;
       u += c12 * i6 * i6 - c6 * i6;
       dU += (-12.0f * c12 * i6 * i6 + 6.0f * c6 * i6) * ir;
@@ -355,6 +372,14 @@ __device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p
     w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
     w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
   }
+}
+
+__device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p, bool valid,
+                                            const double4& vi, int ti, const double l[3], float sa,
+                                            float two_sa_pi, float alpha, const float* cheb,
+                                            double f[3], float& u, float w[6]) {
+  float gx, gy, gz;
+  pair_core32(a, p, valid, vi, ti, sa, two_sa_pi, alpha, cheb, a.lj, gx, gy, gz, u, w);
   f[0] += (double)wsumf(gx);
   f[1] += (double)wsumf(gy);
   f[2] += (double)wsumf(gz);
@@ -388,11 +413,102 @@ __device__ __forceinline__ bool neighbour_segment(int seg, int cx, int cy, int c
   return true;
 }
 
+// The wave's segment table for particle vi in cell c (lane s describes
+// segment s) and the segments' candidate offsets (an exclusive scan): the
+// candidates of the 125 cells become one flat list.  Returns its length.
+__device__ __forceinline__ int segment_table(const RealArgs& a, PairQueue& Q, const double4& vi,
+                                             int c, int nx, int ny, int nz, const double l[3],
+                                             int lane) {
+  const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+  int len = 0;
+  {
+    int c0 = 0, c1 = -1, code = 0;
+    if (lane < kSegments && neighbour_segment(lane, cx, cy, cz, nx, ny, nz, c0, c1, code)) {
+      const int j0 = a.start[c0];
+      len = a.start[c1 + 1] - j0;
+      Q.seg_j0[lane] = j0;
+      Q.seg_code[lane] = code;
+      Q.seg_io[lane] = make_float4((float)(vi.x - l[0] * (double)(code % 3 - 1)),
+                                   (float)(vi.y - l[1] * (double)((code / 3) % 3 - 1)),
+                                   (float)(vi.z - l[2] * (double)(code / 9 - 1)), 0.0f);
+    } else if (lane < kSegments) {
+      Q.seg_j0[lane] = 0;
+      Q.seg_code[lane] = 13;
+      Q.seg_io[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  int incl = len;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane < kSegments) Q.seg_off[lane] = incl - len;
+  const int total = uniform(__shfl(incl, kSegments - 1, 64));
+  if (lane == 0) Q.seg_off[kSegments] = total;
+  wave_sync();
+  return total;
+}
+
+// FP32 bounds of the squared search radius outside of which the FP32 test
+// decides as FP64 would: positions in [0, l] carry an error below 2^-24 l
+// each, so a squared separation near rs errs by less than 8 rs 2^-24 lmax
+__device__ __forceinline__ void radius_band(double rs, const double l[3], float& lo, float& hi) {
+  const double lmax = fmax(l[0], fmax(l[1], l[2]));
+  const double band = 16.0 * rs * lmax * 0x1.0p-24 + 8.0 * lmax * lmax * 0x1.0p-48;
+  lo = (float)(rs * rs - band);
+  hi = (float)(rs * rs + band);
+}
+
+// Block partial of (U, W) in a fixed order (wave sums, then waves in order);
+// the last-arriving block sums the partials in a fixed, parallel order and
+// writes half of each (every pair was counted from both ends).
+__device__ __forceinline__ void block_energy_virial(const RealArgs& a, double u, const double w[6],
+                                                    double (*sh)[8], int& sh_last, int bx, int nbx,
+                                                    int wave, int lane) {
+  double v[7] = {u, w[0], w[1], w[2], w[3], w[4], w[5]};
+  for (int k = 0; k < 7; ++k) {
+    const double s = wsum(v[k]);
+    if (lane == 0) sh[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    double s = 0.0;
+    for (int q = 0; q < kPairWaves; ++q) s += sh[q][threadIdx.x];
+    __hip_atomic_store(&a.part[bx * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
+  __syncthreads();
+  if (!sh_last) return;
+  // the last block: sum the block partials in a fixed order, 32 strided
+  // chunks per component in parallel, then the chunks in order
+  __shared__ double red[7][33];
+  if (threadIdx.x < 7 * 32) {
+    const int k = threadIdx.x / 32, ch = threadIdx.x % 32;
+    double s = 0.0;
+    for (int b = ch; b < nbx; b += 32)
+      s += __hip_atomic_load(&a.part[b * 8 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    red[k][ch] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    double s = 0.0;
+    for (int ch = 0; ch < 32; ++ch) s += red[threadIdx.x][ch];
+    if (threadIdx.x == 0) { if (a.energy) a.energy[0] = 0.5 * s; }
+    else if (a.virial6) a.virial6[threadIdx.x - 1] = 0.5 * s;
+  }
+  if (threadIdx.x == 0) *a.cnt = 0u;
+}
+
 template <bool P32>
 __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   __shared__ PairQueue queue[kPairWaves];
   __shared__ double sh[kPairWaves][8];
   __shared__ int sh_last;
+  if (a.skin > 0.0) return;                     // list mode: k_pairs_list
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
   if (lane < kErfcxTerms) Q.cheb[lane] = kErfcxCheb[lane];
@@ -404,12 +520,8 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   const int nx = a.grid[0], ny = a.grid[1], nz = a.grid[2];
   const double rc2 = a.rc * a.rc, sa = sqrt(a.alpha);
   const double two_sa_pi = 2.0 * sa / sqrt(M_PI);
-  // FP32 positions in [0, l] carry an error below 2^-24 l each; a squared
-  // separation below rc then errs by less than 8 rc 2^-24 lmax + O(2^-48):
-  // outside [rc2_lo, rc2_hi] the FP32 test decides as FP64 would
-  const double lmax = fmax(l[0], fmax(l[1], l[2]));
-  const double band = 16.0 * a.rc * lmax * 0x1.0p-24 + 8.0 * lmax * lmax * 0x1.0p-48;
-  const float rc2_lo = (float)(rc2 - band), rc2_hi = (float)(rc2 + band);
+  float rc2_lo, rc2_hi;
+  radius_band(a.rc, l, rc2_lo, rc2_hi);
   double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
   float u32 = 0.0f, w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // FP32 option: one particle's sums
   for (int k = 0; k < kPairPerWave; ++k) {
@@ -418,39 +530,12 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
     const double4 vi = a.xq[t];
     const int ti = uniform(a.ts[t]);
     const int c = uniform(a.cs[t]);
-    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
     double f[3] = {0.0, 0.0, 0.0};
     int qn = 0;                                   // queued pairs (wave-uniform)
     // the neighbour segments, lane s describing segment s, and their
     // candidate offsets (an exclusive scan): the candidates of the 125 cells
     // become one flat list, tested 64 at a time with every lane in use
-    int len = 0;
-    {
-      int c0 = 0, c1 = -1, code = 0;
-      if (lane < kSegments && neighbour_segment(lane, cx, cy, cz, nx, ny, nz, c0, c1, code)) {
-        const int j0 = a.start[c0];
-        len = a.start[c1 + 1] - j0;
-        Q.seg_j0[lane] = j0;
-        Q.seg_code[lane] = code;
-        Q.seg_io[lane] = make_float4((float)(vi.x - l[0] * (double)(code % 3 - 1)),
-                                     (float)(vi.y - l[1] * (double)((code / 3) % 3 - 1)),
-                                     (float)(vi.z - l[2] * (double)(code / 9 - 1)), 0.0f);
-      } else if (lane < kSegments) {
-        Q.seg_j0[lane] = 0;
-        Q.seg_code[lane] = 13;
-        Q.seg_io[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      }
-    }
-    int incl = len;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
-    }
-    if (lane < kSegments) Q.seg_off[lane] = incl - len;
-    const int total = uniform(__shfl(incl, kSegments - 1, 64));
-    if (lane == 0) Q.seg_off[kSegments] = total;
-    wave_sync();
+    const int total = segment_table(a, Q, vi, c, nx, ny, nz, l, lane);
     // Alternate between testing candidates into the queue until it is
     // nearly full (or the candidates are exhausted) and evaluating the
     // queue, so the two phases' registers are never live together.
@@ -510,7 +595,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
       const int m = done ? qn : (qn & ~63);
       for (int from = 0; from < m; from += 64) {
         PairLoad cur;
-        if (from + lane < m) cur = pair_load(a, Q, from + lane);
+        if (from + lane < m) cur = pair_load(a, Q, from + lane, vi, l);
         if (P32)
           pair_eval32(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
                       (float)a.alpha, Q.cheb32, f, u32, w32);
@@ -534,48 +619,219 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
       for (int q = 0; q < 6; ++q) { w[q] += (double)w32[q]; w32[q] = 0.0f; }
     }
   }
-  // block partial of (U, W), fixed order: wave sums, then waves in order
-  double v[7] = {u, w[0], w[1], w[2], w[3], w[4], w[5]};
-  for (int k = 0; k < 7; ++k) {
-    const double s = wsum(v[k]);
-    if (lane == 0) sh[wave][k] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 7) {
-    double s = 0.0;
-    for (int q = 0; q < kPairWaves; ++q) s += sh[q][threadIdx.x];
-    __hip_atomic_store(&a.part[bx * 8 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0)
-    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
-  __syncthreads();
-  if (!sh_last) return;
-  // the last block: sum the block partials in a fixed order, 32 strided
-  // chunks per component in parallel, then the chunks in order
-  __shared__ double red[7][33];
-  if (threadIdx.x < 7 * 32) {
-    const int k = threadIdx.x / 32, ch = threadIdx.x % 32;
-    double s = 0.0;
-    for (int b = ch; b < nbx; b += 32)
-      s += __hip_atomic_load(&a.part[b * 8 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    red[k][ch] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 7) {
-    double s = 0.0;
-    for (int ch = 0; ch < 32; ++ch) s += red[threadIdx.x][ch];
-    if (threadIdx.x == 0) { if (a.energy) a.energy[0] = 0.5 * s; }
-    else if (a.virial6) a.virial6[threadIdx.x - 1] = 0.5 * s;
-  }
-  if (threadIdx.x == 0) *a.cnt = 0u;
+  block_energy_virial(a, u, w, sh, sh_last, bx, nbx, wave, lane);
 }
 
 __global__ void __launch_bounds__(256) k_bin(RealArgs a) { bin_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(1024) k_scan(RealArgs a) { scan_body(a); }
 __global__ void __launch_bounds__(256) k_fill(RealArgs a) { fill_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(256) k_csort(RealArgs a) { csort_body(a, blockIdx.x); }
+// ---------------------------------------------------------------------------
+// neighbour lists (skin > 0)
+
+// Displacement since the last build: the block maximum of |r - r_ref|^2 into
+// *dmax (FP64 bits order as the values, all being >= 0); the last-arriving
+// block decides whether this evaluation rebuilds the lists and resets *dmax.
+__device__ __forceinline__ void vcheck_body(const RealArgs& a, int bx, int nbx) {
+  __shared__ double sh[4];
+  __shared__ int sh_last;
+  if (!(a.skin > 0.0)) return;
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
+  double d2 = 0.0;
+  if (i < a.n) {
+    const double dx = a.x[i] - a.ref[i], dy = a.y[i] - a.ref[a.n + i], dz = a.z[i] - a.ref[2 * a.n + i];
+    d2 = dx * dx + dy * dy + dz * dz;
+    if (!(d2 == d2)) d2 = 1e300;                // non-finite: rebuild (and fail there)
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, 64));
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    atomicMax(a.dmax, (unsigned long long)__double_as_longlong(m));
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    sh_last = __hip_atomic_fetch_add(a.vcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
+  __syncthreads();
+  if (!sh_last || threadIdx.x != 0) return;
+  const double dm = __longlong_as_double((long long)__hip_atomic_load(a.dmax, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT));
+  double l[3];
+  real_box(a, l);
+  double dl = 0.0;
+  for (int d = 0; d < 3; ++d) dl = fmax(dl, fabs(l[d] - a.ref_box[d]));
+  const int built = __hip_atomic_load(&a.state[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int rebuild = (built == 0 || 2.0 * sqrt(dm) + 1.7320508075688772 * dl >= a.skin) ? 1 : 0;
+  __hip_atomic_store(&a.state[0], rebuild, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a.dmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a.vcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Build the lists (a rebuilding evaluation only): a wave per particle t (cell
+// order) tests the flat candidate list of its 125 cells against rc + skin and
+// appends the cell-ordered indices in candidate order; it records the
+// reference positions and, in block 0, the reference cell.
+__device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
+  __shared__ PairQueue queue[kPairWaves];
+  if (!(a.skin > 0.0) || skip_cells(a)) return;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  PairQueue& Q = queue[wave];
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  double l[3];
+  real_box(a, l);
+  if (bx == 0 && threadIdx.x < 3) a.ref_box[threadIdx.x] = l[threadIdx.x];
+  const int nx = a.grid[0], ny = a.grid[1], nz = a.grid[2];
+  const double rs = search_radius(a), rs2 = rs * rs;
+  float lo, hi;
+  radius_band(rs, l, lo, hi);
+  for (int k = 0; k < kPairPerWave; ++k) {
+    const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);
+    if (t >= a.n) break;
+    const double4 vi = a.xq[t];
+    const int c = uniform(a.cs[t]);
+    const int total = segment_table(a, Q, vi, c, nx, ny, nz, l, lane);
+    int cnt = 0, sg = 0;
+    int32_t* out = a.nbr + (int64_t)t * a.kcap;
+    for (int base = 0; base < total; base += 64) {
+      const int cf = base + lane;
+      bool acc = false;
+      int j = -1;
+      if (cf < total) {
+        while (Q.seg_off[sg + 1] <= cf) ++sg;
+        j = Q.seg_j0[sg] + (cf - Q.seg_off[sg]);
+        if (j != t) {
+          const float4 v = a.xf[j];
+          const float4 io = Q.seg_io[sg];
+          const float ex = v.x - io.x, ey = v.y - io.y, ez = v.z - io.z;
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          if (r2 < lo) acc = true;
+          else if (r2 <= hi) {
+            const int code = Q.seg_code[sg];
+            const double4 d = a.xq[j];
+            const double dx = d.x - (vi.x - l[0] * (double)(code % 3 - 1));
+            const double dy = d.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1));
+            const double dz = d.z - (vi.z - l[2] * (double)(code / 9 - 1));
+            acc = dx * dx + dy * dy + dz * dz < rs2;
+          }
+        }
+      }
+      const uint64_t bal = __ballot(acc);
+      if (acc) {
+        const int pos = cnt + __popcll(bal & below);
+        if (pos < a.kcap) out[pos] = a.ntypes > 0 ? (j | (a.ts[j] << kListTypeShift)) : j;
+      }
+      cnt += __popcll(bal);
+    }
+    if (lane == 0) {
+      a.ncount[t] = min(cnt, a.kcap);
+      if (cnt > a.kcap) atomicOr(a.err, 8);
+      const int i = a.list[t];
+      a.ref[i] = a.x[i]; a.ref[a.n + i] = a.y[i]; a.ref[2 * a.n + i] = a.z[i];
+    }
+    wave_sync();
+  }
+  if (bx == 0 && threadIdx.x == 0)          // the build count
+    __hip_atomic_store(&a.state[1], a.state[1] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Current positions (unwrapped) and charges in the last build's cell order.
+__device__ __forceinline__ void pack_body(const RealArgs& a, int bx) {
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
+  if (!(a.skin > 0.0) || t >= a.n) return;
+  const int i = a.list[t];
+  a.xc[t] = make_double4(a.x[i], a.y[i], a.z[i], a.q[i]);
+}
+
+// Pairs from the lists: a wave per particle t; its list entries 64 at a
+// time, each lane's minimum-image separation tested against rc and the pair
+// evaluated in place (no queue: the skin keeps the accepted share high).  The
+// next batch's positions and the index batch after it are loaded while the
+// current batch is evaluated; force sums are kept per lane and summed over
+// the wave once per particle.  LJL: the Lennard-Jones table (at most
+// kLjLds types) is read from LDS, which keeps its loads off the vector-memory
+// counter the prefetched batch waits on.
+template <bool P32, bool LJL>
+__device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int nbx) {
+  __shared__ double cheb[kErfcxTerms];
+  __shared__ float cheb32[kErfcxTerms32];
+  __shared__ double ljs[LJL ? 2 * kLjLds * kLjLds : 1];
+  __shared__ double sh[kPairWaves][8];
+  __shared__ int sh_last;
+  if (!(a.skin > 0.0)) return;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  if (threadIdx.x < kErfcxTerms) cheb[threadIdx.x] = kErfcxCheb[threadIdx.x];
+  if (threadIdx.x < kErfcxTerms32) cheb32[threadIdx.x] = kErfcxCheb32[threadIdx.x];
+  if (LJL)
+    for (int q = threadIdx.x; q < 2 * a.ntypes * a.ntypes; q += blockDim.x) ljs[q] = a.lj[q];
+  __syncthreads();
+  double l[3];
+  real_box(a, l);
+  const double il[3] = {1.0 / l[0], 1.0 / l[1], 1.0 / l[2]};
+  const double rc2 = a.rc * a.rc, sa = sqrt(a.alpha);
+  const double two_sa_pi = 2.0 * sa / sqrt(M_PI);
+  double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
+  float u32 = 0.0f, w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < kPairPerWave; ++k) {
+    const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);
+    if (t >= a.n) break;
+    const int32_t* lst = a.nbr + (int64_t)t * a.kcap;
+    // the first two index batches lie inside the list's 128 slots, all of
+    // which hold valid indices
+    int jn = lst[lane], jn2 = lst[64 + lane];
+    const double4 vi = a.xc[t];
+    const int ti = uniform(a.ts[t]);
+    const int total = uniform(a.ncount[t]);
+    double4 vn = a.xc[jn & kListIdxMask];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    float fx32 = 0.0f, fy32 = 0.0f, fz32 = 0.0f;
+    for (int base = 0; base < total; base += 64) {
+      const int jc = jn;
+      const double4 vc = vn;
+      jn = jn2;
+      vn = a.xc[jn & kListIdxMask];
+      // unconditional (any slot holds a valid index): a load under a branch
+      // would make the compiler wait for the batch just requested
+      jn2 = lst[min(base + 128 + lane, a.kcap - 1)];
+      double ex = vc.x - vi.x, ey = vc.y - vi.y, ez = vc.z - vi.z;
+      ex -= l[0] * rint(ex * il[0]);
+      ey -= l[1] * rint(ey * il[1]);
+      ez -= l[2] * rint(ez * il[2]);
+      const bool valid = base + lane < total && ex * ex + ey * ey + ez * ez < rc2;
+      PairLoad p;
+      p.ex = ex; p.ey = ey; p.ez = ez;
+      p.qj = vc.w;
+      p.tj = jc >> kListTypeShift;
+      if (P32) {
+        float gx, gy, gz;
+        pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, cheb32,
+                    LJL ? ljs : a.lj, gx, gy, gz, u32, w32);
+        fx32 += gx; fy32 += gy; fz32 += gz;
+      } else {
+        double gx, gy, gz;
+        pair_core(a, p, valid, vi, ti, sa, two_sa_pi, cheb, LJL ? ljs : a.lj, gx, gy, gz, u, w);
+        fx += gx; fy += gy; fz += gz;
+      }
+    }
+    if (P32) { fx = (double)fx32; fy = (double)fy32; fz = (double)fz32; }
+    fx = wsum(fx); fy = wsum(fy); fz = wsum(fz);
+    if (lane == 0) {
+      const int i = a.list[t];
+      if (a.accumulate) { a.fx[i] += fx; a.fy[i] += fy; a.fz[i] += fz; }
+      else { a.fx[i] = fx; a.fy[i] = fy; a.fz[i] = fz; }
+    }
+    if (P32) {
+      u += (double)u32;
+      u32 = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) { w[q] += (double)w32[q]; w32[q] = 0.0f; }
+    }
+  }
+  block_energy_virial(a, u, w, sh, sh_last, bx, nbx, wave, lane);
+}
+
 // four waves per SIMD: the register budget that keeps the pair evaluation
 // from spilling beyond a few registers
 template <bool P32>
@@ -584,7 +840,39 @@ k_pairs(RealArgs a) {
   pairs_body<P32>(a, blockIdx.x, gridDim.x);
 }
 
+__global__ void __launch_bounds__(256) k_vcheck(RealArgs a) { vcheck_body(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(kPairWaves * 64) k_build(RealArgs a) { build_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_pack(RealArgs a) { pack_body(a, blockIdx.x); }
+template <bool P32, bool LJL>
+__global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
+k_pairs_list(RealArgs a) {
+  pairs_list_body<P32, LJL>(a, blockIdx.x, gridDim.x);
+}
+
+template <bool LJL>
+void launch_pairs_list(const RealArgs& a, hipStream_t s) {
+  const dim3 g((unsigned)pair_blocks(a.n)), b(kPairWaves * 64);
+  if (a.prec32) hipLaunchKernelGGL((k_pairs_list<true, LJL>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_pairs_list<false, LJL>), g, b, 0, s, a);
+}
+
+hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s) {
+  const unsigned vb = (unsigned)((a.n + 255) / 256), pb = (unsigned)bin_blocks(a.n);
+  const unsigned qb = (unsigned)pair_blocks(a.n);
+  hipLaunchKernelGGL(k_vcheck, dim3(vb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_bin, dim3(pb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_build, dim3(qb), dim3(kPairWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k_pack, dim3(vb), dim3(256), 0, s, a);
+  if (a.ntypes <= kLjLds) launch_pairs_list<true>(a, s);
+  else launch_pairs_list<false>(a, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
+  if (a.skin > 0.0) return launch_real_list(a, ncell_cap, s);
   const unsigned pb = (unsigned)bin_blocks(a.n);
   hipLaunchKernelGGL(k_bin, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
@@ -648,19 +936,57 @@ k_pairs_m(const RealArgs* tab, const int* bstart, int nsys) {
   pairs_body<P32>(sa, lb, nb);
 }
 
+__global__ void __launch_bounds__(256) k_vcheck_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  vcheck_body(sa, lb, nb);
+}
+__global__ void __launch_bounds__(kPairWaves * 64) k_build_m(const RealArgs* tab, const int* bstart,
+                                                             int nsys) {
+  REAL_MULTI_PROLOGUE
+  (void)nb;
+  build_body(sa, lb);
+}
+__global__ void __launch_bounds__(256) k_pack_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  (void)nb;
+  pack_body(sa, lb);
+}
+template <bool P32, bool LJL>
+__global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
+k_pairs_list_m(const RealArgs* tab, const int* bstart, int nsys) {
+  REAL_MULTI_PROLOGUE
+  pairs_list_body<P32, LJL>(sa, lb, nb);
+}
+
 // bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
 // bstart_q: pair blocks (pair_blocks(n) each)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
-                             int nsys, int prec32, hipStream_t s) {
+                             const int* d_bstart_v, int total_v, int any_list, int any_cells,
+                             int max_types, int nsys, int prec32, hipStream_t s) {
+  if (any_list) hipLaunchKernelGGL(k_vcheck_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
   hipLaunchKernelGGL(k_bin_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_scan_m, dim3(nsys), dim3(1024), 0, s, d_tab, nsys);
   hipLaunchKernelGGL(k_fill_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
-  if (prec32)
-    hipLaunchKernelGGL(k_pairs_m<true>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
-  else
-    hipLaunchKernelGGL(k_pairs_m<false>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+  if (any_list) {
+    hipLaunchKernelGGL(k_build_m, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+    hipLaunchKernelGGL(k_pack_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
+    const dim3 g((unsigned)total_q), b(kPairWaves * 64);
+    if (max_types <= kLjLds) {
+      if (prec32) hipLaunchKernelGGL((k_pairs_list_m<true, true>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+      else hipLaunchKernelGGL((k_pairs_list_m<false, true>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+    } else {
+      if (prec32) hipLaunchKernelGGL((k_pairs_list_m<true, false>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+      else hipLaunchKernelGGL((k_pairs_list_m<false, false>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+    }
+  }
+  if (any_cells) {
+    if (prec32)
+      hipLaunchKernelGGL(k_pairs_m<true>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+    else
+      hipLaunchKernelGGL(k_pairs_m<false>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+  }
   return hipGetLastError();
 }
 

@@ -22,8 +22,9 @@ struct rbe_real_ctx_s {
   int ncell_cap = 0;
   int nblocks = 0;
   double box0[3] = {0, 0, 0};
-  void* bufs[18] = {};
+  void* bufs[28] = {};
   int nbufs = 0;
+  int64_t evals = 0;  // evaluations launched
 };
 
 namespace {
@@ -53,7 +54,8 @@ rbe_status check_real_box(const rbe_real_ctx_s* c, const double* box) {
   if (!box) return rfail(RBE_ERR_ARG, "box pointer is NULL");
   for (int d = 0; d < 3; ++d) {
     if (!(std::isfinite(box[d]) && box[d] > 0.0)) return rfail(RBE_ERR_ARG, "box[%d] = %g is not a positive finite length", d, box[d]);
-    if (box[d] < 2.5 * c->cfg.rc) return rfail(RBE_ERR_ARG, "box[%d] = %g is below 2.5 rc = %g", d, box[d], 2.5 * c->cfg.rc);
+    const double rs = c->cfg.rc + c->a.skin;
+    if (box[d] < 2.5 * rs) return rfail(RBE_ERR_ARG, "box[%d] = %g is below 2.5 x the search radius = %g", d, box[d], 2.5 * rs);
     if (std::floor(2.0 * box[d] / c->cfg.rc) > c->a.nc_cap[d]) return rfail(RBE_ERR_CAPACITY, "box[%d] = %g exceeds the cell capacity", d, box[d]);
   }
   return RBE_OK;
@@ -73,12 +75,21 @@ rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, 
   a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
   a.accumulate = accumulate ? 1 : 0;
   a.virial6 = d_virial6; a.energy = d_energy;
+  ++c->evals;
   *out = a;
   *ncell_cap = c->ncell_cap;
   return RBE_OK;
 }
 
-int64_t real_footprint(const rbe_real_config* cfg, const double* box) {
+int32_t list_capacity(int64_t n, const double* box, double rc, double skin) {
+  const double rho = (double)n / (box[0] * box[1] * box[2]);
+  const double rs = rc + skin;
+  const double mean = rho * 4.18879020478639 * rs * rs * rs;    // (4 pi/3) rs^3 rho
+  const int64_t k = (int64_t)std::ceil(1.6 * mean + 64.0);
+  return (int32_t)std::max<int64_t>((k + 31) / 32 * 32, kListMin);
+}
+
+int64_t real_footprint(const rbe_real_config* cfg, const double* box, double skin) {
   int64_t cap = 1;
   for (int d = 0; d < 3; ++d) {
     long v = (long)std::floor(4.0 * box[d] / cfg->rc);
@@ -92,6 +103,10 @@ int64_t real_footprint(const rbe_real_config* cfg, const double* box) {
   if (cfg->ntypes > 0) t += r(4 * n) + r(16 * (int64_t)cfg->ntypes * cfg->ntypes);
   t += r(4 * n) + r(4 * cap) + r(4 * (cap + 1)) + r(4 * cap) + r(4 * n) + r(32 * n) + r(16 * n) + 2 * r(4 * n) +
        r(16) + r(64 * blocks) + r(4) + r(4);
+  if (skin > 0.0) {
+    const int64_t kc = list_capacity(n, box, cfg->rc, skin);
+    t += r(4 * n * kc) + r(4 * n) + r(24 * n) + r(24) + r(32 * n) + r(8) + r(8) + r(4);
+  }
   return t;
 }
 
@@ -197,6 +212,49 @@ rbe_status rbe_real_forces(rbe_real_ctx c, const double* d_x, const double* d_y,
   return RBE_OK;
 }
 
+rbe_status rbe_real_set_skin(rbe_real_ctx c, double skin) {
+  if (!c) return rfail(RBE_ERR_ARG, "NULL context");
+  if (!(skin >= 0.0 && std::isfinite(skin))) return rfail(RBE_ERR_ARG, "skin = %g must be >= 0", skin);
+  if (c->a.skin > 0.0) return rfail(RBE_ERR_STATE, "the skin is set already");
+  if (skin == 0.0) return RBE_OK;
+  RealArgs& a = c->a;
+  const double rs = a.rc + skin;
+  for (int d = 0; d < 3; ++d)
+    if (c->box0[d] < 2.5 * rs)
+      return rfail(RBE_ERR_ARG, "box[%d] = %g is below 2.5 (rc + skin) = %g", d, c->box0[d], 2.5 * rs);
+  if (a.n > kListIdxMask + 1)
+    return rfail(RBE_ERR_ARG, "n = %lld: neighbour lists take at most 2^25 particles", (long long)a.n);
+  const size_t n = (size_t)a.n;
+  const int32_t kc = list_capacity(a.n, c->box0, a.rc, skin);
+  bool ok = ralloc(c, &a.nbr, n * (size_t)kc) && ralloc(c, &a.ncount, n) && ralloc(c, &a.ref, 3 * n) &&
+            ralloc(c, &a.ref_box, 3) && ralloc(c, &a.xc, n) && ralloc(c, &a.dmax, 1) &&
+            ralloc(c, &a.state, 2) && ralloc(c, &a.vcnt, 1);
+  if (!ok) return rfail(RBE_ERR_ALLOC, "device allocation of the neighbour lists failed");
+  hipError_t e = hipMemsetAsync(a.dmax, 0, sizeof(unsigned long long), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(a.state, 0, 2 * sizeof(int32_t), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(a.vcnt, 0, sizeof(uint32_t), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(a.ref, 0, 3 * n * sizeof(double), c->stream);
+  // every list slot holds a valid index from the start (the pair kernel reads
+  // the first 128 slots of a list before its length is known)
+  if (e == hipSuccess) e = hipMemsetAsync(a.nbr, 0, n * (size_t)kc * sizeof(int32_t), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return rfail(RBE_ERR_DEVICE, "list set-up: %s", hipGetErrorString(e));
+  a.kcap = kc;
+  a.skin = skin;
+  return RBE_OK;
+}
+
+rbe_status rbe_real_list_stats(rbe_real_ctx c, int64_t* h_stats) {
+  if (!c || !h_stats) return rfail(RBE_ERR_ARG, "NULL argument");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return rfail(RBE_ERR_DEVICE, "hipStreamSynchronize failed");
+  int32_t st[2] = {0, 0};
+  if (c->a.skin > 0.0 && hipMemcpy(st, c->a.state, sizeof st, hipMemcpyDeviceToHost) != hipSuccess)
+    return rfail(RBE_ERR_DEVICE, "read the list state");
+  h_stats[0] = c->evals;
+  h_stats[1] = st[1];
+  return RBE_OK;
+}
+
 rbe_status rbe_real_check(rbe_real_ctx c) {
   if (!c) return rfail(RBE_ERR_ARG, "NULL context");
   if (hipStreamSynchronize(c->stream) != hipSuccess) return rfail(RBE_ERR_DEVICE, "hipStreamSynchronize failed");
@@ -205,8 +263,9 @@ rbe_status rbe_real_check(rbe_real_ctx c) {
   if (err) {
     const int32_t zero = 0;
     (void)hipMemcpy(c->a.err, &zero, sizeof zero, hipMemcpyHostToDevice);
-    return rfail(RBE_ERR_CAPACITY, "real space: %s%s", (err & 2) ? "cell below rc or over capacity; " : "",
-                 (err & 4) ? "a cell holds more than 2048 particles" : "");
+    return rfail(RBE_ERR_CAPACITY, "real space: %s%s%s", (err & 2) ? "cell below 2.5 x the search radius or over capacity; " : "",
+                 (err & 4) ? "a cell holds more than 2048 particles; " : "",
+                 (err & 8) ? "a neighbour list over capacity" : "");
   }
   return RBE_OK;
 }

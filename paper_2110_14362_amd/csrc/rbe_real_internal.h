@@ -12,6 +12,12 @@ constexpr int kPairWaves = 4;      // pair kernel: waves per block
 constexpr int kPairPerWave = 1;    // particles i a wave takes in turn
 constexpr int kPairPerBlock = kPairWaves * kPairPerWave;
 constexpr int kPairQueue = 512;    // accepted-pair queue of a wave
+// neighbour-list entries: the cell-order index in the low 25 bits, the
+// Lennard-Jones type above them; lists hold at least 128 entries
+constexpr int kListTypeShift = 25;
+constexpr int kListIdxMask = (1 << kListTypeShift) - 1;
+constexpr int kListMin = 128;
+constexpr int kLjLds = 16;         // list pair kernel: LJ table in LDS up to this many types
 constexpr int kSegments = 50;      // neighbour segments: 25 rows of 5 cells, split at x wraps
 
 constexpr int kBinPer = 2048;      // particles a binning block takes (256 threads)
@@ -44,19 +50,41 @@ struct RealArgs {
   int32_t* grid;                           // cells per axis of the last binning
   double* part;                            // [pair_blocks(n)][8]
   uint32_t* cnt;
-  int32_t* err;                            // bit 1: rc > 2l/5 or cell cap; bit 2: cell overflow
+  int32_t* err;                            // bit 1: rc > 2l/5 or cell cap; bit 2: cell overflow;
+                                           // bit 3: a neighbour list over capacity
+  // neighbour lists (skin > 0): pairs closer than rc + skin at the last
+  // build, rebuilt when 2 max|displacement| + sqrt(3) max|cell change| >= skin
+  double skin;
+  int32_t kcap, pad2;                      // list slots per particle
+  int32_t* nbr;                            // [n][kcap] cell-ordered j of particle t (cell order)
+  int32_t* ncount;                         // [n] list lengths
+  double* ref;                             // [3][n] positions at the last build (input order)
+  double* ref_box;                         // [3] cell at the last build
+  double4* xc;                             // [n] current positions (unwrapped) and q, cell order
+  unsigned long long* dmax;                // max squared displacement (FP64 bits)
+  int32_t* state;                          // [0] 1: this evaluation rebuilds; [1] 1: built once
+  uint32_t* vcnt;                          // arrival counter of the check kernel
 };
 
+// search radius of the cell grid: the cutoff, plus the skin with lists
+__host__ __device__ inline double search_radius(const RealArgs& a) { return a.rc + a.skin; }
+
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
+// list-mode evaluation (a.skin > 0): check, conditional rebuild, pack, pairs
+hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
-                             int nsys, int prec32, hipStream_t s);
+                             const int* d_bstart_v, int total_v, int any_list, int any_cells,
+                             int max_types, int nsys, int prec32, hipStream_t s);
 
 // host side of rbe_real_forces without the launches
 rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,
                           double* d_fx, double* d_fy, double* d_fz, int accumulate,
                           double* d_virial6, double* d_energy, RealArgs* out, int* ncell_cap);
-// device bytes rbe_real_init allocates (each buffer rounded up to 256 bytes)
-int64_t real_footprint(const rbe_real_config* cfg, const double* box);
+// device bytes rbe_real_init allocates (each buffer rounded up to 256 bytes),
+// plus the neighbour lists of rbe_real_set_skin when skin > 0
+int64_t real_footprint(const rbe_real_config* cfg, const double* box, double skin = 0.0);
+// list slots per particle for a skin (rbe_real_set_skin)
+int32_t list_capacity(int64_t n, const double* box, double rc, double skin);
 
 }  // namespace rbe

@@ -18,7 +18,7 @@ class NPTSystem:
         ftm, box_mode ('iso' or 'semiiso'), rc; optional types + lj for the
         real-space Lennard-Jones term; optional rigid = dict(first, count,
         d_oh, d_hh) for rigid 3-site molecules (whole, not split by the
-        periodic boundary).
+        periodic boundary); optional skin (> 0: real-space neighbour lists).
     """
 
     def __init__(self, sysd, md, precision="fp32", seed=0, system_id=0, momenta=None,
@@ -54,6 +54,8 @@ class NPTSystem:
         self.real = RealSpace(q, sysd["box"], sysd["alpha"], md["rc"], coulomb=sysd["coulomb"],
                               types=types, lj=md.get("lj"), stream=stream,
                               precision=real_precision)
+        if md.get("skin", 0.0) > 0.0:
+            self.real.set_skin(md["skin"])
         self.integ = Integrator(t(mass), sysd["box"], md["dt"], md["kT"], md["p_ext"],
                                 md["gamma_p"], md["gamma_cell"], md["mass_cell"],
                                 md.get("mass_cell_z", 0.0), box_mode=mode, ftm=md["ftm"],

@@ -29,7 +29,7 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_real_check", "rbe_real_destroy",
            "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
            "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy",
-           "rbe_md_set_rigid",
+           "rbe_md_set_rigid", "rbe_real_set_skin", "rbe_real_list_stats",
            "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
            "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy",
@@ -78,7 +78,7 @@ class SystemDesc(ctypes.Structure):
                 ("mass_cell", ctypes.c_double), ("mass_cell_z", ctypes.c_double),
                 ("ftm", ctypes.c_double), ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64),
                 ("rigid_first", ctypes.c_int64), ("rigid_count", ctypes.c_int64),
-                ("d_oh", ctypes.c_double), ("d_hh", ctypes.c_double)]
+                ("d_oh", ctypes.c_double), ("d_hh", ctypes.c_double), ("skin", ctypes.c_double)]
 
 
 _lib = None
@@ -115,6 +115,8 @@ def load_library(path=LIB_PATH):
         "rbe_real_set_box_dev": [vp, vp],
         "rbe_real_forces": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "rbe_real_check": [vp],
+        "rbe_real_set_skin": [vp, ctypes.c_double],
+        "rbe_real_list_stats": [vp, ctypes.POINTER(ctypes.c_int64)],
         "rbe_md_init": [ctypes.POINTER(MDConfig), vp, dp, vp, ctypes.POINTER(vp)],
         "rbe_md_pressure": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "rbe_md_set_rigid": [vp, i64, i64, ctypes.c_double, ctypes.c_double],
@@ -318,6 +320,15 @@ class RealSpace:
         boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
         _check(_lib.rbe_real_set_box(self._ctx, boxarr))
 
+    def set_skin(self, skin):
+        _check(_lib.rbe_real_set_skin(self._ctx, float(skin)))
+
+    def list_stats(self):
+        """(evaluations, neighbour-list builds) so far; waits for the stream."""
+        h = (ctypes.c_int64 * 2)()
+        _check(_lib.rbe_real_list_stats(self._ctx, h))
+        return int(h[0]), int(h[1])
+
     def set_box_dev(self, d_box):
         _check(_lib.rbe_real_set_box_dev(self._ctx, _dptr(d_box, "box", 3)))
 
@@ -432,6 +443,7 @@ def system_desc(n, p, alpha, coulomb, rc, md, ntypes=0, seed=0, system_id=0):
     rg = md.get("rigid") or dict(first=0, count=0, d_oh=0.0, d_hh=0.0)
     return SystemDesc(rigid_first=int(rg["first"]), rigid_count=int(rg["count"]),
                       d_oh=float(rg["d_oh"]), d_hh=float(rg["d_hh"]),
+                      skin=float(md.get("skin", 0.0)),
                       n=int(n), p=int(p), ntypes=int(ntypes),
                       box_mode=BOX_MODES[md.get("box_mode", "iso")], reserved=0,
                       alpha=float(alpha), coulomb=float(coulomb), rc=float(rc),

@@ -54,13 +54,16 @@ class Request:
 
 
 def make_requests(count, seed=2110143625, kinds=("ions",), nmin=1000, nmax=200000, p=100,
-                  steps=20):
-    """The served stream's systems (arrival times are set by the caller)."""
+                  steps=20, skin=0.0):
+    """The served stream's systems (arrival times are set by the caller);
+    skin > 0: real-space neighbour lists with at most that skin."""
     reqs = []
     for i in range(count):
         s = workloads.serving_request(i, seed=seed, nmin=nmin, nmax=nmax, p=p, steps=steps,
                                       kinds=kinds)
         md = workloads.npt_real(s["box"], rc=s["rc"])
+        if skin > 0.0:
+            md["skin"] = workloads.list_skin(s["box"], s["rc"], skin)
         if s.get("rigid"):
             md["rigid"] = s["rigid"]
         reqs.append(Request(i, 0.0, s, md, steps))

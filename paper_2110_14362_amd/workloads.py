@@ -314,6 +314,15 @@ def serving_request(i, seed=2110143625, nmin=1000, nmax=200000, p=100, steps=20,
     return s
 
 
+def list_skin(box, rc, skin, margin=2.6):
+    """The real-space neighbour-list skin a box allows: at most `skin`, with
+    margin x (rc + skin) within the shortest side (the kernels need 2.5; the
+    rest leaves room for the barostat to shrink the cell); 0 (no lists) when
+    less than a tenth of an angstrom would remain."""
+    s = min(float(skin), float(np.min(box)) / margin - rc)
+    return s if s >= 0.1 else 0.0
+
+
 # SPC/E oxygen-oxygen Lennard-Jones (sigma 3.166 A, epsilon 0.650 kJ/mol)
 SPCE_SIGMA, SPCE_EPS = 3.166, 0.1553   # A, kcal/mol
 D_OH = R_OH

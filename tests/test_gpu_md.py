@@ -57,7 +57,22 @@ def rigid_water_setup():
     return s, md, mom
 
 
-@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup, rigid_water_setup])
+def electrolyte_lists_setup():
+    # real-space neighbour lists (skin 1.5): the trajectory is unchanged
+    s, md, mom = electrolyte_setup()
+    md["skin"] = 1.5
+    return s, md, mom
+
+
+def rigid_water_lists_setup():
+    s, md, mom = rigid_water_setup()
+    md["skin"] = workloads.list_skin(s["box"], md["rc"], 1.0)
+    assert md["skin"] > 0.5
+    return s, md, mom
+
+
+@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup, rigid_water_setup,
+                                   electrolyte_lists_setup, rigid_water_lists_setup])
 def test_npt_trajectory_matches_oracle(gpu, setup):
     from paper_2110_14362_amd.md import NPTSystem
     s, md, mom = setup()

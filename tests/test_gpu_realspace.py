@@ -31,16 +31,22 @@ def water_types(n):
 TOLR = {"fp64": 1e-10, "fp32": 2e-5}
 
 
-def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=None,
-            precision="fp64"):
+def make_ctx(s, dev, rc, lj=None, types=None, precision="fp64", skin=0.0):
     import torch
     from paper_2110_14362_amd.rbe import RealSpace
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    pos = s["pos"] if shift is None else s["pos"] + shift
     lj_arr = None if lj is None else np.stack(lj, axis=-1)
     tt = None if types is None else torch.tensor(types, dtype=torch.int32, device=dev)
     ctx = RealSpace(t(s["q"]), s["box"], s["alpha"], rc, coulomb=s.get("coulomb", 1.0),
                     types=tt, lj=lj_arr, precision=precision)
+    if skin > 0.0:
+        ctx.set_skin(skin)
+    return ctx
+
+
+def evaluate(ctx, dev, pos, accumulate=False, f0=None):
+    import torch
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     x, y, z = (t(pos[:, a]) for a in range(3))
     f = [t(f0[:, a]) if f0 is not None else torch.zeros_like(x) for a in range(3)]
     vir = torch.zeros(6, dtype=torch.float64, device=dev)
@@ -49,8 +55,15 @@ def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=No
     ctx.check()
     W6 = vir.cpu().numpy()
     W = np.array([[W6[0], W6[3], W6[4]], [W6[3], W6[1], W6[5]], [W6[4], W6[5], W6[2]]])
-    out = dict(forces=np.stack([a.cpu().numpy() for a in f], 1), virial=W,
-               energy=float(en.cpu()[0]))
+    return dict(forces=np.stack([a.cpu().numpy() for a in f], 1), virial=W,
+                energy=float(en.cpu()[0]))
+
+
+def run_gpu(s, dev, rc, lj=None, types=None, accumulate=False, f0=None, shift=None,
+            precision="fp64", skin=0.0):
+    pos = s["pos"] if shift is None else s["pos"] + shift
+    ctx = make_ctx(s, dev, rc, lj=lj, types=types, precision=precision, skin=skin)
+    out = evaluate(ctx, dev, pos, accumulate=accumulate, f0=f0)
     ctx.close()
     return out
 
@@ -137,3 +150,110 @@ def test_rejects_cutoff_above_two_fifths_of_box(gpu):
     q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
     with pytest.raises(RBEError):
         RealSpace(q, (10.0, 10.0, 10.0), 0.3, 4.5)
+
+
+# ---------------------------------------------------------------------------
+# neighbour lists (a skin): the lists are built at the first evaluation and
+# rebuilt only when 2 max|displacement| + sqrt(3) max|box change| reaches the
+# skin; every evaluation must still equal the brute-force sum at rc.
+
+def moved(pos, rng, step):
+    """pos with every particle moved by exactly `step` in a random direction."""
+    d = rng.standard_normal(pos.shape)
+    return pos + step * d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def check_frame(g, o, tol, what):
+    print("%s: force %.2e virial %.2e energy %.2e" %
+          (what, rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
+           abs(g["energy"] - o["energy"]) / abs(o["energy"])), flush=True)
+    assert rel(g["forces"], o["forces"]) < tol
+    assert rel(g["virial"], o["virial"]) < tol
+    assert abs(g["energy"] - o["energy"]) < tol * abs(o["energy"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lists_follow_moves_and_box_changes(gpu, precision):
+    s = workloads.make("electrolyte_1k")          # L = 20, rc = 6: skin up to 2
+    rc, skin = 6.0, 1.5
+    rng = np.random.default_rng(41)
+    box0 = np.asarray(s["box"], dtype=np.float64)
+    p0 = s["pos"]
+    p1 = moved(p0, rng, 0.2 * skin)               # 2 x 0.3 < 1.5: lists kept
+    p2 = moved(p0, rng, 0.6 * skin)               # 2 x 0.9 >= 1.5: rebuilt
+    box3 = box0 * 1.003                           # scaled cell and positions: kept
+    p3 = p2 * 1.003
+    shift = rng.integers(-1, 2, size=p0.shape) * box3
+    p4 = p3 + shift                               # images of p3: rebuilt, same forces
+    frames = [(p0, box0, "first build"), (p1, box0, "lists kept"), (p2, box0, "rebuilt"),
+              (p3, box3, "scaled cell, lists kept"), (p4, box3, "whole-box jumps")]
+    ctx = make_ctx(s, gpu, rc, precision=precision, skin=skin)
+    tol = TOLR[precision]
+    for pos, box, what in frames:
+        if box is not box0:
+            ctx.set_box(box)
+        g = evaluate(ctx, gpu, pos)
+        o = orsp.realspace_nearest(pos, s["q"], box, s["alpha"], rc, coulomb=s["coulomb"])
+        check_frame(g, o, tol, "%s %s" % (precision, what))
+    assert ctx.list_stats() == (5, 3)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lists_water_with_lj(gpu, precision):
+    s = workloads.water(1000, seed=7)
+    s.update(alpha=0.09, coulomb=332.0637)
+    types = water_types(len(s["q"]))
+    lj = lj_table_water()
+    rc, skin = 10.0, 2.0                          # L = 31.0: 2.5 (rc + skin) fits
+    ctx = make_ctx(s, gpu, rc, lj=lj, types=types, precision=precision, skin=skin)
+    rng = np.random.default_rng(43)
+    for k, step in enumerate((0.0, 0.3 * skin, 0.45 * skin)):
+        pos = moved(s["pos"], rng, step) if step > 0 else s["pos"]
+        g = evaluate(ctx, gpu, pos)
+        sk = dict(s, pos=pos)
+        check_frame(g, oracle(sk, rc, lj=lj, types=types), TOLR[precision],
+                    "water lists %s frame %d" % (precision, k))
+    assert ctx.list_stats() == (3, 1)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lists_water_30k_sampled_rows(gpu, precision):
+    s = workloads.make("water_30k")
+    types = water_types(len(s["q"]))
+    lj = lj_table_water()
+    cells = run_gpu(s, gpu, 10.0, lj=lj, types=types, precision=precision)
+    g = run_gpu(s, gpu, 10.0, lj=lj, types=types, precision=precision, skin=2.0)
+    rows = np.random.default_rng(5).choice(len(s["q"]), 3000, replace=False)
+    o = oracle(s, 10.0, lj=lj, types=types, rows=rows)
+    assert rel(g["forces"][rows], o["forces"]) < TOLR[precision]
+    # the same pairs as the cell path's
+    assert rel(g["forces"], cells["forces"]) < TOLR[precision]
+    assert rel(g["virial"], cells["virial"]) < TOLR[precision]
+
+
+def test_list_overflow_is_flagged(gpu):
+    # 300 particles packed in a 3 A ball: far more neighbours than the
+    # capacity sized from the mean density; the host check reports it
+    from paper_2110_14362_amd.rbe import RBEError
+    rng = np.random.default_rng(47)
+    n = 300
+    d = rng.standard_normal((n, 3))
+    pos = 10.0 + 3.0 * d / np.linalg.norm(d, axis=1, keepdims=True) * rng.random((n, 1))
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    s = dict(pos=pos, q=q, box=np.array([20.0, 20.0, 20.0]), alpha=0.09, coulomb=1.0)
+    ctx = make_ctx(s, gpu, 6.0, skin=1.0)
+    with pytest.raises(RBEError):
+        evaluate(ctx, gpu, pos)
+    ctx.close()
+
+
+def test_skin_rejected_when_box_too_small(gpu):
+    import torch
+    from paper_2110_14362_amd.rbe import RealSpace, RBEError
+    q = torch.tensor([1.0, -1.0], dtype=torch.float64, device=gpu)
+    ctx = RealSpace(q, (20.0, 20.0, 20.0), 0.3, 6.0)
+    with pytest.raises(RBEError):
+        ctx.set_skin(2.5)                         # 2.5 x 8.5 > 20
+    ctx.close()

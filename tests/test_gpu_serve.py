@@ -35,7 +35,9 @@ def run_alone(r, steps, fused=True, precision="fp32"):
 
 
 def test_alone_equals_mix_bitwise(gpu):
-    reqs = [request(0, 1500), request(1, 4000, kinds=("water",)), request(2, 9000)]
+    # the water system keeps real-space neighbour lists, the ions do not
+    reqs = [request(0, 1500), request(1, 4000, kinds=("water",), skin=2.0), request(2, 9000)]
+    assert reqs[1].md["skin"] > 0.0 and "skin" not in reqs[0].md
     print("sizes", [r.n for r in reqs], "boxes", [r.sysd["box"].round(2).tolist() for r in reqs],
           flush=True)
     b = Batch(BUDGET, max_systems=8, precision="fp32")
@@ -78,9 +80,10 @@ def test_served_equals_one_system_api(gpu):
     np.testing.assert_array_equal(g["mom"], ref["mom"])
 
 
-@pytest.mark.parametrize("kind", ["ions", "water"])
-def test_served_trajectory_matches_oracle(gpu, kind):
-    r = request(4, 1000, kinds=(kind,))
+@pytest.mark.parametrize("kind,skin", [("ions", 0.0), ("water", 0.0), ("water", 1.0)])
+def test_served_trajectory_matches_oracle(gpu, kind, skin):
+    r = request(4, 1000, kinds=(kind,), skin=skin)
+    assert r.md.get("skin", 0.0) == skin
     steps = 3
     got = run_alone(r, steps, precision="fp64")
     md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"], rigid=r.sysd.get("rigid"))
@@ -89,8 +92,8 @@ def test_served_trajectory_matches_oracle(gpu, kind):
     dpos = np.abs(got["pos"] - o["pos"]).max()
     dmom = np.abs(got["mom"] - o["mom"]).max() / np.abs(o["mom"]).max()
     dbox = np.abs(got["box"] - o["box"]).max() / o["box"].max()
-    print("served %s N=%d: max |dr| %.2e, rel |dp| %.2e, rel |dl| %.2e"
-          % (kind, r.n, dpos, dmom, dbox), flush=True)
+    print("served %s N=%d skin %g: max |dr| %.2e, rel |dp| %.2e, rel |dl| %.2e"
+          % (kind, r.n, skin, dpos, dmom, dbox), flush=True)
     assert dpos < 1e-9 and dmom < 1e-9 and dbox < 1e-11
 
 
@@ -115,7 +118,7 @@ def test_admission_respects_budget(gpu):
 
 def test_served_stream_runs(gpu):
     reqs = serve.make_requests(12, seed=9100, nmin=1000, nmax=20000, steps=5,
-                               kinds=("ions", "water"))
+                               kinds=("ions", "water"), skin=2.0)
     for r, t in zip(reqs, serve.poisson_arrivals(len(reqs), rate=400.0)):
         r.arrival = float(t)
     b = Batch(BUDGET, max_systems=16, precision="fp32")
