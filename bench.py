@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=120,
                     help="requests of the served stream (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--skin", type=float, default=1.0,
+                    help="real-space neighbour-list skin (A) of the full NPT step and the "
+                         "served stream (0: cell lists every step)")
     ap.add_argument("--precision-sweep", action="store_true",
                     help="only run the precision sweep on the 10^6-charge water (P = 100, "
                          "500, 2000; FP64 and FP32 paths against the oracle) and exit")
@@ -175,10 +178,11 @@ def large_roofline(steps, precision, torch):
     return out
 
 
-def md_ns_per_day(steps, precision, torch):
+def md_ns_per_day(steps, precision, torch, skin=0.0, real_precision="fp64"):
     """Full NPT step of the 30k-charge rigid water (10,000 molecules at 1 g/cm^3,
     L = 66.88 A, g = 0.3/A, r_c = 10 A, P = 100, 1 fs, 300 K, 1 atm): every
-    kernel of the step, one system, per-system launches."""
+    kernel of the step, one system, per-system launches; skin > 0: real-space
+    neighbour lists (rebuilds counted)."""
     from paper_2110_14362_amd import workloads
     from paper_2110_14362_amd.rbe import Batch, system_desc
     c = workloads.CONFIGS["water_30k"]
@@ -186,20 +190,24 @@ def md_ns_per_day(steps, precision, torch):
     g, rc = c["g"], c["rc"]
     md = workloads.npt_real(s["box"], rc=rc)
     md["rigid"] = s["rigid"]
+    if skin > 0.0:
+        md["skin"] = skin
     n = len(s["q"])
     desc = system_desc(n, c["p"], g * g, workloads.COULOMB_REAL, rc, md, ntypes=3, seed=1,
                        system_id=1)
-    b = Batch(1 << 32, max_systems=1, precision=precision)
+    b = Batch(1 << 32, max_systems=1, precision=precision, real_precision=real_precision)
     slot = b.admit(desc, s["pos"], s["q"], s["mass"], s["box"], types=s["types"], lj=s["lj"])
     for _ in range(20):
         b.step(fused=False)
     b.sync()
+    ev0, bu0 = b.list_stats(slot)
     t0 = time.perf_counter()
     for _ in range(steps):
         b.step(fused=False)
     b.sync()
     el = time.perf_counter() - t0
     b.check(slot)
+    ev1, bu1 = b.list_stats(slot)
     st = b.read(slot)
     b.close()
     t_step = el / steps
@@ -208,26 +216,30 @@ def md_ns_per_day(steps, precision, torch):
             "workload": "rigid 3-site water, %d molecules, N = %d, box %.2f A, g = %.2f/A, "
                         "r_c = %.0f A, P = %d, NPT 300 K / 1 atm" % (c["n_mol"], n, s["box"][0],
                                                                    g, rc, c["p"]),
-            "step": "integrator first half | Fourier part (%s) | cell list + pairs (FP64) | "
-                    "integrator second half" % precision,
+            "step": "integrator first half | Fourier part (%s) | real-space pairs (%s, %s) | "
+                    "integrator second half" % (precision, real_precision.upper(),
+                                                "neighbour lists, skin %.1f A" % skin
+                                                if skin > 0 else "cell lists"),
+            "list_builds_per_step": (bu1 - bu0) / max(ev1 - ev0, 1),
             "final_box_A": float(st["box"][0])}
 
 
-def served_stream(nreq, budget_gib, precision):
+def served_stream(nreq, budget_gib, precision, skin=0.0):
     """Served mixed-size NPT stream: requests of N log-uniform in [1e3, 2e5]
     (half ions, half rigid water), cubic or 1:1:1.25 cells at 0.100284
-    charges/A^3, P = 100, 20 NPT steps each.  One system at a time, back to
+    charges/A^3, P = 100, 20 NPT steps each, real-space neighbour lists with
+    up to `skin` (as the box allows).  One system at a time, back to
     back, first (the serial capacity); then Poisson arrivals at 0.8 of it,
     served one system at a time (first come, first served) and with
     continuous batching (fused launches); then all requests at once
     (saturated, fused)."""
     from paper_2110_14362_amd import serve
     from paper_2110_14362_amd.rbe import Batch
-    reqs = serve.make_requests(nreq, kinds=("ions", "water"))
+    reqs = serve.make_requests(nreq, kinds=("ions", "water"), skin=skin)
     budget = int(budget_gib * (1 << 30))
     b = Batch(budget, max_systems=1024, precision=precision)
     warm = serve.make_requests(3, seed=77, kinds=("ions", "water"), nmin=2000, nmax=20000,
-                               steps=3)
+                               steps=3, skin=skin)
     serve.serve_serial(b, warm)
     ser = serve.serve_serial(b, reqs)
     note("served: serial %.2f s" % ser["wall_s"])
@@ -426,10 +438,15 @@ def main():
         out["saturated_1m_p2000"] = large_roofline(args.large_steps, args.precision, torch)
     if args.workload == "water_30k" and args.md_steps > 0:
         note("full NPT step")
-        out["ns_per_day"] = md_ns_per_day(args.md_steps, args.precision, torch)
+        out["ns_per_day"] = md_ns_per_day(args.md_steps, args.precision, torch, skin=args.skin)
+        out["ns_per_day_variants"] = {
+            "cell_lists_fp64": md_ns_per_day(args.md_steps, args.precision, torch, skin=0.0),
+            "fp32_pairs": md_ns_per_day(args.md_steps, args.precision, torch, skin=args.skin,
+                                        real_precision="fp32")}
     if args.workload == "water_30k" and args.serve_requests > 0:
         note("served stream")
-        out["served"] = served_stream(args.serve_requests, args.serve_budget_gib, args.precision)
+        out["served"] = served_stream(args.serve_requests, args.serve_budget_gib, args.precision,
+                                      skin=args.skin)
     print(json.dumps(out), flush=True)
 
 

@@ -69,6 +69,16 @@ typedef enum {
   RBE_PREC_FP32 = 1
 } rbe_precision;
 
+typedef enum {
+  /* Exact independent draws of the law of eq. (probexpression) every step
+     (inverse CDF per axis; the default).                                      */
+  RBE_SAMPLER_EXACT = 0,
+  /* Section 4.3, online approach: P Metropolis-Hastings chains, one per batch
+     slot, carried from step to step; rounded continuous Gaussian proposal
+     (see rbe_set_sampler).                                                    */
+  RBE_SAMPLER_MH = 1
+} rbe_sampler;
+
 typedef struct {
   int64_t  n;          /* number of charges, >= 1                              */
   int32_t  p;          /* batch size: frequencies per step, 1..65536; one
@@ -124,6 +134,21 @@ rbe_status rbe_rescale_box_dev(rbe_ctx ctx, const double* d_box);
  * batch for the same cell.  Uses the cell of the last rescale.  Recorded here
  * and drawn inside the next rbe_forces_pressure (or by rbe_get_k). */
 rbe_status rbe_sample_k(rbe_ctx ctx, uint64_t step);
+
+/* Choose how rbe_sample_k draws the batch.  RBE_SAMPLER_MH (section 4.3,
+ * online approach): chain l of the P chains keeps its frequency m_l from the
+ * previous sampled step and takes `iters` (1..64) Metropolis-Hastings moves
+ * towards the law of the current cell: per axis exp(-m^2/(2 sigma_j^2)),
+ * sigma_j = sqrt(alpha) l_j/(pi sqrt 2), m != 0.  Proposal: z ~ N(0, sigma_j^2)
+ * per axis, m'_j = floor(z + 1/2), pmf q_j(m) = Phi((m + 1/2)/sigma_j) -
+ * Phi((m - 1/2)/sigma_j) (independent of the state); acceptance
+ * min(1, pi(m') q(m)/(pi(m) q(m'))), m' = 0 rejected.  Randoms: Philox
+ * counter (step, l, 'mhch', 2 it) -> three Box-Muller normals, (step, l,
+ * 'mhch', 2 it + 1) -> the acceptance uniform.  The chains start from an
+ * exact draw at the next sampled step (also after every call of this
+ * function).  Drawing ahead is off under this sampler.  Allocates the chain
+ * state (2 x 3p int32) on first use; waits. */
+rbe_status rbe_set_sampler(rbe_ctx ctx, int32_t sampler, int32_t iters);
 
 /* Test hook: replace the batch by p_in host vectors h_m (p_in x 3 int32,
  * row-major, every row nonzero, |m_j| <= 2048).  p_in must equal cfg.p.
@@ -276,12 +301,14 @@ void rbe_real_destroy(rbe_real_ctx ctx);
 /* ---------------------------------------------------------------------------
  * Langevin NPT integrator (section 3.2 eq. (24), isotropic scaling of a
  * rectangular cell at its initial aspect ratio; appendix A eq.
- * (99999), semi-isotropic cell with gamma0 = 0), FP64, split as in section
+ * (99999), semi-isotropic cell with gamma0 = 0; appendix A, rectangular cell
+ * with anisotropic fluctuation: side lengths l_j with momenta p^l_j, driven
+ * by V (P_jj - P)/l_j, eq. (e:instrectangular)), FP64, split as in section
  * 3.3:   B_V(h) B_R(h) A_V(h) A_R(h) O^p(dt) O(dt) A_R(h) A_V(h) | F, P | B_R(h) B_V(h)
  * with h = dt/2, every sub-flow solved exactly with the other variables
  * frozen:  A_R  r <- r e^{a h} + (p/m)(e^{a h} - 1)/a,
  *          B_R  p <- p e^{-a h} + F (1 - e^{-a h})/a,
- * a the per-axis scaling rate (V'/3V; or A'/2A, A'/2A, L'/L), the OU steps
+ * a the per-axis scaling rate (V'/3V; or A'/2A, A'/2A, L'/L; or l_j'/l_j), the OU steps
  * exact (section 3.3), B_V driven by the instantaneous pressure tensor
  * (sum_i p_i p_i^T/m_i + W)/V of appendix C (iso: its trace/3; semi: (xx+yy)/2
  * against L, zz against A).  The B_V opening a step uses the pressure formed
@@ -296,15 +323,16 @@ typedef struct rbe_md_ctx_s* rbe_md_ctx;
 
 typedef struct {
   int64_t  n;            /* particles                                           */
-  int32_t  box_mode;     /* RBE_BOX_ISO or RBE_BOX_SEMIISO                       */
+  int32_t  box_mode;     /* RBE_BOX_ISO, RBE_BOX_SEMIISO or RBE_BOX_ANISO         */
   int32_t  reserved;     /* must be 0                                           */
   double   dt;           /* time step                                           */
   double   kT;           /* k_B T (energy units)                                */
   double   p_ext;        /* external pressure (energy / length^3)               */
   double   gamma_p;      /* particle friction (1/time), >= 0                     */
   double   gamma_cell;   /* cell friction (1/time), >= 0                         */
-  double   mass_cell;    /* iso: mass M of V; semi: mass M_A of A                */
-  double   mass_cell_z;  /* semi: mass M_L of L (ignored for iso)                */
+  double   mass_cell;    /* iso: mass M of V; semi: mass M_A of A; aniso: M_x    */
+                         /* = M_y of l_x, l_y                                   */
+  double   mass_cell_z;  /* semi: mass M_L of L; aniso: M_z (ignored for iso)   */
   double   ftm;          /* force units -> mass x length / time^2                */
   uint64_t seed;
   uint64_t system_id;
@@ -364,7 +392,8 @@ const double* rbe_md_box_dev(rbe_md_ctx ctx);
 /* Waits; h_state[32] = lx ly lz, volume, pV, pA, pL, pressure tensor (6,
  * energy/length^3), kinetic tensor sum p p^T/m (6, energy; rigid molecules
  * contribute P P^T/M), error flags, step, A, L, V, the rigid-molecule
- * correction sum sym((r - R) F) (6, energy), rigid molecules, 0. */
+ * correction sum sym((r - R) F) (6, energy), rigid molecules, 0.  In the
+ * anisotropic mode entries 4-6 hold the momenta of l_x, l_y, l_z. */
 rbe_status rbe_md_get_state(rbe_md_ctx ctx, double* h_state);
 
 /* Waits; RBE_ERR_STATE if the cell collapsed or became non-finite, or a
@@ -443,6 +472,10 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused);
 
 /* Waits for the batch's stream. */
 rbe_status rbe_batch_sync(rbe_batch b);
+
+/* Waits; h_stats[2] = the slot's real-space evaluations and neighbour-list
+ * builds so far, as rbe_real_list_stats. */
+rbe_status rbe_batch_list_stats(rbe_batch b, int32_t slot, int64_t* h_stats);
 
 /* Waits; h_pos, h_mom, h_frc [n][3]: positions, momenta and the forces of
  * the last evaluation (each may be NULL); h_state [32] as rbe_md_get_state

@@ -3,14 +3,18 @@
 TEST INFRASTRUCTURE ONLY (FP64 CPU oracle; imported by tests, the smoke check
 and the benchmark's CPU-baseline leg, never by the product path).
 
-Equations of motion: section 3.2 eq. (24) for a cubic cell (V, p^V) and
-appendix A eq. (99999) for the semi-isotropic cell (A, p^A, L, p^L):
+Equations of motion: section 3.2 eq. (24) for a cubic cell (V, p^V),
+appendix A eq. (99999) for the semi-isotropic cell (A, p^A, L, p^L) and the
+appendix's rectangular cell with anisotropic fluctuation (side lengths l_j,
+momenta p^l_j, masses M_j; its pressure eq. (e:instrectangular)):
 
     r' = p/m + D r,         p' = F - D p - gamma p + sqrt(2 kT m gamma) W'
     iso:  D = (V'/3V) I,    V' = p^V/M,  p^V' = P_ins - P - gamma_c p^V + noise
     semi: D = diag(A'/2A, A'/2A, L'/L),
           p^A' = L (P_A - P) - ...,  P_A = (P_xx + P_yy)/2 + gamma0/L (gamma0 = 0),
           p^L' = A (P_zz - P) - ...
+    aniso: D = diag(l_j'/l_j),  l_j' = p^l_j/M_j,
+          p^l_j' = V (P_jj - P)/l_j - gamma_c p^l_j + noise
 
 Time step (section 3.3): the palindromic Trotter order
     B_V(h) B_R(h) A_V(h) A_R(h) O^p(dt) O(dt) A_R(h) A_V(h) [forces, pressure] B_R(h) B_V(h),
@@ -18,8 +22,9 @@ h = dt/2.  Sub-flows, each solved exactly with the other variables frozen
 (reading of the cited exact solutions): with the per-axis rate a = D_aa,
     A_R:  r <- r e^{a h} + (p/m) (e^{a h} - 1)/a
     B_R:  p <- p e^{-a h} + F (1 - e^{-a h})/a
-    A_V:  V <- V + h p^V/M   (A, L likewise)
-    B_V:  p^V <- p^V + h (P_ins - P)   (semi: h L (P_A - P), h A (P_zz - P))
+    A_V:  V <- V + h p^V/M   (A, L, l_j likewise)
+    B_V:  p^V <- p^V + h (P_ins - P)   (semi: h L (P_A - P), h A (P_zz - P);
+          aniso: h V (P_jj - P)/l_j)
     O:    p <- e^{-g dt} p + sqrt(kT m (1 - e^{-2 g dt})) R   (exact OU, section 3.3)
 The instantaneous pressure tensor is (sum_i p_i p_i^T/m_i + W)/V, W the
 virial tensor of the forces (eq. pressuretensorflexible); its trace/3 is the
@@ -40,7 +45,7 @@ Noise: Philox4x64-10 keyed (seed, system_id); particle i at step s uses
 counter (s, i, TAG_NOISE, 0): uniforms u0..u3 give three normals by Box-Muller,
 z0 = sqrt(-2 ln(1-u0)) cos(2 pi u1), z1 = ... sin(2 pi u1),
 z2 = sqrt(-2 ln(1-u2)) cos(2 pi u3).  The cell uses counter (s, 0, TAG_CELL, 0):
-z0 for V (or A), z1 for L.
+z0 for V (or A, or l_x), z1 for L (or l_y), z2 for l_z.
 """
 
 import math
@@ -72,7 +77,8 @@ def _expm1_over(a, h):
 
 
 class NPTState:
-    """Cell and barostat state.  mode 'iso': V, pV, M; 'semi': A, pA, MA, L, pL, ML."""
+    """Cell and barostat state.  mode 'iso': V, pV, M; 'semi': A, pA, MA, L, pL, ML;
+    'aniso': l[3], pl[3], Ml[3] (masses (M_x, M_y, M_z))."""
 
     def __init__(self, mode, box, masses):
         self.mode = mode
@@ -87,6 +93,10 @@ class NPTState:
                 self.asp = np.ones(3)
             else:
                 self.asp = np.array(box) / self.V ** (1.0 / 3.0)
+        elif mode == "aniso":
+            self.l = np.array(box)
+            self.pl = np.zeros(3)
+            self.Ml = np.array([float(v) for v in masses], dtype=np.float64)
         else:
             self.A = box[0] * box[1]
             self.L = box[2]
@@ -99,10 +109,14 @@ class NPTState:
     def box(self):
         if self.mode == "iso":
             return self.asp * self.V ** (1.0 / 3.0)
+        if self.mode == "aniso":
+            return self.l.copy()
         s = math.sqrt(self.A)
         return np.array([s, s, self.L])
 
     def volume(self):
+        if self.mode == "aniso":
+            return float(self.l[0] * self.l[1] * self.l[2])
         return self.V if self.mode == "iso" else self.A * self.L
 
     def rates(self):
@@ -110,6 +124,8 @@ class NPTState:
         if self.mode == "iso":
             a = self.pV / (3.0 * self.M * self.V)
             return np.array([a, a, a])
+        if self.mode == "aniso":
+            return self.pl / (self.Ml * self.l)
         axy = self.pA / (2.0 * self.MA * self.A)
         return np.array([axy, axy, self.pL / (self.ML * self.L)])
 
@@ -162,6 +178,10 @@ class LangevinNPT:
         Pt = st.P_ins
         if st.mode == "iso":
             st.pV += h * (np.trace(Pt) / 3.0 - P)
+        elif st.mode == "aniso":
+            V = st.volume()
+            for j in range(3):
+                st.pl[j] += h * V * (Pt[j, j] - P) / st.l[j]
         else:
             st.pA += h * st.L * (0.5 * (Pt[0, 0] + Pt[1, 1]) - P)
             st.pL += h * st.A * (Pt[2, 2] - P)
@@ -169,6 +189,8 @@ class LangevinNPT:
     def A_V(self, st, h):
         if st.mode == "iso":
             st.V += h * st.pV / st.M
+        elif st.mode == "aniso":
+            st.l = st.l + h * st.pl / st.Ml
         else:
             st.A += h * st.pA / st.MA
             st.L += h * st.pL / st.ML
@@ -193,6 +215,10 @@ class LangevinNPT:
         c1 = math.exp(-self.gc * self.dt)
         if st.mode == "iso":
             st.pV = c1 * st.pV + math.sqrt(self.ftm * self.kT * st.M * (1.0 - c1 * c1)) * z[0]
+        elif st.mode == "aniso":
+            for j in range(3):
+                st.pl[j] = (c1 * st.pl[j]
+                            + math.sqrt(self.ftm * self.kT * st.Ml[j] * (1.0 - c1 * c1)) * z[j])
         else:
             st.pA = c1 * st.pA + math.sqrt(self.ftm * self.kT * st.MA * (1.0 - c1 * c1)) * z[0]
             st.pL = c1 * st.pL + math.sqrt(self.ftm * self.kT * st.ML * (1.0 - c1 * c1)) * z[1]

@@ -51,6 +51,13 @@ struct rbe_ctx_s {
   int32_t* d_m_pre = nullptr;    // 3p
   bool pre_valid = false;        // a batch for step pre_step was drawn ahead (device checks the cell)
   uint64_t pre_step = 0;
+  // online Metropolis-Hastings sampler: chain states [2][3p], the buffer
+  // holding the latest state, and whether the chains have started
+  int32_t sampler = RBE_SAMPLER_EXACT;
+  int32_t mh_iters = 1;
+  int32_t* d_chain = nullptr;
+  int mh_cur = 0;
+  bool mh_started = false;
   // kernel timing (rbe_timing_enable)
   static constexpr int kKinds = 4;
   int timing_cap = 0;
@@ -210,7 +217,7 @@ void destroy_events(rbe_ctx_s* c) {
 void free_all(rbe_ctx_s* c) {
   void* bufs[] = {c->d_q, c->d_qf, c->d_qsum, c->d_bs, c->d_tab, c->d_m, c->d_partial,
                   c->d_gpart, c->d_rho, c->d_terms, c->d_fc32, c->d_fc64, c->d_cnt,
-                  c->d_pre, c->d_m_pre};
+                  c->d_pre, c->d_m_pre, c->d_chain};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -223,8 +230,23 @@ StepArgs step_args(rbe_ctx_s* c) {
   a.box_ptr = c->pend_box_ptr;
   a.sample = c->pend_sample ? 1 : 0;
   a.step = c->pend_step;
-  a.use_pre = (c->pend_sample && c->pre_valid && c->pre_step == c->pend_step) ? 1 : 0;
+  a.use_pre = (c->pend_sample && c->sampler == RBE_SAMPLER_EXACT && c->pre_valid &&
+               c->pre_step == c->pend_step) ? 1 : 0;
   a.predraw = 0;
+  a.sampler = c->sampler;
+  a.mh_iters = c->mh_iters;
+  a.mh_init = 0;
+  a.mh_old = nullptr;
+  a.mh_new = nullptr;
+  if (a.sample && c->sampler == RBE_SAMPLER_MH) {
+    // this call's launch moves the chains: read the latest state, write the other buffer
+    const size_t w = 3 * (size_t)c->p;
+    a.mh_init = c->mh_started ? 0 : 1;
+    a.mh_old = c->d_chain + (size_t)c->mh_cur * w;
+    a.mh_new = c->d_chain + (size_t)(1 - c->mh_cur) * w;
+    c->mh_cur = 1 - c->mh_cur;
+    c->mh_started = true;
+  }
   return a;
 }
 
@@ -268,7 +290,7 @@ rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, con
   a.accumulate = accumulate ? 1 : 0;
   a.virial6 = d_virial6; a.energy = d_energy;
   // a sampled step draws the next step's batch ahead, for its own cell
-  a.predraw = a.sample && env_flag("RBE_PREDRAW", true) ? 1 : 0;
+  a.predraw = a.sample && c->sampler == RBE_SAMPLER_EXACT && env_flag("RBE_PREDRAW", true) ? 1 : 0;
   if (a.predraw) { c->pre_valid = true; c->pre_step = a.step + 1; }
   clear_pending(c);
   *out = a;
@@ -426,6 +448,25 @@ rbe_status rbe_sample_k(rbe_ctx c, uint64_t step) {
   c->pend_sample = true;
   c->pend_step = step;
   c->have_k = true;
+  return RBE_OK;
+}
+
+rbe_status rbe_set_sampler(rbe_ctx c, int32_t sampler, int32_t iters) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (sampler != RBE_SAMPLER_EXACT && sampler != RBE_SAMPLER_MH)
+    return fail(RBE_ERR_ARG, "unknown sampler %d", sampler);
+  if (sampler == RBE_SAMPLER_MH && (iters < 1 || iters > 64))
+    return fail(RBE_ERR_ARG, "iters = %d must be in 1..64", iters);
+  rbe_status st = flush(c);                // a pending draw belongs to the old sampler
+  if (st != RBE_OK) return st;
+  if (sampler == RBE_SAMPLER_MH && !c->d_chain)
+    HIP_TRY(hipMalloc(&c->d_chain, 6 * (size_t)c->p * sizeof(int32_t)), "chain state");
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->sampler = sampler;
+  c->mh_iters = sampler == RBE_SAMPLER_MH ? iters : 1;
+  c->mh_started = false;
+  c->mh_cur = 0;
+  c->pre_valid = false;
   return RBE_OK;
 }
 

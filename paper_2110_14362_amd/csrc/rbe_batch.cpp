@@ -92,8 +92,8 @@ rbe_status check_desc(const rbe_system_desc* d, const double* box) {
   if (!d || !box) return bfail(RBE_ERR_ARG, "NULL system description or box");
   if (d->n < 1) return bfail(RBE_ERR_ARG, "n = %lld must be >= 1", (long long)d->n);
   if (d->p < 1 || d->p > 65536) return bfail(RBE_ERR_ARG, "p = %d must be in 1..65536", d->p);
-  if (d->box_mode != RBE_BOX_ISO && d->box_mode != RBE_BOX_SEMIISO)
-    return bfail(RBE_ERR_ARG, "box_mode must be RBE_BOX_ISO or RBE_BOX_SEMIISO");
+  if (d->box_mode != RBE_BOX_ISO && d->box_mode != RBE_BOX_SEMIISO && d->box_mode != RBE_BOX_ANISO)
+    return bfail(RBE_ERR_ARG, "box_mode must be RBE_BOX_ISO, RBE_BOX_SEMIISO or RBE_BOX_ANISO");
   if (d->reserved != 0) return bfail(RBE_ERR_ARG, "reserved field must be 0");
   if (d->ntypes < 0 || d->ntypes > 64) return bfail(RBE_ERR_ARG, "ntypes = %d must be in 0..64", d->ntypes);
   if (!(d->skin >= 0.0 && fin(d->skin))) return bfail(RBE_ERR_ARG, "skin = %g must be >= 0", d->skin);
@@ -111,7 +111,8 @@ rbe_config kspace_cfg(const rbe_batch_s* b, const rbe_system_desc* d, const doub
   // the Fourier part checks only the cell's shape; isotropic coupling of a
   // non-cubic cell keeps a general rectangular cell
   const bool cubic = box[0] == box[1] && box[0] == box[2];
-  c.box_mode = d->box_mode == RBE_BOX_SEMIISO ? RBE_BOX_SEMIISO : (cubic ? RBE_BOX_ISO : RBE_BOX_ANISO);
+  c.box_mode = d->box_mode == RBE_BOX_SEMIISO ? RBE_BOX_SEMIISO
+               : (cubic && d->box_mode == RBE_BOX_ISO ? RBE_BOX_ISO : RBE_BOX_ANISO);
   c.precision = b ? b->cfg.precision : RBE_PREC_FP32;
   c.alpha = d->alpha;
   c.coulomb = d->coulomb;
@@ -476,6 +477,13 @@ rbe_status rbe_batch_read(rbe_batch b, int32_t slot, double* h_pos, double* h_mo
     }
   if (h_state) return rbe_md_get_state(s.m, h_state);
   return RBE_OK;
+}
+
+rbe_status rbe_batch_list_stats(rbe_batch b, int32_t slot, int64_t* h_stats) {
+  if (!b) return bfail(RBE_ERR_ARG, "NULL batch");
+  if (slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot].active)
+    return bfail(RBE_ERR_ARG, "slot %d is not admitted", slot);
+  return rbe_real_list_stats(b->slots[slot].r, h_stats);
 }
 
 rbe_status rbe_batch_check(rbe_batch b, int32_t slot) {

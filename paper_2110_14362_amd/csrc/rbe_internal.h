@@ -91,6 +91,12 @@ struct StepArgs {
   uint32_t* cnt;        // [Y*NG] + [Y] + [1] arrival counters, zero between launches
   PreDraw* pre;         // [2] batches drawn ahead: step and cell, by step parity
   int32_t* m_pre;       // [2][3p]
+  // online Metropolis-Hastings sampler (sampler == RBE_SAMPLER_MH): the
+  // chains' states at the previous sampled step (read) and at this one
+  // (written); mh_init: no state yet, the chains start from an exact draw
+  int32_t sampler, mh_iters, mh_init;
+  const int32_t* mh_old;
+  int32_t* mh_new;
 };
 
 size_t sfac_lds_bytes(const StepArgs& a);

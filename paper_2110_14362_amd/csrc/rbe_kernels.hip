@@ -257,6 +257,69 @@ hipError_t launch_qsum(const double* d_q, float* d_qf, double* d_out3, int64_t n
 }
 
 // ---------------------------------------------------------------------------
+// online Metropolis-Hastings sampler (section 4.3, online approach): chain l
+// keeps its frequency from step to step and takes mh_iters independence
+// moves per sampled step towards the law of the current cell.  Per axis the
+// law is exp(-m^2/(2 sigma^2)), sigma = sqrt(alpha) l/(pi sqrt 2); the proposal
+// rounds a continuous Gaussian of the same sigma to the integer whose
+// [m - 1/2, m + 1/2) holds it, q(m) = Phi((m + 1/2)/sigma) - Phi((m - 1/2)/sigma);
+// a move m -> m' is accepted with min(1, pi(m') q(m)/(pi(m) q(m'))), m' = 0
+// never.  Move it of chain l at step s: counter (s, l, 'mhch', 2 it) gives
+// the three normals (Box-Muller), (s, l, 'mhch', 2 it + 1) the acceptance
+// uniform.
+
+constexpr uint64_t kTagMH = 0x6D686368ull;  // 'mhch'
+
+// q(m) for one axis, s = sigma sqrt 2, from erfc on the side away from the
+// mode (no cancellation in the tails)
+__device__ __forceinline__ double mh_qpmf(int m, double s) {
+  if (m == 0) return erf(0.5 / s);
+  const double a = (double)abs(m);
+  return 0.5 * (erfc((a - 0.5) / s) - erfc((a + 0.5) / s));
+}
+
+__device__ void mh_frequency(const StepArgs& a, const BoxState& b, int l, int m[3]) {
+  const double sq2 = 1.4142135623730951;
+  double sig[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    sig[j] = sqrt(a.alpha) * b.l[j] / (M_PI * sq2);
+    m[j] = a.mh_old[3 * l + j];
+  }
+  for (int it = 0; it < a.mh_iters; ++it) {
+    uint64_t c[4] = {a.step, (uint64_t)l, kTagMH, 2ull * (uint64_t)it};
+    philox4x64_10(c, a.seed, a.sysid);
+    double u[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] = (double)(c[j] >> 11) * 0x1.0p-53;
+    const double ra = sqrt(-2.0 * log(1.0 - u[0])), rb = sqrt(-2.0 * log(1.0 - u[2]));
+    const double t1 = 2.0 * M_PI * u[1], t3 = 2.0 * M_PI * u[3];
+    const double z[3] = {ra * cos(t1), ra * sin(t1), rb * cos(t3)};
+    int mp[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) mp[j] = (int)floor(sig[j] * z[j] + 0.5);
+    uint64_t c2[4] = {a.step, (uint64_t)l, kTagMH, 2ull * (uint64_t)it + 1ull};
+    philox4x64_10(c2, a.seed, a.sysid);
+    const double ua = (double)(c2[0] >> 11) * 0x1.0p-53;
+    if (mp[0] == 0 && mp[1] == 0 && mp[2] == 0) continue;
+    double e = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) e += (double)(mp[j] * mp[j] - m[j] * m[j]) / (2.0 * sig[j] * sig[j]);
+    double r = exp(-e);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r *= mh_qpmf(m[j], sig[j] * sq2) / mh_qpmf(mp[j], sig[j] * sq2);
+    if (ua < fmin(1.0, r)) { m[0] = mp[0]; m[1] = mp[1]; m[2] = mp[2]; }
+  }
+}
+
+// frequency l of the current step under the context's sampler
+__device__ __forceinline__ void sample_frequency(const StepArgs& a, const BoxState& b,
+                                                 const double* tab, int l, int m[3]) {
+  if (a.sampler == RBE_SAMPLER_MH && !a.mh_init) mh_frequency(a, b, l, m);
+  else draw_frequency(b, tab, a.seed, a.sysid, a.step, l, m);
+}
+
+// ---------------------------------------------------------------------------
 // standalone tables / draw (when the batch or the cell is read on the host
 // before a fused step has run)
 
@@ -283,8 +346,9 @@ __global__ void __launch_bounds__(256) k_sample(StepArgs a) {
   if (l >= a.p) return;
   const BoxState b = *a.bs;
   int m[3];
-  draw_frequency(b, a.tab, a.seed, a.sysid, a.step, l, m);
+  sample_frequency(a, b, a.tab, l, m);
   a.m[3 * l] = m[0]; a.m[3 * l + 1] = m[1]; a.m[3 * l + 2] = m[2];
+  if (a.sampler == RBE_SAMPLER_MH) { a.mh_new[3 * l] = m[0]; a.mh_new[3 * l + 1] = m[1]; a.mh_new[3 * l + 2] = m[2]; }
 }
 
 hipError_t launch_sample(const StepArgs& a, hipStream_t s) {
@@ -566,8 +630,13 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
         mv[0] = m_pre[3 * l]; mv[1] = m_pre[3 * l + 1]; mv[2] = m_pre[3 * l + 2];
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else if (a.sample) {
-        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv);
-        if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
+        sample_frequency(a, sbs, tabs, (int)l, mv);
+        if (x == 0) {
+          a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2];
+          if (a.sampler == RBE_SAMPLER_MH) {
+            a.mh_new[3 * l] = mv[0]; a.mh_new[3 * l + 1] = mv[1]; a.mh_new[3 * l + 2] = mv[2];
+          }
+        }
       } else {
         mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
       }

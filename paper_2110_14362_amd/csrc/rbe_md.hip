@@ -66,6 +66,7 @@ __device__ __forceinline__ double expm1_over(double a, double h) {
 }
 
 __device__ __forceinline__ double cell_volume(const MDCell& c) {
+  if (c.mode == 2) return c.l[0] * c.l[1] * c.l[2];
   return c.mode == 0 ? c.V : c.A * c.L;
 }
 
@@ -73,6 +74,8 @@ __device__ __forceinline__ void cell_rates(const MDCell& c, double a[3]) {
   if (c.mode == 0) {
     const double r = c.pV / (3.0 * c.M * c.V);
     a[0] = a[1] = a[2] = r;
+  } else if (c.mode == 2) {
+    for (int d = 0; d < 3; ++d) a[d] = c.pl[d] / (c.Ml[d] * c.l[d]);
   } else {
     a[0] = a[1] = c.pA / (2.0 * c.MA * c.A);
     a[2] = c.pL / (c.ML * c.L);
@@ -83,6 +86,8 @@ __device__ __forceinline__ void cell_lengths(MDCell& c) {
   if (c.mode == 0) {
     const double L = cbrt(c.V);
     c.l[0] = c.asp[0] * L; c.l[1] = c.asp[1] * L; c.l[2] = c.asp[2] * L;
+  } else if (c.mode == 2) {
+    if (!(c.l[1] > 0.0)) c.err |= 1;
   } else {
     const double s = sqrt(c.A);
     c.l[0] = c.l[1] = s;
@@ -95,7 +100,10 @@ __device__ __forceinline__ void B_V(const MDArgs& a, MDCell& c, double h) {
   const double P = a.ftm * a.P;
   const double* Pt = c.P_ins;
   if (c.mode == 0) c.pV += h * ((Pt[0] + Pt[1] + Pt[2]) / 3.0 - P);
-  else {
+  else if (c.mode == 2) {
+    const double V = cell_volume(c);
+    for (int d = 0; d < 3; ++d) c.pl[d] += h * V * (Pt[d] - P) / c.l[d];
+  } else {
     c.pA += h * c.L * (0.5 * (Pt[0] + Pt[1]) - P);
     c.pL += h * c.A * (Pt[2] - P);
   }
@@ -103,6 +111,7 @@ __device__ __forceinline__ void B_V(const MDArgs& a, MDCell& c, double h) {
 
 __device__ __forceinline__ void A_V(MDCell& c, double h) {
   if (c.mode == 0) c.V += h * c.pV / c.M;
+  else if (c.mode == 2) { for (int d = 0; d < 3; ++d) c.l[d] += h * c.pl[d] / c.Ml[d]; }
   else { c.A += h * c.pA / c.MA; c.L += h * c.pL / c.ML; }
 }
 
@@ -275,7 +284,9 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
     const double c1 = exp(-a.gc * a.dt);
     const double amp = sqrt(a.ftm * a.kT * (1.0 - c1 * c1));
     if (c.mode == 0) c.pV = c1 * c.pV + amp * sqrt(c.M) * z[0];
-    else {
+    else if (c.mode == 2) {
+      for (int d = 0; d < 3; ++d) c.pl[d] = c1 * c.pl[d] + amp * sqrt(c.Ml[d]) * z[d];
+    } else {
       c.pA = c1 * c.pA + amp * sqrt(c.MA) * z[0];
       c.pL = c1 * c.pL + amp * sqrt(c.ML) * z[1];
     }

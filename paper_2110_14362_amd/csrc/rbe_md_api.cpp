@@ -91,13 +91,13 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   if (!cfg || !d_mass || !box_host || !out) return mfail(RBE_ERR_ARG, "NULL argument to rbe_md_init");
   *out = nullptr;
   if (cfg->n < 1) return mfail(RBE_ERR_ARG, "n must be >= 1");
-  if (cfg->box_mode != RBE_BOX_ISO && cfg->box_mode != RBE_BOX_SEMIISO)
-    return mfail(RBE_ERR_ARG, "box_mode must be RBE_BOX_ISO or RBE_BOX_SEMIISO");
+  if (cfg->box_mode != RBE_BOX_ISO && cfg->box_mode != RBE_BOX_SEMIISO && cfg->box_mode != RBE_BOX_ANISO)
+    return mfail(RBE_ERR_ARG, "box_mode must be RBE_BOX_ISO, RBE_BOX_SEMIISO or RBE_BOX_ANISO");
   if (cfg->reserved != 0) return mfail(RBE_ERR_ARG, "reserved field must be 0");
   if (!pos_fin(cfg->dt) || !pos_fin(cfg->kT) || !(std::isfinite(cfg->p_ext)) || !pos_fin(cfg->ftm))
     return mfail(RBE_ERR_ARG, "dt, kT and ftm must be positive, p_ext finite");
   if (!(cfg->gamma_p >= 0.0) || !(cfg->gamma_cell >= 0.0)) return mfail(RBE_ERR_ARG, "frictions must be >= 0");
-  if (!pos_fin(cfg->mass_cell) || (cfg->box_mode == RBE_BOX_SEMIISO && !pos_fin(cfg->mass_cell_z)))
+  if (!pos_fin(cfg->mass_cell) || (cfg->box_mode != RBE_BOX_ISO && !pos_fin(cfg->mass_cell_z)))
     return mfail(RBE_ERR_ARG, "barostat masses must be positive");
   for (int d = 0; d < 3; ++d)
     if (!pos_fin(box_host[d])) return mfail(RBE_ERR_ARG, "box[%d] must be positive", d);
@@ -117,7 +117,7 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
             hipMalloc(&c->d_flags, sizeof(int32_t)) == hipSuccess;
   if (!ok) { mfree(c); delete c; return mfail(RBE_ERR_ALLOC, "device allocation failed"); }
   MDCell cell{};
-  cell.mode = cfg->box_mode == RBE_BOX_ISO ? 0 : 1;
+  cell.mode = cfg->box_mode == RBE_BOX_ISO ? 0 : (cfg->box_mode == RBE_BOX_SEMIISO ? 1 : 2);
   cell.V = box_host[0] * box_host[1] * box_host[2];
   cell.M = cfg->mass_cell;
   cell.A = box_host[0] * box_host[1];
@@ -125,6 +125,8 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   cell.MA = cfg->mass_cell;
   cell.ML = cfg->mass_cell_z;
   for (int d = 0; d < 3; ++d) cell.l[d] = box_host[d];
+  cell.Ml[0] = cell.Ml[1] = cfg->mass_cell;
+  cell.Ml[2] = cfg->mass_cell_z;
   // isotropic coupling keeps the initial aspect ratio (exactly 1:1:1 for a cubic cell)
   const bool cubic = box_host[1] == box_host[0] && box_host[2] == box_host[0];
   const double L0 = std::cbrt(cell.V);
@@ -231,8 +233,9 @@ rbe_status rbe_md_get_state(rbe_md_ctx c, double* h) {
     return mfail(RBE_ERR_DEVICE, "copy cell state");
   const double f = c->cfg.ftm;
   h[0] = cell.l[0]; h[1] = cell.l[1]; h[2] = cell.l[2];
-  h[3] = cell.mode == 0 ? cell.V : cell.A * cell.L;
+  h[3] = cell.mode == 0 ? cell.V : (cell.mode == 1 ? cell.A * cell.L : cell.l[0] * cell.l[1] * cell.l[2]);
   h[4] = cell.pV; h[5] = cell.pA; h[6] = cell.pL;
+  if (cell.mode == 2) { h[4] = cell.pl[0]; h[5] = cell.pl[1]; h[6] = cell.pl[2]; }
   for (int k = 0; k < 6; ++k) { h[7 + k] = cell.P_ins[k] / f; h[13 + k] = cell.K[k] / f; }
   h[19] = (double)cell.err;
   h[20] = (double)cell.step;

@@ -8,11 +8,13 @@ namespace rbe {
 
 // Cell and barostat state (internal units: forces x ftm).
 struct MDCell {
-  int32_t mode;      // 0 isotropic (V, pV), 1 semi-isotropic (A, pA, L, pL)
+  int32_t mode;      // 0 isotropic (V, pV), 1 semi-isotropic (A, pA, L, pL),
+                     // 2 anisotropic rectangular (l, pl)
   int32_t err;       // bit 0: non-positive or non-finite cell
   double V, pV, M;
   double A, pA, MA, L, pL, ML;
-  double l[3];       // side lengths
+  double l[3];       // side lengths (the state itself in mode 2)
+  double pl[3], Ml[3];  // mode 2: momenta and masses of the side lengths
   double asp[3];     // isotropic mode: l = asp * V^(1/3), asp fixed (product 1)
   double P_ins[6];   // pressure tensor xx yy zz xy xz yz (internal units)
   double K[6];       // kinetic tensor sum p p^T / m (rigid molecules: P P^T / M)

@@ -15,7 +15,7 @@ class NPTSystem:
 
     sysd: dict with pos (N,3), q, mass, box; alpha, p, coulomb;
     md: dict with dt, kT, p_ext, gamma_p, gamma_cell, mass_cell, mass_cell_z,
-        ftm, box_mode ('iso' or 'semiiso'), rc; optional types + lj for the
+        ftm, box_mode ('iso', 'semiiso' or 'aniso'), rc; optional types + lj for the
         real-space Lennard-Jones term; optional rigid = dict(first, count,
         d_oh, d_hh) for rigid 3-site molecules (whole, not split by the
         periodic boundary); optional skin (> 0: real-space neighbour lists).

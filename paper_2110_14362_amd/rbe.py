@@ -18,6 +18,7 @@ RBE_ERR_CAPACITY = 6
 STATUS_NAMES = {0: "RBE_OK", 1: "RBE_ERR_ARG", 2: "RBE_ERR_ALLOC", 3: "RBE_ERR_DEVICE",
                 4: "RBE_ERR_STATE", 5: "RBE_ERR_NONNEUTRAL", 6: "RBE_ERR_CAPACITY"}
 BOX_MODES = {"iso": 0, "semiiso": 1, "aniso": 2}
+SAMPLERS = {"exact": 0, "mh": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 # every symbol include/rbe.h declares
@@ -29,7 +30,8 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_real_check", "rbe_real_destroy",
            "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
            "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy",
-           "rbe_md_set_rigid", "rbe_real_set_skin", "rbe_real_list_stats",
+           "rbe_md_set_rigid", "rbe_real_set_skin", "rbe_real_list_stats", "rbe_set_sampler",
+           "rbe_batch_list_stats",
            "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
            "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy",
@@ -116,7 +118,9 @@ def load_library(path=LIB_PATH):
         "rbe_real_forces": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "rbe_real_check": [vp],
         "rbe_real_set_skin": [vp, ctypes.c_double],
+        "rbe_set_sampler": [vp, ctypes.c_int32, ctypes.c_int32],
         "rbe_real_list_stats": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "rbe_batch_list_stats": [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
         "rbe_md_init": [ctypes.POINTER(MDConfig), vp, dp, vp, ctypes.POINTER(vp)],
         "rbe_md_pressure": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "rbe_md_set_rigid": [vp, i64, i64, ctypes.c_double, ctypes.c_double],
@@ -228,6 +232,11 @@ class RBE:
     def rescale_box_dev_ptr(self, ptr):
         """Like rescale_box_dev with a raw device address (e.g. Integrator.box_dev_ptr())."""
         _check(_lib.rbe_rescale_box_dev(self._ctx, ctypes.c_void_p(int(ptr))))
+
+    def set_sampler(self, kind="exact", iters=1):
+        """'exact' (independent draws) or 'mh' (the online Metropolis-Hastings
+        chains, `iters` moves per sampled step)."""
+        _check(_lib.rbe_set_sampler(self._ctx, SAMPLERS[kind], int(iters)))
 
     def sample_k(self, step):
         _check(_lib.rbe_sample_k(self._ctx, ctypes.c_uint64(int(step) & (2**64 - 1))))
@@ -534,6 +543,12 @@ class Batch:
 
     def check(self, slot):
         _check(_lib.rbe_batch_check(self._ctx, int(slot)))
+
+    def list_stats(self, slot):
+        """(real-space evaluations, neighbour-list builds) of a slot; waits."""
+        h = (ctypes.c_int64 * 2)()
+        _check(_lib.rbe_batch_list_stats(self._ctx, int(slot), h))
+        return int(h[0]), int(h[1])
 
     def slot_step(self, slot):
         out = ctypes.c_int64()

@@ -26,8 +26,11 @@ def oracle_forces(sysd, md, pos, box, step, seed, system_id):
 
 
 def oracle_trajectory(sysd, md, momenta, steps, seed, system_id):
-    mode = "iso" if md.get("box_mode", "iso") == "iso" else "semi"
-    st = oint.NPTState(mode, sysd["box"], (md["mass_cell"], md.get("mass_cell_z", 0.0)))
+    mode = {"iso": "iso", "semiiso": "semi", "aniso": "aniso"}[md.get("box_mode", "iso")]
+    masses = (md["mass_cell"], md.get("mass_cell_z", 0.0))
+    if mode == "aniso":                  # M_x = M_y = mass_cell, M_z = mass_cell_z
+        masses = (md["mass_cell"], md["mass_cell"], md["mass_cell_z"])
+    st = oint.NPTState(mode, sysd["box"], masses)
     integ = oint.LangevinNPT(mode, None, md["dt"], md["kT"], md["p_ext"], md["gamma_p"],
                              md["gamma_cell"], md["ftm"], seed, system_id,
                              rigid=md.get("rigid"))

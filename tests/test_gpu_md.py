@@ -1,6 +1,6 @@
 """Device NPT trajectories vs the oracle's: same initial state, same batch
 and noise streams, FP64 path.  10 steps of the primitive electrolyte (cubic,
-isotropic) and of a small rectangular system (semi-isotropic)."""
+isotropic) and of small rectangular systems (semi-isotropic, anisotropic)."""
 import numpy as np
 import pytest
 
@@ -45,6 +45,16 @@ def aspect_setup():
     return s, md, mom
 
 
+def aniso_setup():
+    # rectangular cell, every side length with its own momentum
+    s = workloads.random_neutral(560, (13.0, 14.0, 15.5), seed=37)
+    s.update(alpha=0.5 ** 2, p=48, coulomb=1.0)
+    md = dict(dt=0.004, kT=1.0, p_ext=0.3, gamma_p=1.0, gamma_cell=1.5,
+              mass_cell=2e-3, mass_cell_z=4e-3, ftm=1.0, box_mode="aniso", rc=4.2)
+    mom = np.random.default_rng(20).normal(0.0, 1.0, s["pos"].shape)
+    return s, md, mom
+
+
 def rigid_water_setup():
     # rigid SPC/E-shaped water (150 molecules), O-O Lennard-Jones, real units
     s = workloads.rigid_water(150, seed=31)
@@ -71,8 +81,9 @@ def rigid_water_lists_setup():
     return s, md, mom
 
 
-@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup, rigid_water_setup,
-                                   electrolyte_lists_setup, rigid_water_lists_setup])
+@pytest.mark.parametrize("setup", [electrolyte_setup, slab_setup, aspect_setup, aniso_setup,
+                                   rigid_water_setup, electrolyte_lists_setup,
+                                   rigid_water_lists_setup])
 def test_npt_trajectory_matches_oracle(gpu, setup):
     from paper_2110_14362_amd.md import NPTSystem
     s, md, mom = setup()
@@ -102,6 +113,10 @@ def test_npt_trajectory_matches_oracle(gpu, setup):
                                    rtol=1e-8, atol=1e-12)
     if md["box_mode"] == "semiiso":
         assert g["box"][0] == g["box"][1]
+    elif md["box_mode"] == "aniso":
+        # the three sides move independently
+        rel = g["box"] / np.asarray(s["box"])
+        assert abs(rel[0] - rel[1]) > 1e-9 and abs(rel[1] - rel[2]) > 1e-9
     else:
         b0 = np.asarray(s["box"], dtype=np.float64)
         np.testing.assert_allclose(g["box"] / g["box"][0], b0 / b0[0], rtol=1e-14)

@@ -75,6 +75,49 @@ def test_sampler_draws_the_oracle_batch(gpu, alpha, box, mode, p):
         assert len(bad) == 0, (step, bad[:5], g[bad[:5]], o[bad[:5]])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode,box0,p,iters", [("iso", (20.0, 20.0, 20.0), 100, 1),
+                                               ("aniso", (14.0, 9.0, 20.0), 700, 3)])
+def test_mh_chains_follow_the_oracle(gpu, precision, mode, box0, p, iters):
+    # online Metropolis-Hastings chains over steps with a changing cell: the
+    # batch of every step equals the oracle chain's, whether the draw runs in
+    # the standalone kernel (batch read first) or inside the fused step
+    import torch
+    from oracle import mh_sampler as omh
+    from paper_2110_14362_amd.rbe import RBE
+    s = workloads.random_neutral(300, box0, seed=13)
+    dev = gpu
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = RBE(t(s["q"]), box0, p, 0.09, box_mode=mode, precision=precision, seed=77,
+              system_id=3)
+    ctx.set_sampler("mh", iters)
+    chains = omh.MHChains(0.09, p, seed=77, system_id=3, iters=iters)
+    x, y, z = (t(s["pos"][:, a]) for a in range(3))
+    f = [torch.zeros_like(x) for _ in range(3)]
+    moved = 0
+    prev = None
+    for step in range(8):
+        box = [b * (1.0 + 0.004 * step * (1 + a)) for a, b in enumerate(box0)]
+        if mode == "iso":
+            box = [box[0]] * 3
+        ctx.rescale_box(box)
+        ctx.sample_k(step)
+        if step % 2:
+            ctx.forces_pressure(x, y, z, *f)          # the draw inside the fused step
+        g = ctx.get_k().astype(np.int64)
+        o = chains.sample(box, step)
+        bad = np.where(np.any(g != o, axis=1))[0]
+        assert len(bad) == 0, (step, bad[:5], g[bad[:5]], o[bad[:5]])
+        if prev is not None:
+            moved += int(np.any(g != prev, axis=1).sum())
+        prev = g
+    ctx.check()
+    print("MH chains %s P=%d iters=%d: %d of %d batch slots moved over 7 steps, "
+          "oracle acceptance %.3f" % (mode, p, iters, moved, 7 * p,
+                                      chains.accepted / (7.0 * p * iters)), flush=True)
+    assert moved > 0
+
+
 # ------------------------------------------------------------------ parity
 
 CASES = {

@@ -31,13 +31,16 @@ def test_ou_step_variance_closed_form():
     assert np.allclose((p - math.exp(-g * dt) * p0).mean(), 0.0, atol=0.05)
 
 
-def _energy_drift(with_potential):
+BOXES = {"iso": (6.0, 6.0, 6.0), "semi": (6.0, 6.0, 7.0), "aniso": (6.0, 6.5, 7.0)}
+
+
+def _energy_drift(with_potential, mode):
     n = 16 if with_potential else 12
-    s = workloads.random_neutral(n, (6.0, 6.0, 6.0), seed=3)
+    s = workloads.random_neutral(n, BOXES[mode], seed=3)
     m = np.ones(n)
-    mode = "iso"
     M, P, dt = 0.05, 0.02, 0.002
-    st = oint.NPTState(mode, s["box"], (M, 0.0))
+    masses = {"iso": (M, 0.0), "semi": (M, 1.5 * M), "aniso": (M, 1.3 * M, 0.8 * M)}[mode]
+    st = oint.NPTState(mode, s["box"], masses)
     integ = oint.LangevinNPT(mode, None, dt, 1.0, P, 0.0, 0.0, 1.0, seed=0, system_id=0)
     r = s["pos"].copy()
     p = np.random.default_rng(2).normal(0, 1.0, (n, 3))
@@ -49,31 +52,51 @@ def _energy_drift(with_potential):
         res = ewald.ewald_total(r, s["q"], np.diag(box), alpha, rc, ktol=1e-14)
         return res["forces"], res["virial"], res["energy"]
 
+    def cell_kinetic(st):
+        # the Hamiltonian's cell part for each cell parametrisation
+        if mode == "iso":
+            return 0.5 * st.pV ** 2 / st.M
+        if mode == "semi":
+            return 0.5 * st.pA ** 2 / st.MA + 0.5 * st.pL ** 2 / st.ML
+        return 0.5 * float((st.pl ** 2 / st.Ml).sum())
+
     def H(st, p, U):
-        return 0.5 * (p * p).sum() + U + P * st.volume() + 0.5 * st.pV ** 2 / M
+        return 0.5 * (p * p).sum() + U + P * st.volume() + cell_kinetic(st)
 
     F, W, U = forces(r, st.box())
     st.P_ins = integ.pressure(st, p, m, W)
     H0 = H(st, p, U)
-    Hs = []
+    Hs, boxes = [], []
     for k in range(200 if with_potential else 2000):
         r, p = integ.first_half(st, r, p, m, F, k)
         F, W, U = forces(r, st.box())
         p = integ.second_half(st, p, m, F, W)
         Hs.append(H(st, p, U))
-    Hs = np.array(Hs)
-    return H0, Hs
+        boxes.append(st.box())
+    return H0, np.array(Hs), np.array(boxes)
 
 
+@pytest.mark.parametrize("mode", ["iso", "semi", "aniso"])
 @pytest.mark.parametrize("with_potential", [False, True])
-def test_frictionless_step_conserves_extended_energy(with_potential):
-    # gamma = 0: the splitting is symplectic for H = K + U + P V + p_V^2/2M
-    H0, Hs = _energy_drift(with_potential)
+def test_frictionless_step_conserves_extended_energy(with_potential, mode):
+    # gamma = 0: the splitting is symplectic for H = K + U + P V + (cell
+    # momenta)^2 / 2 (cell masses), in each cell parametrisation
+    H0, Hs, boxes = _energy_drift(with_potential, mode)
     scale = max(1.0, abs(H0))
     assert np.abs(Hs - H0).max() < 2e-3 * scale
     # no secular drift: late fluctuations are as small as early ones
     k = len(Hs) // 4
     assert abs(Hs[-k:].mean() - Hs[:k].mean()) < 1e-3 * scale
+    # the cell moved, with the freedom of its parametrisation
+    rel = boxes / boxes[0]
+    assert np.ptp(boxes, axis=0).min() > 1e-4
+    if mode == "iso":
+        assert np.abs(rel - rel[:, :1]).max() < 1e-12
+    elif mode == "semi":
+        assert np.abs(boxes[:, 0] - boxes[:, 1]).max() < 1e-12
+        assert np.abs(rel[:, 2] - rel[:, 0]).max() > 1e-4
+    else:
+        assert min(np.abs(rel[:, 0] - rel[:, 1]).max(), np.abs(rel[:, 1] - rel[:, 2]).max()) > 1e-4
 
 
 @pytest.mark.slow
