@@ -180,7 +180,7 @@ const T* put(rbe_batch_s* b, const T* src, size_t count) {
 }
 
 size_t stage_bytes_per_system() {
-  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 9 * sizeof(int) + 9 * 64;
+  return 2 * sizeof(StepArgs) + sizeof(RealArgs) + 2 * sizeof(MDArgs) + 10 * sizeof(int) + 10 * 64;
 }
 
 }  // namespace
@@ -363,22 +363,24 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
     for (size_t i = 0; i < cnt.size(); ++i) o[i + 1] = o[i] + cnt[i];
     return o;
   };
-  // binning kernels: bin_blocks(n); pairs: pair_blocks(n); integrator: 256 units (rigid
+  // binning kernels: bin_blocks(n); pairs: pair_blocks(n); integrator: kMdThreads units (rigid
   // molecules or free atoms) per block; cell sort: one block per cell of
   // the capacity
-  std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys), vb(nsys);
+  std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys), vb(nsys), bb(nsys);
+  const bool p32 = b->cfg.real_precision == RBE_PREC_FP32;
   int any_list = 0, any_cells = 0, max_types = 0;
   for (int j = 0; j < nsys; ++j) {
     vb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
     if (ra[j].skin > 0.0) any_list = 1; else any_cells = 1;
     max_types = std::max(max_types, ra[j].ntypes);
     pb[j] = (int)bin_blocks(b->slots[act[j]].desc.n);
-    ub[j] = (int)((md_units(md1[j]) + 255) / 256);
+    ub[j] = (int)md_blocks(md_units(md1[j]));
     cb[j] = ncap[j];
-    qb[j] = (int)pair_blocks(b->slots[act[j]].desc.n);
+    qb[j] = (int)pair_blocks(b->slots[act[j]].desc.n, p32);
+    bb[j] = (int)build_blocks(b->slots[act[j]].desc.n);
   }
   const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb),
-                         qstart = prefix(qb), vstart = prefix(vb);
+                         qstart = prefix(qb), vstart = prefix(vb), bstart = prefix(bb);
   const MDArgs* d_md1 = put(b, md1.data(), nsys);
   const MDArgs* d_md2 = put(b, md2.data(), nsys);
   const RealArgs* d_ra = put(b, ra.data(), nsys);
@@ -386,6 +388,7 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   const int* d_ustart = put(b, ustart.data(), nsys + 1);
   const int* d_qstart = put(b, qstart.data(), nsys + 1);
   const int* d_vstart = put(b, vstart.data(), nsys + 1);
+  const int* d_bstart_b = put(b, bstart.data(), nsys + 1);
   const int* d_cstart = put(b, cstart.data(), nsys + 1);
   // structure factors grouped by lane width, forces by block shape
   struct Group { std::vector<int> idx; const StepArgs* tab; const int* start; int total; size_t lds; };
@@ -440,7 +443,8 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   mark(3);
   if (e == hipSuccess)
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
-                          qstart.back(), d_vstart, vstart.back(), any_list, any_cells, max_types, nsys,
+                          qstart.back(), d_bstart_b, bstart.back(), d_vstart, vstart.back(), any_list,
+                          any_cells, max_types, nsys,
                           b->cfg.real_precision == RBE_PREC_FP32, b->stream);
   mark(4);
   if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);

@@ -359,7 +359,7 @@ __device__ __forceinline__ double wsum_md(double v) {
 // mode 0: closing half step (B_R, pressure, B_V); mode 1: pressure only
 __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int bx, int nbx) {
   __shared__ MDCell sc;
-  __shared__ double sh[4][12];
+  __shared__ double sh[kMdThreads / 64][12];
   __shared__ int sh_last;
   const double h = 0.5 * a.dt;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -423,20 +423,64 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   }
   __syncthreads();
   if (threadIdx.x < 12) {
-    const double s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+    double s = 0.0;
+    for (int q = 0; q < kMdThreads / 64; ++q) s += sh[q][threadIdx.x];
     __hip_atomic_store(&a.part[bx * 16 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  // the last block of each group of kMdGroup blocks sums the group (one
+  // block per thread, all loads in flight at once), the last group sums the
+  // groups; both in a fixed order
+  __shared__ double red[12][kMdThreads + 1];
+  __shared__ double ksum[12];
+  const int g = bx / kMdGroup, ng = (nbx + kMdGroup - 1) / kMdGroup;
+  const int gsize = min(kMdGroup, nbx - g * kMdGroup);
   if (threadIdx.x == 0)
-    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
+    sh_last = __hip_atomic_fetch_add(&a.cnt[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)gsize - 1u;
   __syncthreads();
   if (!sh_last) return;
-  __shared__ double ksum[12];
+  static_assert(kMdGroup <= kMdThreads, "one group member per thread");
+  {
+    double pv[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      pv[k] = (int)threadIdx.x < gsize ? __hip_atomic_load(&a.part[(g * kMdGroup + threadIdx.x) * 16 + k],
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = pv[k];
+  }
+  __syncthreads();
+  double* gp = a.part + (int64_t)nbx * 16;
   if (threadIdx.x < 12) {
     double s = 0.0;
-    for (int b = 0; b < nbx; ++b)
-      s += __hip_atomic_load(&a.part[b * 16 + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int j = 0; j < gsize; ++j) s += red[threadIdx.x][j];
+    __hip_atomic_store(&gp[g * 16 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(&a.cnt[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    sh_last = __hip_atomic_fetch_add(&a.cnt[ng], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)ng - 1u;
+  __syncthreads();
+  if (!sh_last) return;
+  {
+    // thread t adds groups t, t + kMdThreads, ... in turn; then thread k adds
+    // the threads' sums in order
+    double pv[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int gi = threadIdx.x; gi < ng; gi += kMdThreads) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        pv[k] += __hip_atomic_load(&gp[gi * 16 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = pv[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    double s = 0.0;
+    const int m = min(ng, kMdThreads);
+    for (int j = 0; j < m; ++j) s += red[threadIdx.x][j];
     ksum[threadIdx.x] = s;
   }
   __syncthreads();
@@ -453,24 +497,24 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
     }
     if (!prime) B_V(a, c, h);
     *a.cell_out = c;
-    *a.cnt = 0u;
+    __hip_atomic_store(&a.cnt[ng], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-__global__ void __launch_bounds__(256) k_md_first(MDArgs a) { md_first_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_md_second(MDArgs a, int prime) {
+__global__ void __launch_bounds__(kMdThreads) k_md_first(MDArgs a) { md_first_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(kMdThreads) k_md_second(MDArgs a, int prime) {
   md_second_body(a, prime, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((md_units(a) + 255) / 256);
-  hipLaunchKernelGGL(k_md_first, dim3(blocks), dim3(256), 0, s, a);
+  const unsigned blocks = (unsigned)md_blocks(md_units(a));
+  hipLaunchKernelGGL(k_md_first, dim3(blocks), dim3(kMdThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_md_second(const MDArgs& a, int prime, hipStream_t s) {
-  const unsigned blocks = (unsigned)((md_units(a) + 255) / 256);
-  hipLaunchKernelGGL(k_md_second, dim3(blocks), dim3(256), 0, s, a, prime);
+  const unsigned blocks = (unsigned)md_blocks(md_units(a));
+  hipLaunchKernelGGL(k_md_second, dim3(blocks), dim3(kMdThreads), 0, s, a, prime);
   return hipGetLastError();
 }
 
@@ -484,7 +528,7 @@ __device__ __forceinline__ int find_sys_m(const int* bstart, int nsys, int b) {
   return lo;
 }
 
-__global__ void __launch_bounds__(256) k_md_first_m(const MDArgs* tab, const int* bstart, int nsys) {
+__global__ void __launch_bounds__(kMdThreads) k_md_first_m(const MDArgs* tab, const int* bstart, int nsys) {
   __shared__ MDArgs sa;
   const int sys = find_sys_m(bstart, nsys, blockIdx.x);
   if (threadIdx.x == 0) sa = tab[sys];
@@ -492,7 +536,7 @@ __global__ void __launch_bounds__(256) k_md_first_m(const MDArgs* tab, const int
   md_first_body(sa, blockIdx.x - bstart[sys]);
 }
 
-__global__ void __launch_bounds__(256) k_md_second_m(const MDArgs* tab, const int* bstart, int nsys,
+__global__ void __launch_bounds__(kMdThreads) k_md_second_m(const MDArgs* tab, const int* bstart, int nsys,
                                                      int prime) {
   __shared__ MDArgs sa;
   const int sys = find_sys_m(bstart, nsys, blockIdx.x);
@@ -503,13 +547,13 @@ __global__ void __launch_bounds__(256) k_md_second_m(const MDArgs* tab, const in
 
 hipError_t launch_md_first_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_md_first_m, dim3(total), dim3(256), 0, s, d_tab, d_bstart, nsys);
+  hipLaunchKernelGGL(k_md_first_m, dim3(total), dim3(kMdThreads), 0, s, d_tab, d_bstart, nsys);
   return hipGetLastError();
 }
 
 hipError_t launch_md_second_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
                                   int prime, hipStream_t s) {
-  hipLaunchKernelGGL(k_md_second_m, dim3(total), dim3(256), 0, s, d_tab, d_bstart, nsys, prime);
+  hipLaunchKernelGGL(k_md_second_m, dim3(total), dim3(kMdThreads), 0, s, d_tab, d_bstart, nsys, prime);
   return hipGetLastError();
 }
 

@@ -79,7 +79,8 @@ rbe_status md_second_args(rbe_md_ctx c, const double* d_x, const double* d_y, co
 
 int64_t md_footprint(int64_t n) {
   auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
-  return r(2 * sizeof(MDCell)) + r(8 * n) + r(128 * ((n + 255) / 256)) + r(4) + r(4);
+  const int64_t blocks = md_blocks(n), groups = md_groups(blocks);
+  return r(2 * sizeof(MDCell)) + r(8 * n) + r(128 * (blocks + groups)) + r(4 * (groups + 1)) + r(4);
 }
 
 }  // namespace rbe
@@ -109,11 +110,12 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   c->cfg = *cfg;
   c->stream = (hipStream_t)stream;
   const size_t n = (size_t)cfg->n;
-  const size_t blocks = (n + 255) / 256;
+  // sized for n units (no rigid molecules); rigid molecules need fewer
+  const size_t blocks = (size_t)md_blocks((int64_t)n), groups = (size_t)md_groups((int64_t)blocks);
   bool ok = hipMalloc(&c->d_cell, 2 * sizeof(MDCell)) == hipSuccess &&
             hipMalloc(&c->d_mass, n * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->d_part, blocks * 16 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->d_cnt, sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(&c->d_part, (blocks + groups) * 16 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_cnt, (groups + 1) * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(&c->d_flags, sizeof(int32_t)) == hipSuccess;
   if (!ok) { mfree(c); delete c; return mfail(RBE_ERR_ALLOC, "device allocation failed"); }
   MDCell cell{};
@@ -136,7 +138,7 @@ rbe_status rbe_md_init(const rbe_md_config* cfg, const double* d_mass, const dou
   do {
     if ((e = hipMemcpyAsync(c->d_mass, d_mass, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess) break;
     if ((e = hipMemcpyAsync(c->d_cell, cells, sizeof cells, hipMemcpyHostToDevice, c->stream)) != hipSuccess) break;
-    if ((e = hipMemsetAsync(c->d_cnt, 0, sizeof(uint32_t), c->stream)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(c->d_cnt, 0, (groups + 1) * sizeof(uint32_t), c->stream)) != hipSuccess) break;
     if ((e = hipMemsetAsync(c->d_flags, 0, sizeof(int32_t), c->stream)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (0);

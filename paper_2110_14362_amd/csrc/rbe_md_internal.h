@@ -33,8 +33,8 @@ struct MDArgs {
   uint64_t seed, sysid, step;
   const MDCell* cell_in;
   MDCell* cell_out;
-  double* part;      // [blocks][16]
-  uint32_t* cnt;
+  double* part;      // [blocks][16] block partials, then [md_groups][16] group partials
+  uint32_t* cnt;     // [md_groups + 1] arrival counters
   // rigid 3-site molecules: atoms rig_first + 3k (O), +1, +2 (H) for
   // k < rig_count; one thread per molecule, one per remaining atom
   int64_t rig_first, rig_count;
@@ -45,6 +45,15 @@ struct MDArgs {
 
 // threads (units) of the integrator kernels: molecules plus free atoms
 __host__ __device__ inline int64_t md_units(const MDArgs& a) { return a.n - 2 * a.rig_count; }
+
+// integrator blocks are one wave: a rigid molecule's update is long FP64
+// work, so small blocks spread a system's molecules over more CUs
+constexpr int kMdThreads = 64;
+__host__ __device__ inline int64_t md_blocks(int64_t units) { return (units + kMdThreads - 1) / kMdThreads; }
+// pressure reduction: block partials summed by the last block of each group
+// of kMdGroup blocks, group partials by the last group
+constexpr int kMdGroup = 64;
+__host__ __device__ inline int64_t md_groups(int64_t blocks) { return (blocks + kMdGroup - 1) / kMdGroup; }
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s);
 hipError_t launch_md_second(const MDArgs& a, int prime, hipStream_t s);

@@ -460,12 +460,40 @@ __device__ __forceinline__ void radius_band(double rs, const double l[3], float&
   hi = (float)(rs * rs + band);
 }
 
-// Block partial of (U, W) in a fixed order (wave sums, then waves in order);
-// the last-arriving block sums the partials in a fixed, parallel order and
-// writes half of each (every pair was counted from both ends).
+// Sum 7 x m values held in LDS (red[k][j], j < m <= 256) in a fixed order:
+// threads (k, c) add j = c, c + 32, ... in turn, then thread k adds its 32
+// chunk sums in order.  Every thread of the block calls it.
+__device__ __forceinline__ void fixed_sum7(double (*red)[kRedGroup + 1], double (*red2)[33], int m,
+                                           double out[7]) {
+  if (threadIdx.x < 7 * 32) {
+    const int k = threadIdx.x / 32, ch = threadIdx.x % 32;
+    double s = 0.0;
+    for (int j = ch; j < m; j += 32) s += red[k][j];
+    red2[k][ch] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    double s = 0.0;
+    for (int ch = 0; ch < 32; ++ch) s += red2[threadIdx.x][ch];
+    out[threadIdx.x] = s;
+  }
+}
+
+// Block partial of (U, W) in a fixed order (wave sums, then waves in order).
+// The last-arriving block of each group of kRedGroup blocks sums the group's
+// partials (every thread loads its block's seven at once) and the last group
+// sums the group partials; both sums have a fixed order, so the result does
+// not depend on which block arrives last.  Writes half of each total (every
+// pair was counted from both ends).
+// scratch: LDS of at least kRedScratch doubles that the caller no longer
+// needs (its queue or list staging), written only after a block barrier.
+constexpr int kRedScratch = 7 * (kRedGroup + 1) + 7 * 33;
 __device__ __forceinline__ void block_energy_virial(const RealArgs& a, double u, const double w[6],
                                                     double (*sh)[8], int& sh_last, int bx, int nbx,
-                                                    int wave, int lane) {
+                                                    int wave, int lane, double* scratch) {
+  double (*red)[kRedGroup + 1] = reinterpret_cast<double (*)[kRedGroup + 1]>(scratch);
+  double (*red2)[33] = reinterpret_cast<double (*)[33]>(scratch + 7 * (kRedGroup + 1));
+  __shared__ double tot[7];
   double v[7] = {u, w[0], w[1], w[2], w[3], w[4], w[5]};
   for (int k = 0; k < 7; ++k) {
     const double s = wsum(v[k]);
@@ -479,28 +507,55 @@ __device__ __forceinline__ void block_energy_virial(const RealArgs& a, double u,
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  const int g = bx / kRedGroup, ng = (nbx + kRedGroup - 1) / kRedGroup;
+  const int gsize = min(kRedGroup, nbx - g * kRedGroup);
   if (threadIdx.x == 0)
-    sh_last = __hip_atomic_fetch_add(a.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nbx - 1u;
+    sh_last = __hip_atomic_fetch_add(&a.cnt[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)gsize - 1u;
   __syncthreads();
   if (!sh_last) return;
-  // the last block: sum the block partials in a fixed order, 32 strided
-  // chunks per component in parallel, then the chunks in order
-  __shared__ double red[7][33];
-  if (threadIdx.x < 7 * 32) {
-    const int k = threadIdx.x / 32, ch = threadIdx.x % 32;
-    double s = 0.0;
-    for (int b = ch; b < nbx; b += 32)
-      s += __hip_atomic_load(&a.part[b * 8 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    red[k][ch] = s;
+  // the group's last block
+  for (int j = threadIdx.x; j < kRedGroup; j += blockDim.x) {
+    double pv[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      pv[k] = j < gsize ? __hip_atomic_load(&a.part[(g * kRedGroup + j) * 8 + k], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) red[k][j] = pv[k];
   }
   __syncthreads();
+  fixed_sum7(red, red2, gsize, tot);
+  double* gp = a.part + (int64_t)nbx * 8;
+  if (threadIdx.x < 7)
+    __hip_atomic_store(&gp[g * 8 + threadIdx.x], tot[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(&a.cnt[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    sh_last = __hip_atomic_fetch_add(&a.cnt[ng], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)ng - 1u;
+  __syncthreads();
+  if (!sh_last) return;
+  // the last group: thread t adds groups t, t + 256, ... in turn, then the
+  // thread sums in the fixed order above
+  double pv[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (threadIdx.x < kRedGroup)
+    for (int gi = threadIdx.x; gi < ng; gi += kRedGroup) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k)
+        pv[k] += __hip_atomic_load(&gp[gi * 8 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  if (threadIdx.x < kRedGroup) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = pv[k];
+  }
+  __syncthreads();
+  fixed_sum7(red, red2, min(ng, kRedGroup), tot);
   if (threadIdx.x < 7) {
-    double s = 0.0;
-    for (int ch = 0; ch < 32; ++ch) s += red[threadIdx.x][ch];
+    const double s = tot[threadIdx.x];
     if (threadIdx.x == 0) { if (a.energy) a.energy[0] = 0.5 * s; }
     else if (a.virial6) a.virial6[threadIdx.x - 1] = 0.5 * s;
   }
-  if (threadIdx.x == 0) *a.cnt = 0u;
+  if (threadIdx.x == 0) __hip_atomic_store(&a.cnt[ng], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool P32>
@@ -524,8 +579,9 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   radius_band(a.rc, l, rc2_lo, rc2_hi);
   double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
   float u32 = 0.0f, w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // FP32 option: one particle's sums
-  for (int k = 0; k < kPairPerWave; ++k) {
-    const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);   // the wave's i
+  constexpr int ppw = pair_per_wave(P32);
+  for (int k = 0; k < ppw; ++k) {
+    const int t = (int)((int64_t)bx * kPairWaves * ppw + wave * ppw + k);   // the wave's i
     if (t >= a.n) break;
     const double4 vi = a.xq[t];
     const int ti = uniform(a.ts[t]);
@@ -619,7 +675,8 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
       for (int q = 0; q < 6; ++q) { w[q] += (double)w32[q]; w32[q] = 0.0f; }
     }
   }
-  block_energy_virial(a, u, w, sh, sh_last, bx, nbx, wave, lane);
+  static_assert(sizeof(queue) >= kRedScratch * sizeof(double), "reduction scratch");
+  block_energy_virial(a, u, w, sh, sh_last, bx, nbx, wave, lane, reinterpret_cast<double*>(queue));
 }
 
 __global__ void __launch_bounds__(256) k_bin(RealArgs a) { bin_body(a, blockIdx.x); }
@@ -687,9 +744,9 @@ __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
   const double rs = search_radius(a), rs2 = rs * rs;
   float lo, hi;
   radius_band(rs, l, lo, hi);
-  for (int k = 0; k < kPairPerWave; ++k) {
-    const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);
-    if (t >= a.n) break;
+  {
+    const int t = (int)((int64_t)bx * kPairWaves + wave);
+    if (t >= a.n) goto done;
     const double4 vi = a.xq[t];
     const int c = uniform(a.cs[t]);
     const int total = segment_table(a, Q, vi, c, nx, ny, nz, l, lane);
@@ -733,6 +790,7 @@ __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
     }
     wave_sync();
   }
+done:
   if (bx == 0 && threadIdx.x == 0)          // the build count
     __hip_atomic_store(&a.state[1], a.state[1] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -755,6 +813,7 @@ __device__ __forceinline__ void pack_body(const RealArgs& a, int bx) {
 // counter the prefetched batch waits on.
 template <bool P32, bool LJL>
 __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int nbx) {
+  __shared__ int32_t lidx[kPairWaves][kListChunk];
   __shared__ double cheb[kErfcxTerms];
   __shared__ float cheb32[kErfcxTerms32];
   __shared__ double ljs[LJL ? 2 * kLjLds * kLjLds : 1];
@@ -774,46 +833,61 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
   const double two_sa_pi = 2.0 * sa / sqrt(M_PI);
   double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
   float u32 = 0.0f, w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k = 0; k < kPairPerWave; ++k) {
-    const int t = (int)((int64_t)bx * kPairPerBlock + wave * kPairPerWave + k);
+  constexpr int ppw = pair_per_wave(P32);
+  for (int k = 0; k < ppw; ++k) {
+    const int t = (int)((int64_t)bx * kPairWaves * ppw + wave * ppw + k);
     if (t >= a.n) break;
     const int32_t* lst = a.nbr + (int64_t)t * a.kcap;
-    // the first two index batches lie inside the list's 128 slots, all of
-    // which hold valid indices
-    int jn = lst[lane], jn2 = lst[64 + lane];
     const double4 vi = a.xc[t];
     const int ti = uniform(a.ts[t]);
     const int total = uniform(a.ncount[t]);
-    double4 vn = a.xc[jn & kListIdxMask];
+    int32_t* L = lidx[wave];
     double fx = 0.0, fy = 0.0, fz = 0.0;
     float fx32 = 0.0f, fy32 = 0.0f, fz32 = 0.0f;
-    for (int base = 0; base < total; base += 64) {
-      const int jc = jn;
-      const double4 vc = vn;
-      jn = jn2;
-      vn = a.xc[jn & kListIdxMask];
-      // unconditional (any slot holds a valid index): a load under a branch
-      // would make the compiler wait for the batch just requested
-      jn2 = lst[min(base + 128 + lane, a.kcap - 1)];
-      double ex = vc.x - vi.x, ey = vc.y - vi.y, ez = vc.z - vi.z;
-      ex -= l[0] * rint(ex * il[0]);
-      ey -= l[1] * rint(ey * il[1]);
-      ez -= l[2] * rint(ez * il[2]);
-      const bool valid = base + lane < total && ex * ex + ey * ey + ez * ez < rc2;
-      PairLoad p;
-      p.ex = ex; p.ey = ey; p.ez = ez;
-      p.qj = vc.w;
-      p.tj = jc >> kListTypeShift;
-      if (P32) {
-        float gx, gy, gz;
-        pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, cheb32,
-                    LJL ? ljs : a.lj, gx, gy, gz, u32, w32);
-        fx32 += gx; fy32 += gy; fz32 += gz;
-      } else {
-        double gx, gy, gz;
-        pair_core(a, p, valid, vi, ti, sa, two_sa_pi, cheb, LJL ? ljs : a.lj, gx, gy, gz, u, w);
-        fx += gx; fy += gy; fz += gz;
+    for (int c0 = 0; c0 < total; c0 += kListChunk) {
+      const int cnt = min(total - c0, kListChunk);
+      // stage the chunk: independent loads, all in flight at once (every
+      // slot of a list holds a valid index, so none needs a guard)
+      // (one batch beyond the chunk's entries: the loop reads one ahead)
+      {
+        int32_t v[kListChunk / 64];
+#pragma unroll
+        for (int q = 0; q < kListChunk / 64; ++q)
+          if (q * 64 < cnt + 64) v[q] = lst[min(c0 + q * 64 + lane, a.kcap - 1)];
+#pragma unroll
+        for (int q = 0; q < kListChunk / 64; ++q)
+          if (q * 64 < cnt + 64) L[q * 64 + lane] = v[q];
       }
+      wave_sync();
+      const int jmax = (int)a.n - 1;
+      int jn = L[lane];
+      double4 vn = a.xc[min(jn & kListIdxMask, jmax)];
+      for (int base = 0; base < cnt; base += 64) {
+        const int jc = jn;
+        const double4 vc = vn;
+        jn = L[min(base + 64 + lane, kListChunk - 1)];
+        vn = a.xc[min(jn & kListIdxMask, jmax)];
+        double ex = vc.x - vi.x, ey = vc.y - vi.y, ez = vc.z - vi.z;
+        ex -= l[0] * rint(ex * il[0]);
+        ey -= l[1] * rint(ey * il[1]);
+        ez -= l[2] * rint(ez * il[2]);
+        const bool valid = base + lane < cnt && ex * ex + ey * ey + ez * ez < rc2;
+        PairLoad p;
+        p.ex = ex; p.ey = ey; p.ez = ez;
+        p.qj = vc.w;
+        p.tj = jc >> kListTypeShift;
+        if (P32) {
+          float gx, gy, gz;
+          pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, cheb32,
+                      LJL ? ljs : a.lj, gx, gy, gz, u32, w32);
+          fx32 += gx; fy32 += gy; fz32 += gz;
+        } else {
+          double gx, gy, gz;
+          pair_core(a, p, valid, vi, ti, sa, two_sa_pi, cheb, LJL ? ljs : a.lj, gx, gy, gz, u, w);
+          fx += gx; fy += gy; fz += gz;
+        }
+      }
+      wave_sync();
     }
     if (P32) { fx = (double)fx32; fy = (double)fy32; fz = (double)fz32; }
     fx = wsum(fx); fy = wsum(fy); fz = wsum(fz);
@@ -829,7 +903,8 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
       for (int q = 0; q < 6; ++q) { w[q] += (double)w32[q]; w32[q] = 0.0f; }
     }
   }
-  block_energy_virial(a, u, w, sh, sh_last, bx, nbx, wave, lane);
+  static_assert(sizeof(lidx) >= kRedScratch * sizeof(double), "reduction scratch");
+  block_energy_virial(a, u, w, sh, sh_last, bx, nbx, wave, lane, reinterpret_cast<double*>(&lidx[0][0]));
 }
 
 // four waves per SIMD: the register budget that keeps the pair evaluation
@@ -851,14 +926,14 @@ k_pairs_list(RealArgs a) {
 
 template <bool LJL>
 void launch_pairs_list(const RealArgs& a, hipStream_t s) {
-  const dim3 g((unsigned)pair_blocks(a.n)), b(kPairWaves * 64);
+  const dim3 g((unsigned)pair_blocks(a.n, a.prec32 != 0)), b(kPairWaves * 64);
   if (a.prec32) hipLaunchKernelGGL((k_pairs_list<true, LJL>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_pairs_list<false, LJL>), g, b, 0, s, a);
 }
 
 hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s) {
   const unsigned vb = (unsigned)((a.n + 255) / 256), pb = (unsigned)bin_blocks(a.n);
-  const unsigned qb = (unsigned)pair_blocks(a.n);
+  const unsigned qb = (unsigned)build_blocks(a.n);
   hipLaunchKernelGGL(k_vcheck, dim3(vb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_bin, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
@@ -879,9 +954,9 @@ hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
   if (a.prec32)
-    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)pair_blocks(a.n)), dim3(kPairWaves * 64), 0, s, a);
+    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)pair_blocks(a.n, true)), dim3(kPairWaves * 64), 0, s, a);
   else
-    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)pair_blocks(a.n)), dim3(kPairWaves * 64), 0, s, a);
+    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)pair_blocks(a.n, false)), dim3(kPairWaves * 64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -959,9 +1034,11 @@ k_pairs_list_m(const RealArgs* tab, const int* bstart, int nsys) {
 }
 
 // bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
-// bstart_q: pair blocks (pair_blocks(n) each)
+// bstart_q: pair blocks (pair_blocks(n, prec32) each); bstart_b: list-build
+// blocks (build_blocks(n) each)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
+                             const int* d_bstart_b, int total_b,
                              const int* d_bstart_v, int total_v, int any_list, int any_cells,
                              int max_types, int nsys, int prec32, hipStream_t s) {
   if (any_list) hipLaunchKernelGGL(k_vcheck_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
@@ -970,7 +1047,7 @@ hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int t
   hipLaunchKernelGGL(k_fill_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
   if (any_list) {
-    hipLaunchKernelGGL(k_build_m, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+    hipLaunchKernelGGL(k_build_m, dim3(total_b), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_b, nsys);
     hipLaunchKernelGGL(k_pack_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
     const dim3 g((unsigned)total_q), b(kPairWaves * 64);
     if (max_types <= kLjLds) {

@@ -97,12 +97,12 @@ int64_t real_footprint(const rbe_real_config* cfg, const double* box, double ski
     if (v < 5) v = 5;
     cap *= v;
   }
-  const int64_t n = cfg->n, blocks = pair_blocks(n);
+  const int64_t n = cfg->n, blocks = pair_blocks_max(n);
   auto r = [](int64_t b) { return (b + 16 + 255) / 256 * 256; };
   int64_t t = r(8 * n);
   if (cfg->ntypes > 0) t += r(4 * n) + r(16 * (int64_t)cfg->ntypes * cfg->ntypes);
   t += r(4 * n) + r(4 * cap) + r(4 * (cap + 1)) + r(4 * cap) + r(4 * n) + r(32 * n) + r(16 * n) + 2 * r(4 * n) +
-       r(16) + r(64 * blocks) + r(4) + r(4);
+       r(16) + r(64 * (blocks + red_groups(blocks))) + r(4 * (red_groups(blocks) + 1)) + r(4);
   if (skin > 0.0) {
     const int64_t kc = list_capacity(n, box, cfg->rc, skin);
     t += r(4 * n * kc) + r(4 * n) + r(24 * n) + r(24) + r(32 * n) + r(8) + r(8) + r(4);
@@ -149,7 +149,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
     if (st != RBE_OK) { delete c; return st; }
   }
   c->ncell_cap = (int)cap;
-  c->nblocks = (int)pair_blocks(cfg->n);
+  c->nblocks = (int)pair_blocks_max(cfg->n);
   const size_t n = (size_t)cfg->n;
   bool ok = true;
   double* dq = nullptr; int32_t* dt = nullptr; double* dlj = nullptr;
@@ -161,8 +161,8 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
   ok = ok && ralloc(c, &a.cellof, n) && ralloc(c, &a.count, (size_t)cap) &&
        ralloc(c, &a.start, (size_t)cap + 1) && ralloc(c, &a.cursor, (size_t)cap) &&
        ralloc(c, &a.list, n) && ralloc(c, &a.xq, n) && ralloc(c, &a.xf, n) && ralloc(c, &a.ts, n) && ralloc(c, &a.cs, n) &&
-       ralloc(c, &a.grid, 4) && ralloc(c, &a.part, (size_t)c->nblocks * 8) &&
-       ralloc(c, &a.cnt, 1) && ralloc(c, &a.err, 1);
+       ralloc(c, &a.grid, 4) && ralloc(c, &a.part, (size_t)(c->nblocks + red_groups(c->nblocks)) * 8) &&
+       ralloc(c, &a.cnt, (size_t)red_groups(c->nblocks) + 1) && ralloc(c, &a.err, 1);
   if (!ok) { rfree(c); delete c; return rfail(RBE_ERR_ALLOC, "device allocation failed"); }
   a.q = dq; a.type = dt; a.lj = dlj;
   hipError_t e = hipSuccess;
@@ -173,7 +173,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
       if ((e = hipMemcpyAsync(dlj, h_lj, (size_t)cfg->ntypes * cfg->ntypes * 2 * sizeof(double), hipMemcpyHostToDevice, c->stream)) != hipSuccess) break;
     }
     if ((e = hipMemsetAsync(a.count, 0, (size_t)cap * sizeof(int32_t), c->stream)) != hipSuccess) break;
-    if ((e = hipMemsetAsync(a.cnt, 0, sizeof(uint32_t), c->stream)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(a.cnt, 0, ((size_t)red_groups(c->nblocks) + 1) * sizeof(uint32_t), c->stream)) != hipSuccess) break;
     if ((e = hipMemsetAsync(a.err, 0, sizeof(int32_t), c->stream)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (0);

@@ -9,8 +9,11 @@ namespace rbe {
 constexpr int kCellMax = 2048;     // members of one cell the sort kernel can order
 constexpr int kCellAxisMax = 96;   // cells per axis
 constexpr int kPairWaves = 4;      // pair kernel: waves per block
-constexpr int kPairPerWave = 1;    // particles i a wave takes in turn
-constexpr int kPairPerBlock = kPairWaves * kPairPerWave;
+// particles a wave of the pair kernels takes in turn: two on the FP32 path
+// (the block's fixed costs and the arrival atomic are spread over more work),
+// one on the FP64 path (its registers allow three waves per SIMD only)
+constexpr int kPairPerWave64 = 1, kPairPerWave32 = 2;
+__host__ __device__ constexpr int pair_per_wave(bool p32) { return p32 ? kPairPerWave32 : kPairPerWave64; }
 constexpr int kPairQueue = 512;    // accepted-pair queue of a wave
 // neighbour-list entries: the cell-order index in the low 25 bits, the
 // Lennard-Jones type above them; lists hold at least 128 entries
@@ -25,9 +28,24 @@ constexpr int kBinLds = 8192;      // cells counted in LDS by the binning kernel
 
 __host__ __device__ inline int64_t bin_blocks(int64_t n) { return (n + kBinPer - 1) / kBinPer; }
 
-__host__ __device__ inline int64_t pair_blocks(int64_t n) {
-  return (n + kPairPerBlock - 1) / kPairPerBlock;
+__host__ __device__ inline int64_t pair_blocks(int64_t n, bool p32) {
+  const int per = kPairWaves * pair_per_wave(p32);
+  return (n + per - 1) / per;
 }
+// the list build: one particle per wave
+__host__ __device__ inline int64_t build_blocks(int64_t n) { return (n + kPairWaves - 1) / kPairWaves; }
+// the most pair blocks of either path (sizes the block partials)
+__host__ __device__ inline int64_t pair_blocks_max(int64_t n) { return build_blocks(n); }
+
+// energy / virial reduction of the pair kernels: block partials summed by
+// the last block of each group of kRedGroup blocks, group partials by the
+// last group
+constexpr int kRedGroup = 256;
+__host__ __device__ inline int64_t red_groups(int64_t blocks) {
+  return (blocks + kRedGroup - 1) / kRedGroup;
+}
+// list pair kernel: list entries staged in LDS per wave, this many at a time
+constexpr int kListChunk = 1024;
 
 struct RealArgs {
   const double* x; const double* y; const double* z;
@@ -48,8 +66,9 @@ struct RealArgs {
   float4* xf;                              // the same positions in FP32 (candidate tests)
   int32_t* ts; int32_t* cs;
   int32_t* grid;                           // cells per axis of the last binning
-  double* part;                            // [pair_blocks(n)][8]
-  uint32_t* cnt;
+  double* part;                            // [pair_blocks_max(n)][8] block partials, then
+                                           // [red_groups][8] group partials
+  uint32_t* cnt;                           // [red_groups + 1] arrival counters
   int32_t* err;                            // bit 1: rc > 2l/5 or cell cap; bit 2: cell overflow;
                                            // bit 3: a neighbour list over capacity
   // neighbour lists (skin > 0): pairs closer than rc + skin at the last
@@ -74,6 +93,7 @@ hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
+                             const int* d_bstart_b, int total_b,
                              const int* d_bstart_v, int total_v, int any_list, int any_cells,
                              int max_types, int nsys, int prec32, hipStream_t s);
 
