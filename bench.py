@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=120,
                     help="requests of the served stream (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--md-variants", type=int, default=1,
+                    help="also time the full step with cell lists and with FP32 pairs (0: skip)")
     ap.add_argument("--skin", type=float, default=1.0,
                     help="real-space neighbour-list skin (A) of the full NPT step and the "
                          "served stream (0: cell lists every step)")
@@ -439,10 +441,11 @@ def main():
     if args.workload == "water_30k" and args.md_steps > 0:
         note("full NPT step")
         out["ns_per_day"] = md_ns_per_day(args.md_steps, args.precision, torch, skin=args.skin)
-        out["ns_per_day_variants"] = {
-            "cell_lists_fp64": md_ns_per_day(args.md_steps, args.precision, torch, skin=0.0),
-            "fp32_pairs": md_ns_per_day(args.md_steps, args.precision, torch, skin=args.skin,
-                                        real_precision="fp32")}
+        if args.md_variants:
+            out["ns_per_day_variants"] = {
+                "cell_lists_fp64": md_ns_per_day(args.md_steps, args.precision, torch, skin=0.0),
+                "fp32_pairs": md_ns_per_day(args.md_steps, args.precision, torch, skin=args.skin,
+                                            real_precision="fp32")}
     if args.workload == "water_30k" and args.serve_requests > 0:
         note("served stream")
         out["served"] = served_stream(args.serve_requests, args.serve_budget_gib, args.precision,

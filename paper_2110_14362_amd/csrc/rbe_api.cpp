@@ -284,6 +284,11 @@ rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, con
   if (!c) return fail(RBE_ERR_ARG, "NULL context");
   if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return fail(RBE_ERR_ARG, "NULL particle array");
   if (!c->have_k) return fail(RBE_ERR_STATE, "rbe_forces_pressure before rbe_sample_k / rbe_set_k");
+  if (c->pend_sample && c->sampler == RBE_SAMPLER_MH) {
+    // the chains move in the standalone table and draw kernels
+    rbe_status st = flush(c);
+    if (st != RBE_OK) return st;
+  }
   StepArgs a = step_args(c);
   a.x = d_x; a.y = d_y; a.z = d_z;
   a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;

@@ -312,7 +312,9 @@ __device__ void mh_frequency(const StepArgs& a, const BoxState& b, int l, int m[
   }
 }
 
-// frequency l of the current step under the context's sampler
+// frequency l of the current step under the context's sampler (the chains
+// move in the standalone draw kernel only: inlined into the structure-factor
+// kernel, their FP64 transcendentals would raise its register budget)
 __device__ __forceinline__ void sample_frequency(const StepArgs& a, const BoxState& b,
                                                  const double* tab, int l, int m[3]) {
   if (a.sampler == RBE_SAMPLER_MH && !a.mh_init) mh_frequency(a, b, l, m);
@@ -630,13 +632,8 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
         mv[0] = m_pre[3 * l]; mv[1] = m_pre[3 * l + 1]; mv[2] = m_pre[3 * l + 2];
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else if (a.sample) {
-        sample_frequency(a, sbs, tabs, (int)l, mv);
-        if (x == 0) {
-          a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2];
-          if (a.sampler == RBE_SAMPLER_MH) {
-            a.mh_new[3 * l] = mv[0]; a.mh_new[3 * l + 1] = mv[1]; a.mh_new[3 * l + 2] = mv[2];
-          }
-        }
+        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv);
+        if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else {
         mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
       }
