@@ -226,43 +226,30 @@ def md_ns_per_day(steps, precision, torch, skin=0.0, real_precision="fp64"):
             "final_box_A": float(st["box"][0])}
 
 
-def served_stream(nreq, budget_gib, precision, skin=0.0):
-    """Served mixed-size NPT stream: requests of N log-uniform in [1e3, 2e5]
-    (half ions, half rigid water), cubic or 1:1:1.25 cells at 0.100284
-    charges/A^3, P = 100, 20 NPT steps each, real-space neighbour lists with
-    up to `skin` (as the box allows).  One system at a time, back to
-    back, first (the serial capacity); then Poisson arrivals at 0.8 of it,
-    served one system at a time (first come, first served) and with
-    continuous batching (fused launches); then all requests at once
-    (saturated, fused)."""
+def _serve_legs(b, reqs, fourier_only, tag):
+    """Serial capacity, then Poisson arrivals at 0.8 of it served one system at
+    a time and with continuous batching, then everything at once (fused)."""
     from paper_2110_14362_amd import serve
-    from paper_2110_14362_amd.rbe import Batch
-    reqs = serve.make_requests(nreq, kinds=("ions", "water"), skin=skin)
-    budget = int(budget_gib * (1 << 30))
-    b = Batch(budget, max_systems=1024, precision=precision)
-    warm = serve.make_requests(3, seed=77, kinds=("ions", "water"), nmin=2000, nmax=20000,
-                               steps=3, skin=skin)
-    serve.serve_serial(b, warm)
-    ser = serve.serve_serial(b, reqs)
-    note("served: serial %.2f s" % ser["wall_s"])
+    nreq = len(reqs)
+    ser = serve.serve_serial(b, reqs, fourier_only=fourier_only)
+    note("served %s: serial %.2f s" % (tag, ser["wall_s"]))
     rate = 0.8 * nreq / ser["wall_s"]
     arrivals = serve.poisson_arrivals(nreq, rate)
     for r, t in zip(reqs, arrivals):
         r.arrival, r.lat, r.done = float(t), [], 0
-    fifo = serve.serve(b, reqs, fused=False, max_active=1)
-    note("served: one at a time, Poisson %.2f s" % fifo["wall_s"])
+    fifo = serve.serve(b, reqs, fused=False, max_active=1, fourier_only=fourier_only)
+    note("served %s: one at a time, Poisson %.2f s" % (tag, fifo["wall_s"]))
     for r, t in zip(reqs, arrivals):
         r.arrival, r.lat, r.done = float(t), [], 0
-    fused = serve.serve(b, reqs, fused=True)
-    note("served: fused Poisson %.2f s" % fused["wall_s"])
+    fused = serve.serve(b, reqs, fused=True, fourier_only=fourier_only)
+    note("served %s: fused Poisson %.2f s" % (tag, fused["wall_s"]))
     for r in reqs:
         r.arrival, r.lat, r.done = 0.0, [], 0
     b.timing_enable(4 * reqs[0].steps)
-    sat = serve.serve(b, reqs, fused=True)
+    sat = serve.serve(b, reqs, fused=True, fourier_only=fourier_only)
     kt = b.timing_read()
     b.timing_enable(0)
-    note("served: fused saturated %.2f s" % sat["wall_s"])
-    b.close()
+    note("served %s: fused saturated %.2f s" % (tag, sat["wall_s"]))
     fourier = {}
     for k in ("sfac", "force"):
         if kt[k] > 0:
@@ -273,14 +260,39 @@ def served_stream(nreq, budget_gib, precision, skin=0.0):
     fourier["device_ms_per_step"] = {k: kt[k] / max(kt["steps"], 1) for k in b.BATCH_KINDS}
     fourier["timed_steps"] = kt["steps"]
     keep = ("wall_s", "np_per_s", "p50_ms", "p99_ms")
-    return {"requests": nreq, "steps_per_request": reqs[0].steps,
-            "mean_n": ser["mean_n"], "budget_bytes": budget, "arrival_rate_per_s": rate,
+    return {"steps_per_request": reqs[0].steps, "arrival_rate_per_s": rate,
             "serial_capacity": {k: ser[k] for k in keep},
             "one_at_a_time_poisson": {k: fifo[k] for k in keep},
             "fused_poisson": {k: fused[k] for k in keep + ("max_active", "ticks")},
             "fused_saturated": {k: sat[k] for k in keep + ("max_active", "ticks")},
             "throughput_gain_saturated": sat["np_per_s"] / ser["np_per_s"],
-            "saturated_kernels": fourier,
+            "throughput_gain_poisson": fused["np_per_s"] / fifo["np_per_s"],
+            "saturated_kernels": fourier}
+
+
+def served_stream(nreq, budget_gib, precision, skin=0.0, fourier_steps=400):
+    """Served mixed-size stream: requests of N log-uniform in [1e3, 2e5] (half
+    ions, half rigid water), cubic or 1:1:1.25 cells at 0.100284 charges/A^3,
+    P = 100, real-space neighbour lists with up to `skin` (as the box allows).
+    Two streams of the same systems: 20 full NPT steps per request, and
+    `fourier_steps` Fourier-space steps per request (the k-space step alone,
+    rbe_batch_step_fourier).  Each: one system at a time back to back (the
+    serial capacity), Poisson arrivals at 0.8 of it served one at a time and
+    with continuous batching (fused launches), all requests at once (fused)."""
+    from paper_2110_14362_amd import serve
+    from paper_2110_14362_amd.rbe import Batch
+    budget = int(budget_gib * (1 << 30))
+    b = Batch(budget, max_systems=1024, precision=precision)
+    warm = serve.make_requests(3, seed=77, kinds=("ions", "water"), nmin=2000, nmax=20000,
+                               steps=3, skin=skin)
+    serve.serve_serial(b, warm)
+    reqs = serve.make_requests(nreq, kinds=("ions", "water"), skin=skin)
+    npt = _serve_legs(b, reqs, False, "NPT")
+    reqs_f = serve.make_requests(nreq, kinds=("ions", "water"), skin=skin, steps=fourier_steps)
+    four = _serve_legs(b, reqs_f, True, "Fourier")
+    b.close()
+    return {"requests": nreq, "mean_n": float(np.mean([r.n for r in reqs])), "budget_bytes": budget,
+            "npt_step": npt, "fourier_step": four,
             "note": "latency = time between a request's consecutive step completions, the "
                     "first from its arrival (queueing included); (N*P)/s counts the "
                     "Fourier-space pairs of all steps over the wall time, admission included"}

@@ -470,6 +470,16 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* desc, const doubl
  * arithmetic).  Asynchronous. */
 rbe_status rbe_batch_step(rbe_batch b, int32_t fused);
 
+/* The Fourier-space step alone for every admitted system (a1-a6: cell
+ * tables, the batch of the system's current step, rho, forces, virial and
+ * energy, section 4.2 eq. (appforce), (apppress)) at its current positions
+ * and cell: forces overwrite the system's force arrays; positions, momenta
+ * and cell stay; the step counter advances.  fused as rbe_batch_step (one
+ * launch per kernel shape for all systems, or per-system launches).  Not to
+ * be mixed with rbe_batch_step on the same systems (a full step would start
+ * from Fourier-only forces).  Asynchronous. */
+rbe_status rbe_batch_step_fourier(rbe_batch b, int32_t fused);
+
 /* Waits for the batch's stream. */
 rbe_status rbe_batch_sync(rbe_batch b);
 

@@ -312,7 +312,12 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* d, const double* 
   return RBE_OK;
 }
 
-rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
+namespace {
+
+// One step of every active system: the whole NPT step, or (fourier_only)
+// the Fourier-space forces, virial and energy at the current positions and
+// cell (the batch of the system's current step).
+rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
   if (!b) return bfail(RBE_ERR_ARG, "NULL batch");
   std::vector<int> act;
   for (int i = 0; i < (int)b->slots.size(); ++i)
@@ -326,13 +331,18 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   std::vector<int> ncap(nsys);
   for (int j = 0; j < nsys; ++j) {
     Slot& s = b->slots[act[j]];
-    rbe_status st = md_first_args(s.m, s.step, s.x, s.y, s.z, s.px, s.py, s.pz, s.fx, s.fy, s.fz, &md1[j]);
-    if (st == RBE_OK) st = rbe_rescale_box_dev(s.k, s.box_dev);
+    rbe_status st = RBE_OK;
+    if (!fourier_only) {
+      st = md_first_args(s.m, s.step, s.x, s.y, s.z, s.px, s.py, s.pz, s.fx, s.fy, s.fz, &md1[j]);
+      if (st == RBE_OK) st = rbe_rescale_box_dev(s.k, s.box_dev);
+    }
     if (st == RBE_OK) st = rbe_sample_k(s.k, s.step);
     if (st == RBE_OK) st = kspace_step_args(s.k, s.x, s.y, s.z, s.fx, s.fy, s.fz, 0, s.vk, s.ek, &ka[j]);
-    if (st == RBE_OK) st = real_step_args(s.r, s.x, s.y, s.z, s.fx, s.fy, s.fz, 1, s.vr, s.er, &ra[j], &ncap[j]);
-    if (st == RBE_OK)
-      st = md_second_args(s.m, s.x, s.y, s.z, s.px, s.py, s.pz, s.fx, s.fy, s.fz, s.vk, s.vr, &md2[j]);
+    if (!fourier_only) {
+      if (st == RBE_OK) st = real_step_args(s.r, s.x, s.y, s.z, s.fx, s.fy, s.fz, 1, s.vr, s.er, &ra[j], &ncap[j]);
+      if (st == RBE_OK)
+        st = md_second_args(s.m, s.x, s.y, s.z, s.px, s.py, s.pz, s.fx, s.fy, s.fz, s.vk, s.vr, &md2[j]);
+    }
     if (st != RBE_OK) return st;
     s.step++;
   }
@@ -340,11 +350,13 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   if (!fused) {
     // every system's kernels launched by themselves, one system after another
     for (int j = 0; j < nsys && e == hipSuccess; ++j) {
-      e = launch_md_first(md1[j], b->stream);
+      if (!fourier_only) e = launch_md_first(md1[j], b->stream);
       if (e == hipSuccess) e = launch_sfac(prec, ka[j], b->stream);
       if (e == hipSuccess) e = launch_force(prec, ka[j], b->stream);
-      if (e == hipSuccess) e = launch_real(ra[j], ncap[j], b->stream);
-      if (e == hipSuccess) e = launch_md_second(md2[j], 0, b->stream);
+      if (!fourier_only) {
+        if (e == hipSuccess) e = launch_real(ra[j], ncap[j], b->stream);
+        if (e == hipSuccess) e = launch_md_second(md2[j], 0, b->stream);
+      }
     }
     b->steps_launched++;
     if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "step launches: %s", hipGetErrorString(e));
@@ -369,7 +381,7 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys), vb(nsys), bb(nsys);
   const bool p32 = b->cfg.real_precision == RBE_PREC_FP32;
   int any_list = 0, any_cells = 0, max_types = 0;
-  for (int j = 0; j < nsys; ++j) {
+  for (int j = 0; j < nsys && !fourier_only; ++j) {
     vb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
     if (ra[j].skin > 0.0) any_list = 1; else any_cells = 1;
     max_types = std::max(max_types, ra[j].ntypes);
@@ -381,15 +393,20 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
   }
   const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb),
                          qstart = prefix(qb), vstart = prefix(vb), bstart = prefix(bb);
-  const MDArgs* d_md1 = put(b, md1.data(), nsys);
-  const MDArgs* d_md2 = put(b, md2.data(), nsys);
-  const RealArgs* d_ra = put(b, ra.data(), nsys);
-  const int* d_pstart = put(b, pstart.data(), nsys + 1);
-  const int* d_ustart = put(b, ustart.data(), nsys + 1);
-  const int* d_qstart = put(b, qstart.data(), nsys + 1);
-  const int* d_vstart = put(b, vstart.data(), nsys + 1);
-  const int* d_bstart_b = put(b, bstart.data(), nsys + 1);
-  const int* d_cstart = put(b, cstart.data(), nsys + 1);
+  const MDArgs* d_md1 = nullptr; const MDArgs* d_md2 = nullptr; const RealArgs* d_ra = nullptr;
+  const int *d_pstart = nullptr, *d_ustart = nullptr, *d_qstart = nullptr, *d_vstart = nullptr,
+            *d_bstart_b = nullptr, *d_cstart = nullptr;
+  if (!fourier_only) {
+    d_md1 = put(b, md1.data(), nsys);
+    d_md2 = put(b, md2.data(), nsys);
+    d_ra = put(b, ra.data(), nsys);
+    d_pstart = put(b, pstart.data(), nsys + 1);
+    d_ustart = put(b, ustart.data(), nsys + 1);
+    d_qstart = put(b, qstart.data(), nsys + 1);
+    d_vstart = put(b, vstart.data(), nsys + 1);
+    d_bstart_b = put(b, bstart.data(), nsys + 1);
+    d_cstart = put(b, cstart.data(), nsys + 1);
+  }
   // structure factors grouped by lane width, forces by block shape
   struct Group { std::vector<int> idx; const StepArgs* tab; const int* start; int total; size_t lds; };
   std::map<int, Group> sg, fg;
@@ -429,7 +446,7 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
     if (tev && e == hipSuccess) e = hipEventRecord(tev[k], b->stream);
   };
   mark(0);
-  if (e == hipSuccess) e = launch_md_first_multi(d_md1, d_ustart, nsys, ustart.back(), b->stream);
+  if (e == hipSuccess && !fourier_only) e = launch_md_first_multi(d_md1, d_ustart, nsys, ustart.back(), b->stream);
   mark(1);
   for (auto& kv : sg)
     if (e == hipSuccess)
@@ -441,19 +458,26 @@ rbe_status rbe_batch_step(rbe_batch b, int32_t fused) {
       e = launch_force_multi(prec, kv.first, kv.second.tab, kv.second.start, (int)kv.second.idx.size(),
                              kv.second.total, b->stream);
   mark(3);
-  if (e == hipSuccess)
+  if (e == hipSuccess && !fourier_only)
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
                           qstart.back(), d_bstart_b, bstart.back(), d_vstart, vstart.back(), any_list,
                           any_cells, max_types, nsys,
                           b->cfg.real_precision == RBE_PREC_FP32, b->stream);
   mark(4);
-  if (e == hipSuccess) e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
+  if (e == hipSuccess && !fourier_only)
+    e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);
   mark(5);
   b->cur ^= 1;
   b->steps_launched++;
   if (e != hipSuccess) return bfail(RBE_ERR_DEVICE, "fused step launches: %s", hipGetErrorString(e));
   return RBE_OK;
 }
+
+}  // namespace
+
+rbe_status rbe_batch_step(rbe_batch b, int32_t fused) { return batch_step(b, fused, false); }
+
+rbe_status rbe_batch_step_fourier(rbe_batch b, int32_t fused) { return batch_step(b, fused, true); }
 
 rbe_status rbe_batch_sync(rbe_batch b) {
   if (!b) return bfail(RBE_ERR_ARG, "NULL batch");

@@ -352,14 +352,14 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
 
 __device__ __forceinline__ double wsum_md(double v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = kMdThreads / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kMdThreads);
   return v;
 }
 
 // mode 0: closing half step (B_R, pressure, B_V); mode 1: pressure only
 __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int bx, int nbx) {
   __shared__ MDCell sc;
-  __shared__ double sh[kMdThreads / 64][12];
+  __shared__ double sh[(kMdThreads + 63) / 64][12];
   __shared__ int sh_last;
   const double h = 0.5 * a.dt;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   __syncthreads();
   if (threadIdx.x < 12) {
     double s = 0.0;
-    for (int q = 0; q < kMdThreads / 64; ++q) s += sh[q][threadIdx.x];
+    for (int q = 0; q < (kMdThreads + 63) / 64; ++q) s += sh[q][threadIdx.x];
     __hip_atomic_store(&a.part[bx * 16 + threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0);

@@ -52,7 +52,7 @@ constexpr int kMdThreads = 64;
 __host__ __device__ inline int64_t md_blocks(int64_t units) { return (units + kMdThreads - 1) / kMdThreads; }
 // pressure reduction: block partials summed by the last block of each group
 // of kMdGroup blocks, group partials by the last group
-constexpr int kMdGroup = 64;
+constexpr int kMdGroup = kMdThreads;
 __host__ __device__ inline int64_t md_groups(int64_t blocks) { return (blocks + kMdGroup - 1) / kMdGroup; }
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s);

@@ -31,7 +31,7 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
            "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy",
            "rbe_md_set_rigid", "rbe_real_set_skin", "rbe_real_list_stats", "rbe_set_sampler",
-           "rbe_batch_list_stats",
+           "rbe_batch_list_stats", "rbe_batch_step_fourier",
            "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
            "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy",
@@ -121,6 +121,7 @@ def load_library(path=LIB_PATH):
         "rbe_set_sampler": [vp, ctypes.c_int32, ctypes.c_int32],
         "rbe_real_list_stats": [vp, ctypes.POINTER(ctypes.c_int64)],
         "rbe_batch_list_stats": [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
+        "rbe_batch_step_fourier": [vp, ctypes.c_int32],
         "rbe_md_init": [ctypes.POINTER(MDConfig), vp, dp, vp, ctypes.POINTER(vp)],
         "rbe_md_pressure": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "rbe_md_set_rigid": [vp, i64, i64, ctypes.c_double, ctypes.c_double],
@@ -524,8 +525,11 @@ class Batch:
         self.n_of[slot.value] = n
         return slot.value
 
-    def step(self, fused=True):
-        _check(_lib.rbe_batch_step(self._ctx, 1 if fused else 0))
+    def step(self, fused=True, fourier_only=False):
+        """One step of every admitted system: the NPT step, or with
+        fourier_only the Fourier-space forces/virial/energy alone."""
+        fn = _lib.rbe_batch_step_fourier if fourier_only else _lib.rbe_batch_step
+        _check(fn(self._ctx, 1 if fused else 0))
 
     def sync(self):
         _check(_lib.rbe_batch_sync(self._ctx))

@@ -83,11 +83,12 @@ def _admit(batch, r):
 
 
 def serve(batch, reqs, fused=True, max_active=None, keep_results=False, check=True,
-          clock=time.perf_counter):
+          clock=time.perf_counter, fourier_only=False):
     """Run the stream; reqs carry arrival times (s from the start).  Returns
     summary statistics; per-request latencies stay in r.lat.  max_active = 1
     with fused = False is the one-system-at-a-time server (first come, first
-    served, each system's kernels launched on their own)."""
+    served, each system's kernels launched on their own).  fourier_only: each
+    step is the Fourier-space step alone (rbe_batch_step_fourier)."""
     pending = collections.deque(sorted(reqs, key=lambda r: r.arrival))
     active = {}
     t0 = clock()
@@ -116,7 +117,7 @@ def serve(batch, reqs, fused=True, max_active=None, keep_results=False, check=Tr
             continue
         peak_active = max(peak_active, len(active))
         ts = clock()
-        batch.step(fused=fused)
+        batch.step(fused=fused, fourier_only=fourier_only)
         batch.sync()
         t = clock()
         busy += t - ts
@@ -138,7 +139,8 @@ def serve(batch, reqs, fused=True, max_active=None, keep_results=False, check=Tr
     return summarize(reqs, wall, ticks=ticks, max_active=peak_active, busy=busy)
 
 
-def serve_serial(batch, reqs, keep_results=False, check=True, clock=time.perf_counter):
+def serve_serial(batch, reqs, keep_results=False, check=True, clock=time.perf_counter,
+                 fourier_only=False):
     """The same requests one system at a time, each with its own per-kernel
     launches, back to back (all taken as arrived at t = 0)."""
     t0 = clock()
@@ -150,7 +152,7 @@ def serve_serial(batch, reqs, keep_results=False, check=True, clock=time.perf_co
         r.slot = slot
         r.t_last = clock() - t0
         for _ in range(r.steps):
-            batch.step(fused=False)
+            batch.step(fused=False, fourier_only=fourier_only)
             batch.sync()
             t = clock() - t0
             r.lat.append(t - r.t_last)

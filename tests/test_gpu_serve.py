@@ -127,3 +127,64 @@ def test_served_stream_runs(gpu):
     print(st, flush=True)
     assert st["steps"] == 60 and all(len(r.lat) == 5 for r in reqs)
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+# ---------------------------------------------------------------------------
+# the Fourier-space step alone, served (rbe_batch_step_fourier)
+
+def fourier_alone(r, steps, fused=True, precision="fp32"):
+    b = Batch(BUDGET, max_systems=2, precision=precision)
+    slot = serve._admit(b, r)
+    for _ in range(steps):
+        b.step(fused=fused, fourier_only=True)
+    b.sync()
+    b.check(slot)
+    out = b.read(slot)
+    b.close()
+    return out
+
+
+def test_fourier_steps_alone_equal_mix_bitwise(gpu):
+    reqs = [request(10, 1500), request(11, 4000, kinds=("water",)), request(12, 9000)]
+    b = Batch(BUDGET, max_systems=8, precision="fp32")
+    s0 = serve._admit(b, reqs[0])
+    s1 = serve._admit(b, reqs[1])
+    b.step(fourier_only=True)
+    b.step(fourier_only=True)
+    s2 = serve._admit(b, reqs[2])
+    for _ in range(3):
+        b.step(fourier_only=True)
+    b.sync()
+    mix = {}
+    for r, s in ((reqs[0], s0), (reqs[1], s1), (reqs[2], s2)):
+        b.check(s)
+        mix[r.rid] = (b.read(s), b.slot_step(s))
+    b.close()
+    assert mix[10][1] == 5 and mix[12][1] == 3
+    for r in reqs:
+        got, steps = mix[r.rid]
+        # positions untouched by Fourier-only steps
+        np.testing.assert_array_equal(got["pos"], np.asarray(r.sysd["pos"], dtype=np.float64))
+        for fused in (True, False):
+            ref = fourier_alone(r, steps, fused=fused)
+            np.testing.assert_array_equal(got["forces"], ref["forces"])
+        print("request %d (N=%d, %d Fourier steps): forces identical alone and in the mix"
+              % (r.rid, r.n, steps), flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_fourier_step_matches_oracle(gpu, precision, tol):
+    from oracle import rbe as orbe
+    from oracle import sampler as osamp
+    r = request(13, 1200)
+    steps = 2                        # the last step's batch is that of step 1
+    got = fourier_alone(r, steps, precision=precision)
+    s = r.sysd
+    m = osamp.sample_k(s["alpha"], s["box"], s["p"], seed=r.desc.seed,
+                       system_id=r.desc.system_id, step=steps - 1)
+    S = osamp.box_tables(s["alpha"], s["box"])["S"]
+    o = orbe.rbe_kspace(np.asarray(s["pos"]), s["q"], s["box"], s["alpha"], m, S,
+                        coulomb=s["coulomb"])
+    err = np.linalg.norm(got["forces"] - o["forces"]) / np.linalg.norm(o["forces"])
+    print("served Fourier step %s: force RMS rel. %.2e" % (precision, err), flush=True)
+    assert err < tol
