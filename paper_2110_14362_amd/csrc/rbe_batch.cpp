@@ -388,7 +388,8 @@ rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
     pb[j] = (int)bin_blocks(b->slots[act[j]].desc.n);
     ub[j] = (int)md_blocks(md_units(md1[j]));
     cb[j] = ncap[j];
-    qb[j] = (int)pair_blocks(b->slots[act[j]].desc.n, p32);
+    qb[j] = (int)(ra[j].skin > 0.0 ? list_blocks(b->slots[act[j]].desc.n, p32)
+                                    : pair_blocks(b->slots[act[j]].desc.n, p32));
     bb[j] = (int)build_blocks(b->slots[act[j]].desc.n);
   }
   const std::vector<int> pstart = prefix(pb), ustart = prefix(ub), cstart = prefix(cb),

@@ -803,6 +803,23 @@ __device__ __forceinline__ void pack_body(const RealArgs& a, int bx) {
   a.xc[t] = make_double4(a.x[i], a.y[i], a.z[i], a.q[i]);
 }
 
+// Entries [c0, c0 + kListChunk) of particle t's list copied to LDS without
+// passing through registers (global_load_lds: lane i's 16 bytes land at
+// L + 16 i); entries past the row's slots are clamped to its last slots.
+// Every slot of a list holds a valid index.  The caller waits (vmcnt) before
+// reading L.
+typedef __attribute__((address_space(3))) void lds_void_t;
+__device__ __forceinline__ void list_to_lds(const RealArgs& a, int t, int c0, int32_t* L, int lane) {
+  const int32_t* lst = a.nbr + (int64_t)t * a.kcap;
+  const int nq = min(kListChunk, a.kcap - c0 + 255) / 256;     // 256 entries per instruction
+#pragma unroll
+  for (int q = 0; q < kListChunk / 256; ++q)
+    if (q < nq) {
+      const int e = min(c0 + q * 256 + 4 * lane, a.kcap - 4);
+      __builtin_amdgcn_global_load_lds((const void*)(lst + e), (lds_void_t*)(L + q * 256), 16, 0, 0);
+    }
+}
+
 // Pairs from the lists: a wave per particle t; its list entries 64 at a
 // time, each lane's minimum-image separation tested against rc and the pair
 // evaluated in place (no queue: the skin keeps the accepted share high).  The
@@ -813,7 +830,7 @@ __device__ __forceinline__ void pack_body(const RealArgs& a, int bx) {
 // counter the prefetched batch waits on.
 template <bool P32, bool LJL>
 __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int nbx) {
-  __shared__ int32_t lidx[kPairWaves][kListChunk];
+  __shared__ int32_t lidx[kPairWaves][2][kListChunk];
   __shared__ double cheb[kErfcxTerms];
   __shared__ float cheb32[kErfcxTerms32];
   __shared__ double ljs[LJL ? 2 * kLjLds * kLjLds : 1];
@@ -833,30 +850,37 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
   const double two_sa_pi = 2.0 * sa / sqrt(M_PI);
   double u = 0, w[6] = {0, 0, 0, 0, 0, 0};
   float u32 = 0.0f, w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  constexpr int ppw = pair_per_wave(P32);
-  for (int k = 0; k < ppw; ++k) {
-    const int t = (int)((int64_t)bx * kPairWaves * ppw + wave * ppw + k);
-    if (t >= a.n) break;
-    const int32_t* lst = a.nbr + (int64_t)t * a.kcap;
-    const double4 vi = a.xc[t];
-    const int ti = uniform(a.ts[t]);
-    const int total = uniform(a.ncount[t]);
-    int32_t* L = lidx[wave];
+  constexpr int ppw = list_per_wave(P32);
+  const int t0 = (int)((int64_t)bx * kPairWaves * ppw + wave * ppw);
+  const int nt = uniform(max(0, min(ppw, (int)(a.n - t0))));   // the wave's particles
+  // the header of the wave's next particle and the first chunk of its list
+  // (copied straight to LDS) are requested while the current one is worked
+  double4 vi_n = make_double4(0.0, 0.0, 0.0, 0.0);
+  int ti_n = 0, tot_n = 0;
+  if (nt > 0) {
+    vi_n = a.xc[t0]; ti_n = a.ts[t0]; tot_n = a.ncount[t0];
+    list_to_lds(a, t0, 0, lidx[wave][0], lane);
+  }
+  for (int k = 0; k < nt; ++k) {
+    const int t = t0 + k, cur = k & 1;
+    __builtin_amdgcn_s_waitcnt(0);              // header and list chunk of t in place
+    wave_sync();
+    const double4 vi = vi_n;
+    const int ti = uniform(ti_n);
+    const int total = uniform(tot_n);
+    if (k + 1 < nt) {
+      vi_n = a.xc[t + 1]; ti_n = a.ts[t + 1]; tot_n = a.ncount[t + 1];
+      list_to_lds(a, t + 1, 0, lidx[wave][cur ^ 1], lane);
+    }
+    int32_t* L = lidx[wave][cur];
     double fx = 0.0, fy = 0.0, fz = 0.0;
     float fx32 = 0.0f, fy32 = 0.0f, fz32 = 0.0f;
     for (int c0 = 0; c0 < total; c0 += kListChunk) {
       const int cnt = min(total - c0, kListChunk);
-      // stage the chunk: independent loads, all in flight at once (every
-      // slot of a list holds a valid index, so none needs a guard)
-      // (one batch beyond the chunk's entries: the loop reads one ahead)
-      {
-        int32_t v[kListChunk / 64];
-#pragma unroll
-        for (int q = 0; q < kListChunk / 64; ++q)
-          if (q * 64 < cnt + 64) v[q] = lst[min(c0 + q * 64 + lane, a.kcap - 1)];
-#pragma unroll
-        for (int q = 0; q < kListChunk / 64; ++q)
-          if (q * 64 < cnt + 64) L[q * 64 + lane] = v[q];
+      if (c0 > 0) {                             // a list longer than one chunk
+        wave_sync();
+        list_to_lds(a, t, c0, L, lane);
+        __builtin_amdgcn_s_waitcnt(0);
       }
       wave_sync();
       const int jmax = (int)a.n - 1;
@@ -926,7 +950,7 @@ k_pairs_list(RealArgs a) {
 
 template <bool LJL>
 void launch_pairs_list(const RealArgs& a, hipStream_t s) {
-  const dim3 g((unsigned)pair_blocks(a.n, a.prec32 != 0)), b(kPairWaves * 64);
+  const dim3 g((unsigned)list_blocks(a.n, a.prec32 != 0)), b(kPairWaves * 64);
   if (a.prec32) hipLaunchKernelGGL((k_pairs_list<true, LJL>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_pairs_list<false, LJL>), g, b, 0, s, a);
 }
@@ -1034,8 +1058,9 @@ k_pairs_list_m(const RealArgs* tab, const int* bstart, int nsys) {
 }
 
 // bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
-// bstart_q: pair blocks (pair_blocks(n, prec32) each); bstart_b: list-build
-// blocks (build_blocks(n) each)
+// bstart_q: pair blocks (pair_blocks(n, prec32) each for a cell-list
+// system, list_blocks(n, prec32) for a neighbour-list one); bstart_b:
+// list-build blocks (build_blocks(n) each)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
                              const int* d_bstart_b, int total_b,

@@ -32,6 +32,14 @@ __host__ __device__ inline int64_t pair_blocks(int64_t n, bool p32) {
   const int per = kPairWaves * pair_per_wave(p32);
   return (n + per - 1) / per;
 }
+// the list pair kernel: a wave takes several particles in turn, requesting
+// the next one's list while it works on the current one
+constexpr int kListPerWave64 = 4, kListPerWave32 = 4;
+__host__ __device__ constexpr int list_per_wave(bool p32) { return p32 ? kListPerWave32 : kListPerWave64; }
+__host__ __device__ inline int64_t list_blocks(int64_t n, bool p32) {
+  const int per = kPairWaves * list_per_wave(p32);
+  return (n + per - 1) / per;
+}
 // the list build: one particle per wave
 __host__ __device__ inline int64_t build_blocks(int64_t n) { return (n + kPairWaves - 1) / kPairWaves; }
 // the most pair blocks of either path (sizes the block partials)
