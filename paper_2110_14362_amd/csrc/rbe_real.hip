@@ -693,10 +693,17 @@ __device__ __forceinline__ void vcheck_body(const RealArgs& a, int bx, int nbx) 
   __shared__ double sh[4];
   __shared__ int sh_last;
   if (!(a.skin > 0.0)) return;
-  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  double d2 = 0.0;
-  if (i < a.n) {
-    const double dx = a.x[i] - a.ref[i], dy = a.y[i] - a.ref[a.n + i], dz = a.z[i] - a.ref[2 * a.n + i];
+  // thread t takes the particle at place t of the last build's cell order and
+  // also gathers its current position and charge there for the pair kernel
+  // (a rebuilding evaluation rewrites them in the new order)
+  const bool built = __hip_atomic_load(&a.state[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
+  double d2 = built ? 0.0 : 1e300;              // no lists yet: build them
+  if (built && t < a.n) {
+    const int i = a.list[t];
+    const double x = a.x[i], y = a.y[i], z = a.z[i];
+    a.xc[t] = make_double4(x, y, z, a.q[i]);
+    const double dx = x - a.ref[i], dy = y - a.ref[a.n + i], dz = z - a.ref[2 * a.n + i];
     d2 = dx * dx + dy * dy + dz * dz;
     if (!(d2 == d2)) d2 = 1e300;                // non-finite: rebuild (and fail there)
   }
@@ -720,8 +727,7 @@ __device__ __forceinline__ void vcheck_body(const RealArgs& a, int bx, int nbx) 
   real_box(a, l);
   double dl = 0.0;
   for (int d = 0; d < 3; ++d) dl = fmax(dl, fabs(l[d] - a.ref_box[d]));
-  const int built = __hip_atomic_load(&a.state[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int rebuild = (built == 0 || 2.0 * sqrt(dm) + 1.7320508075688772 * dl >= a.skin) ? 1 : 0;
+  const int rebuild = (!built || 2.0 * sqrt(dm) + 1.7320508075688772 * dl >= a.skin) ? 1 : 0;
   __hip_atomic_store(&a.state[0], rebuild, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(a.dmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(a.vcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -786,7 +792,9 @@ __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
       a.ncount[t] = min(cnt, a.kcap);
       if (cnt > a.kcap) atomicOr(a.err, 8);
       const int i = a.list[t];
-      a.ref[i] = a.x[i]; a.ref[a.n + i] = a.y[i]; a.ref[2 * a.n + i] = a.z[i];
+      const double x = a.x[i], y = a.y[i], z = a.z[i];
+      a.ref[i] = x; a.ref[a.n + i] = y; a.ref[2 * a.n + i] = z;
+      a.xc[t] = make_double4(x, y, z, a.q[i]);
     }
     wave_sync();
   }
@@ -795,13 +803,6 @@ done:
     __hip_atomic_store(&a.state[1], a.state[1] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Current positions (unwrapped) and charges in the last build's cell order.
-__device__ __forceinline__ void pack_body(const RealArgs& a, int bx) {
-  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
-  if (!(a.skin > 0.0) || t >= a.n) return;
-  const int i = a.list[t];
-  a.xc[t] = make_double4(a.x[i], a.y[i], a.z[i], a.q[i]);
-}
 
 // Entries [c0, c0 + kListChunk) of particle t's list copied to LDS without
 // passing through registers (global_load_lds: lane i's 16 bytes land at
@@ -941,7 +942,6 @@ k_pairs(RealArgs a) {
 
 __global__ void __launch_bounds__(256) k_vcheck(RealArgs a) { vcheck_body(a, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(kPairWaves * 64) k_build(RealArgs a) { build_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_pack(RealArgs a) { pack_body(a, blockIdx.x); }
 template <bool P32, bool LJL>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pairs_list(RealArgs a) {
@@ -964,7 +964,6 @@ hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_build, dim3(qb), dim3(kPairWaves * 64), 0, s, a);
-  hipLaunchKernelGGL(k_pack, dim3(vb), dim3(256), 0, s, a);
   if (a.ntypes <= kLjLds) launch_pairs_list<true>(a, s);
   else launch_pairs_list<false>(a, s);
   return hipGetLastError();
@@ -1045,11 +1044,6 @@ __global__ void __launch_bounds__(kPairWaves * 64) k_build_m(const RealArgs* tab
   (void)nb;
   build_body(sa, lb);
 }
-__global__ void __launch_bounds__(256) k_pack_m(const RealArgs* tab, const int* bstart, int nsys) {
-  REAL_MULTI_PROLOGUE
-  (void)nb;
-  pack_body(sa, lb);
-}
 template <bool P32, bool LJL>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pairs_list_m(const RealArgs* tab, const int* bstart, int nsys) {
@@ -1073,7 +1067,6 @@ hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int t
   hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
   if (any_list) {
     hipLaunchKernelGGL(k_build_m, dim3(total_b), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_b, nsys);
-    hipLaunchKernelGGL(k_pack_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
     const dim3 g((unsigned)total_q), b(kPairWaves * 64);
     if (max_types <= kLjLds) {
       if (prec32) hipLaunchKernelGGL((k_pairs_list_m<true, true>), g, b, 0, s, d_tab, d_bstart_q, nsys);

@@ -97,7 +97,7 @@ struct RealArgs {
 __host__ __device__ inline double search_radius(const RealArgs& a) { return a.rc + a.skin; }
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
-// list-mode evaluation (a.skin > 0): check, conditional rebuild, pack, pairs
+// list-mode evaluation (a.skin > 0): check (and gather), conditional rebuild, pairs
 hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
