@@ -242,8 +242,16 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // t = (x - K)/(x + K) (Clenshaw); erfc(x) = exp(-x^2) erfcx(x) then shares
 // exp(-x^2) with the force term.  The coefficients are read from LDS, which
 // keeps them out of the scalar registers.
+// 1/d for d > 0: the hardware estimate refined by two Newton steps (an ulp or
+// two; the correctly rounded division takes twice the instructions)
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = fma(fma(-d, y, 1.0), y, y);
+  return fma(fma(-d, y, 1.0), y, y);
+}
+
 __device__ __forceinline__ double erfcx_pos(double x, const double* cheb) {
-  const double t = (x - kErfcxK) / (x + kErfcxK), t2 = 2.0 * t;
+  const double t = (x - kErfcxK) * rcp_nr(x + kErfcxK), t2 = 2.0 * t;
   double b1 = 0.0, b2 = 0.0;
 #pragma unroll
   for (int k = kErfcxTerms - 1; k >= 1; --k) {
@@ -289,7 +297,7 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
   if (valid) {
     const double ex = p.ex, ey = p.ey, ez = p.ez;
     const double r2 = ex * ex + ey * ey + ez * ez;
-    const double r = sqrt(r2), ir = 1.0 / r;
+    const double ir = rsqrt(r2), r = r2 * ir;
     // Coulomb: phi = C qi qj erfc(sa r)/r,  -phi' = C qi qj G(r)
     const double qq = a.coulomb * vi.w * p.qj;
     const double g2 = exp(-a.alpha * r2);
