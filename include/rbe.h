@@ -425,8 +425,10 @@ typedef struct {
   int64_t  n;            /* particles                                          */
   int32_t  p;            /* frequencies per step (batch size P)                */
   int32_t  ntypes;       /* Lennard-Jones types (0: none)                      */
-  int32_t  box_mode;     /* RBE_BOX_ISO (any aspect ratio, kept) or RBE_BOX_SEMIISO */
-  int32_t  reserved;     /* must be 0                                          */
+  int32_t  box_mode;     /* RBE_BOX_ISO (any aspect ratio, kept),              */
+                         /* RBE_BOX_SEMIISO or RBE_BOX_ANISO                    */
+  int32_t  sampler;      /* rbe_sampler of the Fourier part (RBE_SAMPLER_MH:    */
+                         /* one chain move per step, as rbe_set_sampler)        */
   double   alpha;        /* Ewald splitting parameter (length^-2)              */
   double   coulomb;      /* Coulomb constant in the force units                */
   double   rc;           /* real-space cutoff                                  */

@@ -94,7 +94,8 @@ rbe_status check_desc(const rbe_system_desc* d, const double* box) {
   if (d->p < 1 || d->p > 65536) return bfail(RBE_ERR_ARG, "p = %d must be in 1..65536", d->p);
   if (d->box_mode != RBE_BOX_ISO && d->box_mode != RBE_BOX_SEMIISO && d->box_mode != RBE_BOX_ANISO)
     return bfail(RBE_ERR_ARG, "box_mode must be RBE_BOX_ISO, RBE_BOX_SEMIISO or RBE_BOX_ANISO");
-  if (d->reserved != 0) return bfail(RBE_ERR_ARG, "reserved field must be 0");
+  if (d->sampler != RBE_SAMPLER_EXACT && d->sampler != RBE_SAMPLER_MH)
+    return bfail(RBE_ERR_ARG, "sampler = %d is not a known rbe_sampler", d->sampler);
   if (d->ntypes < 0 || d->ntypes > 64) return bfail(RBE_ERR_ARG, "ntypes = %d must be in 0..64", d->ntypes);
   if (!(d->skin >= 0.0 && fin(d->skin))) return bfail(RBE_ERR_ARG, "skin = %g must be >= 0", d->skin);
   if (!(d->alpha > 0 && fin(d->alpha)) || !(d->rc > 0 && fin(d->rc)) || !(d->coulomb > 0 && fin(d->coulomb)))
@@ -282,6 +283,7 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* d, const double* 
   const rbe_real_config rc = real_cfg(b, d);
   const rbe_md_config mc = md_cfg(d);
   st = rbe_init(&kc, s.q, box_host, b->stream, &s.k);
+  if (st == RBE_OK && d->sampler == RBE_SAMPLER_MH) st = rbe_set_sampler(s.k, RBE_SAMPLER_MH, 1);
   if (st == RBE_OK) st = rbe_real_init(&rc, s.q, d->ntypes > 0 ? s.type : nullptr, h_lj, box_host, b->stream, &s.r);
   if (st == RBE_OK && d->skin > 0.0) st = rbe_real_set_skin(s.r, d->skin);
   if (st == RBE_OK) st = rbe_md_init(&mc, s.mass, box_host, b->stream, &s.m);

@@ -18,7 +18,8 @@ class NPTSystem:
         ftm, box_mode ('iso', 'semiiso' or 'aniso'), rc; optional types + lj for the
         real-space Lennard-Jones term; optional rigid = dict(first, count,
         d_oh, d_hh) for rigid 3-site molecules (whole, not split by the
-        periodic boundary); optional skin (> 0: real-space neighbour lists).
+        periodic boundary); optional skin (> 0: real-space neighbour lists);
+        optional sampler ('exact' or 'mh', with mh_iters moves per step).
     """
 
     def __init__(self, sysd, md, precision="fp32", seed=0, system_id=0, momenta=None,
@@ -48,6 +49,8 @@ class NPTSystem:
         self.kspace = RBE(q, sysd["box"], sysd["p"], sysd["alpha"], coulomb=sysd["coulomb"],
                           precision=precision, box_mode=kmode, seed=seed, system_id=system_id,
                           stream=stream)
+        if md.get("sampler", "exact") != "exact":
+            self.kspace.set_sampler(md["sampler"], int(md.get("mh_iters", 1)))
         types = None
         if md.get("lj") is not None:
             types = torch.tensor(np.asarray(md["types"], dtype=np.int32), device=dev)

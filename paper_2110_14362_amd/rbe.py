@@ -73,7 +73,7 @@ class BatchConfig(ctypes.Structure):
 
 class SystemDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("ntypes", ctypes.c_int32),
-                ("box_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("box_mode", ctypes.c_int32), ("sampler", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("coulomb", ctypes.c_double), ("rc", ctypes.c_double),
                 ("dt", ctypes.c_double), ("kT", ctypes.c_double), ("p_ext", ctypes.c_double),
                 ("gamma_p", ctypes.c_double), ("gamma_cell", ctypes.c_double),
@@ -449,13 +449,15 @@ def _hp(a, dtype=np.float64):
 
 def system_desc(n, p, alpha, coulomb, rc, md, ntypes=0, seed=0, system_id=0):
     """rbe_system_desc from the integrator parameter dict used by NPTSystem
-    (md["rigid"]: optional dict(first, count, d_oh, d_hh))."""
+    (md["rigid"]: optional dict(first, count, d_oh, d_hh); md["skin"]: the
+    real-space list skin; md["sampler"]: 'exact' or 'mh')."""
     rg = md.get("rigid") or dict(first=0, count=0, d_oh=0.0, d_hh=0.0)
     return SystemDesc(rigid_first=int(rg["first"]), rigid_count=int(rg["count"]),
                       d_oh=float(rg["d_oh"]), d_hh=float(rg["d_hh"]),
                       skin=float(md.get("skin", 0.0)),
                       n=int(n), p=int(p), ntypes=int(ntypes),
-                      box_mode=BOX_MODES[md.get("box_mode", "iso")], reserved=0,
+                      box_mode=BOX_MODES[md.get("box_mode", "iso")],
+                      sampler=SAMPLERS[md.get("sampler", "exact")],
                       alpha=float(alpha), coulomb=float(coulomb), rc=float(rc),
                       dt=float(md["dt"]), kT=float(md["kT"]), p_ext=float(md["p_ext"]),
                       gamma_p=float(md["gamma_p"]), gamma_cell=float(md["gamma_cell"]),

@@ -54,9 +54,10 @@ class Request:
 
 
 def make_requests(count, seed=2110143625, kinds=("ions",), nmin=1000, nmax=200000, p=100,
-                  steps=20, skin=0.0):
+                  steps=20, skin=0.0, sampler="exact"):
     """The served stream's systems (arrival times are set by the caller);
-    skin > 0: real-space neighbour lists with at most that skin."""
+    skin > 0: real-space neighbour lists with at most that skin; sampler:
+    'exact' or 'mh' (the online Metropolis-Hastings chains)."""
     reqs = []
     for i in range(count):
         s = workloads.serving_request(i, seed=seed, nmin=nmin, nmax=nmax, p=p, steps=steps,
@@ -64,6 +65,8 @@ def make_requests(count, seed=2110143625, kinds=("ions",), nmin=1000, nmax=20000
         md = workloads.npt_real(s["box"], rc=s["rc"])
         if skin > 0.0:
             md["skin"] = workloads.list_skin(s["box"], s["rc"], skin)
+        if sampler != "exact":
+            md["sampler"] = sampler
         if s.get("rigid"):
             md["rigid"] = s["rigid"]
         reqs.append(Request(i, 0.0, s, md, steps))

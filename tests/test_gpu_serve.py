@@ -188,3 +188,45 @@ def test_fourier_step_matches_oracle(gpu, precision, tol):
     err = np.linalg.norm(got["forces"] - o["forces"]) / np.linalg.norm(o["forces"])
     print("served Fourier step %s: force RMS rel. %.2e" % (precision, err), flush=True)
     assert err < tol
+
+
+# ---------------------------------------------------------------------------
+# served systems on the online Metropolis-Hastings sampler
+
+def test_mh_system_alone_equals_mix_bitwise(gpu):
+    reqs = [request(20, 2000), request(21, 3000, sampler="mh"), request(22, 2500, kinds=("water",))]
+    assert reqs[1].desc.sampler == 1 and reqs[0].desc.sampler == 0
+    b = Batch(BUDGET, max_systems=8, precision="fp32")
+    slots = [serve._admit(b, r) for r in reqs]
+    for _ in range(4):
+        b.step()
+    b.sync()
+    mix = {r.rid: b.read(s) for r, s in zip(reqs, slots)}
+    b.close()
+    for r in reqs:
+        for fused in (True, False):
+            ref = run_alone(r, 4, fused=fused)
+            np.testing.assert_array_equal(mix[r.rid]["pos"], ref["pos"])
+            np.testing.assert_array_equal(mix[r.rid]["mom"], ref["mom"])
+
+
+def test_served_mh_fourier_steps_follow_the_oracle_chain(gpu):
+    from oracle import mh_sampler as omh
+    from oracle import rbe as orbe
+    from oracle import sampler as osamp
+    from tests.md_cases import INIT_STEP
+    r = request(23, 900, sampler="mh")
+    steps = 3
+    got = fourier_alone(r, steps, precision="fp64")
+    s = r.sysd
+    chains = omh.MHChains(s["alpha"], s["p"], seed=r.desc.seed, system_id=r.desc.system_id)
+    chains.sample(s["box"], INIT_STEP)              # the admission's evaluation
+    for k in range(steps):
+        m = chains.sample(s["box"], k)
+    S = osamp.box_tables(s["alpha"], s["box"])["S"]
+    o = orbe.rbe_kspace(np.asarray(s["pos"]), s["q"], s["box"], s["alpha"], m, S,
+                        coulomb=s["coulomb"])
+    err = np.linalg.norm(got["forces"] - o["forces"]) / np.linalg.norm(o["forces"])
+    print("served MH Fourier step: force RMS rel. %.2e, oracle acceptance %.2f"
+          % (err, chains.accepted / (steps * s["p"])), flush=True)
+    assert err < 1e-10
