@@ -270,7 +270,9 @@ rbe_status rbe_real_set_box_dev(rbe_real_ctx ctx, const double* d_box);
 /* Forces (written, or added when accumulate != 0), virial tensor (6 doubles,
  * xx yy zz xy xz yz; NULL to skip) and energy (1 double; NULL to skip) of the
  * real-space sum.  All arrays are DEVICE memory; positions may lie outside
- * the cell.  Asynchronous (five kernels on the context's stream). */
+ * the cell.  Asynchronous (five kernels on the context's stream; with
+ * neighbour lists seven, of which the five that rebuild exit at once unless
+ * the device decided to rebuild). */
 rbe_status rbe_real_forces(rbe_real_ctx ctx, const double* d_x, const double* d_y,
                            const double* d_z, double* d_fx, double* d_fy, double* d_fz,
                            int accumulate, double* d_virial6, double* d_energy);
@@ -282,8 +284,9 @@ rbe_status rbe_real_forces(rbe_real_ctx ctx, const double* d_x, const double* d_
  * on the device when 2 max|displacement since the build| + sqrt(3) max|cell
  * side change| >= skin (first evaluation: always).  The same pairs as without
  * lists, summed in the order of the list.  Needs every side >= 2.5 (rc +
- * skin); a list holds 1.6 x the mean number of neighbours + 64 (a fuller one
- * is flagged). */
+ * skin) and n <= 2^25; a list holds 1.6 x the mean number of neighbours + 64
+ * entries, at least 128 (a fuller one is flagged).  RBE_ERR_STATE if a skin is
+ * set already. */
 rbe_status rbe_real_set_skin(rbe_real_ctx ctx, double skin);
 
 /* Wait; h_stats[0] = evaluations launched on the context, h_stats[1] =
