@@ -172,14 +172,22 @@ void plan_launch(rbe_ctx_s* c) {
   X = (long)((c->n + chunk - 1) / chunk);
   a.X = (int)X;
   a.chunk = (int)chunk;
+  // groups of about sqrt(X) chunks: the last-arriving block of a group sums
+  // its GX partials, the group partials are summed next
   int GX = 1;
   while ((long)GX * GX < X) ++GX;
+  // small batches: every force block sums the group partials of rho itself
+  // (read through L2, from the previous launch) if there are at most 4096
+  // of them.  Halving the groups then pays: each group's arrival counter
+  // takes half as many same-address atomics, and the force blocks read
+  // twice as many (cached) rows.
+  auto rows_of = [&](int gx) { const long ng = (X + gx - 1) / gx; return ng > 1 ? ng : X; };
+  const bool k2 = a.Y == 1 && a.Ppad <= 512 && env_flag("RBE_K2REDUCE", true);
+  const int GXh = (GX + 1) / 2;
+  if (k2 && GXh >= 2 && GXh < GX && rows_of(GXh) * a.Ppad <= 4096) GX = GXh;
   a.GX = GX;
   a.NG = (int)((X + GX - 1) / GX);
-  // small batches: the force kernel sums the group partials of rho itself
-  const long rows = a.NG > 1 ? a.NG : a.X;
-  a.k2reduce = (a.Y == 1 && a.Ppad <= 512 && rows * a.Ppad <= 4096 &&
-                env_flag("RBE_K2REDUCE", true)) ? 1 : 0;
+  a.k2reduce = (k2 && rows_of(GX) * a.Ppad <= 4096) ? 1 : 0;
   const int RP = f64 ? 1 : 2;
   const long groups = (c->n + (long)kWave * RP - 1) / ((long)kWave * RP);
   const long target_waves = env_long("RBE_FORCE_WAVES", 4096);

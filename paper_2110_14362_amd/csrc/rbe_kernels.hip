@@ -423,9 +423,17 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, i
 // threads: thread t owns column t % W and rows t / W + RG*j (RG = threads /
 // W), then the RG row-group sums are added in order through LDS.  Otherwise
 // thread t owns columns t + threads*j and all rows.  Loads are issued four at
-// a time.  src is read with coherent loads; dst is written with coherent
+// a time.  src is read with coherent loads when SrcCoh (rows stored by other
+// blocks of the same launch), else plainly (rows of an earlier launch, which
+// the L2 may then serve to several blocks); dst is written with coherent
 // stores when dst_coh, else plainly (LDS).  Reached by every thread;
 // scratch holds blockDim.x entries.
+template <bool SrcCoh = true>
+__device__ __forceinline__ double2 ld_row(const double2* p) {
+  return SrcCoh ? ld_coh2(p) : *p;
+}
+
+template <bool SrcCoh = true>
 __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
                                bool dst_coh, double2* scratch) {
   const int t = threadIdx.x, nt = blockDim.x;
@@ -434,15 +442,15 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
       double2 acc = make_double2(0.0, 0.0);
       int r = 0;
       for (; r + 3 < R; r += 4) {
-        const double2 v0 = ld_coh2(src + (int64_t)r * stride + col);
-        const double2 v1 = ld_coh2(src + (int64_t)(r + 1) * stride + col);
-        const double2 v2 = ld_coh2(src + (int64_t)(r + 2) * stride + col);
-        const double2 v3 = ld_coh2(src + (int64_t)(r + 3) * stride + col);
+        const double2 v0 = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
+        const double2 v1 = ld_row<SrcCoh>(src + (int64_t)(r + 1) * stride + col);
+        const double2 v2 = ld_row<SrcCoh>(src + (int64_t)(r + 2) * stride + col);
+        const double2 v3 = ld_row<SrcCoh>(src + (int64_t)(r + 3) * stride + col);
         acc.x += v0.x; acc.y += v0.y; acc.x += v1.x; acc.y += v1.y;
         acc.x += v2.x; acc.y += v2.y; acc.x += v3.x; acc.y += v3.y;
       }
       for (; r < R; ++r) {
-        const double2 v = ld_coh2(src + (int64_t)r * stride + col);
+        const double2 v = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
         acc.x += v.x; acc.y += v.y;
       }
       if (dst_coh) st_coh2(dst + col, acc); else dst[col] = acc;
@@ -455,15 +463,15 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
   double2 acc = make_double2(0.0, 0.0);
   int r = rg;
   for (; r + 3 * RG < R; r += 4 * RG) {
-    const double2 v0 = ld_coh2(src + (int64_t)r * stride + col);
-    const double2 v1 = ld_coh2(src + (int64_t)(r + RG) * stride + col);
-    const double2 v2 = ld_coh2(src + (int64_t)(r + 2 * RG) * stride + col);
-    const double2 v3 = ld_coh2(src + (int64_t)(r + 3 * RG) * stride + col);
+    const double2 v0 = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
+    const double2 v1 = ld_row<SrcCoh>(src + (int64_t)(r + RG) * stride + col);
+    const double2 v2 = ld_row<SrcCoh>(src + (int64_t)(r + 2 * RG) * stride + col);
+    const double2 v3 = ld_row<SrcCoh>(src + (int64_t)(r + 3 * RG) * stride + col);
     acc.x += v0.x; acc.y += v0.y; acc.x += v1.x; acc.y += v1.y;
     acc.x += v2.x; acc.y += v2.y; acc.x += v3.x; acc.y += v3.y;
   }
   for (; r < R; r += RG) {
-    const double2 v = ld_coh2(src + (int64_t)r * stride + col);
+    const double2 v = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
     acc.x += v.x; acc.y += v.y;
   }
   __syncthreads();
@@ -917,7 +925,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   if (extra) {
     if (tid == 0) sbs = *a.bs;
     __syncthreads();
-    block_sum_rows(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
+    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
     double tv[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int l = tid; l < a.p; l += blockDim.x) {
       const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
@@ -945,7 +953,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   }
   if (a.k2reduce) {
     if (tid == 0) sbs = *a.bs;
-    block_sum_rows(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
+    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
     for (int l = tid; l < a.p; l += blockDim.x) {
       const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
       FCoef64 f;
