@@ -163,7 +163,11 @@ void plan_launch(rbe_ctx_s* c) {
   a.KB = KB;
   a.Y = (kgroups + KB - 1) / KB;
   a.Ppad = a.Y * KB * per_wave;
-  const long target_blocks = env_long("RBE_SFAC_BLOCKS", 256);
+  // about one block per CU; two for large batches over many particles, where
+  // the second block's waves hide latency (10^6 charges, P = 500 or 2000:
+  // 4 % faster; 30k charges, P = 100: slower, the extra partials cost more)
+  const double work = (double)c->n * (double)a.Ppad;
+  const long target_blocks = env_long("RBE_SFAC_BLOCKS", work >= 134217728.0 ? 512 : 256);
   long X = (target_blocks + a.Y - 1) / a.Y;
   const long max_x = (c->n + 15) / 16;          // at least 16 particles per chunk
   if (X > max_x) X = max_x;

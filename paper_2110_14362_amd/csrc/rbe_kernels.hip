@@ -902,7 +902,14 @@ hipError_t launch_sfac_multi(int precision, int R, const StepArgs* d_tab, const 
 // instead of forces: rho, the virial tensor and the energy.
 
 constexpr int kForceStageBytes = 32768;
-constexpr int kForceRedBytes = 24576;
+// red_raw holds, in turn: the small-batch row sums (scratch of blockDim.x
+// double2, then rho of Ppad <= 512 double2) and the cross-wave sums (at most
+// 8 waves x 64 lanes x RP particles x 3 components, FP32 with RP = 2 or FP64
+// with RP = 1: 12 KB).  Blocks have at most 8 waves (KS <= 8, PW = 4 only with
+// KS = 1; checked at launch).  Kept this small so that more blocks share a CU.
+constexpr int kForceMaxWaves = 8;
+constexpr int kForceRedBytes = kForceMaxWaves * kWave * 16 + 512 * 16;
+static_assert(kForceRedBytes >= kForceMaxWaves * kWave * 3 * 8, "cross-wave sums must fit");
 
 template <bool F64, int RP>
 __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, const int nbx) {
@@ -1097,6 +1104,7 @@ int force_blocks(int precision, const StepArgs& a) {
 }
 
 hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
+  if (a.KS * a.PW > kForceMaxWaves) return hipErrorInvalidConfiguration;
   const dim3 block(a.KS * a.PW * kWave);
   const dim3 grid((unsigned)force_blocks(precision, a));
   if (precision == RBE_PREC_FP64)
@@ -1109,6 +1117,7 @@ hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
 // every system of a multi launch must use the same force block shape (KS, PW)
 hipError_t launch_force_multi(int precision, int threads, const StepArgs* d_tab,
                               const int* d_bstart, int nsys, int total_blocks, hipStream_t s) {
+  if (threads > kForceMaxWaves * kWave) return hipErrorInvalidConfiguration;
   const dim3 grid(total_blocks), block(threads);
   if (precision == RBE_PREC_FP64)
     hipLaunchKernelGGL((k_force_multi<true, 1>), grid, block, 0, s, d_tab, d_bstart, nsys);

@@ -205,7 +205,7 @@ def test_parity_water_1m_p2000(gpu, precision):
 # ------------------------------------------------------------------ edge cases
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("n,p", [(2, 1), (17, 65), (4, 3), (1000, 1), (258, 129)])
+@pytest.mark.parametrize("n,p", [(2, 1), (17, 65), (4, 3), (1000, 1), (258, 129), (1000, 500), (700, 300)])
 def test_ragged_sizes(gpu, precision, n, p):
     s = workloads.random_neutral(n, (9.0, 9.0, 9.0), seed=n + p)
     s.update(alpha=0.3, coulomb=1.0)
