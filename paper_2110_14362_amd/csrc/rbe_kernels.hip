@@ -656,7 +656,10 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   const double ix = sbs.inv_l[0], iy = sbs.inv_l[1], iz = sbs.inv_l[2];
   double2 part[R];
   if (!F64) {
-    constexpr int kRun = (R >= 4) ? 8 : kKahan;   // plain FP32 run between compensated folds
+    // plain FP32 runs of kKahan terms between compensated folds: for random
+    // rounding errors the total over N particles grows like sqrt(N) eps |q|
+    // whatever the run length, and longer runs issue fewer fold operations
+    constexpr int kRun = kKahan;
     const int runlen = SUB * kRun;
     float4* tA = reinterpret_cast<float4*>(base);           // sh.x sh.y sh.z q
     float4* tB = tA + kTile;                                // sl.x sl.y sl.z 0
