@@ -150,6 +150,18 @@ rbe_status rbe_sample_k(rbe_ctx ctx, uint64_t step);
  * state (2 x 3p int32) on first use; waits. */
 rbe_status rbe_set_sampler(rbe_ctx ctx, int32_t sampler, int32_t iters);
 
+/* Sample reuse, the parallel strategy of section 4.3: the steps are grouped
+ * in blocks [kM, (k+1)M) of the step counter, M = `period`; every draw of a
+ * block uses the sampler law of the cell current at the block's first sampled
+ * step (frozen then), while the forces, k vectors and S use the current cell.
+ * Draw of step s: as rbe_sample_k, counter (s, l, 'ksam', 0), with the frozen
+ * cell's tables, so the M batches of a block are independent and any one of
+ * them can be drawn first.  period = 1 (the default) draws every step from
+ * the current cell.  Exact sampler only (RBE_ERR_ARG under the MH sampler).
+ * Draws then run in the standalone kernels before the step.  Allocates the
+ * frozen cell's tables on first use; waits. */
+rbe_status rbe_set_sample_reuse(rbe_ctx ctx, int32_t period);
+
 /* Test hook: replace the batch by p_in host vectors h_m (p_in x 3 int32,
  * row-major, every row nonzero, |m_j| <= 2048).  p_in must equal cfg.p.
  * Copies synchronously. */

@@ -78,3 +78,30 @@ def pressure_variance(r, q, box, alpha, S, p, coulomb=1.0, tol=1e-16):
     second = float(np.sum(4.0 * math.pi ** 2 * coulomb ** 2 * rho2 ** 2 * S
                           / (V ** 4 * k2 ** 2) * e * fac ** 2))
     return (second - P2 * P2) / p, P2
+
+
+def reuse_expected(r, q, box_now, box_frozen, alpha, coulomb=1.0, tol=1e-16):
+    """Expectation of the RBE estimator (forces, virial, energy without the
+    self term) at cell box_now when the batch is drawn from the law of cell
+    box_frozen (sample reuse, section 4.3): the estimator weights every drawn
+    mode by S_now/p (eq. (appforce), (apppress)) while mode m is drawn with
+    probability w_frozen(m)/S_frozen, so the expectation is the mode sum with
+    weights S_now w_frozen(m)/S_frozen, w(m) = exp(-|k|^2/(4 alpha)) of the
+    respective cell (eq. (probexpression)).  With box_frozen = box_now the
+    weights are w_now(m): the Ewald sum, which makes the estimator unbiased
+    (section 4.2).  The modes are those of the larger cell within `tol`."""
+    box_now = np.asarray(box_now, dtype=np.float64)
+    box_frozen = np.asarray(box_frozen, dtype=np.float64)
+    big = np.maximum(box_now, box_frozen)
+    m, _ = ewald_modes(np.diag(big), alpha, tol)
+    mf = m.astype(np.float64)
+
+    def weights(box):
+        k2 = (((2.0 * math.pi) * mf / box[None, :]) ** 2).sum(axis=1)
+        return np.exp(-k2 / (4.0 * alpha))
+
+    from .sampler import box_tables
+    S_now = box_tables(alpha, tuple(box_now))["S"]
+    S_fr = box_tables(alpha, tuple(box_frozen))["S"]
+    w = S_now * weights(box_frozen) / S_fr
+    return kspace_weighted(r, q, np.diag(box_now), alpha, m, w, coulomb)

@@ -14,6 +14,10 @@ What it follows:
   Gaussians restricted to m != 0.
 * Appendix C, first remark on sampling: for a rectangular cell the three
   components are independent discrete Gaussians, each with its own side length.
+* Section 4.3, the parallel sampling strategy (sample reuse, `ReusedDraws`):
+  the batches of M consecutive steps are drawn at the first of them, from the
+  law of the cell at that step; the paper notes the small error this adds
+  while the cell changes slowly.
 
 The paper draws the sample with a Metropolis chain (section 4.3).  This code
 draws exact independent samples of the same law (reading: exact i.i.d.
@@ -150,3 +154,27 @@ def marginal_pmf(alpha, box, axis, m):
         if j != axis:
             other *= Hs[j]
     return w * (other - (m == 0)) / S
+
+
+class ReusedDraws:
+    """Sample reuse (section 4.3, parallel strategy).  The steps are grouped
+    in blocks [kM, (k+1)M) of the step counter; the cell given at a block's
+    first sampled step is frozen, and the batch of every step s of the block
+    is the exact draw of step s (counter (s, l, 'ksam', 0)) from the frozen
+    cell's law.  The draws of a block are independent, as the M independent
+    sampling processes of the paper are; step j of a block takes the j-th.
+    period = 1 is the exact sampler of the current cell."""
+
+    def __init__(self, alpha, P, seed, system_id, period):
+        self.alpha, self.P = alpha, P
+        self.seed, self.system_id = seed, system_id
+        self.period = int(period)
+        self.block = None
+        self.frozen = None
+
+    def sample(self, box, step):
+        block = int(step) // self.period
+        if self.block is None or block != self.block:
+            self.block = block
+            self.frozen = tuple(float(b) for b in box)
+        return sample_k(self.alpha, self.frozen, self.P, self.seed, self.system_id, step)

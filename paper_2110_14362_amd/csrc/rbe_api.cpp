@@ -2,6 +2,7 @@
 // context ownership and the launch sequence.  Declarations and contracts are
 // in include/rbe.h.
 #include "rbe_internal.h"
+#include <cstddef>
 
 #include <cmath>
 #include <cstdarg>
@@ -58,6 +59,13 @@ struct rbe_ctx_s {
   int32_t* d_chain = nullptr;
   int mh_cur = 0;
   bool mh_started = false;
+  // sample reuse (section 4.3, parallel strategy): draws of the steps of one
+  // block [kM, (k+1)M) all use the cell of the block's first sampled step
+  int32_t reuse = 1;
+  bool frozen_valid = false;
+  uint64_t frozen_block = 0;
+  BoxState* d_bs_frozen = nullptr;   // that cell's values and tables
+  double* d_tab_frozen = nullptr;
   // kernel timing (rbe_timing_enable)
   static constexpr int kKinds = 4;
   int timing_cap = 0;
@@ -229,7 +237,7 @@ void destroy_events(rbe_ctx_s* c) {
 void free_all(rbe_ctx_s* c) {
   void* bufs[] = {c->d_q, c->d_qf, c->d_qsum, c->d_bs, c->d_tab, c->d_m, c->d_partial,
                   c->d_gpart, c->d_rho, c->d_terms, c->d_fc32, c->d_fc64, c->d_cnt,
-                  c->d_pre, c->d_m_pre, c->d_chain};
+                  c->d_pre, c->d_m_pre, c->d_chain, c->d_bs_frozen, c->d_tab_frozen};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -272,13 +280,35 @@ void clear_pending(rbe_ctx_s* c) {
 rbe_status flush(rbe_ctx_s* c) {
   if (c->pend_box == BOX_COMMITTED && !c->pend_sample) return RBE_OK;
   const StepArgs a = step_args(c);
+  hipError_t e;
+  const bool reuse = c->pend_sample && c->reuse > 1;
+  if (reuse) {
+    // first sampled step of a new block: freeze this step's cell (the pending
+    // one, else the committed one) for the block's draws
+    const uint64_t block = c->pend_step / (uint64_t)c->reuse;
+    if (!c->frozen_valid || block != c->frozen_block) {
+      StepArgs f = a;
+      f.bs = c->d_bs_frozen;
+      f.tab = c->d_tab_frozen;
+      if (a.box_src == BOX_COMMITTED) {   // the committed cell: BoxState::l on the device
+        f.box_src = BOX_PTR;
+        f.box_ptr = reinterpret_cast<const double*>(reinterpret_cast<const char*>(c->a.bs) +
+                                                    offsetof(BoxState, l));
+      }
+      if ((e = launch_tables(f, c->stream)) != hipSuccess) return hip_fail(e, "table kernel");
+      c->frozen_block = block;
+      c->frozen_valid = true;
+    }
+  }
   int ts = timed_begin(c, K_TABLES);
-  hipError_t e = launch_tables(a, c->stream);
+  e = launch_tables(a, c->stream);
   timed_end(c, K_TABLES, ts);
   if (e != hipSuccess) return hip_fail(e, "table kernel");
   if (c->pend_sample) {
+    StepArgs d = a;
+    if (reuse) { d.bs = c->d_bs_frozen; d.tab = c->d_tab_frozen; }
     ts = timed_begin(c, K_SAMPLE);
-    e = launch_sample(a, c->stream);
+    e = launch_sample(d, c->stream);
     timed_end(c, K_SAMPLE, ts);
     if (e != hipSuccess) return hip_fail(e, "sample kernel");
   }
@@ -296,8 +326,9 @@ rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, con
   if (!c) return fail(RBE_ERR_ARG, "NULL context");
   if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return fail(RBE_ERR_ARG, "NULL particle array");
   if (!c->have_k) return fail(RBE_ERR_STATE, "rbe_forces_pressure before rbe_sample_k / rbe_set_k");
-  if (c->pend_sample && c->sampler == RBE_SAMPLER_MH) {
-    // the chains move in the standalone table and draw kernels
+  if (c->pend_sample && (c->sampler == RBE_SAMPLER_MH || c->reuse > 1)) {
+    // the chains move, and draws from a frozen cell run, in the standalone
+    // table and draw kernels
     rbe_status st = flush(c);
     if (st != RBE_OK) return st;
   }
@@ -474,6 +505,8 @@ rbe_status rbe_set_sampler(rbe_ctx c, int32_t sampler, int32_t iters) {
     return fail(RBE_ERR_ARG, "unknown sampler %d", sampler);
   if (sampler == RBE_SAMPLER_MH && (iters < 1 || iters > 64))
     return fail(RBE_ERR_ARG, "iters = %d must be in 1..64", iters);
+  if (sampler == RBE_SAMPLER_MH && c->reuse > 1)
+    return fail(RBE_ERR_ARG, "sample reuse (period %d) goes with the exact sampler", c->reuse);
   rbe_status st = flush(c);                // a pending draw belongs to the old sampler
   if (st != RBE_OK) return st;
   if (sampler == RBE_SAMPLER_MH && !c->d_chain)
@@ -483,6 +516,25 @@ rbe_status rbe_set_sampler(rbe_ctx c, int32_t sampler, int32_t iters) {
   c->mh_iters = sampler == RBE_SAMPLER_MH ? iters : 1;
   c->mh_started = false;
   c->mh_cur = 0;
+  c->pre_valid = false;
+  return RBE_OK;
+}
+
+rbe_status rbe_set_sample_reuse(rbe_ctx c, int32_t period) {
+  if (!c) return fail(RBE_ERR_ARG, "NULL context");
+  if (period < 1 || period > 1000000) return fail(RBE_ERR_ARG, "period = %d must be in 1..1000000", period);
+  if (period > 1 && c->sampler != RBE_SAMPLER_EXACT)
+    return fail(RBE_ERR_ARG, "sample reuse goes with the exact sampler");
+  rbe_status st = flush(c);                // a pending draw belongs to the old setting
+  if (st != RBE_OK) return st;
+  if (period > 1 && !c->d_bs_frozen) {
+    HIP_TRY(hipMalloc(&c->d_bs_frozen, sizeof(BoxState)), "frozen cell");
+    HIP_TRY(hipMalloc(&c->d_tab_frozen, (size_t)c->tab_stride * sizeof(double)), "frozen tables");
+    HIP_TRY(hipMemsetAsync(c->d_bs_frozen, 0, sizeof(BoxState), c->stream), "hipMemsetAsync");
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->reuse = period;
+  c->frozen_valid = false;
   c->pre_valid = false;
   return RBE_OK;
 }

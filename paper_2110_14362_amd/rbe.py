@@ -30,7 +30,7 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_real_check", "rbe_real_destroy",
            "rbe_md_init", "rbe_md_pressure", "rbe_md_first_half", "rbe_md_second_half",
            "rbe_md_box_dev", "rbe_md_get_state", "rbe_md_check", "rbe_md_destroy",
-           "rbe_md_set_rigid", "rbe_real_set_skin", "rbe_real_list_stats", "rbe_set_sampler",
+           "rbe_md_set_rigid", "rbe_real_set_skin", "rbe_real_list_stats", "rbe_set_sampler", "rbe_set_sample_reuse",
            "rbe_batch_list_stats", "rbe_batch_step_fourier",
            "rbe_batch_create", "rbe_batch_footprint", "rbe_batch_admit", "rbe_batch_step",
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
@@ -119,6 +119,7 @@ def load_library(path=LIB_PATH):
         "rbe_real_check": [vp],
         "rbe_real_set_skin": [vp, ctypes.c_double],
         "rbe_set_sampler": [vp, ctypes.c_int32, ctypes.c_int32],
+        "rbe_set_sample_reuse": [vp, ctypes.c_int32],
         "rbe_real_list_stats": [vp, ctypes.POINTER(ctypes.c_int64)],
         "rbe_batch_list_stats": [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
         "rbe_batch_step_fourier": [vp, ctypes.c_int32],
@@ -238,6 +239,11 @@ class RBE:
         """'exact' (independent draws) or 'mh' (the online Metropolis-Hastings
         chains, `iters` moves per sampled step)."""
         _check(_lib.rbe_set_sampler(self._ctx, SAMPLERS[kind], int(iters)))
+
+    def set_sample_reuse(self, period):
+        """Draws of the steps of each block of `period` steps use the cell of
+        the block's first sampled step (section 4.3, parallel strategy)."""
+        _check(_lib.rbe_set_sample_reuse(self._ctx, int(period)))
 
     def sample_k(self, step):
         _check(_lib.rbe_sample_k(self._ctx, ctypes.c_uint64(int(step) & (2**64 - 1))))

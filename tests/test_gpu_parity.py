@@ -118,6 +118,64 @@ def test_mh_chains_follow_the_oracle(gpu, precision, mode, box0, p, iters):
     assert moved > 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sample_reuse_follows_the_oracle(gpu, precision):
+    # sample reuse (section 4.3, parallel strategy) with period 4 over 11 steps
+    # whose cell changes every step, given from the host, from device memory
+    # or not at all (the committed cell): every batch equals the oracle's
+    # draw from the cell frozen at its block's first step, and the forces,
+    # virial and energy are the oracle's estimator at the CURRENT cell on that
+    # batch.  The draw also runs when the batch is read first.
+    import torch
+    from oracle import rbe as orbe
+    from paper_2110_14362_amd.rbe import RBE
+    alpha, p, M = 0.09, 130, 4
+    box0 = (14.0, 14.0, 14.0)
+    s = workloads.random_neutral(260, box0, seed=21)
+    dev = gpu
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = RBE(t(s["q"]), box0, p, alpha, box_mode="iso", precision=precision, seed=41,
+              system_id=6)
+    ctx.set_sample_reuse(M)
+    rd = osamp.ReusedDraws(alpha, p, seed=41, system_id=6, period=M)
+    x, y, z = (t(s["pos"][:, a]) for a in range(3))
+    f = [torch.zeros_like(x) for _ in range(3)]
+    vir = torch.zeros(6, dtype=torch.float64, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    box = list(box0)
+    frozen_differs = 0
+    for step in range(1, 12):
+        how = step % 3                      # 0: host, 1: device memory, 2: unchanged
+        if how != 2:
+            box = [box0[0] * (1.0 + 0.01 * step)] * 3
+            if how == 0:
+                ctx.rescale_box(box)
+            else:
+                d_box = t(box)
+                ctx.rescale_box_dev(d_box)
+        ctx.sample_k(step)
+        if step % 2:
+            g = ctx.get_k().astype(np.int64)          # draw before the step
+        ctx.forces_pressure(x, y, z, *f, virial6=vir, energy=en)
+        torch.cuda.synchronize()
+        if step % 2 == 0:
+            g = ctx.get_k().astype(np.int64)
+        o = rd.sample(box, step)
+        np.testing.assert_array_equal(g, o, err_msg="step %d" % step)
+        frozen_differs += int(rd.frozen[0] != box[0])
+        S = osamp.box_tables(alpha, box)["S"]
+        ref = orbe.rbe_kspace(s["pos"], s["q"], box, alpha, o, S)
+        W6 = vir.cpu().numpy()
+        Wg = np.array([[W6[0], W6[3], W6[4]], [W6[3], W6[1], W6[5]], [W6[4], W6[5], W6[2]]])
+        Fg = np.stack([fi.cpu().numpy() for fi in f], axis=1)
+        fr = np.sqrt(((Fg - ref["forces"]) ** 2).sum() / (ref["forces"] ** 2).sum())
+        wr = np.linalg.norm(Wg - ref["virial"]) / np.linalg.norm(ref["virial"])
+        er = abs(float(en.cpu()[0]) - ref["energy"]) / abs(ref["energy"])
+        assert max(fr, wr, er) < TOL[precision], (step, fr, wr, er)
+    ctx.check()
+    assert frozen_differs >= 5          # most steps drew from a stale cell
+
+
 # ------------------------------------------------------------------ parity
 
 CASES = {
