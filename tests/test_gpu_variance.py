@@ -3,7 +3,9 @@ converges to the Ewald Fourier-space force and pressure and its variance
 matches the closed forms eq. (ForceExp) / (PressExp), for several batch sizes
 p.  Force and pressure batches may differ in size (p != p~, section 4.2):
 forces from one context, the pressure from a second one with its own batch
-stream."""
+stream.  The online Metropolis-Hastings sampler (section 4.3) against the
+exact one: both unbiased, the chains' force noise correlated from step to
+step by about their rejection rate."""
 import math
 
 import numpy as np
@@ -95,3 +97,70 @@ def test_separate_force_and_pressure_batches(gpu):
     rp = (sp2 / B - (sp / B) ** 2) / var_p64
     print("p=8 forces: variance emp/closed %.3f; p~=64 pressure: %.3f" % (rf, rp), flush=True)
     assert abs(rf - 1.0) < 0.08 and abs(rp - 1.0) < 0.15
+
+
+def noise_series(s, p, T, dev, alpha, system_id, sampler="exact", iters=1):
+    """Force noise chi_t = F*_t - F_1 (F_1 the Ewald Fourier-space force) over
+    T consecutive steps at a fixed cell, FP64 device estimator: T x N x 3."""
+    import torch
+    from paper_2110_14362_amd.rbe import RBE
+    box = np.asarray(s["box"])
+    _, F1 = orbe.force_variance(s["pos"], s["q"], box, alpha, osamp.box_tables(alpha, box)["S"], p)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    n = len(s["q"])
+    ctx = RBE(t(s["q"]), s["box"], p, alpha, box_mode="iso", precision="fp64", seed=2022,
+              system_id=system_id)
+    ctx.set_sampler(sampler, iters)
+    x, y, z = (t(s["pos"][:, a]) for a in range(3))
+    f = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    out = torch.zeros((T, n, 3), dtype=torch.float64, device=dev)
+    for b in range(T):
+        ctx.sample_k(b)
+        ctx.forces_pressure(x, y, z, *f)
+        out[b] = torch.stack(f, 1)
+    ctx.check()
+    ctx.close()
+    return out.cpu().numpy() - F1[None, :, :]
+
+
+def autocorr(chi, lag):
+    a = chi[:-lag].reshape(len(chi) - lag, -1)
+    b = chi[lag:].reshape(len(chi) - lag, -1)
+    return float((a * b).sum() / np.sqrt((a * a).sum() * (b * b).sum()))
+
+
+def test_mh_sampler_is_unbiased_with_correlated_noise(gpu):
+    from oracle import mh_sampler as omh
+    s = system()
+    p, T = 16, 2000
+    res = {}
+    for alpha in (0.3, 0.05):
+        # the chains' rejection rate at this cell (oracle, from exact draws)
+        m0 = osamp.sample_k(alpha, s["box"], 4000, 3, 0, 0)
+        m1, acc = omh.chain_moves(m0, alpha, s["box"], 3, 0, 1, iters=1)
+        reject = 1.0 - acc / 4000.0
+        var_f, _, _, _ = closed_forms_alpha(s, p, alpha)
+        for kind, iters in (("exact", 1), ("mh", 1), ("mh", 4)):
+            chi = noise_series(s, p, T, gpu, alpha, 8000 + iters, kind, iters)
+            r1 = autocorr(chi, 1)
+            tau = 1.0 + 2.0 * max(r1, 0.0) / (1.0 - min(max(r1, 0.0), 0.9))
+            mean = chi.mean(axis=0)
+            z = (mean ** 2).sum() / (var_f.sum() * tau / T)
+            res[(alpha, kind, iters)] = (r1, z, reject)
+            print("alpha %.2f %s x%d: lag-1 autocorrelation %.3f, chain rejection %.3f, "
+                  "|mean noise|^2 / expected %.2f" % (alpha, kind, iters, r1, reject, z), flush=True)
+            assert z < 4.0, (alpha, kind, iters, z)          # unbiased
+        r_ex = res[(alpha, "exact", 1)][0]
+        r_m1 = res[(alpha, "mh", 1)][0]
+        r_m4 = res[(alpha, "mh", 4)][0]
+        assert abs(r_ex) < 0.03
+        assert 0.3 * reject < r_m1 < 3.0 * reject + 0.03
+        assert r_m4 < r_m1
+
+
+def closed_forms_alpha(s, p, alpha):
+    box = np.asarray(s["box"])
+    S = osamp.box_tables(alpha, box)["S"]
+    var_f, F1 = orbe.force_variance(s["pos"], s["q"], box, alpha, S, p)
+    var_p, P2 = orbe.pressure_variance(s["pos"], s["q"], box, alpha, S, p)
+    return var_f, F1, var_p, P2
