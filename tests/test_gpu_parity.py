@@ -352,6 +352,22 @@ def test_error_paths(gpu):
     assert ei.value.status == 6
     ctx.rescale_box((10.0, 10.0, 10.0))
     ctx.check()
+    # sample reuse: the period's range, and it goes with the exact sampler only
+    for bad in (0, -3, 1000001):
+        with pytest.raises(RBEError) as ei:
+            ctx.set_sample_reuse(bad)
+        assert ei.value.status == 1
+    ctx.set_sample_reuse(4)
+    with pytest.raises(RBEError) as ei:
+        ctx.set_sampler("mh", 1)
+    assert ei.value.status == 1
+    ctx.set_sample_reuse(1)
+    ctx.set_sampler("mh", 1)
+    with pytest.raises(RBEError) as ei:
+        ctx.set_sample_reuse(2)
+    assert ei.value.status == 1
+    ctx.set_sampler("exact")
+    ctx.check()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
