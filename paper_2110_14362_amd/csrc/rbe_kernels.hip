@@ -229,6 +229,33 @@ __device__ __forceinline__ void kahan_add(float& sum, float& comp, float v) {
   sum = t;
 }
 
+// FP64 cos and sin of 2 pi f for |f| <= 1/2: the nearest of kSinCosTab table
+// angles 2 pi k/kSinCosTab (cos, sin in LDS) rotated by the remainder angle
+// u = 2 pi (f - k/kSinCosTab), |u| <= pi/kSinCosTab, whose cos - 1 and sin
+// are short Taylor series (next terms below 2e-20).  f - k/kSinCosTab is exact
+// (Sterbenz), so the error is that of the table entries and a few roundings:
+// a few 1e-16 absolute.
+constexpr int kSinCosTab = 256;
+
+__device__ __forceinline__ void fill_sincos_tab(double2* tab) {
+  for (int k = threadIdx.x; k < kSinCosTab; k += blockDim.x) {
+    double sn, cs;
+    sincospi((double)k * (2.0 / kSinCosTab), &sn, &cs);
+    tab[k] = make_double2(cs, sn);
+  }
+}
+
+__device__ __forceinline__ void sincos2pi(double f, const double2* tab, double& sn, double& cs) {
+  const double kf = rint(f * (double)kSinCosTab);
+  const double2 e = tab[(int)kf & (kSinCosTab - 1)];
+  const double u = (f - kf * (1.0 / kSinCosTab)) * (2.0 * M_PI);
+  const double u2 = u * u;
+  const double cm1 = u2 * fma(u2, fma(u2, -1.0 / 720.0, 1.0 / 24.0), -0.5);
+  const double su = fma(u * u2, fma(u2, fma(u2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), u);
+  cs = fma(-e.y, su, fma(e.x, cm1, e.x));
+  sn = fma(e.x, su, fma(e.y, cm1, e.y));
+}
+
 // ---------------------------------------------------------------------------
 // charges: sums for the neutrality check and the self term, FP32 copy
 
@@ -553,8 +580,10 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   __shared__ double sh_T[3];
   __shared__ int sh_flag;
   __shared__ double sh_vs[7][8];
+  __shared__ double2 sctab[F64 ? kSinCosTab : 1];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;
+  if (F64) fill_sincos_tab(sctab);        // read after the barriers below
   unsigned char* base = lds_raw;
   int* sm = reinterpret_cast<int*>(base + kR0);                     // batch slice, 3 ints each
   double* tabs = reinterpret_cast<double*>(base + kR0 + sfac_r1(a));  // R2
@@ -749,7 +778,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
           const double t = mx[r] * pa.x + my[r] * pa.y + mz[r] * pb.x;
           const double f = t - rint(t);
           double sn, cs;
-          sincospi(2.0 * f, &sn, &cs);
+          sincos2pi(f, sctab, sn, cs);
           A[r] = fma(pb.y, cs, A[r]);
           B[r] = fma(pb.y, sn, B[r]);
         }
@@ -922,10 +951,12 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   __shared__ __align__(16) Coef scoef[kChunk];
   __shared__ BoxState sbs;
   __shared__ double sh_vs[7][8];
+  __shared__ double2 sctab[F64 ? kSinCosTab : 1];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int nw = blockDim.x / kWave;
   const int PW = a.PW, KS = nw / PW;
   const bool extra = a.k2reduce && bx == nbx - 1;
+  if (F64 && !extra) fill_sincos_tab(sctab);   // read after the barriers below
   // rows of rho partials left by k_sfac in k2reduce mode
   const double2* rows = a.NG > 1 ? a.gpart : a.partial;
   const int Rr = a.NG > 1 ? a.NG : a.X;
@@ -1038,7 +1069,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
           const double t = c.m[0] * sx[r] + c.m[1] * sy[r] + c.m[2] * sz[r];
           const double f = t - rint(t);
           double sn, cs;
-          sincospi(2.0 * f, &sn, &cs);
+          sincos2pi(f, sctab, sn, cs);
           const double gg = cs * c.cB - sn * c.cA;
           gx[r] = fma(gg, c.k[0], gx[r]);
           gy[r] = fma(gg, c.k[1], gy[r]);
