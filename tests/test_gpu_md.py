@@ -120,3 +120,17 @@ def test_npt_trajectory_matches_oracle(gpu, setup):
     else:
         b0 = np.asarray(s["box"], dtype=np.float64)
         np.testing.assert_allclose(g["box"] / g["box"][0], b0 / b0[0], rtol=1e-14)
+
+
+def test_long_run_pressure_and_temperature_averages(gpu):
+    # section 3: the Langevin NPT dynamics holds the time-averaged
+    # instantaneous pressure at the imposed one and the kinetic temperature at
+    # kT; 1000 ions with a repulsive core in reduced units, full device step
+    # (random batch Fourier part, pairs, integrator), 4000 + 12000 steps
+    from tests.measure_npt import run
+    r = run(equil=4000, prod=12000, every=4, precision="fp32")
+    print("<P_ins> = %.5f +- %.5f (P = %.3f), <T> = %.4f +- %.4f, <V> = %.1f"
+          % (r["p_mean"], r["p_se"], r["p_ext"], r["t_mean"], r["t_se"], r["v_mean"]), flush=True)
+    assert abs(r["p_mean"] - r["p_ext"]) < 4.0 * r["p_se"] + 0.02 * r["p_ext"]
+    assert abs(r["t_mean"] - r["kT"]) < 4.0 * r["t_se"] + 0.01
+    assert r["p_se"] < 0.05 * r["p_ext"]
