@@ -32,7 +32,13 @@ METRIC = "RBE k-space (N·P)/s and ns/day, 30k-charge water NPT; served p50/p99 
 # per CU per clock; v_sin_f32 / v_cos_f32 issue at a quarter of that, 32 per CU
 # per clock -> 256 * 2.4e9 * 32 = 1.966e13 transcendental ops/s.
 TRANS_PEAK = 256 * 2.4e9 * 32
-TRANS_PER_PAIR = 2          # sin + cos of one reduced phase per (particle, frequency)
+# sines and cosines the method needs per (particle, frequency) pair: the
+# structure factor takes cos and sin of k.r (real and imaginary part of rho);
+# the force takes Im(exp(-i k.r) rho) = |rho| sin(arg rho - k.r), one sine
+TRANS_PER_PAIR = {"sfac": 2, "force": 1}
+TRANS_PER_PAIR_STEP = TRANS_PER_PAIR["sfac"] + TRANS_PER_PAIR["force"]
+PER_UNIT = {"sfac": "2 transcendentals (cos, sin of k.r) per (particle, frequency) pair",
+            "force": "1 transcendental (sin of arg rho - k.r) per (particle, frequency) pair"}
 
 
 def parse():
@@ -170,7 +176,7 @@ def large_roofline(steps, precision, torch):
            "kernels_us": kern}
     for k in ("sfac", "force"):
         if kern.get(k):
-            a = TRANS_PER_PAIR * N * P / (kern[k] * 1e-6)
+            a = TRANS_PER_PAIR[k] * N * P / (kern[k] * 1e-6)
             out["roofline_" + k] = {"bound": "alu", "achieved": a / 1e12, "peak": TRANS_PEAK / 1e12,
                                     "unit": "Ttrans/s", "frac": a / TRANS_PEAK}
     out["plan"] = plan
@@ -250,7 +256,7 @@ def _serve_legs(b, reqs, fourier_only, tag):
     fourier = {}
     for k in ("sfac", "force"):
         if kt[k] > 0:
-            a = TRANS_PER_PAIR * kt["np"] / (kt[k] * 1e-3)
+            a = TRANS_PER_PAIR[k] * kt["np"] / (kt[k] * 1e-3)
             fourier["roofline_" + k] = {"bound": "alu", "achieved": a / 1e12,
                                         "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
                                         "frac": a / TRANS_PEAK}
@@ -345,7 +351,7 @@ def main():
             for k, v in main_r["kernels"].items()}
     dom = max(("sfac", "force"), key=lambda k: kern[k]["avg_us"] or 0.0)
     t_dom = kern[dom]["avg_us"] * 1e-6
-    achieved = TRANS_PER_PAIR * N * P / t_dom
+    achieved = TRANS_PER_PAIR[dom] * N * P / t_dom
     step_dev = sum((v["avg_us"] or 0.0) for v in kern.values()) * 1e-6
     plan = main_r["plan"]
     f64 = args.precision == "fp64"
@@ -355,8 +361,7 @@ def main():
             "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
             "frac": achieved / TRANS_PEAK, "traffic": profiled_traffic(kname, args.workload + (
                 "_p%d" % args.p if args.p else "")),
-            "per_unit": "2 transcendentals (sin, cos) per (particle, frequency) pair; "
-                        "%d x %d pairs per launch" % (N, P),
+            "per_unit": PER_UNIT[dom] + "; %d x %d pairs per launch" % (N, P),
             "timing": "HIP events on the library stream around each launch, over %d steps"
                       % main_r["steps"]}
     out = {
@@ -368,11 +373,13 @@ def main():
                    "alpha": s["alpha"], "box": box, "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": roof,
-        "roofline_step": {"bound": "alu", "achieved": TRANS_PER_PAIR * N * P / step_dev / 1e12,
+        "roofline_step": {"bound": "alu",
+                          "achieved": TRANS_PER_PAIR_STEP * N * P / step_dev / 1e12,
                           "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
-                          "frac": TRANS_PER_PAIR * N * P / step_dev / TRANS_PEAK,
-                          "note": "one complex exponential per pair over the summed device "
-                                  "time of all kernels of a step"},
+                          "frac": TRANS_PER_PAIR_STEP * N * P / step_dev / TRANS_PEAK,
+                          "note": "three transcendentals per pair (cos, sin for rho; one sine "
+                                  "for the force) over the summed device time of all kernels "
+                                  "of a step"},
         "kernels_us": kern,
         "plan": plan,
     }

@@ -31,7 +31,8 @@ struct BoxState {
 // Force-pass constants of one frequency, FP32 path (32 B: one scalar load).
 struct alignas(32) FCoef32 {
   float m[3];        // m (exact small integers)
-  float cA, cB;      // c Re rho, c Im rho with c = C (S/p) 4 pi / (V k^2)
+  float phi;         // arg(rho) / (2 pi), revolutions in [-1/2, 1/2]
+  float amp;         // c |rho| with c = C (S/p) 4 pi / (V k^2)
   float k[3];        // k = 2 pi m / l
 };
 // FP64 path.

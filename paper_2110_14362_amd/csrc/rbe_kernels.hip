@@ -514,7 +514,10 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
 
 // Per-frequency constants from rho_l and m_l (eq. (appforce), eq. (apppress)
 // in tensor form, appendix C):
-//   k = 2 pi m / l,  c = C (S/p) 4 pi / (V |k|^2)  ->  force coefficients (c Re rho, c Im rho)
+//   k = 2 pi m / l,  c = C (S/p) 4 pi / (V |k|^2)  ->  force coefficients (c Re rho, c Im rho);
+//   the FP32 path keeps c |rho| and arg(rho) instead: Im(exp(-i theta) rho) =
+//   |rho| sin(arg(rho) - theta) takes one sine per pair where the cos / sin
+//   form takes two
 //   tv = |rho|^2/|k|^2 [delta_ab - 2 (1/|k|^2 + 1/(4 alpha)) k_a k_b]  (xx yy zz xy xz yz) and
 //   tv[6] = |rho|^2/|k|^2, to be scaled by C (2 pi / V)(S/p) after the batch sum.
 __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const BoxState& b,
@@ -542,7 +545,9 @@ __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const Bo
     h.m[c] = (float)km[c]; h.k[c] = (float)kk[c];
   }
   f.cA = cl * r.x; f.cB = cl * r.y;
-  h.cA = (float)f.cA; h.cB = (float)f.cB;
+  // the phase is kept in FP32, so its arctangent is taken in FP32 too
+  h.amp = (float)(cl * sqrt(r.x * r.x + r.y * r.y));
+  h.phi = atan2f((float)r.y, (float)r.x) * (float)(0.5 / M_PI);
 }
 
 // Batch sum of the virial summands held per thread (tv: the thread's own
@@ -1052,9 +1057,8 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
         for (int r = 0; r < RP; ++r) {
           const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx[r], shy[r], shz[r], slx[r],
                                     sly[r], slz[r]);
-          const float cs = __builtin_amdgcn_cosf(f);
-          const float sn = __builtin_amdgcn_sinf(f);
-          const float gg = fmaf(cs, c.cB, -sn * c.cA);
+          // c Im(exp(-i 2 pi f) rho) = c |rho| sin(2 pi (arg(rho)/(2 pi) - f))
+          const float gg = c.amp * __builtin_amdgcn_sinf(c.phi - f);
           hx[r] = fmaf(gg, c.k[0], hx[r]);
           hy[r] = fmaf(gg, c.k[1], hy[r]);
           hz[r] = fmaf(gg, c.k[2], hz[r]);
