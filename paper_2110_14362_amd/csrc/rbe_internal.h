@@ -32,8 +32,8 @@ struct BoxState {
 struct alignas(32) FCoef32 {
   float m[3];        // m (exact small integers)
   float phi;         // arg(rho) / (2 pi), revolutions in [-1/2, 1/2]
-  float amp;         // c |rho| with c = C (S/p) 4 pi / (V k^2)
-  float k[3];        // k = 2 pi m / l
+  float ak[3];       // c |rho| k with c = C (S/p) 4 pi / (V k^2), k = 2 pi m / l
+  float pad;
 };
 // FP64 path.
 struct alignas(64) FCoef64 {

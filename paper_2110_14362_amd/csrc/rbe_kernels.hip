@@ -540,13 +540,14 @@ __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const Bo
   tv[4] = -fac * beta * kk[0] * kk[2];
   tv[5] = -fac * beta * kk[1] * kk[2];
   tv[6] = fac;
+  // the phase is kept in FP32, so its arctangent is taken in FP32 too
+  const double amp = cl * sqrt(r.x * r.x + r.y * r.y);
   for (int c = 0; c < 3; ++c) {
     f.m[c] = km[c]; f.k[c] = kk[c];
-    h.m[c] = (float)km[c]; h.k[c] = (float)kk[c];
+    h.m[c] = (float)km[c]; h.ak[c] = (float)(amp * kk[c]);
   }
+  h.pad = 0.0f;
   f.cA = cl * r.x; f.cB = cl * r.y;
-  // the phase is kept in FP32, so its arctangent is taken in FP32 too
-  h.amp = (float)(cl * sqrt(r.x * r.x + r.y * r.y));
   h.phi = atan2f((float)r.y, (float)r.x) * (float)(0.5 / M_PI);
 }
 
@@ -1057,11 +1058,11 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
         for (int r = 0; r < RP; ++r) {
           const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx[r], shy[r], shz[r], slx[r],
                                     sly[r], slz[r]);
-          // c Im(exp(-i 2 pi f) rho) = c |rho| sin(2 pi (arg(rho)/(2 pi) - f))
-          const float gg = c.amp * __builtin_amdgcn_sinf(c.phi - f);
-          hx[r] = fmaf(gg, c.k[0], hx[r]);
-          hy[r] = fmaf(gg, c.k[1], hy[r]);
-          hz[r] = fmaf(gg, c.k[2], hz[r]);
+          // c Im(exp(-i 2 pi f) rho) k = sin(2 pi (arg(rho)/(2 pi) - f)) c |rho| k
+          const float sg = __builtin_amdgcn_sinf(c.phi - f);
+          hx[r] = fmaf(sg, c.ak[0], hx[r]);
+          hy[r] = fmaf(sg, c.ak[1], hy[r]);
+          hz[r] = fmaf(sg, c.ak[2], hz[r]);
         }
       }
     } else {
