@@ -82,3 +82,50 @@ def test_reuse_bias_is_first_order_in_the_cell_change():
     assert biases[1] / biases[0] == pytest.approx(2.0, rel=0.02)
     assert biases[2] / biases[1] == pytest.approx(2.0, rel=0.02)
     assert 1e-6 < biases[0] < 1e-2
+
+
+def test_reuse_expected_is_the_mean_of_stale_batches():
+    # Monte Carlo pin of reuse_expected at a stale cell: batches drawn by
+    # ReusedDraws from the law of a frozen cell 4 % smaller than the current
+    # one, each evaluated by the RBE estimator at the CURRENT cell (weight
+    # S_now/p, eq. (appforce), (apppress)), average to reuse_expected within
+    # a few standard errors, component by component.  A version without the
+    # S_now/S_frozen factor (weights w_frozen(m) alone) lies many standard
+    # errors away, and so does the unbiased Ewald sum.
+    s = workloads.random_neutral(24, (9.0, 9.0, 9.0), seed=11)
+    alpha, P, nb = 0.3, 400, 250
+    box = np.array([9.0, 9.0, 9.0])
+    frozen = box * 0.96
+    r, q = s["pos"], s["q"]
+    rd = osamp.ReusedDraws(alpha, P, seed=17, system_id=4, period=10 ** 6)
+    rd.sample(tuple(frozen), 0)                     # the block's first step freezes this cell
+    S_now = osamp.box_tables(alpha, tuple(box))["S"]
+    self_e = ewald.self_energy(q, alpha, 1.0)
+    est = []
+    for step in range(1, nb + 1):
+        m = rd.sample(tuple(box), step)
+        e = orbe.rbe_kspace(r, q, box, alpha, m, S_now)
+        est.append(np.concatenate([e["forces"].ravel(), e["virial"][np.triu_indices(3)],
+                                   [e["energy"] - self_e]]))
+    est = np.array(est)
+    mean, se = est.mean(axis=0), est.std(axis=0, ddof=1) / np.sqrt(nb)
+
+    def flat(d):
+        return np.concatenate([d["forces"].ravel(), d["virial"][np.triu_indices(3)],
+                               [d["energy"]]])
+
+    z = (mean - flat(orbe.reuse_expected(r, q, box, frozen, alpha))) / se
+    print("stale-law expectation: max |z| %.2f, mean z^2 %.2f over %d components"
+          % (np.abs(z).max(), (z * z).mean(), len(z)))
+    assert np.abs(z).max() < 4.5
+    assert 0.6 < (z * z).mean() < 1.5
+    # planted mistakes: the S_now/S_frozen factor dropped; no reuse bias at all
+    m_all, _ = ewald.ewald_modes(np.diag(np.maximum(box, frozen)), alpha, 1e-16)
+    k2f = (((2.0 * np.pi) * m_all / frozen[None, :]) ** 2).sum(axis=1)
+    wrong = ewald.kspace_weighted(r, q, np.diag(box), alpha, m_all, np.exp(-k2f / (4.0 * alpha)))
+    unbiased = ewald.kspace_weighted(r, q, np.diag(box), alpha,
+                                     *ewald.ewald_modes(np.diag(box), alpha))
+    for other in (wrong, unbiased):
+        zo = (mean - flat(other)) / se
+        assert np.abs(zo).max() > 8.0
+        assert (zo * zo).mean() > 4.0
