@@ -484,7 +484,10 @@ rbe_status rbe_batch_admit(rbe_batch b, const rbe_system_desc* desc, const doubl
  * then advances).  fused = 1: every kernel launched once for all systems,
  * the argument tables copied in one transfer; fused = 0: each system's
  * kernels launched on their own, one system after another (the same
- * arithmetic).  Asynchronous. */
+ * arithmetic).  Asynchronous.  A step that fails after some systems' host
+ * state has advanced (an argument-table overflow, a launch error) leaves
+ * the batch refusing every later step with RBE_ERR_STATE: release or
+ * destroy it. */
 rbe_status rbe_batch_step(rbe_batch b, int32_t fused);
 
 /* The Fourier-space step alone for every admitted system (a1-a6: cell

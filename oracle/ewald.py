@@ -64,27 +64,42 @@ def _row_blocks(N, K, budget=2_000_000):
     return [(a, min(N, a + step)) for a in range(0, N, step)]
 
 
-def structure_factor(r, q, h, m):
+def structure_factor(r, q, h, m, threads=1):
     """rho(k_l) = sum_j q_j exp(i k_l . r_j) for each row of m (complex128).
 
-    The particle sum runs over row blocks only to bound memory."""
+    The particle sum runs over row blocks only to bound memory; with
+    threads > 1 the blocks are evaluated by a thread pool (numpy releases
+    the interpreter lock inside its array operations) and their sums are
+    added in block order."""
     s = reduced(r, h)
     mf = np.asarray(m, dtype=np.float64)
-    rho = np.zeros(mf.shape[0], dtype=np.complex128)
-    for a, b in _row_blocks(s.shape[0], mf.shape[0]):
+
+    def block(ab):
+        a, b = ab
         phase = 2.0 * math.pi * (s[a:b] @ mf.T)
-        rho += (q[a:b, None] * np.exp(1j * phase)).sum(axis=0)
+        return (q[a:b, None] * np.exp(1j * phase)).sum(axis=0)
+
+    blocks = _row_blocks(s.shape[0], mf.shape[0])
+    if threads > 1 and len(blocks) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(block, blocks))
+    else:
+        parts = [block(ab) for ab in blocks]
+    rho = np.zeros(mf.shape[0], dtype=np.complex128)
+    for part in parts:
+        rho += part
     return rho
 
 
-def kspace_weighted(r, q, h, alpha, m, weight, coulomb=1.0, force_rows=None):
+def kspace_weighted(r, q, h, alpha, m, weight, coulomb=1.0, force_rows=None, threads=1):
     """Fourier-space sum over the modes m with per-mode weights.
 
     With weight_l = exp(-k_l^2/(4 alpha)) over all nonzero m in a converged
     range this is the Ewald U1 (without self term), F_i1 and W1.  With the
     random batch weight S/p over a sampled batch it is the RBE estimator.
     force_rows: optional particle indices; forces are then returned for those
-    rows only.
+    rows only.  threads: thread pool size of the structure-factor sum.
 
     Returns dict(rho, energy, forces, virial, k, k2) -- energy excludes the
     self term.
@@ -96,7 +111,7 @@ def kspace_weighted(r, q, h, alpha, m, weight, coulomb=1.0, force_rows=None):
     V = cell_volume(h)
     k = kvectors(h, m)
     k2 = (k * k).sum(axis=1)
-    rho = structure_factor(r, q, h, m)
+    rho = structure_factor(r, q, h, m, threads)
     A, B = rho.real, rho.imag
     rho2 = A * A + B * B
     energy = coulomb * (2.0 * math.pi / V) * float(np.sum(w * rho2 / k2))

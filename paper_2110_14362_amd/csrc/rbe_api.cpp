@@ -135,23 +135,6 @@ rbe_status check_box(const rbe_ctx_s* c, const double* box) {
   return RBE_OK;
 }
 
-long env_long(const char* name, long dflt) {
-  if (const char* e = std::getenv(name)) {
-    const long v = std::atol(e);
-    if (v > 0) return v;
-  }
-  return dflt;
-}
-
-// 0/1 switch from the environment (anything else: the default)
-bool env_flag(const char* name, bool dflt) {
-  if (const char* e = std::getenv(name)) {
-    if (e[0] == '0' && e[1] == 0) return false;
-    if (e[0] == '1' && e[1] == 0) return true;
-  }
-  return dflt;
-}
-
 // Launch geometry.  Structure factors: 8-wave blocks; a lane owns R
 // frequencies (FP32: more per lane for larger batches, so each particle read
 // from LDS serves more pairs), KB waves cover distinct frequency groups
@@ -175,7 +158,7 @@ void plan_launch(rbe_ctx_s* c) {
   // the second block's waves hide latency (10^6 charges, P = 500 or 2000:
   // 4 % faster; 30k charges, P = 100: slower, the extra partials cost more)
   const double work = (double)c->n * (double)a.Ppad;
-  const long target_blocks = env_long("RBE_SFAC_BLOCKS", work >= 134217728.0 ? 512 : 256);
+  const long target_blocks = work >= 134217728.0 ? 512 : 256;
   long X = (target_blocks + a.Y - 1) / a.Y;
   const long max_x = (c->n + 15) / 16;          // at least 16 particles per chunk
   if (X > max_x) X = max_x;
@@ -194,7 +177,7 @@ void plan_launch(rbe_ctx_s* c) {
   // takes half as many same-address atomics, and the force blocks read
   // twice as many (cached) rows.
   auto rows_of = [&](int gx) { const long ng = (X + gx - 1) / gx; return ng > 1 ? ng : X; };
-  const bool k2 = a.Y == 1 && a.Ppad <= 512 && env_flag("RBE_K2REDUCE", true);
+  const bool k2 = a.Y == 1 && a.Ppad <= 512;
   const int GXh = (GX + 1) / 2;
   if (k2 && GXh >= 2 && GXh < GX && rows_of(GXh) * a.Ppad <= 4096) GX = GXh;
   a.GX = GX;
@@ -202,7 +185,7 @@ void plan_launch(rbe_ctx_s* c) {
   a.k2reduce = (k2 && rows_of(GX) * a.Ppad <= 4096) ? 1 : 0;
   const int RP = f64 ? 1 : 2;
   const long groups = (c->n + (long)kWave * RP - 1) / ((long)kWave * RP);
-  const long target_waves = env_long("RBE_FORCE_WAVES", 4096);
+  const long target_waves = 4096;
   int KS = 1;
   while (KS < 8 && (long)(KS * 2) * groups <= target_waves && KS * 2 <= c->p) KS <<= 1;
   a.KS = KS;
@@ -276,11 +259,14 @@ void clear_pending(rbe_ctx_s* c) {
   c->pend_sample = false;
 }
 
-// Run pending table / draw work with the standalone kernels.
-rbe_status flush(rbe_ctx_s* c) {
+// Pending table / draw work as standalone launches, recorded without
+// launching (plan_flush) and launched later in stream order (run_flush).
+// The host-side state (frozen block, chain buffer flip, pending flags) is
+// advanced by plan_flush.
+rbe_status plan_flush(rbe_ctx_s* c, PendingLaunch* pl) {
+  *pl = PendingLaunch{};
   if (c->pend_box == BOX_COMMITTED && !c->pend_sample) return RBE_OK;
   const StepArgs a = step_args(c);
-  hipError_t e;
   const bool reuse = c->pend_sample && c->reuse > 1;
   if (reuse) {
     // first sampled step of a new block: freeze this step's cell (the pending
@@ -295,25 +281,49 @@ rbe_status flush(rbe_ctx_s* c) {
         f.box_ptr = reinterpret_cast<const double*>(reinterpret_cast<const char*>(c->a.bs) +
                                                     offsetof(BoxState, l));
       }
-      if ((e = launch_tables(f, c->stream)) != hipSuccess) return hip_fail(e, "table kernel");
+      pl->frozen = 1;
+      pl->frozen_args = f;
       c->frozen_block = block;
       c->frozen_valid = true;
     }
   }
-  int ts = timed_begin(c, K_TABLES);
-  e = launch_tables(a, c->stream);
-  timed_end(c, K_TABLES, ts);
-  if (e != hipSuccess) return hip_fail(e, "table kernel");
+  pl->tables = 1;
+  pl->table_args = a;
   if (c->pend_sample) {
     StepArgs d = a;
     if (reuse) { d.bs = c->d_bs_frozen; d.tab = c->d_tab_frozen; }
-    ts = timed_begin(c, K_SAMPLE);
-    e = launch_sample(d, c->stream);
-    timed_end(c, K_SAMPLE, ts);
-    if (e != hipSuccess) return hip_fail(e, "sample kernel");
+    pl->sample = 1;
+    pl->sample_args = d;
   }
   clear_pending(c);
   return RBE_OK;
+}
+
+rbe_status run_flush(rbe_ctx_s* c, const PendingLaunch& pl) {
+  hipError_t e;
+  if (pl.frozen && (e = launch_tables(pl.frozen_args, c->stream)) != hipSuccess)
+    return hip_fail(e, "table kernel");
+  if (pl.tables) {
+    const int ts = timed_begin(c, K_TABLES);
+    e = launch_tables(pl.table_args, c->stream);
+    timed_end(c, K_TABLES, ts);
+    if (e != hipSuccess) return hip_fail(e, "table kernel");
+  }
+  if (pl.sample) {
+    const int ts = timed_begin(c, K_SAMPLE);
+    e = launch_sample(pl.sample_args, c->stream);
+    timed_end(c, K_SAMPLE, ts);
+    if (e != hipSuccess) return hip_fail(e, "sample kernel");
+  }
+  return RBE_OK;
+}
+
+// Run pending table / draw work with the standalone kernels now.
+rbe_status flush(rbe_ctx_s* c) {
+  PendingLaunch pl;
+  rbe_status st = plan_flush(c, &pl);
+  if (st != RBE_OK) return st;
+  return run_flush(c, pl);
 }
 
 }  // namespace
@@ -322,14 +332,17 @@ namespace rbe {
 
 rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, const double* d_z,
                             double* d_fx, double* d_fy, double* d_fz, int accumulate,
-                            double* d_virial6, double* d_energy, StepArgs* out) {
+                            double* d_virial6, double* d_energy, StepArgs* out,
+                            PendingLaunch* pre) {
+  if (pre) *pre = PendingLaunch{};
   if (!c) return fail(RBE_ERR_ARG, "NULL context");
   if (!d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz) return fail(RBE_ERR_ARG, "NULL particle array");
   if (!c->have_k) return fail(RBE_ERR_STATE, "rbe_forces_pressure before rbe_sample_k / rbe_set_k");
   if (c->pend_sample && (c->sampler == RBE_SAMPLER_MH || c->reuse > 1)) {
     // the chains move, and draws from a frozen cell run, in the standalone
-    // table and draw kernels
-    rbe_status st = flush(c);
+    // table and draw kernels: launched now, or by the caller (pre) just
+    // before the step's own kernels, once the cell they read is final
+    rbe_status st = pre ? plan_flush(c, pre) : flush(c);
     if (st != RBE_OK) return st;
   }
   StepArgs a = step_args(c);
@@ -338,7 +351,7 @@ rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, con
   a.accumulate = accumulate ? 1 : 0;
   a.virial6 = d_virial6; a.energy = d_energy;
   // a sampled step draws the next step's batch ahead, for its own cell
-  a.predraw = a.sample && c->sampler == RBE_SAMPLER_EXACT && env_flag("RBE_PREDRAW", true) ? 1 : 0;
+  a.predraw = a.sample && c->sampler == RBE_SAMPLER_EXACT ? 1 : 0;
   if (a.predraw) { c->pre_valid = true; c->pre_step = a.step + 1; }
   clear_pending(c);
   *out = a;
@@ -346,6 +359,8 @@ rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, con
 }
 
 int kspace_precision(rbe_ctx c) { return c->cfg.precision; }
+
+rbe_status kspace_run_pending(rbe_ctx c, const PendingLaunch& pre) { return run_flush(c, pre); }
 
 int64_t kspace_footprint(const rbe_config* cfg, const double* box) {
   rbe_ctx_s c;
@@ -571,7 +586,7 @@ rbe_status rbe_forces_pressure(rbe_ctx c, const double* d_x, const double* d_y, 
                                double* d_virial6, double* d_energy) {
   StepArgs a;
   rbe_status st = rbe::kspace_step_args(c, d_x, d_y, d_z, d_fx, d_fy, d_fz, accumulate, d_virial6,
-                                        d_energy, &a);
+                                        d_energy, &a, nullptr);
   if (st != RBE_OK) return st;
   const int prec = c->cfg.precision;
   int ts = timed_begin(c, K_SFAC);

@@ -72,6 +72,10 @@ struct rbe_batch_s {
   int timing_cap = 0, timed = 0;
   std::vector<hipEvent_t> ev;        // [timing_cap][kKinds + 1]
   double timed_np = 0.0;             // sum of N p over the timed steps
+  // a step failed after some systems' host state had advanced (step
+  // counters, Metropolis-Hastings chain buffers): the systems no longer agree
+  // with what ran on the device, so every later step is refused
+  bool broken = false;
 };
 
 namespace {
@@ -319,8 +323,19 @@ namespace {
 // One step of every active system: the whole NPT step, or (fourier_only)
 // the Fourier-space forces, virial and energy at the current positions and
 // cell (the batch of the system's current step).
+rbe_status batch_step_impl(rbe_batch b, int32_t fused, bool fourier_only);
+
 rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
   if (!b) return bfail(RBE_ERR_ARG, "NULL batch");
+  if (b->broken)
+    return bfail(RBE_ERR_STATE, "an earlier step failed part way; the batch refuses further steps "
+                                "(release or destroy it)");
+  const rbe_status st = batch_step_impl(b, fused, fourier_only);
+  if (st != RBE_OK) b->broken = true;
+  return st;
+}
+
+rbe_status batch_step_impl(rbe_batch b, int32_t fused, bool fourier_only) {
   std::vector<int> act;
   for (int i = 0; i < (int)b->slots.size(); ++i)
     if (b->slots[i].active) act.push_back(i);
@@ -329,6 +344,7 @@ rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
   const int prec = b->cfg.precision;
   std::vector<MDArgs> md1(nsys), md2(nsys);
   std::vector<StepArgs> ka(nsys);
+  std::vector<PendingLaunch> pend(nsys);   // Metropolis-Hastings / frozen-cell draws
   std::vector<RealArgs> ra(nsys);
   std::vector<int> ncap(nsys);
   for (int j = 0; j < nsys; ++j) {
@@ -339,7 +355,10 @@ rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
       if (st == RBE_OK) st = rbe_rescale_box_dev(s.k, s.box_dev);
     }
     if (st == RBE_OK) st = rbe_sample_k(s.k, s.step);
-    if (st == RBE_OK) st = kspace_step_args(s.k, s.x, s.y, s.z, s.fx, s.fy, s.fz, 0, s.vk, s.ek, &ka[j]);
+    // draws that need standalone kernels are launched after the integrator's
+    // first half, which writes the cell they read
+    if (st == RBE_OK)
+      st = kspace_step_args(s.k, s.x, s.y, s.z, s.fx, s.fy, s.fz, 0, s.vk, s.ek, &ka[j], &pend[j]);
     if (!fourier_only) {
       if (st == RBE_OK) st = real_step_args(s.r, s.x, s.y, s.z, s.fx, s.fy, s.fz, 1, s.vr, s.er, &ra[j], &ncap[j]);
       if (st == RBE_OK)
@@ -353,6 +372,8 @@ rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
     // every system's kernels launched by themselves, one system after another
     for (int j = 0; j < nsys && e == hipSuccess; ++j) {
       if (!fourier_only) e = launch_md_first(md1[j], b->stream);
+      if (e == hipSuccess && kspace_run_pending(b->slots[act[j]].k, pend[j]) != RBE_OK)
+        e = hipErrorLaunchFailure;
       if (e == hipSuccess) e = launch_sfac(prec, ka[j], b->stream);
       if (e == hipSuccess) e = launch_force(prec, ka[j], b->stream);
       if (!fourier_only) {
@@ -451,6 +472,8 @@ rbe_status batch_step(rbe_batch b, int32_t fused, bool fourier_only) {
   mark(0);
   if (e == hipSuccess && !fourier_only) e = launch_md_first_multi(d_md1, d_ustart, nsys, ustart.back(), b->stream);
   mark(1);
+  for (int j = 0; j < nsys && e == hipSuccess; ++j)
+    if (kspace_run_pending(b->slots[act[j]].k, pend[j]) != RBE_OK) e = hipErrorLaunchFailure;
   for (auto& kv : sg)
     if (e == hipSuccess)
       e = launch_sfac_multi(prec, kv.first, kv.second.tab, kv.second.start, (int)kv.second.idx.size(),

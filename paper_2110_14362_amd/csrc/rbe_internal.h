@@ -118,12 +118,25 @@ hipError_t launch_sfac_multi(int precision, int R, const StepArgs* d_tab, const 
 hipError_t launch_force_multi(int precision, int threads, const StepArgs* d_tab,
                               const int* d_bstart, int nsys, int total_blocks, hipStream_t s);
 
-// host side of rbe_forces_pressure without the launches: the arguments of
-// the two kernels, with the pending cell and draw folded in (the context's
-// pending state is consumed as by a launch)
+// Standalone table / draw launches that must precede a step's kernels (the
+// Metropolis-Hastings chains, draws from a frozen cell under sample reuse).
+struct PendingLaunch {
+  int32_t frozen = 0, tables = 0, sample = 0;
+  StepArgs frozen_args{}, table_args{}, sample_args{};
+};
+
+// host side of rbe_forces_pressure without the step's own launches: the
+// arguments of its kernels, with the pending cell and draw folded in (the
+// context's pending state is consumed as by a launch).  Standalone table and
+// draw work the step needs first is launched at once when pre is NULL, else
+// recorded in *pre for kspace_run_pending, which the caller must launch on
+// the context's stream before the step's kernels (after whatever writes the
+// cell they read).
 rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, const double* d_z,
                             double* d_fx, double* d_fy, double* d_fz, int accumulate,
-                            double* d_virial6, double* d_energy, StepArgs* out);
+                            double* d_virial6, double* d_energy, StepArgs* out,
+                            PendingLaunch* pre);
+rbe_status kspace_run_pending(rbe_ctx c, const PendingLaunch& pre);
 int kspace_precision(rbe_ctx c);
 // device bytes rbe_init allocates for this configuration (each buffer rounded
 // up to 256 bytes)

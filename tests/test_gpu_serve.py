@@ -230,3 +230,28 @@ def test_served_mh_fourier_steps_follow_the_oracle_chain(gpu):
     print("served MH Fourier step: force RMS rel. %.2e, oracle acceptance %.2f"
           % (err, chains.accepted / (steps * s["p"])), flush=True)
     assert err < 1e-10
+
+
+def test_served_mh_npt_trajectory_matches_oracle(gpu):
+    # NPT steps of a served system on the Metropolis-Hastings sampler: the
+    # chains must move towards the law of the cell the integrator's first
+    # half has just produced (the cell changes every step), so the trajectory
+    # equals the oracle integrator driven by the oracle chains
+    from oracle import mh_sampler as omh
+    r = request(24, 1000, sampler="mh")
+    steps = 4
+    got = run_alone(r, steps, precision="fp64")
+    s = r.sysd
+    chains = omh.MHChains(s["alpha"], s["p"], seed=r.desc.seed, system_id=r.desc.system_id)
+    md = dict(r.md, types=s["types"], lj=s["lj"], rigid=s.get("rigid"))
+    o = oracle_trajectory(s, md, np.zeros((r.n, 3)), steps, seed=r.desc.seed,
+                          system_id=r.desc.system_id, draw=chains.sample)
+    dpos = np.abs(got["pos"] - o["pos"]).max()
+    dmom = np.abs(got["mom"] - o["mom"]).max() / np.abs(o["mom"]).max()
+    dbox = np.abs(got["box"] - o["box"]).max() / o["box"].max()
+    moved = np.abs(o["box"] - np.asarray(s["box"])).max() / o["box"].max()
+    print("served MH NPT N=%d: max |dr| %.2e, rel |dp| %.2e, rel |dl| %.2e (cell moved %.1e), "
+          "oracle acceptance %.2f" % (r.n, dpos, dmom, dbox, moved,
+                                      chains.accepted / ((steps + 1) * s["p"])), flush=True)
+    assert moved > 1e-9
+    assert dpos < 1e-9 and dmom < 1e-9 and dbox < 1e-11
