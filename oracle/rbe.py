@@ -17,7 +17,9 @@ Fourier sums by sample means with weight S/p:
   the U1 summand, a diagnostic whose gradient is exactly F*):
     U1* = (2 pi C / V) sum_l (S/p) |rho_l|^2/k_l^2 - C sum_i q_i^2 sqrt(alpha/pi)
 
-Reading: one batch serves force and pressure (p = p~, as in all of section 5).
+Reading: one batch serves force and pressure (p = p~, as in all of section 5)
+in `rbe_kspace`; `rbe_kspace_split` takes a pressure batch of p~ >= p draws
+whose first p serve the forces (the remark after eq. (apppress)).
 Proposition 1 (eq. EE, ForceExp, PressExp) gives the mean and variance of the
 per-batch deviations; `force_variance` and `pressure_variance` evaluate them.
 """
@@ -44,35 +46,77 @@ def rbe_kspace(r, q, box, alpha, m, S, coulomb=1.0):
     return res
 
 
-def force_variance(r, q, box, alpha, S, p, coulomb=1.0, tol=1e-16):
-    """Prop. 1, eq. (ForceExp): E|chi_i|^2 for every particle (length N)."""
+def rbe_kspace_split(r, q, box, alpha, m, S, p_force, coulomb=1.0):
+    """Separate force and pressure batches (the remark after eq. (apppress):
+    the pressure batch size p~ may differ from the force batch size p).
+    Reading: one batch of p~ = len(m) >= p i.i.d. draws; the force estimator
+    of eq. (appforce) takes its first p draws with weight S/p, the pressure
+    (virial tensor) and the energy take all p~ draws with weight S/p~.  Each
+    estimator is the batch mean of i.i.d. draws, so each is unbiased with the
+    variance of Proposition 1 at its own batch size.
+
+    Returns dict(rho (complex, all p~), forces, virial, energy (with the self
+    term), pressure2)."""
+    m = np.asarray(m, dtype=np.int64).reshape(-1, 3)
+    pp = m.shape[0]
+    if not 1 <= p_force <= pp:
+        raise ValueError("need 1 <= p_force <= len(m)")
+    h = np.diag(np.asarray(box, dtype=np.float64))
+    V = float(np.prod(box))
+    press = kspace_weighted(r, q, h, alpha, m, S / pp, coulomb)
+    force = kspace_weighted(r, q, h, alpha, m[:p_force], S / p_force, coulomb)
+    return dict(rho=press["rho"], forces=force["forces"], virial=press["virial"],
+                energy=press["energy"] + self_energy(q, alpha, coulomb),
+                pressure2=float(np.trace(press["virial"])) / (3.0 * V))
+
+
+def mode_sums(r, q, box, alpha, tol=1e-16, threads=1):
+    """The Ewald modes m != 0 with weight e = exp(-k^2/(4 alpha)) >= tol and
+    their structure factors: (m, e, rho), shared by the closed forms below."""
+    from .ewald import structure_factor
+    h = np.diag(np.asarray(box, dtype=np.float64))
+    m, e = ewald_modes(h, alpha, tol)
+    return m, e, structure_factor(r, q, h, m, threads)
+
+
+def force_variance(r, q, box, alpha, S, p, coulomb=1.0, tol=1e-16, rows=None, threads=1,
+                   sums=None):
+    """Prop. 1, eq. (ForceExp): E|chi_i|^2 for every particle (length N), or
+    for the particles `rows`; returns it with the Ewald force F_1 of those
+    particles.  The mode sums run over particle blocks (memory) with
+    `threads` threads for rho; `sums` = mode_sums(...) if already formed."""
+    from .ewald import _row_blocks
     r = np.asarray(r, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     box = np.asarray(box, dtype=np.float64)
     V = float(np.prod(box))
-    h = np.diag(box)
-    m, e = ewald_modes(h, alpha, tol)
-    full = kspace_weighted(r, q, h, alpha, m, e, coulomb)
-    k2 = full["k2"]
-    rho = full["rho"]
-    s = r / box
-    phase = 2.0 * math.pi * (s @ m.T.astype(np.float64))
-    im = np.cos(phase) * rho.imag[None, :] - np.sin(phase) * rho.real[None, :]
-    second = ((4.0 * math.pi * coulomb * q[:, None]) ** 2 * S / (V * V * k2[None, :])
-              * e[None, :] * im * im).sum(axis=1)
-    F1 = full["forces"]
+    m, e, rho = sums if sums is not None else mode_sums(r, q, box, alpha, tol, threads)
+    mf = m.astype(np.float64)
+    k = 2.0 * math.pi * mf / box[None, :]
+    k2 = (k * k).sum(axis=1)
+    rows = np.arange(r.shape[0]) if rows is None else np.asarray(rows)
+    s = r[rows] / box
+    second = np.zeros(len(rows))
+    F1 = np.zeros((len(rows), 3))
+    coef = 4.0 * math.pi * coulomb / (V * k2)
+    for a, b in _row_blocks(len(rows), m.shape[0]):
+        phase = 2.0 * math.pi * (s[a:b] @ mf.T)
+        im = np.cos(phase) * rho.imag[None, :] - np.sin(phase) * rho.real[None, :]
+        qa = q[rows[a:b], None]
+        # F_1 (eq. force, Fourier part) and the second moment of one draw
+        F1[a:b] = -qa * ((im * (e * coef)[None, :]) @ k)
+        second[a:b] = ((qa * coef[None, :]) ** 2 * S * k2[None, :] * e[None, :] * im * im).sum(axis=1)
     return (second - (F1 * F1).sum(axis=1)) / p, F1
 
 
-def pressure_variance(r, q, box, alpha, S, p, coulomb=1.0, tol=1e-16):
+def pressure_variance(r, q, box, alpha, S, p, coulomb=1.0, tol=1e-16, threads=1, sums=None):
     """Prop. 1, eq. (PressExp): E|chi~|^2 of the isotropic P2*, and P2."""
     box = np.asarray(box, dtype=np.float64)
     V = float(np.prod(box))
-    h = np.diag(box)
-    m, e = ewald_modes(h, alpha, tol)
-    full = kspace_weighted(r, q, h, alpha, m, e, coulomb)
-    k2 = full["k2"]
-    rho2 = np.abs(full["rho"]) ** 2
+    m, e, rho = sums if sums is not None else mode_sums(r, q, box, alpha, tol, threads)
+    k = 2.0 * math.pi * m.astype(np.float64) / box[None, :]
+    k2 = (k * k).sum(axis=1)
+    rho2 = np.abs(rho) ** 2
     fac = (1.0 / 3.0 - k2 / (6.0 * alpha))
     P2 = coulomb * (2.0 * math.pi / V ** 2) * float(np.sum(e * rho2 / k2 * fac))
     second = float(np.sum(4.0 * math.pi ** 2 * coulomb ** 2 * rho2 ** 2 * S

@@ -349,3 +349,42 @@ def test_lennard_jones_oracle_gradients_and_virial():
         sc[a] -= 2 * eps
         dn = realspace.lj_nearest(s["pos"] * sc, types, s["box"] * sc, c12, c6, rc)["energy"]
         assert abs(-(up - dn) / (2 * eps) - base["virial"][a, a]) < 1e-6 * max(1.0, np.abs(base["virial"]).max())
+
+
+@pytest.mark.slow
+def test_split_batches_unbiased_with_their_own_variances():
+    # separate force and pressure batches (p = 4 for forces, p~ = 16 for the
+    # pressure, drawn as one batch): both means converge to the Ewald values,
+    # the force variance is Prop. 1's at p and the pressure variance Prop. 1's
+    # at p~ (a force weight of S/p~, or a pressure over the force rows only,
+    # would fail these)
+    s = workloads.random_neutral(24, (5.0, 5.0, 5.0), seed=31)
+    alpha, p, pp, B = 0.6, 4, 16, 2500
+    box = s["box"]
+    tb = sampler.box_tables(alpha, box)
+    S = tb["S"]
+    h = np.diag(box)
+    modes, w = ewald.ewald_modes(h, alpha)
+    full = ewald.kspace_weighted(s["pos"], s["q"], h, alpha, modes, w)
+    F1 = full["forces"]
+    P2 = np.trace(full["virial"]) / (3 * box.prod())
+    var_f, _ = rbe.force_variance(s["pos"], s["q"], box, alpha, S, p)
+    var_p, _ = rbe.pressure_variance(s["pos"], s["q"], box, alpha, S, pp)
+    Fs, Ps = [], []
+    for b in range(B):
+        m = sampler.sample_k(alpha, box, pp, seed=78, system_id=0, step=b, tables=tb)
+        res = rbe.rbe_kspace_split(s["pos"], s["q"], box, alpha, m, S, p)
+        Fs.append(res["forces"]); Ps.append(res["pressure2"])
+        if b == 0:
+            same = rbe.rbe_kspace(s["pos"], s["q"], box, alpha, m, S)
+            whole = rbe.rbe_kspace_split(s["pos"], s["q"], box, alpha, m, S, pp)
+            assert np.array_equal(whole["forces"], same["forces"])
+            assert whole["pressure2"] == same["pressure2"]
+    Fs = np.array(Fs); Ps = np.array(Ps)
+    z = ((Fs.mean(0) - F1) ** 2).sum() / (var_f.sum() / B)
+    assert 0.3 < z < 2.5, z
+    assert (Ps.mean() - P2) ** 2 / (var_p / B) < 16.0
+    emp = ((Fs - F1) ** 2).sum(axis=(0, 2)) / B
+    assert abs(emp.sum() / var_f.sum() - 1.0) < 0.08
+    empp = ((Ps - P2) ** 2).mean()
+    assert abs(empp / var_p - 1.0) < 0.15
