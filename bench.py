@@ -35,10 +35,12 @@ TRANS_PEAK = 256 * 2.4e9 * 32
 # sines and cosines the method needs per (particle, frequency) pair: the
 # structure factor takes cos and sin of k.r (real and imaginary part of rho);
 # the force takes Im(exp(-i k.r) rho) = |rho| sin(arg rho - k.r), one sine
-TRANS_PER_PAIR = {"sfac": 2, "force": 1}
+TRANS_PER_PAIR = {"sfac": 2, "force": 1, "step": 3}
 TRANS_PER_PAIR_STEP = TRANS_PER_PAIR["sfac"] + TRANS_PER_PAIR["force"]
 PER_UNIT = {"sfac": "2 transcendentals (cos, sin of k.r) per (particle, frequency) pair",
-            "force": "1 transcendental (sin of arg rho - k.r) per (particle, frequency) pair"}
+            "force": "1 transcendental (sin of arg rho - k.r) per (particle, frequency) pair",
+            "step": "3 transcendentals per (particle, frequency) pair: cos, sin of k.r for rho "
+                    "and sin of arg rho - k.r for the force"}
 
 
 def parse():
@@ -63,6 +65,10 @@ def parse():
     ap.add_argument("--skin", type=float, default=1.0,
                     help="real-space neighbour-list skin (A) of the full NPT step and the "
                          "served stream (0: cell lists every step)")
+    ap.add_argument("--slab-steps", type=int, default=1000,
+                    help="timed Fourier steps of the membrane-shaped slab (0: skip)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure the device's sine / FMA issue rates and exit")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 10 times (for scaling "
                          "the HBM byte counters of a profiler run) and exit")
@@ -350,10 +356,67 @@ def served_stream(nreq, budget_gib, precision, skin=0.0, fourier_steps=400):
                     "Fourier-space pairs of all steps over the wall time, admission included"}
 
 
+def issue_rates():
+    """The device's own issue rates behind the peaks (rbe_measure_issue_rates)."""
+    from paper_2110_14362_amd.rbe import measure_issue_rates
+    r = measure_issue_rates()
+    r["sin32_frac_of_peak_used"] = r["sin32"] / TRANS_PEAK
+    return r
+
+
+def slab_step(steps, precision, torch):
+    """The membrane-shaped slab (80 x 80 x 100 A, two sheets of 1,024
+    zwitterion dipoles, 3-site water in |z| > 25 A, 36,187 charges, g = 0.3/A,
+    P = 200), semi-isotropic: every step scales lx = ly and lz by different
+    small factors (a new cell, tables and normaliser per step)."""
+    from paper_2110_14362_amd import workloads
+    from paper_2110_14362_amd.rbe import RBE
+    dev = torch.device("cuda:0")
+    s = workloads.make("slab_36k")
+    N, P = len(s["q"]), s["p"]
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    x, y, z, q = t(s["pos"][:, 0]), t(s["pos"][:, 1]), t(s["pos"][:, 2]), t(s["q"])
+    f = [torch.zeros(N, dtype=torch.float64, device=dev) for _ in range(3)]
+    vir = torch.zeros(6, dtype=torch.float64, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    box = [float(b) for b in s["box"]]
+    ctx = RBE(q, box, P, s["alpha"], coulomb=s["coulomb"], precision=precision,
+              box_mode="semiiso", seed=2110143620, system_id=3)
+
+    def step(i):
+        fa = 1.0 + 3e-5 * math.sin(float(i))
+        fz = 1.0 - 2e-5 * math.cos(float(i))
+        ctx.rescale_box([box[0] * fa, box[1] * fa, box[2] * fz])
+        ctx.sample_k(i)
+        ctx.forces_pressure(x, y, z, *f, accumulate=False, virial6=vir, energy=en)
+    el = time_steps(step, steps, 50, torch)
+    ctx.timing_enable(steps)
+    time_steps(step, steps, 0, torch)
+    kt = ctx.timing_read()
+    ctx.timing_enable(0)
+    ctx.check()
+    plan = ctx.plan()
+    ctx.close()
+    kern = {k: (v[0] / v[1] * 1e3) if v[1] else None for k, v in kt.items()}
+    out = {"workload": "slab_36k: %s, N = %d, P = %d, semi-isotropic, %s"
+                       % (s["name"], N, P, precision),
+           "ms_per_step": el / steps * 1e3, "value": N * P / (el / steps), "unit": "(N*P)/s",
+           "steps": steps, "kernels_us": kern, "plan": plan}
+    for k in ("sfac", "force"):
+        if kern.get(k):
+            a = TRANS_PER_PAIR[k] * N * P / (kern[k] * 1e-6)
+            out["roofline_" + k] = {"bound": "alu", "achieved": a / 1e12, "peak": TRANS_PEAK / 1e12,
+                                    "unit": "Ttrans/s", "frac": a / TRANS_PEAK}
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.issue_rates:
+        print(json.dumps(issue_rates()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the multi-GPU "
@@ -404,14 +467,16 @@ def main():
     value = N * P / (ms * 1e-3)
     kern = {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None, "launches": v[1]}
             for k, v in main_r["kernels"].items()}
-    dom = max(("sfac", "force"), key=lambda k: kern[k]["avg_us"] or 0.0)
+    dom = max(("sfac", "force", "step"), key=lambda k: kern[k]["avg_us"] or 0.0)
     t_dom = kern[dom]["avg_us"] * 1e-6
     achieved = TRANS_PER_PAIR[dom] * N * P / t_dom
     step_dev = sum((v["avg_us"] or 0.0) for v in kern.values()) * 1e-6
     plan = main_r["plan"]
     f64 = args.precision == "fp64"
-    kname = ("k_sfac<%s,%d>" % ("true" if f64 else "false", 1 if f64 else plan["R"]) if dom == "sfac"
-             else "k_force<%s,%d>" % ("true" if f64 else "false", 1 if f64 else 2))
+    tf = "true" if f64 else "false"
+    kname = {"sfac": "k_sfac<%s,%d>" % (tf, 1 if f64 else plan["R"]),
+             "force": "k_force<%s,%d>" % (tf, 1 if f64 else 2),
+             "step": "k_step<%s,%d>" % (tf, 1 if f64 else plan["R"])}[dom]
     roof = {"bound": "alu", "kernel": kname,
             "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
             "frac": achieved / TRANS_PEAK, "traffic": profiled_traffic(kname, args.workload + (
@@ -453,6 +518,11 @@ def main():
     if not args.no_cpu_baseline:
         note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    note("issue rates")
+    out["issue_rates"] = issue_rates()
+    if args.workload == "water_30k" and args.slab_steps > 0:
+        note("membrane-shaped slab")
+        out["slab_36k"] = slab_step(args.slab_steps, args.precision, torch)
     if args.workload == "water_30k" and args.large_steps > 0:
         note("10^6-charge Fourier step")
         out["saturated_1m_p2000"] = large_roofline(args.large_steps, args.precision, torch)

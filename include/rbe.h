@@ -56,7 +56,16 @@ typedef enum {
 typedef enum {
   RBE_BOX_ISO = 0,      /* cubic cell, isotropic coupling (section 3.2)        */
   RBE_BOX_SEMIISO = 1,  /* lx == ly, xy and z coupled separately (appendix A)  */
-  RBE_BOX_ANISO = 2     /* any rectangular cell                                */
+  RBE_BOX_ANISO = 2,    /* any rectangular cell                                */
+  /* Triclinic cell (appendix C), Fourier part only: h = [[lx, xy, xz],
+     [0, ly, yz], [0, 0, lz]] (columns = cell vectors), given as 6 doubles
+     (lx, ly, lz, xy, xz, yz) wherever a cell is passed from the host, with
+     |xy| <= lx, |xz| <= lx, |yz| <= ly; k = 2 pi h^-T m, the sampling law
+     exp(-|k|^2/(4 alpha))/S no longer factorises over the three components of
+     m and is drawn exactly by rejection (rbe_sample_k).  Not with
+     rbe_rescale_box_dev, the Metropolis-Hastings sampler or sample reuse
+     (RBE_ERR_ARG), nor in the served batch.                                   */
+  RBE_BOX_TRICLINIC = 3
 } rbe_box_mode;
 
 typedef enum {
@@ -81,11 +90,16 @@ typedef enum {
 
 typedef struct {
   int64_t  n;          /* number of charges, >= 1                              */
-  int32_t  p;          /* batch size: frequencies per step, 1..65536; one
-                          batch serves force and pressure (p == p~)            */
+  int32_t  p;          /* force batch size, 1..65536                          */
   int32_t  box_mode;   /* rbe_box_mode                                         */
   int32_t  precision;  /* rbe_precision                                        */
-  int32_t  reserved;   /* must be 0                                            */
+  int32_t  p_pressure; /* pressure batch size p~ (the remark after eq.
+                          (apppress): it may differ from p): 0 means p~ = p,
+                          else p <= p~ <= 65536.  Each step draws ONE batch of
+                          p~ frequencies and forms rho for all of them; the
+                          forces use its first p (weight S/p), the virial
+                          tensor and the energy all p~ (weight S/p~).  Below,
+                          "the batch" means these p~ frequencies.             */
   double   alpha;      /* splitting parameter (1/length^2), > 0               */
   double   coulomb;    /* Coulomb constant C, > 0                              */
   uint64_t seed;       /* Philox key word 0                                    */
@@ -97,9 +111,10 @@ typedef struct {
  *   d_q      : DEVICE pointer to n FP64 charges; copied into the context, so
  *              the caller may free it afterwards.  Must be neutral
  *              (RBE_ERR_NONNEUTRAL otherwise).
- *   box_host : HOST pointer to (lx, ly, lz) > 0.  Semi-isotropic mode needs
- *              |lx - ly| <= 1e-12 * lx.  The sampler tables are sized for
- *              side lengths up to 2x these values.
+ *   box_host : HOST pointer to (lx, ly, lz) > 0 (triclinic mode: (lx, ly,
+ *              lz, xy, xz, yz), see RBE_BOX_TRICLINIC).  Semi-isotropic mode
+ *              needs |lx - ly| <= 1e-12 * lx.  The sampler tables are sized
+ *              for side lengths up to 2x these values.
  *   stream   : hipStream_t to queue work on (NULL = default stream).
  *   out      : receives the context.
  * Waits for the stream (the neutrality check reads a device sum).  Calls
@@ -110,7 +125,9 @@ rbe_status rbe_init(const rbe_config* cfg, const double* d_q, const double* box_
 /* Set the stream used by later calls (NULL = default stream). */
 rbe_status rbe_set_stream(rbe_ctx ctx, void* stream);
 
-/* New cell (section 4.2 eq. (S), (psf); appendix C, rectangular sampling).
+/* New cell (section 4.2 eq. (S), (psf); appendix C, rectangular sampling;
+ * triclinic mode: 6 values, see RBE_BOX_TRICLINIC and rbe_sample_k; S then
+ * from its Poisson-summed lattice form).
  * Sets the cell from which V, the per-axis discrete-Gaussian tables
  *   w_j(m) = exp(-pi^2 m^2 / (alpha l_j^2)),  |m| <= ceil(sqrt(53 ln2 alpha) l_j / pi),
  * their running sums, H_j and S = H_x H_y H_z - 1 are computed.  box_host is
@@ -127,10 +144,17 @@ rbe_status rbe_rescale_box(rbe_ctx ctx, const double* box_host);
 rbe_status rbe_rescale_box_dev(rbe_ctx ctx, const double* d_box);
 
 /* Draw the batch of step `step` (section 4.2 eq. (probexpression); section
- * 4.3): p independent nonzero integer vectors m with probability
+ * 4.3): the batch (p~ independent nonzero integer vectors m, p~ = p unless
+ * cfg.p_pressure is set) with probability
  * exp(-|k|^2/(4 alpha))/S, k = 2 pi (mx/lx, my/ly, mz/lz), from the
  * counter-based Philox4x64-10 stream keyed by (seed, system_id) with counter
- * (step, l, 'ksam', 0) for sample l.  The same step always gives the same
+ * (step, l, 'ksam', 0) for sample l.  Triclinic cell: k = 2 pi h^-T m and
+ * Q(m) = |k|^2/(4 alpha) = m^T A m; attempt a of sample l proposes m from
+ * the separable law exp(-sum_j d_j m_j^2) (d = t diag(A), t = (1 - 1e-9) x
+ * the smallest eigenvalue of diag(A)^-1/2 A diag(A)^-1/2, so that
+ * Q(m) >= sum d_j m_j^2) with counter (step, l, 'ksam', a) and accepts it
+ * with probability exp(-(Q(m) - sum d_j m_j^2)), the uniform from counter
+ * (step, l, 'kacc', a); after 256 rejections the last proposal is kept.  The same step always gives the same
  * batch for the same cell.  Uses the cell of the last rescale.  Recorded here
  * and drawn inside the next rbe_forces_pressure (or by rbe_get_k). */
 rbe_status rbe_sample_k(rbe_ctx ctx, uint64_t step);
@@ -163,22 +187,24 @@ rbe_status rbe_set_sampler(rbe_ctx ctx, int32_t sampler, int32_t iters);
 rbe_status rbe_set_sample_reuse(rbe_ctx ctx, int32_t period);
 
 /* Test hook: replace the batch by p_in host vectors h_m (p_in x 3 int32,
- * row-major, every row nonzero, |m_j| <= 2048).  p_in must equal cfg.p.
+ * row-major, every row nonzero, |m_j| <= 2048).  p_in must equal the batch
+ * size max(cfg.p, cfg.p_pressure).
  * Copies synchronously. */
 rbe_status rbe_set_k(rbe_ctx ctx, const int32_t* h_m, int32_t p_in);
 
-/* Copy the current batch (p x 3 int32) to host memory.  Waits. */
+/* Copy the current batch (p~ x 3 int32) to host memory.  Waits. */
 rbe_status rbe_get_k(rbe_ctx ctx, int32_t* h_m);
 
 /* Fourier-space forces, virial tensor and energy of the current batch
  * (section 4.2 eq. (appforce), (apppress); appendix C eq.
  * (pressuretensorflexible) with exp(-k^2/4alpha) replaced by S/p):
- *   rho_l = sum_j q_j exp(i k_l.r_j)
- *   F_i  -= q_i sum_l c_l (cos(k_l.r_i) Im rho_l - sin(k_l.r_i) Re rho_l) k_l,
+ *   rho_l = sum_j q_j exp(i k_l.r_j)                       (l < p~)
+ *   F_i  -= q_i sum_{l < p} c_l (cos(k_l.r_i) Im rho_l - sin(k_l.r_i) Re rho_l) k_l,
  *           c_l = C (S/p) 4 pi / (V |k_l|^2)
- *   W_ab  = C (2 pi / V)(S/p) sum_l |rho_l|^2/|k_l|^2
+ *   W_ab  = C (2 pi / V)(S/p~) sum_{l < p~} |rho_l|^2/|k_l|^2
  *           [delta_ab - 2 (1/|k_l|^2 + 1/(4 alpha)) k_la k_lb]
- *   U1*   = C (2 pi / V)(S/p) sum_l |rho_l|^2/|k_l|^2 - C sum_i q_i^2 sqrt(alpha/pi)
+ *   U1*   = C (2 pi / V)(S/p~) sum_{l < p~} |rho_l|^2/|k_l|^2 - C sum_i q_i^2 sqrt(alpha/pi)
+ * (p~ = p unless cfg.p_pressure is set).
  * The Fourier-space pressure tensor is W / V; the scalar pressure P2* of eq.
  * (apppress) is (Wxx + Wyy + Wzz)/(3V).
  *   d_x, d_y, d_z   : DEVICE positions (n doubles each).
@@ -193,7 +219,7 @@ rbe_status rbe_forces_pressure(rbe_ctx ctx, const double* d_x, const double* d_y
                                double* d_fz, int accumulate, double* d_virial6,
                                double* d_energy);
 
-/* Copy rho of the last rbe_forces_pressure (p complex numbers as 2p doubles:
+/* Copy rho of the last rbe_forces_pressure (p~ complex numbers as 2p~ doubles:
  * re0, im0, re1, ...) to host memory.  Waits. */
 rbe_status rbe_get_rho(rbe_ctx ctx, double* h_rho);
 
@@ -202,16 +228,74 @@ rbe_status rbe_get_rho(rbe_ctx ctx, double* h_rho);
  * h_info[10] = mcut_z; h_info[11] = device error flags (0 = none). */
 rbe_status rbe_get_box_info(rbe_ctx ctx, double* h_info);
 
-/* Launch geometry chosen at rbe_init (no device work): h_plan[12] = X
+/* Launch geometry chosen at rbe_init (no device work): h_plan[16] = X
  * (particle chunks), Y (frequency slices), KB (frequency groups per block),
  * R (frequencies per lane), GX (chunks per reduction group), NG (groups),
  * chunk (particles per chunk), Ppad, KS (force waves per particle group),
  * PW (particle waves per force block), k2reduce (1: the force kernel sums
- * the rho partials), 0. */
+ * the rho partials) of the two-launch form; fused (1: rbe_forces_pressure
+ * runs as one launch, see rbe_set_fused); the single launch's chunks, chunk
+ * size and force slices; 0. */
 rbe_status rbe_get_plan(rbe_ctx ctx, int32_t* h_plan);
 
+/* Test and measurement hook: the launch form of rbe_forces_pressure.  With
+ * enable = 1 a context whose plan allows it (every particle
+ * chunk within one 512-particle LDS tile, p <= 512 frequencies in one
+ * block, every block resident at once: n up to about 131,000 charges on
+ * MI355X) runs the whole step of section 4.2 as ONE launch: each
+ * block forms its chunk's rho partial, the partials are reduced in a fixed
+ * order by the last-arriving blocks, the last of which stores the force
+ * constants while the other blocks wait for them on a device counter, and
+ * each block then forms its own particles' forces (eq. (appforce)) from
+ * positions still in LDS.  The wait is bounded (about 0.2 s); a block that
+ * gives up (only possible when another application keeps some of the grid's
+ * blocks off the device) skips its forces and rbe_check reports it.
+ * enable = 0 (the default, measured faster on MI355X: the single launch's
+ * partial sums written in the same launch must be read through the
+ * coherence point, the second launch reads them through L2): two launches
+ * (structure factors, then forces).
+ * Both forms do the same arithmetic in the same order: identical results.
+ * RBE_ERR_ARG unless enable is 0 or 1.  No device work. */
+rbe_status rbe_set_fused(rbe_ctx ctx, int32_t enable);
+
+/* Proposition 1 measured on the device (section 4.4, eq. (ForceExp),
+ * (PressExp)): `batches` (2..10^6) evaluations of rbe_forces_pressure at the
+ * DEVICE positions d_x, d_y, d_z and the current cell, with the batches of
+ * steps first_step, first_step + 1, ... under the context's sampler; the
+ * device keeps per particle and component the sums of F* and F*^2, and the
+ * sums of the isotropic P2* = tr W/(3V) and of its square.  HOST outputs:
+ * h_out[4] = { sum over particles of the sample variance of F*_i across
+ * batches (summed over components: the total of E|chi_i|^2, eq.
+ * (ForceExp)), sample variance of P2* (eq. (PressExp)), sum over particles
+ * of |mean F*_i|^2, mean P2* }; h_var [n] (nullable) = the per-particle
+ * sample variances.  Allocates and frees 9n + 8 doubles of device scratch:
+ * a measurement call, not for time steps.  Waits.  Leaves the context's
+ * batch and last results as the final evaluation left them. */
+rbe_status rbe_variance_probe(rbe_ctx ctx, const double* d_x, const double* d_y,
+                              const double* d_z, int32_t batches, uint64_t first_step,
+                              double* h_out, double* h_var);
+
+/* The batch size for a target variance by the 1/p law of Proposition 1
+ * (eq. (ForceExp), (PressExp): the variance of a batch mean of p i.i.d.
+ * draws is the one-draw variance over p): given the variance `var` measured
+ * at batch size p (e.g. h_out[0] or h_out[1] of rbe_variance_probe),
+ * *p_out = ceil(p var / target), clamped to 1..65536.  RBE_ERR_ARG for p < 1,
+ * var < 0 or target <= 0 (or non-finite).  Host arithmetic only. */
+rbe_status rbe_batch_size_for_variance(int32_t p, double var, double target, int32_t* p_out);
+
+/* Issue rates of the current device behind the roofline peaks: FP32 sines
+ * (v_sin_f32, the transcendental unit), FP32 FMAs, FP64 FMAs, and sines with
+ * four FP32 FMAs beside each (whether both kinds issue side by side), from
+ * eight independent chains per thread on 16 blocks of 4 waves per compute
+ * unit, timed with HIP events.  h_out[5] (HOST) = {sines/s, FP32 FMAs/s,
+ * FP64 FMAs/s, sines/s of the mixed kernel, compute units}.  Allocates and
+ * frees two small device buffers; runs on the null stream; waits. */
+rbe_status rbe_measure_issue_rates(double* h_out);
+
 /* Wait for the stream and report device-side errors (capacity overflow of a
- * device rescale) as a status.  Clears the device error flags. */
+ * device rescale: RBE_ERR_CAPACITY; a single-launch step whose bounded wait
+ * for the other blocks' partial sums gave up: RBE_ERR_DEVICE, its forces not
+ * written) as a status.  Clears the device error flags. */
 rbe_status rbe_check(rbe_ctx ctx);
 
 /* Kernel timing for measurement.  While enabled, each kernel this context
@@ -223,8 +307,10 @@ rbe_status rbe_timing_enable(rbe_ctx ctx, int32_t max_launches);
 
 /* Wait for the stream and read the timing since the last read or enable:
  * h_ms[k] = total device milliseconds and h_count[k] = launches of kernel kind
- * k, for k = 0 tables, 1 sample, 2 structure factors, 3 reduction, 4 batch
- * sum (virial/energy), 5 forces.  Resets the totals (timing stays enabled). */
+ * k, for k = 0 standalone tables, 1 standalone draw, 2 structure factors
+ * (with the reduction, virial and energy), 3 forces, 4 single-launch step
+ * (rbe_set_fused); h_ms and h_count hold 5 entries.  Resets the totals
+ * (timing stays enabled). */
 rbe_status rbe_timing_read(rbe_ctx ctx, double* h_ms, int32_t* h_count);
 
 /* Release the context and its device memory (waits for the stream). */

@@ -24,6 +24,17 @@ namespace rbe {
 // ---------------------------------------------------------------------------
 // helpers
 
+// Block barrier that orders LDS only: waits for this wave's LDS operations,
+// not for its global loads and stores, which stay in flight across it (a
+// __syncthreads waits for those too).  Global data exchanged between waves
+// of a block goes through LDS after its loads returned, or is ordered by
+// the explicit waits of arrive_last and publish.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ double wave_incl_scan(double v, int lane) {
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
@@ -77,12 +88,24 @@ __device__ __forceinline__ void table_offsets(const int mc[3], int off[3]) {
 // same m without m = 0.  One wave per (axis, table); a lane owns a contiguous
 // segment, the lane totals are scanned across the wave.  Writes the cell
 // values to *out (LDS).  Must be reached by every thread of the block.
-__device__ void build_tables(const double l[3], double alpha, double tail_ln, const int mcap[3],
-                             double* tab, BoxState* out, double* sh_T) {
+__device__ void build_tables(const double l[3], const TriCell* tcp, double alpha, double tail_ln,
+                             const int mcap[3], double* tab, BoxState* out, double* sh_T) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int nw = blockDim.x / kWave;
   int err = 0, mc[3], off[3];
-  for (int a = 0; a < 3; ++a) mc[a] = table_halfwidth(alpha, tail_ln, l[a], mcap[a], err);
+  const bool tri = tcp != nullptr && tcp->on;
+  const TriCell& tc = *tcp;          // read only when tri
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (tri) {
+      // triclinic: the envelope's axis law exp(-d m^2), |m| <= ceil(sqrt(53 ln2 / d))
+      const double mcd = ceil(sqrt(tail_ln / tc.d[a]));
+      if (mcd >= 1.0 && mcd <= (double)mcap[a]) mc[a] = (int)mcd;
+      else { err |= 1; mc[a] = mcd >= 1.0 ? mcap[a] : 1; }
+    } else {
+      mc[a] = table_halfwidth(alpha, tail_ln, l[a], mcap[a], err);
+    }
+  }
   table_offsets(mc, off);
   const double pi2 = M_PI * M_PI;
   for (int task = wave; task < 6; task += nw) {
@@ -95,7 +118,8 @@ __device__ void build_tables(const double l[3], double alpha, double tail_ln, co
     double loc = 0.0;
     for (int i = b0; i < b1; ++i) {
       const int m = nz ? (i < mc[a] ? i - mc[a] : i - mc[a] + 1) : i - mc[a];
-      const double w = exp(-(pi2 * ((double)m * (double)m)) / den);
+      const double w = tri ? exp(-(tc.d[a] * ((double)m * (double)m)))
+                           : exp(-(pi2 * ((double)m * (double)m)) / den);
       t[i] = w;
       loc += w;
     }
@@ -108,11 +132,11 @@ __device__ void build_tables(const double l[3], double alpha, double tail_ln, co
     }
     if (nz && lane == kWave - 1) sh_T[a] = incl;
   }
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     const double Tx = sh_T[0], Ty = sh_T[1], Tz = sh_T[2];
     const double Hx = 1.0 + Tx, Hy = 1.0 + Ty, Hz = 1.0 + Tz;
-    BoxState b;
+    BoxState& b = *out;
     for (int a = 0; a < 3; ++a) { b.l[a] = l[a]; b.inv_l[a] = 1.0 / l[a]; b.mcut[a] = mc[a]; }
     b.V = l[0] * l[1] * l[2];
     b.H[0] = Hx; b.H[1] = Hy; b.H[2] = Hz;
@@ -121,9 +145,14 @@ __device__ void build_tables(const double l[3], double alpha, double tail_ln, co
     b.case_w[2] = Tz;
     b.S = b.case_w[0] + b.case_w[1] + b.case_w[2];
     b.err = err;
-    *out = b;
+    if (tri) {
+      b.tri = tc;
+      b.S = tc.S;                // the estimator's normaliser; the tables are the envelope's
+    } else {
+      b.tri.on = 0;
+    }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 __device__ __forceinline__ int first_greater(const double* c, int n, double t) {
@@ -142,16 +171,17 @@ __device__ __forceinline__ int first_greater(const double* c, int n, double t) {
 // Uniforms: the four Philox outputs of counter (step, l, 'ksam', 0), top 53
 // bits.  A table draw is the first index whose running sum exceeds u times
 // the table total; the three axes' binary searches run in lockstep.
-__device__ __forceinline__ void draw_frequency(const BoxState& b, const double* tab, uint64_t seed,
-                                               uint64_t sysid, uint64_t step, int l, int m[3]) {
+__device__ __forceinline__ void propose_frequency(const BoxState& b, const double* tab, uint64_t seed,
+                                                  uint64_t sysid, uint64_t step, int l,
+                                                  uint64_t attempt, int m[3]) {
   int off[3];
   table_offsets(b.mcut, off);
-  uint64_t c[4] = {step, (uint64_t)l, kTagKSample, 0ull};
+  uint64_t c[4] = {step, (uint64_t)l, kTagKSample, attempt};
   philox4x64_10(c, seed, sysid);
   double u[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) u[j] = (double)(c[j] >> 11) * 0x1.0p-53;
-  const double t = u[0] * b.S;
+  const double t = u[0] * (b.case_w[0] + b.case_w[1] + b.case_w[2]);
   const int pivot = (t < b.case_w[0]) ? 0 : ((t < b.case_w[0] + b.case_w[1]) ? 1 : 2);
   const double* base[3];
   int lo[3], hi[3];
@@ -187,6 +217,37 @@ __device__ __forceinline__ void draw_frequency(const BoxState& b, const double* 
   }
 }
 
+constexpr uint64_t kTagKAccept = 0x6B616363ull;  // 'kacc': acceptance uniforms, triclinic draws
+constexpr int kMaxAttempts = 256;
+
+// Frequency l of a step.  Rectangular cell: the exact draw (attempt 0).
+// Triclinic cell (appendix C): attempt a proposes from the separable
+// envelope exp(-sum d_j m_j^2) with the uniforms of counter (step, l, 'ksam',
+// a) and accepts with probability exp(-(Q(m) - sum d_j m_j^2)), the uniform
+// from counter (step, l, 'kacc', a); the accepted m has law exp(-Q(m))/S.
+// After kMaxAttempts rejections the last proposal is kept.
+__device__ __forceinline__ void draw_frequency(const BoxState& b, const double* tab, uint64_t seed,
+                                               uint64_t sysid, uint64_t step, int l, int m[3]) {
+  if (!b.tri.on) {
+    propose_frequency(b, tab, seed, sysid, step, l, 0ull, m);
+    return;
+  }
+  for (int att = 0; att < kMaxAttempts; ++att) {
+    propose_frequency(b, tab, seed, sysid, step, l, (uint64_t)att, m);
+    const double x = m[0], y = m[1], z = m[2];
+    const double* A = b.tri.A;
+    const double Q = A[0] * x * x + A[1] * y * y + A[2] * z * z +
+                     2.0 * (A[3] * x * y + A[4] * x * z + A[5] * y * z);
+    const double excess = Q - (b.tri.d[0] * x * x + b.tri.d[1] * y * y + b.tri.d[2] * z * z);
+    uint64_t c[4] = {step, (uint64_t)l, kTagKAccept, (uint64_t)att};
+    philox4x64_10(c, seed, sysid);
+    const double ua = (double)(c[0] >> 11) * 0x1.0p-53;
+    if (ua < exp(-excess)) return;
+  }
+}
+
+// The sides of a launch's cell (the arguments, device memory, or the
+// committed cell values).
 __device__ __forceinline__ void box_source(const StepArgs& a, double l[3]) {
   if (a.box_src == BOX_ARGS) {
     l[0] = a.box_arg[0]; l[1] = a.box_arg[1]; l[2] = a.box_arg[2];
@@ -197,14 +258,68 @@ __device__ __forceinline__ void box_source(const StepArgs& a, double l[3]) {
   }
 }
 
-// Reduced coordinate s = x/l - floor(x/l) in [0,1), split as s = sh + sl with
+// The launch's triclinic cell data copied to LDS (s), or NULL for a
+// rectangular cell.  (A copy, not a pointer into the kernel arguments: a
+// pointer that may address either the arguments or global memory makes the
+// compiler copy all the arguments to scratch memory.)  Called once at the
+// top of a kernel, so that no argument value stays live across the kernel.
+// Reached by every thread; one barrier in triclinic contexts.
+__device__ __forceinline__ const TriCell* stage_tri(const StepArgs& a, TriCell* s) {
+  if (!a.tri_mode) return nullptr;           // a rectangular-cell context: nothing to stage
+  if (threadIdx.x == 0) {
+    if (a.box_src == BOX_ARGS) *s = a.tri_arg;
+    else if (a.box_src == BOX_COMMITTED) *s = a.bs->tri;
+    else s->on = 0;
+  }
+  lds_barrier();
+  return s->on ? s : nullptr;
+}
+
+// The cell values of this launch become the committed ones (keeping any
+// error flag already set); field by field, no local copy of the struct.
+__device__ __forceinline__ void commit_cell(const BoxState& b, BoxState* dst) {
+  const int32_t e0 = dst->err;
+  *dst = b;
+  dst->err = b.err | e0;
+}
+
+// Whether a batch drawn ahead for cell pb is the batch of this launch's cell.
+__device__ __forceinline__ bool same_cell(const StepArgs& a, const BoxState& pb) {
+  double l[3];
+  box_source(a, l);
+  int on = 0;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  if (a.box_src == BOX_ARGS) {
+    on = a.tri_arg.on; t0 = a.tri_arg.tilt[0]; t1 = a.tri_arg.tilt[1]; t2 = a.tri_arg.tilt[2];
+  } else if (a.box_src == BOX_COMMITTED) {
+    on = a.bs->tri.on; t0 = a.bs->tri.tilt[0]; t1 = a.bs->tri.tilt[1]; t2 = a.bs->tri.tilt[2];
+  }
+  return l[0] == pb.l[0] && l[1] == pb.l[1] && l[2] == pb.l[2] && on == pb.tri.on &&
+         (!on || (t0 == pb.tri.tilt[0] && t1 == pb.tri.tilt[1] && t2 == pb.tri.tilt[2]));
+}
+
+// Reduced coordinates s = h^-1 r wrapped into [0, 1): x/l per axis for a
+// rectangular cell, back substitution through the upper-triangular h^-1 for
+// a triclinic one (appendix C: k.r = 2 pi m.s).
+__device__ __forceinline__ void reduce_pos(const BoxState& b, double x, double y, double z,
+                                           double& sx, double& sy, double& sz) {
+  if (b.tri.on) {
+    const double* hi = b.tri.hinv;
+    sx = hi[0] * x + hi[1] * y + hi[2] * z;
+    sy = hi[3] * y + hi[4] * z;
+    sz = hi[5] * z;
+  } else {
+    sx = x * b.inv_l[0]; sy = y * b.inv_l[1]; sz = z * b.inv_l[2];
+  }
+  sx -= floor(sx); sy -= floor(sy); sz -= floor(sz);
+}
+
+// Reduced coordinate s in [0,1) (reduce_pos), split as s = sh + sl with
 // sh a multiple of 2^-11 (exact in FP32) and 0 <= sl < 2^-11.  For |m| <= 2048
 // the product m.sh is a multiple of 2^-11 below 2^13 in magnitude: it and its
 // fractional part are exact in FP32, so the integer part of the phase m.s is
 // removed without rounding; m.sl is added after.
-__device__ __forceinline__ void split_coord(double x, double inv_l, float& sh, float& sl) {
-  double s = x * inv_l;
-  s -= floor(s);
+__device__ __forceinline__ void split_coord(double s, float& sh, float& sl) {
   const double h = floor(s * 2048.0) * (1.0 / 2048.0);
   sh = (float)h;
   sl = (float)(s - h);
@@ -260,13 +375,15 @@ __device__ __forceinline__ void sincos2pi(double f, const double2* tab, double& 
 // charges: sums for the neutrality check and the self term, FP32 copy
 
 __global__ void k_qsum(const double* __restrict__ q, float* __restrict__ qf,
-                       double* __restrict__ out, int64_t n) {
+                       double* __restrict__ out, int64_t n, uint32_t* __restrict__ zero,
+                       int64_t nzero) {
   __shared__ double s0[1024], s1[1024], s2[1024];
   const int t = threadIdx.x;
+  for (int64_t i = t; i < nzero; i += blockDim.x) zero[i] = 0u;   // words to clear, if any
   double a = 0.0, b = 0.0, c = 0.0;
   for (int64_t i = t; i < n; i += blockDim.x) {
     const double v = q[i];
-    qf[i] = (float)v;
+    if (qf) qf[i] = (float)v;
     a += v; b += fabs(v); c += v * v;
   }
   s0[t] = a; s1[t] = b; s2[t] = c;
@@ -278,8 +395,9 @@ __global__ void k_qsum(const double* __restrict__ q, float* __restrict__ qf,
   if (t == 0) { out[0] = s0[0]; out[1] = s1[0]; out[2] = s2[0]; }
 }
 
-hipError_t launch_qsum(const double* d_q, float* d_qf, double* d_out3, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_qsum, dim3(1), dim3(1024), 0, s, d_q, d_qf, d_out3, n);
+hipError_t launch_qsum(const double* d_q, float* d_qf, double* d_out3, int64_t n, hipStream_t s,
+                       uint32_t* d_zero, int64_t nzero) {
+  hipLaunchKernelGGL(k_qsum, dim3(1), dim3(1024), 0, s, d_q, d_qf, d_out3, n, d_zero, nzero);
   return hipGetLastError();
 }
 
@@ -354,14 +472,14 @@ __device__ __forceinline__ void sample_frequency(const StepArgs& a, const BoxSta
 
 __global__ void __launch_bounds__(256) k_tables(StepArgs a) {
   __shared__ BoxState sbs;
+  __shared__ TriCell stc;
   __shared__ double sh_T[3];
   double l[3];
+  const TriCell* tc = stage_tri(a, &stc);
   box_source(a, l);
-  build_tables(l, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T);
+  build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T);
   if (threadIdx.x == 0) {
-    BoxState b = sbs;
-    b.err |= a.bs->err;
-    *a.bs = b;
+    commit_cell(sbs, a.bs);
   }
 }
 
@@ -449,8 +567,8 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, i
 // order, by the whole block (W and the block size powers of two).  If W <
 // threads: thread t owns column t % W and rows t / W + RG*j (RG = threads /
 // W), then the RG row-group sums are added in order through LDS.  Otherwise
-// thread t owns columns t + threads*j and all rows.  Loads are issued four at
-// a time.  src is read with coherent loads when SrcCoh (rows stored by other
+// thread t owns columns t + threads*j and all rows.  Loads are issued kB
+// (8 unless given) at a time.  src is read with coherent loads when SrcCoh (rows stored by other
 // blocks of the same launch), else plainly (rows of an earlier launch, which
 // the L2 may then serve to several blocks); dst is written with coherent
 // stores when dst_coh, else plainly (LDS).  Reached by every thread;
@@ -460,77 +578,75 @@ __device__ __forceinline__ double2 ld_row(const double2* p) {
   return SrcCoh ? ld_coh2(p) : *p;
 }
 
-template <bool SrcCoh = true>
+template <bool SrcCoh = true, int kB = 8>
 __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
                                bool dst_coh, double2* scratch) {
+  // rows r0, r0 + step, ... (< R) of column col added in that order; loads
+  // issued kB at a time (independent, all in flight) before the adds
+  auto column_sum = [&](int col, int r0, int step) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int r = r0; r < R; r += kB * step) {
+      double2 v[kB];
+#pragma unroll
+      for (int k = 0; k < kB; ++k)
+        v[k] = (r + k * step < R) ? ld_row<SrcCoh>(src + (int64_t)(r + k * step) * stride + col)
+                                  : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < kB; ++k)
+        if (r + k * step < R) { acc.x += v[k].x; acc.y += v[k].y; }
+    }
+    return acc;
+  };
   const int t = threadIdx.x, nt = blockDim.x;
   if (W >= nt) {
     for (int col = t; col < W; col += nt) {
-      double2 acc = make_double2(0.0, 0.0);
-      int r = 0;
-      for (; r + 3 < R; r += 4) {
-        const double2 v0 = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
-        const double2 v1 = ld_row<SrcCoh>(src + (int64_t)(r + 1) * stride + col);
-        const double2 v2 = ld_row<SrcCoh>(src + (int64_t)(r + 2) * stride + col);
-        const double2 v3 = ld_row<SrcCoh>(src + (int64_t)(r + 3) * stride + col);
-        acc.x += v0.x; acc.y += v0.y; acc.x += v1.x; acc.y += v1.y;
-        acc.x += v2.x; acc.y += v2.y; acc.x += v3.x; acc.y += v3.y;
-      }
-      for (; r < R; ++r) {
-        const double2 v = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
-        acc.x += v.x; acc.y += v.y;
-      }
+      const double2 acc = column_sum(col, 0, 1);
       if (dst_coh) st_coh2(dst + col, acc); else dst[col] = acc;
     }
-    __syncthreads();
+    lds_barrier();
     return;
   }
   const int RG = nt / W;
   const int col = t % W, rg = t / W;
-  double2 acc = make_double2(0.0, 0.0);
-  int r = rg;
-  for (; r + 3 * RG < R; r += 4 * RG) {
-    const double2 v0 = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
-    const double2 v1 = ld_row<SrcCoh>(src + (int64_t)(r + RG) * stride + col);
-    const double2 v2 = ld_row<SrcCoh>(src + (int64_t)(r + 2 * RG) * stride + col);
-    const double2 v3 = ld_row<SrcCoh>(src + (int64_t)(r + 3 * RG) * stride + col);
-    acc.x += v0.x; acc.y += v0.y; acc.x += v1.x; acc.y += v1.y;
-    acc.x += v2.x; acc.y += v2.y; acc.x += v3.x; acc.y += v3.y;
-  }
-  for (; r < R; r += RG) {
-    const double2 v = ld_row<SrcCoh>(src + (int64_t)r * stride + col);
-    acc.x += v.x; acc.y += v.y;
-  }
-  __syncthreads();
+  const double2 acc = column_sum(col, rg, RG);
+  lds_barrier();
   scratch[t] = acc;
-  __syncthreads();
+  lds_barrier();
   if (t < W) {
     double2 s2 = scratch[t];
     for (int g = 1; g < RG; ++g) { const double2 v = scratch[g * W + t]; s2.x += v.x; s2.y += v.y; }
     if (dst_coh) st_coh2(dst + t, s2); else dst[t] = s2;
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Per-frequency constants from rho_l and m_l (eq. (appforce), eq. (apppress)
 // in tensor form, appendix C):
-//   k = 2 pi m / l,  c = C (S/p) 4 pi / (V |k|^2)  ->  force coefficients (c Re rho, c Im rho);
+//   k = 2 pi m / l (triclinic: 2 pi h^-T m),  c = C (S/p_force) 4 pi / (V |k|^2)
+//   ->  force coefficients (c Re rho, c Im rho);
 //   the FP32 path keeps c |rho| and arg(rho) instead: Im(exp(-i theta) rho) =
 //   |rho| sin(arg(rho) - theta) takes one sine per pair where the cos / sin
 //   form takes two
 //   tv = |rho|^2/|k|^2 [delta_ab - 2 (1/|k|^2 + 1/(4 alpha)) k_a k_b]  (xx yy zz xy xz yz) and
 //   tv[6] = |rho|^2/|k|^2, to be scaled by C (2 pi / V)(S/p) after the batch sum.
 __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const BoxState& b,
-                                            double alpha, double coulomb, int p, FCoef64& f,
+                                            double alpha, double coulomb, int p_force, FCoef64& f,
                                             FCoef32& h, double tv[7]) {
   double km[3], kk[3];
   for (int c = 0; c < 3; ++c) {
     km[c] = (double)mi[c];
     kk[c] = 2.0 * M_PI * km[c] * b.inv_l[c];
   }
+  if (b.tri.on) {
+    // k = 2 pi h^-T m (appendix C), h^-1 upper triangular
+    const double* hi = b.tri.hinv;
+    kk[0] = 2.0 * M_PI * (hi[0] * km[0]);
+    kk[1] = 2.0 * M_PI * (hi[1] * km[0] + hi[3] * km[1]);
+    kk[2] = 2.0 * M_PI * (hi[2] * km[0] + hi[4] * km[1] + hi[5] * km[2]);
+  }
   const double k2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
   const double ik2 = 1.0 / k2;
-  const double cl = coulomb * (b.S / (double)p) * 4.0 * M_PI / b.V * ik2;
+  const double cl = coulomb * (b.S / (double)p_force) * 4.0 * M_PI / b.V * ik2;
   const double fac = (r.x * r.x + r.y * r.y) * ik2;
   const double beta = 2.0 * (ik2 + 0.25 / alpha);
   tv[0] = fac * (1.0 - beta * kk[0] * kk[0]);
@@ -560,16 +676,16 @@ __device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8
                               const BoxState& b, double coulomb, int p, double self_energy,
                               double* virial6, double* energy) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  __syncthreads();
+  lds_barrier();
   for (int c = 0; c < 7; ++c) stv[c * nt + tid] = tv[c];
-  __syncthreads();
+  lds_barrier();
   if (tid < 56) {
     const int c = tid / 8, part_i = tid % 8;
     double v = 0.0;
     for (int l = part_i; l < nt; l += 8) v += stv[c * nt + l];
     sh_vs[c][part_i] = v;
   }
-  __syncthreads();
+  lds_barrier();
   if (tid < 7) {
     double v = 0.0;
     for (int w = 0; w < 8; ++w) v += sh_vs[tid][w];
@@ -579,10 +695,94 @@ __device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8
   }
 }
 
+// rho sums over one LDS tile, FP32 path: lane frequencies (mx, my, mz)[r];
+// the wave takes particles sub, sub + SUB, ... of the tile in runs of kKahan
+// plain FP32 FMAs, each run folded into the per-lane Kahan pairs (SA, CA),
+// (SB, CB).  The tile holds (sh.x, sh.y, sh.z, q) and (sl.x, sl.y, sl.z, 0)
+// per particle, padded with zero charges to a multiple of SUB * kKahan.
+template <int R>
+__device__ __forceinline__ void sfac_tile32(const float4* tA, const float4* tB, int cntp, int sub,
+                                            int SUB, const float (&mx)[R], const float (&my)[R],
+                                            const float (&mz)[R], float (&SA)[R], float (&CA)[R],
+                                            float (&SB)[R], float (&CB)[R]) {
+  const int runlen = SUB * kKahan;
+  for (int j0 = sub; j0 < cntp; j0 += runlen) {
+    float ra[R], rb[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { ra[r] = 0.f; rb[r] = 0.f; }
+#pragma unroll
+    for (int u = 0; u < kKahan; ++u) {
+      const int j = j0 + u * SUB;
+      const float4 pa = tA[j], pb = tB[j];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float f = phase_rev(mx[r], my[r], mz[r], pa.x, pa.y, pa.z, pb.x, pb.y, pb.z);
+        const float cs = __builtin_amdgcn_cosf(f);
+        const float sn = __builtin_amdgcn_sinf(f);
+        ra[r] = fmaf(pa.w, cs, ra[r]);
+        rb[r] = fmaf(pa.w, sn, rb[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      kahan_add(SA[r], CA[r], ra[r]);
+      kahan_add(SB[r], CB[r], rb[r]);
+    }
+  }
+}
+
+// rho sums over one LDS tile, FP64 path: the tile holds (s.x, s.y) and
+// (s.z, q) per particle (reduced coordinates in [0, 1)), padded to a
+// multiple of SUB with zero charges.
+template <int R>
+__device__ __forceinline__ void sfac_tile64(const double2* tA, const double2* tB, int cntp, int sub,
+                                            int SUB, const double2* sctab, const double (&mx)[R],
+                                            const double (&my)[R], const double (&mz)[R],
+                                            double (&A)[R], double (&B)[R]) {
+  for (int j = sub; j < cntp; j += SUB) {
+    const double2 pa = tA[j], pb = tB[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double t = mx[r] * pa.x + my[r] * pa.y + mz[r] * pb.x;
+      const double f = t - rint(t);
+      double sn, cs;
+      sincos2pi(f, sctab, sn, cs);
+      A[r] = fma(pb.y, cs, A[r]);
+      B[r] = fma(pb.y, sn, B[r]);
+    }
+  }
+}
+
+// Block partial of rho: the SUB particle sub-slices of every frequency slot
+// summed in order (through red, kSfacThreads entries of LDS) and stored with
+// coherent stores to dst[slot] (slot = kg*64R + r*64 + lane).  Reached by
+// every thread.
+template <int R>
+__device__ __forceinline__ void store_block_partial(const double2 (&part)[R], double2* red, int KB,
+                                                    int SUB, double2* dst) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    lds_barrier();
+    red[tid] = part[r];
+    lds_barrier();
+    if (tid < KB * kWave) {                // (kg', lane') = (tid / 64, tid % 64)
+      double2 s2 = make_double2(0.0, 0.0);
+      for (int sb = 0; sb < SUB; ++sb) {   // wave = sb*KB + kg'  ->  index sb*KB*64 + tid
+        const double2 v = red[sb * KB * kWave + tid];
+        s2.x += v.x; s2.y += v.y;
+      }
+      const int sl = (tid / kWave) * kWave * R + r * kWave + (tid % kWave);
+      st_coh2(dst + sl, s2);
+    }
+  }
+}
+
 template <bool F64, int R>
 __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const int y,
                                           unsigned char* lds_raw) {
   __shared__ BoxState sbs;
+  __shared__ TriCell stc;
   __shared__ double sh_T[3];
   __shared__ int sh_flag;
   __shared__ double sh_vs[7][8];
@@ -590,6 +790,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;
   if (F64) fill_sincos_tab(sctab);        // read after the barriers below
+  const TriCell* tc = stage_tri(a, &stc);
   unsigned char* base = lds_raw;
   int* sm = reinterpret_cast<int*>(base + kR0);                     // batch slice, 3 ints each
   double* tabs = reinterpret_cast<double*>(base + kR0 + sfac_r1(a));  // R2
@@ -599,7 +800,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     if (y != 0) return;
     double l[3];
     box_source(a, l);
-    build_tables(l, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
     const uint64_t next = a.step + 1;
     const int slot = (int)(next & 1);
     int32_t* mp = a.m_pre + (int64_t)slot * 3 * a.p;
@@ -631,15 +832,13 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   if (tid == 0) {
     int ok = 0;
     if (a.sample && a.use_pre && a.pre[pslot].valid && a.pre[pslot].step == a.step) {
-      double l[3];
-      box_source(a, l);
       const PreDraw& pd = a.pre[pslot];
-      ok = (l[0] == pd.bs.l[0] && l[1] == pd.bs.l[1] && l[2] == pd.bs.l[2]) ? 1 : 0;
+      ok = same_cell(a, pd.bs) ? 1 : 0;
       if (ok) sbs = pd.bs;
     }
     sh_flag = ok;
   }
-  __syncthreads();
+  lds_barrier();
   const bool pre = sh_flag != 0;
   const int32_t* m_pre = a.m_pre + (int64_t)pslot * 3 * a.p;
 
@@ -647,22 +846,18 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   const bool need_tables = !pre && (a.sample || a.box_src != BOX_COMMITTED);
   if (pre) {
     if (x == 0 && y == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
-      BoxState b = sbs;
-      b.err |= a.bs->err;
-      *a.bs = b;
+      commit_cell(sbs, a.bs);
     }
   } else if (need_tables) {
     double l[3];
     box_source(a, l);
-    build_tables(l, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
     if (x == 0 && y == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
-      BoxState b = sbs;
-      b.err |= a.bs->err;
-      *a.bs = b;
+      commit_cell(sbs, a.bs);
     }
   } else {
     if (tid == 0) sbs = *a.bs;
-    __syncthreads();
+    lds_barrier();
   }
 
   // ---- this block's slice of the batch
@@ -683,7 +878,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     }
     sm[3 * s2] = mv[0]; sm[3 * s2 + 1] = mv[1]; sm[3 * s2 + 2] = mv[2];
   }
-  __syncthreads();
+  lds_barrier();
 
   // ---- structure factors over the chunk: lane owns frequencies
   // kg*64R + r*64 + lane (r < R); wave = sub*KB + kg
@@ -708,43 +903,24 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
       const int cnt = (int)min((int64_t)kTile, c1 - t0);
       const int cntp = (cnt + runlen - 1) / runlen * runlen;
-      __syncthreads();
+      lds_barrier();
       for (int j = tid; j < cntp; j += kSfacThreads) {
         float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j < cnt) {
           const int64_t i = t0 + j;
           const bool first = (t0 == c0);     // j == tid here: prefetched above
-          split_coord(first ? px : a.x[i], ix, u.x, v.x);
-          split_coord(first ? py : a.y[i], iy, u.y, v.y);
-          split_coord(first ? pz : a.z[i], iz, u.z, v.z);
+          double sx, sy, sz;
+          reduce_pos(sbs, first ? px : a.x[i], first ? py : a.y[i], first ? pz : a.z[i], sx, sy,
+                     sz);
+          split_coord(sx, u.x, v.x);
+          split_coord(sy, u.y, v.y);
+          split_coord(sz, u.z, v.z);
           u.w = first ? (float)pq : a.qf[i];
         }
         tA[j] = u; tB[j] = v;
       }
-      __syncthreads();
-      for (int j0 = sub; j0 < cntp; j0 += runlen) {
-        float ra[R], rb[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) { ra[r] = 0.f; rb[r] = 0.f; }
-#pragma unroll
-        for (int u = 0; u < kRun; ++u) {
-          const int j = j0 + u * SUB;
-          const float4 pa = tA[j], pb = tB[j];
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const float f = phase_rev(mx[r], my[r], mz[r], pa.x, pa.y, pa.z, pb.x, pb.y, pb.z);
-            const float cs = __builtin_amdgcn_cosf(f);
-            const float sn = __builtin_amdgcn_sinf(f);
-            ra[r] = fmaf(pa.w, cs, ra[r]);
-            rb[r] = fmaf(pa.w, sn, rb[r]);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          kahan_add(SA[r], CA[r], ra[r]);
-          kahan_add(SB[r], CB[r], rb[r]);
-        }
-      }
+      lds_barrier();
+      sfac_tile32<R>(tA, tB, cntp, sub, SUB, mx, my, mz, SA, CA, SB, CB);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -762,33 +938,22 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
       const int cnt = (int)min((int64_t)kTile, c1 - t0);
       const int cntp = (cnt + SUB - 1) / SUB * SUB;
-      __syncthreads();
+      lds_barrier();
       for (int j = tid; j < cntp; j += kSfacThreads) {
         double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
         if (j < cnt) {
           const int64_t i = t0 + j;
           const bool first = (t0 == c0);     // j == tid here: prefetched above
-          double sx = (first ? px : a.x[i]) * ix, sy = (first ? py : a.y[i]) * iy;
-          double sz = (first ? pz : a.z[i]) * iz;
-          sx -= floor(sx); sy -= floor(sy); sz -= floor(sz);
+          double sx, sy, sz;
+          reduce_pos(sbs, first ? px : a.x[i], first ? py : a.y[i], first ? pz : a.z[i], sx, sy,
+                     sz);
           u = make_double2(sx, sy);
           v = make_double2(sz, first ? pq : a.q[i]);
         }
         tA[j] = u; tB[j] = v;
       }
-      __syncthreads();
-      for (int j = sub; j < cntp; j += SUB) {
-        const double2 pa = tA[j], pb = tB[j];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double t = mx[r] * pa.x + my[r] * pa.y + mz[r] * pb.x;
-          const double f = t - rint(t);
-          double sn, cs;
-          sincos2pi(f, sctab, sn, cs);
-          A[r] = fma(pb.y, cs, A[r]);
-          B[r] = fma(pb.y, sn, B[r]);
-        }
-      }
+      lds_barrier();
+      sfac_tile64<R>(tA, tB, cntp, sub, SUB, sctab, mx, my, mz, A, B);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) part[r] = make_double2(A[r], B[r]);
@@ -796,30 +961,17 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
 
   // ---- block partial: sum the SUB particle sub-slices, in order, per slot
   double2* red = reinterpret_cast<double2*>(base);          // kSfacThreads entries (R0)
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    __syncthreads();
-    red[tid] = part[r];
-    __syncthreads();
-    if (tid < KB * kWave) {                // (kg', lane') = (tid / 64, tid % 64)
-      double2 s2 = make_double2(0.0, 0.0);
-      for (int sb = 0; sb < SUB; ++sb) {   // wave = sb*KB + kg'  ->  index sb*KB*64 + tid
-        const double2 v = red[sb * KB * kWave + tid];
-        s2.x += v.x; s2.y += v.y;
-      }
-      const int sl = (tid / kWave) * kWave * R + r * kWave + (tid % kWave);
-      st_coh2(a.partial + (int64_t)x * a.Ppad + slice + sl, s2);
-    }
-  }
+  store_block_partial<R>(part, red, KB, SUB, a.partial + (int64_t)x * a.Ppad + slice);
 
   // ---- level 1: the last block of each chunk group sums the group's partials
   const int g = x / a.GX;
   const int gsize = min(a.GX, a.X - g * a.GX);
   if (a.NG > 1) {
-    if (!arrive_last(&a.cnt[y * a.NG + g], (uint32_t)gsize, &sh_flag)) return;
+    if (!arrive_last(a.cnt + cnt_index(a, CNT_GROUP, y * a.NG + g), (uint32_t)gsize, &sh_flag))
+      return;
     block_sum_rows(a.partial + (int64_t)g * a.GX * a.Ppad + slice, a.Ppad, gsize, FB,
                    a.gpart + (int64_t)g * a.Ppad + slice, true, red);
-    if (tid == 0) a.cnt[y * a.NG + g] = 0u;
+    if (tid == 0) a.cnt[cnt_index(a, CNT_GROUP, y * a.NG + g)] = 0u;
   }
 
   // the force kernel takes it from here (small batches: every force block
@@ -828,7 +980,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
 
   // ---- level 2: the last group of the slice forms rho, the force
   // coefficients and the per-frequency virial summands
-  if (!arrive_last(&a.cnt[a.Y * a.NG + y], (uint32_t)a.NG, &sh_flag)) return;
+  if (!arrive_last(a.cnt + cnt_index(a, CNT_SLICE, y), (uint32_t)a.NG, &sh_flag)) return;
   double2* srho = reinterpret_cast<double2*>(tabs);          // R2 (tables are dead)
   if (a.NG > 1)
     block_sum_rows(a.gpart + slice, a.Ppad, a.NG, FB, srho, false, red);
@@ -844,7 +996,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     FCoef64 f;
     FCoef32 h;
     double tl[7];
-    freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tl);
+    freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.pf, f, h, tl);
     if (a.Y > 1) {
       double* tr = a.terms + (int64_t)l * 8;
       for (int c = 0; c < 7; ++c) st_coh(tr + c, tl[c]);
@@ -853,19 +1005,19 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     a.fc64[l] = f;
     a.fc32[l] = h;
   }
-  if (tid == 0) a.cnt[a.Y * a.NG + y] = 0u;
+  if (tid == 0) a.cnt[cnt_index(a, CNT_SLICE, y)] = 0u;
 
   // ---- level 3: the batch sum -> virial tensor and energy.  With one slice
   // the level-2 block holds every summand; otherwise the last slice loads
   // them back, thread t taking frequencies t, t + kSfacThreads, ...
   if (a.Y > 1) {
-    if (!arrive_last(&a.cnt[a.Y * a.NG + a.Y], (uint32_t)a.Y, &sh_flag)) return;
+    if (!arrive_last(a.cnt + cnt_index(a, CNT_BATCH), (uint32_t)a.Y, &sh_flag)) return;
     for (int c = 0; c < 7; ++c) tv[c] = 0.0;
     for (int l = tid; l < a.p; l += kSfacThreads)
       for (int c = 0; c < 7; ++c) tv[c] += ld_coh(a.terms + (int64_t)l * 8 + c);
   }
   virial_energy(tv, tabs, sh_vs, sbs, a.coulomb, a.p, a.self_energy, a.virial6, a.energy);
-  if (tid == 0 && a.Y > 1) a.cnt[a.Y * a.NG + a.Y] = 0u;
+  if (tid == 0 && a.Y > 1) a.cnt[cnt_index(a, CNT_BATCH)] = 0u;
 }
 
 template <bool F64, int R>
@@ -894,7 +1046,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac_multi(const StepArgs* tab
   const int b = blockIdx.x;
   const int sys = find_system(bstart, nsys, b);
   if (threadIdx.x == 0) sa = tab[sys];
-  __syncthreads();
+  lds_barrier();
   const int local = b - bstart[sys];
   const int xs = sa.X + (sa.predraw ? 1 : 0);
   sfac_body<F64, R>(sa, local % xs, local / xs, lds_raw);
@@ -949,6 +1101,52 @@ constexpr int kForceMaxWaves = 8;
 constexpr int kForceRedBytes = kForceMaxWaves * kWave * 16 + 512 * 16;
 static_assert(kForceRedBytes >= kForceMaxWaves * kWave * 3 * 8, "cross-wave sums must fit");
 
+// Force sums of RP particles per lane over the frequencies [l0, l1) of the
+// constants in LDS, FP32 path: h += sin(2 pi (arg(rho)/(2 pi) - f)) c |rho| k,
+// which is c Im(exp(-i 2 pi f) rho) k (eq. (appforce)), one sine per pair.
+template <int RP>
+__device__ __forceinline__ void force_slice32(const FCoef32* sc, int l0, int l1,
+                                              const float (&shx)[RP], const float (&shy)[RP],
+                                              const float (&shz)[RP], const float (&slx)[RP],
+                                              const float (&sly)[RP], const float (&slz)[RP],
+                                              float (&hx)[RP], float (&hy)[RP], float (&hz)[RP]) {
+#pragma unroll 2
+  for (int l = l0; l < l1; ++l) {
+    const FCoef32 c = sc[l];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx[r], shy[r], shz[r], slx[r], sly[r],
+                                slz[r]);
+      const float sg = __builtin_amdgcn_sinf(c.phi - f);
+      hx[r] = fmaf(sg, c.ak[0], hx[r]);
+      hy[r] = fmaf(sg, c.ak[1], hy[r]);
+      hz[r] = fmaf(sg, c.ak[2], hz[r]);
+    }
+  }
+}
+
+// FP64 path: g += (cos(k.r) c Im rho - sin(k.r) c Re rho) k.
+template <int RP>
+__device__ __forceinline__ void force_slice64(const FCoef64* sc, int l0, int l1, const double2* sctab,
+                                              const double (&sx)[RP], const double (&sy)[RP],
+                                              const double (&sz)[RP], double (&gx)[RP],
+                                              double (&gy)[RP], double (&gz)[RP]) {
+  for (int l = l0; l < l1; ++l) {
+    const FCoef64 c = sc[l];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const double t = c.m[0] * sx[r] + c.m[1] * sy[r] + c.m[2] * sz[r];
+      const double f = t - rint(t);
+      double sn, cs;
+      sincos2pi(f, sctab, sn, cs);
+      const double gg = cs * c.cB - sn * c.cA;
+      gx[r] = fma(gg, c.k[0], gx[r]);
+      gy[r] = fma(gg, c.k[1], gy[r]);
+      gz[r] = fma(gg, c.k[2], gz[r]);
+    }
+  }
+}
+
 template <bool F64, int RP>
 __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, const int nbx) {
   using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
@@ -971,7 +1169,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
 
   if (extra) {
     if (tid == 0) sbs = *a.bs;
-    __syncthreads();
+    lds_barrier();
     block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
     double tv[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int l = tid; l < a.p; l += blockDim.x) {
@@ -981,7 +1179,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       FCoef64 f;
       FCoef32 h;
       double tl[7];
-      freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.p, f, h, tl);
+      freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.pf, f, h, tl);
       for (int c = 0; c < 7; ++c) tv[c] += tl[c];
     }
     virial_energy(tv, reinterpret_cast<double*>(scoef), sh_vs, sbs, a.coulomb, a.p,
@@ -1006,15 +1204,14 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       FCoef64 f;
       FCoef32 h;
       double tl[7];
-      freq_consts(mi, srho[l], sbs, a.alpha, a.coulomb, a.p, f, h, tl);
+      freq_consts(mi, srho[l], sbs, a.alpha, a.coulomb, a.pf, f, h, tl);
       if (F64) reinterpret_cast<FCoef64*>(scoef)[l] = f;
       else reinterpret_cast<FCoef32*>(scoef)[l] = h;
     }
   } else {
     if (tid == 0) sbs = *a.bs;
   }
-  __syncthreads();
-  const double ix = sbs.inv_l[0], iy = sbs.inv_l[1], iz = sbs.inv_l[2];
+  lds_barrier();
   const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)
                           : reinterpret_cast<const Coef*>(a.fc32);
   double gx[RP], gy[RP], gz[RP];
@@ -1023,65 +1220,36 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
 #pragma unroll
   for (int r = 0; r < RP; ++r) {
     gx[r] = gy[r] = gz[r] = 0.0;
+    reduce_pos(sbs, xi[r], yi[r], zi[r], sx[r], sy[r], sz[r]);
     if (!F64) {
-      split_coord(xi[r], ix, shx[r], slx[r]);
-      split_coord(yi[r], iy, shy[r], sly[r]);
-      split_coord(zi[r], iz, shz[r], slz[r]);
-    } else {
-      sx[r] = xi[r] * ix; sy[r] = yi[r] * iy; sz[r] = zi[r] * iz;
-      sx[r] -= floor(sx[r]); sy[r] -= floor(sy[r]); sz[r] -= floor(sz[r]);
+      split_coord(sx[r], shx[r], slx[r]);
+      split_coord(sy[r], shy[r], sly[r]);
+      split_coord(sz[r], shz[r], slz[r]);
     }
   }
   float hx[RP], hy[RP], hz[RP];
 #pragma unroll
   for (int r = 0; r < RP; ++r) hx[r] = hy[r] = hz[r] = 0.f;
-  const int nchunk = a.k2reduce ? 1 : (a.p + kChunk - 1) / kChunk;
+  const int nchunk = a.k2reduce ? 1 : (a.pf + kChunk - 1) / kChunk;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int cb = ch * kChunk;
-    const int cnt = min(kChunk, a.p - cb);
+    const int cnt = min(kChunk, a.pf - cb);
     if (!a.k2reduce) {
-      __syncthreads();
+      lds_barrier();
       const int nvec = (int)((size_t)cnt * sizeof(Coef) / 16);
       const uint4* src = reinterpret_cast<const uint4*>(gcoef + cb);
       uint4* dst = reinterpret_cast<uint4*>(scoef);
       for (int v = tid; v < nvec; v += blockDim.x) dst[v] = src[v];
-      __syncthreads();
+      lds_barrier();
     }
     const int per = (cnt + KS - 1) / KS;
     const int l0 = min(cnt, ks * per), l1 = min(cnt, l0 + per);
-    if (!F64) {
-      const FCoef32* sc = reinterpret_cast<const FCoef32*>(scoef);
-#pragma unroll 2
-      for (int l = l0; l < l1; ++l) {
-        const FCoef32 c = sc[l];
-#pragma unroll
-        for (int r = 0; r < RP; ++r) {
-          const float f = phase_rev(c.m[0], c.m[1], c.m[2], shx[r], shy[r], shz[r], slx[r],
-                                    sly[r], slz[r]);
-          // c Im(exp(-i 2 pi f) rho) k = sin(2 pi (arg(rho)/(2 pi) - f)) c |rho| k
-          const float sg = __builtin_amdgcn_sinf(c.phi - f);
-          hx[r] = fmaf(sg, c.ak[0], hx[r]);
-          hy[r] = fmaf(sg, c.ak[1], hy[r]);
-          hz[r] = fmaf(sg, c.ak[2], hz[r]);
-        }
-      }
-    } else {
-      const FCoef64* sc = reinterpret_cast<const FCoef64*>(scoef);
-      for (int l = l0; l < l1; ++l) {
-        const FCoef64 c = sc[l];
-#pragma unroll
-        for (int r = 0; r < RP; ++r) {
-          const double t = c.m[0] * sx[r] + c.m[1] * sy[r] + c.m[2] * sz[r];
-          const double f = t - rint(t);
-          double sn, cs;
-          sincos2pi(f, sctab, sn, cs);
-          const double gg = cs * c.cB - sn * c.cA;
-          gx[r] = fma(gg, c.k[0], gx[r]);
-          gy[r] = fma(gg, c.k[1], gy[r]);
-          gz[r] = fma(gg, c.k[2], gz[r]);
-        }
-      }
-    }
+    if (!F64)
+      force_slice32<RP>(reinterpret_cast<const FCoef32*>(scoef), l0, l1, shx, shy, shz, slx, sly,
+                        slz, hx, hy, hz);
+    else
+      force_slice64<RP>(reinterpret_cast<const FCoef64*>(scoef), l0, l1, sctab, sx, sy, sz, gx,
+                        gy, gz);
     if (!F64) {
       // fold the chunk's FP32 sums into FP64 (chunks of up to 1024 terms)
 #pragma unroll
@@ -1092,7 +1260,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
     }
   }
   // cross-wave (k-slice) sums, fixed order, then -q_i times the sum
-  __syncthreads();                          // scratch / srho in red_raw are dead
+  lds_barrier();                          // scratch / srho in red_raw are dead
   float* redf = reinterpret_cast<float*>(red_raw);
   double* redd = reinterpret_cast<double*>(red_raw);
 #pragma unroll
@@ -1101,7 +1269,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
     if (F64) { redd[3 * idx] = gx[r]; redd[3 * idx + 1] = gy[r]; redd[3 * idx + 2] = gz[r]; }
     else { redf[3 * idx] = (float)gx[r]; redf[3 * idx + 1] = (float)gy[r]; redf[3 * idx + 2] = (float)gz[r]; }
   }
-  __syncthreads();
+  lds_barrier();
   if (ks == 0) {
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
@@ -1132,7 +1300,7 @@ __global__ void __launch_bounds__(1024) k_force_multi(const StepArgs* tab, const
   const int b = blockIdx.x;
   const int sys = find_system(bstart, nsys, b);
   if (threadIdx.x == 0) sa = tab[sys];
-  __syncthreads();
+  lds_barrier();
   force_body<F64, RP>(sa, b - bstart[sys], bstart[sys + 1] - bstart[sys]);
 }
 
@@ -1162,6 +1330,387 @@ hipError_t launch_force_multi(int precision, int threads, const StepArgs* d_tab,
     hipLaunchKernelGGL((k_force_multi<true, 1>), grid, block, 0, s, d_tab, d_bstart, nsys);
   else
     hipLaunchKernelGGL((k_force_multi<false, 2>), grid, block, 0, s, d_tab, d_bstart, nsys);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// k_step: the whole Fourier-space step of one system in ONE launch, for
+// systems whose particle chunks fit one LDS tile and whose batch fits one
+// block (every block of the grid must be resident at once, see below).  Its
+// plan has its own chunks: up to 512 particles, about 64 of them.  Per block:
+//   1. its chunk's particles in LDS (split or reduced coordinates and FP64
+//      charges, kept to the end), the cell tables and the batch in LDS, as
+//      k_sfac builds them (section 4.2 eq. (S), (psf), (probexpression));
+//   2. the chunk's rho partial (eq. (U1fourier)) -> partial[x], then one
+//      count on the ready word;
+//   3. once all X partials are in, every block sums the X rows in chunk
+//      order (so every block holds the same rho, bit for bit) and forms the
+//      force constants in LDS; block 0 also writes rho, the batch, the
+//      constants, the virial tensor and the energy (eq. (apppress));
+//   4. the forces of its particles (eq. (appforce)) from the LDS copies: no
+//      second launch, no reload of positions, one grid-wide wait.
+// Counters (zero between launches, each on its own line, cnt_index): ready
+// (one count per block), done (blocks past the wait; the last one resets
+// ready and itself), and the error word of the bounded wait (a block that
+// gives up sets it and skips its forces).
+// Residency: the grid is at most the number of blocks the device holds at
+// once (checked by the host against the occupancy of this kernel); a plain
+// launch is used (a cooperative launch measured ~20 us of runtime overhead
+// per step here).  Blocks that would not get a compute unit while others
+// wait (another application holding the device) make the waits give up:
+// an error, not a hang.
+
+constexpr uint32_t kSpinCap = 1u << 22;      // polls (~0.2 s) before a wait gives up
+
+// LDS of k_step: particle tile | FP64 charges | batch | tables, then rho and
+// the force constants | scratch (block partial, row sums, virial summands,
+// cross-wave force sums)
+constexpr size_t kStepTile = (size_t)kTile * 32;
+constexpr size_t kStepQ = (size_t)kTile * 8;
+constexpr size_t kStepRed = (size_t)7 * kSfacThreads * 8;
+__host__ __device__ static size_t step_sm_bytes(const StepArgs& a) {
+  return ((size_t)a.Ppad * 3 * sizeof(int) + 15) / 16 * 16;
+}
+__host__ __device__ static size_t step_r2_bytes(const StepArgs& a) {
+  const int cap = a.mcap[0] + a.mcap[1] + a.mcap[2];
+  const size_t tab = ((size_t)(4 * cap + 3) * sizeof(double) + 15) / 16 * 16;
+  const size_t rc = (size_t)a.Ppad * sizeof(double2) + (size_t)a.Ppad * sizeof(FCoef64);
+  return tab > rc ? tab : rc;
+}
+size_t step_lds_bytes(const StepArgs& a) {
+  return kStepTile + kStepQ + step_sm_bytes(a) + step_r2_bytes(a) + kStepRed;
+}
+
+// Thread 0 polls *c (coherent loads) until it reaches target; false if the
+// bounded wait gave up.  Block-uniform result; reached by every thread.
+__device__ __forceinline__ bool wait_count(uint32_t* c, uint32_t target, int* sh_flag) {
+  if (threadIdx.x == 0) {
+    int ok = 0;
+    for (uint32_t it = 0; it < kSpinCap; ++it) {
+      if (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *sh_flag = ok;
+  }
+  lds_barrier();
+  return *sh_flag != 0;
+}
+
+// Every thread's coherent stores complete (waitcnt), then one increment of
+// *c: whoever sees the new count may read them.
+__device__ __forceinline__ void publish(uint32_t* c) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    (void)__hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool F64, int R>
+__global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
+  using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BoxState sbs;
+  __shared__ TriCell stc;
+  __shared__ double sh_T[3];
+  __shared__ int sh_flag;
+  __shared__ double sh_vs[7][8];
+  __shared__ double2 sctab[F64 ? kSinCosTab : 1];
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int x = blockIdx.x;
+  const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;   // FB = Ppad >= p
+  if (F64) fill_sincos_tab(sctab);          // read after the barriers below
+  const TriCell* tc = stage_tri(a, &stc);
+  unsigned char* tile = lds_raw;
+  double* qd = reinterpret_cast<double*>(lds_raw + kStepTile);
+  int* sm = reinterpret_cast<int*>(lds_raw + kStepTile + kStepQ);
+  unsigned char* r2 = lds_raw + kStepTile + kStepQ + step_sm_bytes(a);
+  double* tabs = reinterpret_cast<double*>(r2);
+  double2* srho = reinterpret_cast<double2*>(r2);
+  Coef* scoef = reinterpret_cast<Coef*>(r2 + (size_t)a.Ppad * sizeof(double2));
+  unsigned char* red_raw = r2 + step_r2_bytes(a);
+  double2* red2 = reinterpret_cast<double2*>(red_raw);
+  double* redd = reinterpret_cast<double*>(red_raw);
+  float* redf = reinterpret_cast<float*>(red_raw);
+
+  // ---- 1. the chunk's particles: loads issued now, used after the tables
+  const int64_t c0 = (int64_t)x * a.chunk;
+  const int cnt = (int)min((int64_t)a.chunk, a.n - c0);        // 1 .. kTile (plan)
+  double px = 0.0, py = 0.0, pz = 0.0, pq = 0.0;
+  if (tid < cnt) {
+    px = a.x[c0 + tid]; py = a.y[c0 + tid]; pz = a.z[c0 + tid]; pq = a.q[c0 + tid];
+  }
+  if (a.sample || a.box_src != BOX_COMMITTED) {
+    double l[3];
+    box_source(a, l);
+    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    if (x == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
+      commit_cell(sbs, a.bs);
+    }
+  } else {
+    if (tid == 0) sbs = *a.bs;
+    lds_barrier();
+  }
+  for (int l = tid; l < FB; l += kSfacThreads) {
+    int mv[3] = {0, 0, 0};
+    if (l < a.p) {
+      if (a.sample) {
+        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, l, mv);
+        if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
+      } else {
+        mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
+      }
+    }
+    sm[3 * l] = mv[0]; sm[3 * l + 1] = mv[1]; sm[3 * l + 2] = mv[2];
+  }
+  // the whole tile, zero beyond the chunk (thread j owns entry j: blockDim
+  // = kTile); the structure-factor loop reads the first cntp entries
+  const int cntp = F64 ? (cnt + SUB - 1) / SUB * SUB
+                       : (cnt + SUB * kKahan - 1) / (SUB * kKahan) * (SUB * kKahan);
+  static_assert(kSfacThreads == kTile, "one tile entry per thread");
+  {
+    if (!F64) {
+      float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (tid < cnt) {
+        double sx, sy, sz;
+        reduce_pos(sbs, px, py, pz, sx, sy, sz);
+        split_coord(sx, u.x, v.x);
+        split_coord(sy, u.y, v.y);
+        split_coord(sz, u.z, v.z);
+        u.w = (float)pq;
+      }
+      reinterpret_cast<float4*>(tile)[tid] = u;
+      reinterpret_cast<float4*>(tile)[kTile + tid] = v;
+    } else {
+      double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+      if (tid < cnt) {
+        double sx, sy, sz;
+        reduce_pos(sbs, px, py, pz, sx, sy, sz);
+        u = make_double2(sx, sy);
+        v = make_double2(sz, pq);
+      }
+      reinterpret_cast<double2*>(tile)[tid] = u;
+      reinterpret_cast<double2*>(tile)[kTile + tid] = v;
+    }
+    qd[tid] = tid < cnt ? pq : 0.0;
+  }
+  lds_barrier();
+
+  // ---- 2. rho partial of the chunk: lane owns frequencies kg*64R + r*64 + lane
+  const int kg = wave % KB, sub = wave / KB;
+  double2 part[R];
+  if (!F64) {
+    float mx[R], my[R], mz[R], SA[R], CA[R], SB[R], CB[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = kg * kWave * R + r * kWave + lane;
+      mx[r] = (float)sm[3 * sl]; my[r] = (float)sm[3 * sl + 1]; mz[r] = (float)sm[3 * sl + 2];
+      SA[r] = CA[r] = SB[r] = CB[r] = 0.f;
+    }
+    const float4* tA = reinterpret_cast<const float4*>(tile);
+    sfac_tile32<R>(tA, tA + kTile, cntp, sub, SUB, mx, my, mz, SA, CA, SB, CB);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      part[r] = make_double2((double)SA[r] - (double)CA[r], (double)SB[r] - (double)CB[r]);
+  } else {
+    double mx[R], my[R], mz[R], A[R], B[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = kg * kWave * R + r * kWave + lane;
+      mx[r] = (double)sm[3 * sl]; my[r] = (double)sm[3 * sl + 1]; mz[r] = (double)sm[3 * sl + 2];
+      A[r] = B[r] = 0.0;
+    }
+    const double2* tA = reinterpret_cast<const double2*>(tile);
+    sfac_tile64<R>(tA, tA + kTile, cntp, sub, SUB, sctab, mx, my, mz, A, B);
+#pragma unroll
+    for (int r = 0; r < R; ++r) part[r] = make_double2(A[r], B[r]);
+  }
+  store_block_partial<R>(part, red2, KB, SUB, a.partial + (int64_t)x * a.Ppad);
+
+  // ---- 3. every block's partial stored: one count per block; then every
+  // block sums all X chunk rows itself, in chunk order (each block gets the
+  // same rho, bit for bit), and forms the force constants in LDS
+  uint32_t* ready = a.cnt + cnt_index(a, CNT_READY);
+  uint32_t* done = a.cnt + cnt_index(a, CNT_DONE);
+  uint32_t* errw = a.cnt + cnt_index(a, CNT_ERR);
+  publish(ready);
+  const bool ok = wait_count(ready, (uint32_t)a.X, &sh_flag);
+  if (tid == 0) {
+    if (!ok) __hip_atomic_fetch_or(errw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        (uint32_t)a.X - 1u) {
+      __hip_atomic_store(ready, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (!ok) return;
+  block_sum_rows<true, 16>(a.partial, a.Ppad, a.X, a.Ppad, srho, false, red2);
+  double tv[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int l = tid; l < a.p; l += kSfacThreads) {
+    const int mi[3] = {sm[3 * l], sm[3 * l + 1], sm[3 * l + 2]};
+    const double2 r = srho[l];
+    FCoef64 f;
+    FCoef32 h;
+    double tl[7];
+    freq_consts(mi, r, sbs, a.alpha, a.coulomb, a.pf, f, h, tl);
+    if (F64) reinterpret_cast<FCoef64*>(scoef)[l] = f;
+    else reinterpret_cast<FCoef32*>(scoef)[l] = h;
+    if (x == 0) {
+      a.rho[l] = r;
+      a.fc64[l] = f;
+      a.fc32[l] = h;
+      for (int c = 0; c < 7; ++c) tv[c] += tl[c];
+    }
+  }
+  // ---- 4. block 0: the virial tensor and the energy (the self term from the
+  // host, or from the charge sums on the device)
+  if (x == 0) {
+    const double self = a.qsum_dev ? -a.coulomb * a.qsum_dev[2] * sqrt(a.alpha / M_PI)
+                                   : a.self_energy;
+    virial_energy(tv, redd, sh_vs, sbs, a.coulomb, a.p, self, a.virial6, a.energy);
+  }
+  lds_barrier();
+
+  // ---- 5. forces: KS waves split the batch, 8/KS particle waves side by
+  // side, rounds of (8/KS) x 64 x RP particles (one round when the plan's KS
+  // is chosen for the chunk)
+  constexpr int RP = F64 ? 1 : 2;
+  const int KS = a.KS, PWp = kSfacWaves / KS;
+  const int ks = wave / PWp, pw = wave % PWp;
+  const int per = (a.pf + KS - 1) / KS;
+  const int l0 = min(a.pf, ks * per), l1 = min(a.pf, l0 + per);
+  const int rounds = (cnt + PWp * kWave * RP - 1) / (PWp * kWave * RP);
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int jbase = (rd * PWp + pw) * kWave * RP + lane;
+    double gx[RP], gy[RP], gz[RP];
+    float shx[RP], shy[RP], shz[RP], slx[RP], sly[RP], slz[RP];
+    double sx[RP], sy[RP], sz[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int j = min(jbase + r * kWave, kTile - 1);     // beyond cnt: a padding entry, not stored
+      gx[r] = gy[r] = gz[r] = 0.0;
+      if (!F64) {
+        const float4 u = reinterpret_cast<const float4*>(tile)[j];
+        const float4 v = reinterpret_cast<const float4*>(tile)[kTile + j];
+        shx[r] = u.x; shy[r] = u.y; shz[r] = u.z; slx[r] = v.x; sly[r] = v.y; slz[r] = v.z;
+      } else {
+        const double2 u = reinterpret_cast<const double2*>(tile)[j];
+        const double2 v = reinterpret_cast<const double2*>(tile)[kTile + j];
+        sx[r] = u.x; sy[r] = u.y; sz[r] = v.x;
+      }
+    }
+    if (!F64) {
+      float hx[RP], hy[RP], hz[RP];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) hx[r] = hy[r] = hz[r] = 0.f;
+      force_slice32<RP>(reinterpret_cast<const FCoef32*>(scoef), l0, l1, shx, shy, shz, slx, sly,
+                        slz, hx, hy, hz);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        gx[r] += (double)hx[r]; gy[r] += (double)hy[r]; gz[r] += (double)hz[r];
+      }
+    } else {
+      force_slice64<RP>(reinterpret_cast<const FCoef64*>(scoef), l0, l1, sctab, sx, sy, sz, gx, gy,
+                        gz);
+    }
+    // cross-wave sums in slice order, then -q_i times the sum
+    lds_barrier();                          // red is free (virial summands, last round)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int idx = (wave * RP + r) * kWave + lane;
+      if (F64) { redd[3 * idx] = gx[r]; redd[3 * idx + 1] = gy[r]; redd[3 * idx + 2] = gz[r]; }
+      else { redf[3 * idx] = (float)gx[r]; redf[3 * idx + 1] = (float)gy[r]; redf[3 * idx + 2] = (float)gz[r]; }
+    }
+    lds_barrier();
+    if (ks == 0) {
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int j = jbase + r * kWave;
+        if (j >= cnt) continue;
+        double sx2 = 0.0, sy2 = 0.0, sz2 = 0.0;
+        for (int k2 = 0; k2 < KS; ++k2) {
+          const int idx = ((k2 * PWp + pw) * RP + r) * kWave + lane;
+          if (F64) { sx2 += redd[3 * idx]; sy2 += redd[3 * idx + 1]; sz2 += redd[3 * idx + 2]; }
+          else { sx2 += redf[3 * idx]; sy2 += redf[3 * idx + 1]; sz2 += redf[3 * idx + 2]; }
+        }
+        const int64_t i = c0 + j;
+        const double qi = -qd[j];
+        if (a.accumulate) { a.fx[i] += qi * sx2; a.fy[i] += qi * sy2; a.fz[i] += qi * sz2; }
+        else { a.fx[i] = qi * sx2; a.fy[i] = qi * sy2; a.fz[i] = qi * sz2; }
+      }
+    }
+  }
+}
+
+bool step_supported(int precision, const StepArgs& a) {
+  return a.Y == 1 && a.Ppad <= 512 && a.chunk <= kTile && a.KS * a.PW == kSfacWaves &&
+         (precision == RBE_PREC_FP64 ? a.R == 1 : (a.R == 1 || a.R == 2 || a.R == 4));
+}
+
+template <bool F64, int R>
+static hipError_t step_occupancy(const StepArgs& a, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step<F64, R>, kSfacThreads,
+                                                      step_lds_bytes(a));
+}
+
+hipError_t step_max_blocks(int precision, const StepArgs& a, int* max_blocks) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (precision == RBE_PREC_FP64) e = step_occupancy<true, 1>(a, &per);
+  else if (a.R == 4) e = step_occupancy<false, 4>(a, &per);
+  else if (a.R == 2) e = step_occupancy<false, 2>(a, &per);
+  else e = step_occupancy<false, 1>(a, &per);
+  *max_blocks = cus * per;
+  return e;
+}
+
+hipError_t launch_step(int precision, const StepArgs& a, hipStream_t s) {
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  const dim3 grid(a.X), block(kSfacThreads);
+  const size_t lds = step_lds_bytes(a);
+  const void* fn;
+  if (precision == RBE_PREC_FP64) fn = reinterpret_cast<const void*>(&k_step<true, 1>);
+  else if (a.R == 4) fn = reinterpret_cast<const void*>(&k_step<false, 4>);
+  else if (a.R == 2) fn = reinterpret_cast<const void*>(&k_step<false, 2>);
+  else fn = reinterpret_cast<const void*>(&k_step<false, 1>);
+  return hipLaunchKernel(fn, grid, block, args, lds, s);
+}
+
+
+// ---------------------------------------------------------------------------
+// batch moments of the estimator (Proposition 1 on the device): per particle
+// and component the running sums of F* and F*^2 over batches, and of the
+// isotropic P2* = tr W/(3V) and its square (thread 0)
+
+__global__ void k_moments(const double* __restrict__ fx, const double* __restrict__ fy,
+                          const double* __restrict__ fz, const double* __restrict__ vir, double V,
+                          int64_t n, double* __restrict__ sum, double* __restrict__ sq,
+                          double* __restrict__ psum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double f[3] = {fx[i], fy[i], fz[i]};
+    for (int c = 0; c < 3; ++c) {
+      sum[c * n + i] += f[c];
+      sq[c * n + i] += f[c] * f[c];
+    }
+  }
+  if (i == 0) {
+    const double P2 = (vir[0] + vir[1] + vir[2]) / (3.0 * V);
+    psum[0] += P2;
+    psum[1] += P2 * P2;
+  }
+}
+
+hipError_t launch_moments(const double* fx, const double* fy, const double* fz, const double* vir,
+                          double V, int64_t n, double* sum, double* sq, double* psum,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_moments, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fx, fy, fz, vir,
+                     V, n, sum, sq, psum);
   return hipGetLastError();
 }
 

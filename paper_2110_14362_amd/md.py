@@ -19,7 +19,9 @@ class NPTSystem:
         real-space Lennard-Jones term; optional rigid = dict(first, count,
         d_oh, d_hh) for rigid 3-site molecules (whole, not split by the
         periodic boundary); optional skin (> 0: real-space neighbour lists);
-        optional sampler ('exact' or 'mh', with mh_iters moves per step).
+        optional sampler ('exact' or 'mh', with mh_iters moves per step);
+        optional fused (True: the Fourier step as one launch, False: two
+        launches, the default; see RBE.set_fused).
     """
 
     def __init__(self, sysd, md, precision="fp32", seed=0, system_id=0, momenta=None,
@@ -51,6 +53,8 @@ class NPTSystem:
                           stream=stream)
         if md.get("sampler", "exact") != "exact":
             self.kspace.set_sampler(md["sampler"], int(md.get("mh_iters", 1)))
+        if md.get("fused") is not None:
+            self.kspace.set_fused(1 if md["fused"] else 0)
         types = None
         if md.get("lj") is not None:
             types = torch.tensor(np.asarray(md["types"], dtype=np.int32), device=dev)

@@ -17,14 +17,27 @@ RBE_OK = 0
 RBE_ERR_CAPACITY = 6
 STATUS_NAMES = {0: "RBE_OK", 1: "RBE_ERR_ARG", 2: "RBE_ERR_ALLOC", 3: "RBE_ERR_DEVICE",
                 4: "RBE_ERR_STATE", 5: "RBE_ERR_NONNEUTRAL", 6: "RBE_ERR_CAPACITY"}
-BOX_MODES = {"iso": 0, "semiiso": 1, "aniso": 2}
+BOX_MODES = {"iso": 0, "semiiso": 1, "aniso": 2, "triclinic": 3}
+
+
+def _cell(box, box_mode):
+    """Host cell: 3 sides, or (lx, ly, lz, xy, xz, yz) for a triclinic cell."""
+    k = 6 if box_mode == "triclinic" else 3
+    v = [float(b) for b in box]
+    if len(v) != k:
+        raise ValueError("a %s cell takes %d numbers, got %d" % (box_mode, k, len(v)))
+    return (ctypes.c_double * k)(*v)
 SAMPLERS = {"exact": 0, "mh": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 # every symbol include/rbe.h declares
 EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev",
            "rbe_sample_k", "rbe_set_k", "rbe_get_k", "rbe_forces_pressure", "rbe_get_rho",
-           "rbe_get_box_info", "rbe_get_plan", "rbe_check", "rbe_timing_enable", "rbe_timing_read",
+           "rbe_get_box_info", "rbe_get_plan", "rbe_set_fused", "rbe_variance_probe",
+           "rbe_batch_size_for_variance", "rbe_measure_issue_rates",
+           "rbe_check",
+           "rbe_timing_enable",
+           "rbe_timing_read",
            "rbe_destroy", "rbe_last_error", "rbe_version",
            "rbe_real_init", "rbe_real_set_box", "rbe_real_set_box_dev", "rbe_real_forces",
            "rbe_real_check", "rbe_real_destroy",
@@ -36,7 +49,7 @@ EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev
            "rbe_batch_sync", "rbe_batch_read", "rbe_batch_check", "rbe_batch_slot_step",
            "rbe_batch_release", "rbe_batch_info", "rbe_batch_destroy",
            "rbe_batch_timing_enable", "rbe_batch_timing_read"]
-KERNEL_KINDS = ["tables", "sample", "sfac", "force"]
+KERNEL_KINDS = ["tables", "sample", "sfac", "force", "step"]
 
 
 class RBEError(RuntimeError):
@@ -47,7 +60,7 @@ class RBEError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("box_mode", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("p_pressure", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("coulomb", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("system_id", ctypes.c_uint64)]
 
@@ -110,6 +123,10 @@ def load_library(path=LIB_PATH):
         "rbe_get_box_info": [vp, dp],
         "rbe_check": [vp],
         "rbe_get_plan": [vp, ctypes.POINTER(i32)],
+        "rbe_set_fused": [vp, i32],
+        "rbe_measure_issue_rates": [dp],
+        "rbe_variance_probe": [vp, vp, vp, vp, i32, ctypes.c_uint64, dp, dp],
+        "rbe_batch_size_for_variance": [i32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32)],
         "rbe_timing_enable": [vp, i32],
         "rbe_timing_read": [vp, dp, ctypes.POINTER(i32)],
         "rbe_real_init": [ctypes.POINTER(RealConfig), vp, vp, dp, dp, vp, ctypes.POINTER(vp)],
@@ -194,20 +211,24 @@ class RBE:
     """One system's Fourier-space RBE context (rbe_init ... rbe_destroy)."""
 
     def __init__(self, q, box, p, alpha, coulomb=1.0, precision="fp32", box_mode="iso",
-                 seed=0, system_id=0, stream=None):
+                 seed=0, system_id=0, stream=None, p_pressure=0):
+        """p: force batch size; p_pressure: pressure batch size p~ >= p (0: p)."""
         lib = load_library()
         n = int(q.numel())
         cfg = Config(n=n, p=int(p), box_mode=BOX_MODES[box_mode],
-                     precision=PRECISIONS[precision], reserved=0, alpha=float(alpha),
+                     precision=PRECISIONS[precision], p_pressure=int(p_pressure),
+                     alpha=float(alpha),
                      coulomb=float(coulomb), seed=int(seed) & (2**64 - 1),
                      system_id=int(system_id) & (2**64 - 1))
-        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
+        boxarr = _cell(box, box_mode)
         ctx = ctypes.c_void_p()
         _check(lib.rbe_init(ctypes.byref(cfg), _dptr(q, "q", n), boxarr,
                             _stream_handle(stream), ctypes.byref(ctx)))
         self._ctx = ctx
         self.n = n
         self.p = int(p)
+        self.p_batch = max(int(p), int(p_pressure))      # frequencies drawn per step
+        self.box_mode = box_mode
         self.precision = precision
 
     def close(self):
@@ -225,8 +246,7 @@ class RBE:
         _check(_lib.rbe_set_stream(self._ctx, _stream_handle(stream)))
 
     def rescale_box(self, box):
-        boxarr = (ctypes.c_double * 3)(*[float(b) for b in box])
-        _check(_lib.rbe_rescale_box(self._ctx, boxarr))
+        _check(_lib.rbe_rescale_box(self._ctx, _cell(box, self.box_mode)))
 
     def rescale_box_dev(self, d_box):
         _check(_lib.rbe_rescale_box_dev(self._ctx, _dptr(d_box, "box", 3)))
@@ -254,7 +274,7 @@ class RBE:
                               m.shape[0]))
 
     def get_k(self):
-        out = np.zeros((self.p, 3), dtype=np.int32)
+        out = np.zeros((self.p_batch, 3), dtype=np.int32)
         _check(_lib.rbe_get_k(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
 
@@ -267,7 +287,7 @@ class RBE:
             _dptr(energy, "energy", 1) if energy is not None else None))
 
     def get_rho(self):
-        out = np.zeros(2 * self.p, dtype=np.float64)
+        out = np.zeros(2 * self.p_batch, dtype=np.float64)
         _check(_lib.rbe_get_rho(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out[0::2] + 1j * out[1::2]
 
@@ -281,10 +301,36 @@ class RBE:
         _check(_lib.rbe_check(self._ctx))
 
     def plan(self):
-        h = np.zeros(12, dtype=np.int32)
+        h = np.zeros(16, dtype=np.int32)
         _check(_lib.rbe_get_plan(self._ctx, h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
-        keys = ["X", "Y", "KB", "R", "GX", "NG", "chunk", "Ppad", "KS", "PW", "k2reduce"]
+        keys = ["X", "Y", "KB", "R", "GX", "NG", "chunk", "Ppad", "KS", "PW", "k2reduce", "fused",
+                "fused_X", "fused_chunk", "fused_KS"]
         return {k: int(h[i]) for i, k in enumerate(keys)}
+
+    def variance_probe(self, x, y, z, batches, first_step=0, per_particle=False):
+        """Proposition 1 on the device (rbe_variance_probe): dict of the total
+        force variance (sum over particles and components), the variance of
+        P2*, sum |mean F|^2, mean P2*, and optionally the per-particle force
+        variances."""
+        n = self.n
+        out = np.zeros(4, dtype=np.float64)
+        var = np.zeros(n, dtype=np.float64) if per_particle else None
+        pd = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.rbe_variance_probe(self._ctx, _dptr(x, "x", n), _dptr(y, "y", n),
+                                       _dptr(z, "z", n), int(batches),
+                                       ctypes.c_uint64(int(first_step) & (2**64 - 1)),
+                                       out.ctypes.data_as(pd),
+                                       var.ctypes.data_as(pd) if var is not None else None))
+        r = dict(force_var=float(out[0]), pressure_var=float(out[1]), force_mean2=float(out[2]),
+                 pressure_mean=float(out[3]))
+        if var is not None:
+            r["force_var_particles"] = var
+        return r
+
+    def set_fused(self, enable):
+        """1: the whole step as one launch where the plan allows
+        it (default); 0: two launches.  Same results either way."""
+        _check(_lib.rbe_set_fused(self._ctx, int(enable)))
 
     def timing_enable(self, max_launches):
         _check(_lib.rbe_timing_enable(self._ctx, int(max_launches)))
@@ -591,3 +637,22 @@ class Batch:
         out = {k: ms[i] for i, k in enumerate(self.BATCH_KINDS)}
         out.update(steps=steps.value, np=npairs.value)
         return out
+
+
+def batch_size_for_variance(p, var, target):
+    """rbe_batch_size_for_variance: the batch size giving `target` variance by
+    Proposition 1's 1/p law, from a variance `var` measured at batch size p."""
+    lib = load_library()
+    out = ctypes.c_int32()
+    _check(lib.rbe_batch_size_for_variance(int(p), float(var), float(target), ctypes.byref(out)))
+    return int(out.value)
+
+
+def measure_issue_rates():
+    """rbe_measure_issue_rates: the device's own issue rates (per second) of
+    FP32 sines, FP32 FMAs, FP64 FMAs, and sines with four FMAs beside each."""
+    lib = load_library()
+    out = np.zeros(5, dtype=np.float64)
+    _check(lib.rbe_measure_issue_rates(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return dict(sin32=float(out[0]), fma32=float(out[1]), fma64=float(out[2]),
+                sin32_with_4fma=float(out[3]), compute_units=int(out[4]))

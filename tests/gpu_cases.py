@@ -12,14 +12,17 @@ def to_dev(a, dev):
 
 
 def gpu_eval(sysd, dev, precision, p=None, m=None, step=None, seed=11, system_id=0,
-             box_mode="iso", accumulate=False, f0=None, shift=None):
+             box_mode="iso", accumulate=False, f0=None, shift=None, p_pressure=0, fused=None):
     import torch
     from paper_2110_14362_amd.rbe import RBE
     pos = sysd["pos"] if shift is None else sysd["pos"] + shift
     p = int(p if p is not None else (len(m) if m is not None else sysd["p"]))
     q = to_dev(sysd["q"], dev)
     ctx = RBE(q, sysd["box"], p, sysd["alpha"], coulomb=sysd.get("coulomb", 1.0),
-              precision=precision, box_mode=box_mode, seed=seed, system_id=system_id)
+              precision=precision, box_mode=box_mode, seed=seed, system_id=system_id,
+              p_pressure=p_pressure)
+    if fused is not None:
+        ctx.set_fused(fused)
     if m is not None:
         ctx.set_k(m)
     else:

@@ -43,7 +43,7 @@ def _init(cfg, box=(10.0, 10.0, 10.0)):
 
 
 def good_cfg(**kw):
-    c = dict(n=10, p=4, box_mode=0, precision=1, reserved=0, alpha=0.09, coulomb=1.0,
+    c = dict(n=10, p=4, box_mode=0, precision=1, p_pressure=0, alpha=0.09, coulomb=1.0,
              seed=1, system_id=0)
     c.update(kw)
     return rbe.Config(**c)
@@ -52,7 +52,8 @@ def good_cfg(**kw):
 @pytest.mark.parametrize("field,value,msg", [("n", 0, "n ="), ("p", 0, "p ="), ("p", 70000, "p ="),
                                              ("alpha", -1.0, "alpha"), ("coulomb", 0.0, "coulomb"),
                                              ("box_mode", 7, "box_mode"), ("precision", 5, "precision"),
-                                             ("reserved", 1, "reserved")])
+                                             ("p_pressure", 3, "p_pressure"),
+                                             ("p_pressure", 70000, "p_pressure")])
 def test_init_rejects_bad_config(field, value, msg):
     st, err = _init(good_cfg(**{field: value}))
     assert st == 1 and msg in err

@@ -373,3 +373,103 @@ def test_consecutive_steps(gpu, case, precision, p, fixed_cell):
         e = errors(g, o, s["q"])
         report("%s p=%d step %d %s" % (case, p, step, precision), e)
         assert_parity(e, precision, step)
+
+
+# ------------------------------------------------------------------ one launch vs two
+
+def _steps(s, dev, precision, fused, steps, p):
+    import torch
+    from paper_2110_14362_amd.rbe import RBE
+    q = torch.tensor(s["q"], dtype=torch.float64, device=dev)
+    mode = "semiiso" if s["box"][0] != s["box"][2] else "iso"
+    ctx = RBE(q, s["box"], p, s["alpha"], coulomb=s.get("coulomb", 1.0), precision=precision,
+              box_mode=mode, seed=31, system_id=2)
+    ctx.set_fused(fused)
+    plan = ctx.plan()
+    x, y, z = (torch.tensor(s["pos"][:, a], dtype=torch.float64, device=dev) for a in range(3))
+    out = []
+    for step in steps:
+        box = np.asarray(s["box"]) * (1.0 + 1e-4 * step)      # a new cell every step
+        ctx.rescale_box(box)
+        ctx.sample_k(step)
+        f = [torch.zeros_like(x) for _ in range(3)]
+        vir = torch.zeros(6, dtype=torch.float64, device=dev)
+        en = torch.zeros(1, dtype=torch.float64, device=dev)
+        ctx.forces_pressure(x, y, z, *f, virial6=vir, energy=en)
+        torch.cuda.synchronize()
+        out.append(dict(F=np.stack([t.cpu().numpy() for t in f], 1), W=vir.cpu().numpy(),
+                        U=en.cpu().numpy(), rho=ctx.get_rho(), m=ctx.get_k()))
+    ctx.check()
+    ctx.close()
+    return plan, out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case,p", [("water_30k", 100), ("electrolyte_1k", 100), ("water_3k", 500),
+                                    ("ragged_17", 65), ("ragged_30001", 257), ("slab_36k", 200)])
+def test_single_launch_and_two_launches(gpu, case, p, precision):
+    # the single launch (rbe_set_fused(1), its own chunks and one grid-wide
+    # wait) and the two launches draw the same batches and both match the
+    # oracle, over steps with a new cell and a new batch each time; the
+    # single launch is bitwise reproducible
+    from oracle import rbe as orbe
+    if case.startswith("ragged"):
+        n = int(case.split("_")[1])
+        s = workloads.random_neutral(n + (n % 2), (23.0, 23.0, 23.0), seed=n)
+        s.update(alpha=0.09, coulomb=1.0)
+    elif case == "water_3k":
+        s = small_water()
+    else:
+        s = workloads.make(case)
+    steps = (0, 1, 5)
+    plan1, one = _steps(s, gpu, precision, 1, steps, p)
+    plan2, two = _steps(s, gpu, precision, 0, steps, p)
+    _, again = _steps(s, gpu, precision, 1, steps, p)
+    print("%s p=%d %s: plan %s" % (case, p, precision, plan1), flush=True)
+    assert plan2["fused"] == 0
+    if case in ("water_30k", "electrolyte_1k", "water_3k", "ragged_17"):
+        assert plan1["fused"] == 1
+    for step, a, b, c in zip(steps, one, two, again):
+        np.testing.assert_array_equal(a["m"], b["m"])
+        for key in ("F", "W", "U", "rho"):
+            np.testing.assert_array_equal(a[key], c[key], err_msg=key)
+        box = np.asarray(s["box"]) * (1.0 + 1e-4 * step)
+        S = osamp.box_tables(s["alpha"], box)["S"]
+        o = orbe.rbe_kspace(s["pos"], s["q"], box, s["alpha"], a["m"].astype(np.int64), S,
+                            coulomb=s.get("coulomb", 1.0))
+        for g in (a, b):
+            W6 = g["W"]
+            W = np.array([[W6[0], W6[3], W6[4]], [W6[3], W6[1], W6[5]], [W6[4], W6[5], W6[2]]])
+            e = errors(dict(forces=g["F"], virial=W, energy=float(g["U"][0]), rho=g["rho"]), o,
+                       s["q"])
+            assert_parity(e, precision, (case, step))
+
+
+# ------------------------------------------------------------------ p != p~
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("case,p,pp", [("water_3k", 40, 160), ("electrolyte_1k", 100, 300),
+                                       ("water_30k", 100, 400), ("ragged_701", 3, 700)])
+def test_split_force_pressure_batches(gpu, case, p, pp, precision, fused):
+    # a pressure batch of p~ draws whose first p serve the forces (the remark
+    # after eq. (apppress)): one draw of p~ frequencies, one rho pass, forces
+    # with weight S/p over the first p, virial and energy with S/p~ over all
+    from oracle import rbe as orbe
+    if case.startswith("ragged"):
+        s = workloads.random_neutral(702, (12.0, 12.0, 12.0), seed=7)
+        s.update(alpha=0.3, coulomb=1.0)
+    elif case == "water_3k":
+        s = small_water()
+    else:
+        s = workloads.make(case)
+    g = gpu_eval(s, gpu, precision, p=p, step=9, seed=5, system_id=1, p_pressure=pp,
+                 fused=fused)
+    m_o = osamp.sample_k(s["alpha"], s["box"], pp, seed=5, system_id=1, step=9)
+    assert g["m"].shape == (pp, 3) and np.array_equal(g["m"], m_o)
+    S = osamp.box_tables(s["alpha"], s["box"])["S"]
+    o = orbe.rbe_kspace_split(s["pos"], s["q"], s["box"], s["alpha"], m_o, S, p,
+                              coulomb=s.get("coulomb", 1.0))
+    e = errors(g, o, s["q"])
+    report("%s p=%d p~=%d %s fused=%d" % (case, p, pp, precision, fused), e)
+    assert_parity(e, precision)

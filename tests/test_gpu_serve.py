@@ -68,16 +68,28 @@ def test_alone_equals_mix_bitwise(gpu):
 
 
 def test_served_equals_one_system_api(gpu):
+    # the served runtime launches the Fourier step as two kernels; the
+    # one-system API in that form gives the same bits, and in its default
+    # single launch (another chunking, so another rounding) the same
+    # trajectory to FP32 rounding
     from paper_2110_14362_amd.md import NPTSystem
     r = request(3, 2500)
     steps = 4
     ref = run_alone(r, steps)
-    md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"])
-    sysg = NPTSystem(r.sysd, md, precision="fp32", seed=r.desc.seed, system_id=r.desc.system_id)
-    sysg.step(steps)
-    g = sysg.state()
-    np.testing.assert_array_equal(g["pos"], ref["pos"])
-    np.testing.assert_array_equal(g["mom"], ref["mom"])
+    out = {}
+    for fused in (False, True):
+        md = dict(r.md, types=r.sysd["types"], lj=r.sysd["lj"], fused=fused)
+        sysg = NPTSystem(r.sysd, md, precision="fp32", seed=r.desc.seed,
+                         system_id=r.desc.system_id)
+        sysg.step(steps)
+        out[fused] = sysg.state()
+    np.testing.assert_array_equal(out[False]["pos"], ref["pos"])
+    np.testing.assert_array_equal(out[False]["mom"], ref["mom"])
+    dr = np.abs(out[True]["pos"] - ref["pos"]).max()
+    dp = np.abs(out[True]["mom"] - ref["mom"]).max() / np.abs(ref["mom"]).max()
+    print("single launch vs two launches over %d NPT steps: max |dr| %.2e, rel |dp| %.2e"
+          % (steps, dr, dp), flush=True)
+    assert dr < 1e-6 and dp < 1e-4
 
 
 @pytest.mark.parametrize("kind,skin", [("ions", 0.0), ("water", 0.0), ("water", 1.0)])

@@ -34,7 +34,7 @@ def closed_forms(s, p):
     return var_f, F1, var_p, P2
 
 
-def gpu_moments(s, p, B, dev, system_id, precision="fp64"):
+def gpu_moments(s, p, B, dev, system_id, precision="fp64", p_pressure=0):
     """Sum and sum of squares of F* and P2* over B batches (steps 0..B-1),
     accumulated on the device."""
     import torch
@@ -42,7 +42,7 @@ def gpu_moments(s, p, B, dev, system_id, precision="fp64"):
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     n = len(s["q"])
     ctx = RBE(t(s["q"]), s["box"], p, ALPHA, box_mode="iso", precision=precision, seed=2021,
-              system_id=system_id)
+              system_id=system_id, p_pressure=p_pressure)
     x, y, z = (t(s["pos"][:, a]) for a in range(3))
     f = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
     vir = torch.zeros(6, dtype=torch.float64, device=dev)
@@ -85,18 +85,90 @@ def test_device_estimator_mean_and_variance(gpu, p):
 
 
 def test_separate_force_and_pressure_batches(gpu):
-    # p = 8 frequencies for the forces, p~ = 64 for the pressure, from two
-    # contexts with independent streams: each estimator keeps its own variance
+    # p = 8 frequencies for the forces, p~ = 64 for the pressure, in one
+    # context (one draw of 64 frequencies per step, forces from the first 8):
+    # each estimator keeps its own variance (Proposition 1 at its batch size)
     s = system()
     B = 3000
     var_f8, F1, _, _ = closed_forms(s, 8)
     _, _, var_p64, P2 = closed_forms(s, 64)
-    sf, sf2, _, _ = gpu_moments(s, 8, B, gpu, system_id=1008)
-    _, _, sp, sp2 = gpu_moments(s, 64, B, gpu, system_id=1064)
+    sf, sf2, sp, sp2 = gpu_moments(s, 8, B, gpu, system_id=1008, p_pressure=64)
     rf = ((sf2 / B - (sf / B) ** 2).sum(axis=1)).sum() / var_f8.sum()
     rp = (sp2 / B - (sp / B) ** 2) / var_p64
-    print("p=8 forces: variance emp/closed %.3f; p~=64 pressure: %.3f" % (rf, rp), flush=True)
+    zf = ((sf / B - F1) ** 2).sum() / (var_f8.sum() / B)
+    zp = (sp / B - P2) ** 2 / (var_p64 / B)
+    print("p=8 forces: variance emp/closed %.3f, mean z %.2f; p~=64 pressure: %.3f, mean z %.2f"
+          % (rf, zf, rp, zp), flush=True)
     assert abs(rf - 1.0) < 0.08 and abs(rp - 1.0) < 0.15
+    assert 0.3 < zf < 2.5 and zp < 16.0
+
+
+def _water_30k_closed_forms(s, rows, threads):
+    box = np.asarray(s["box"])
+    S = osamp.box_tables(s["alpha"], box)["S"]
+    sums = orbe.mode_sums(s["pos"], s["q"], box, s["alpha"], tol=1e-6, threads=threads)
+    v1, _ = orbe.force_variance(s["pos"], s["q"], box, s["alpha"], S, 1, coulomb=s["coulomb"],
+                                rows=rows, sums=sums)
+    pv1, _ = orbe.pressure_variance(s["pos"], s["q"], box, s["alpha"], S, 1,
+                                    coulomb=s["coulomb"], sums=sums)
+    return v1.sum(), pv1
+
+
+def test_variance_against_batch_size_water_30k(gpu):
+    # Proposition 1 on 30k-charge water (FP32 path): the device probe's force
+    # variance (force batch P) and pressure variance (pressure batch 2P)
+    # against the closed forms eq. (ForceExp), (PressExp) for P = 50 .. 500,
+    # and the batch size the 1/p law picks for a target.  The sweep runs on
+    # 10,000 waters with their oxygens uniform in the cells of the 22^3
+    # lattice (jitter = half the spacing): no long-range order.  The
+    # benchmark's water (jitter 0.15 A) keeps Bragg peaks of that lattice
+    # (|m| = 22 along an axis): draws of probability ~1e-8 whose |rho|^4
+    # dominates the pressure's second moment, so no affordable number of
+    # batches samples that variance; its force variance is checked at P = 100.
+    import os
+    import torch
+    from paper_2110_14362_amd import workloads
+    from paper_2110_14362_amd.rbe import RBE, batch_size_for_variance
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    c = workloads.CONFIGS["water_30k"]
+    L = workloads.water_box_side(c["n_mol"])
+    disordered = workloads.water(c["n_mol"], seed=c["seed"], jitter=0.5 * L / 22.0)
+    disordered.update(alpha=0.09, coulomb=workloads.COULOMB_REAL)
+    lattice = workloads.make("water_30k")
+    n = len(lattice["q"])
+    rows = np.random.default_rng(30).choice(n, 2000, replace=False)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=gpu)
+    B = 1000
+
+    def probe(s, P, pp):
+        x, y, z = (t(s["pos"][:, a]) for a in range(3))
+        ctx = RBE(t(s["q"]), s["box"], P, s["alpha"], coulomb=s["coulomb"], precision="fp32",
+                  seed=4040, system_id=P, p_pressure=pp)
+        r = ctx.variance_probe(x, y, z, B, first_step=0, per_particle=True)
+        ctx.check()
+        ctx.close()
+        return r["force_var_particles"][rows].sum(), r["pressure_var"]
+
+    vf1, pv1 = _water_30k_closed_forms(disordered, rows, threads)
+    meas = {}
+    for P in (50, 100, 200, 500):
+        vf, vp = probe(disordered, P, 2 * P)
+        rf, rp = vf / (vf1 / P), vp / (pv1 / (2 * P))
+        meas[P] = vf
+        print("water_30k (disordered) P=%d, pressure batch %d: force variance device/closed %.3f, "
+              "pressure variance device/closed %.3f" % (P, 2 * P, rf, rp), flush=True)
+        assert abs(rf - 1.0) < 0.1, (P, rf)
+        assert abs(rp - 1.0) < 0.25, (P, rp)
+    # the 1/p law picks the batch that reaches a target: a quarter of the
+    # variance measured at P = 100 needs P = 400
+    assert batch_size_for_variance(100, meas[100], meas[100] / 4.0) == 400
+    assert meas[500] < meas[100] / 3.0
+    # the benchmark's lattice water: forces
+    vl1, _ = _water_30k_closed_forms(lattice, rows, threads)
+    vf, _ = probe(lattice, 100, 0)
+    print("water_30k (benchmark, jittered lattice) P=100: force variance device/closed %.3f"
+          % (vf / (vl1 / 100)), flush=True)
+    assert abs(vf / (vl1 / 100) - 1.0) < 0.1
 
 
 def noise_series(s, p, T, dev, alpha, system_id, sampler="exact", iters=1):
