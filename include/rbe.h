@@ -316,6 +316,38 @@ rbe_status rbe_timing_read(rbe_ctx ctx, double* h_ms, int32_t* h_count);
 /* Release the context and its device memory (waits for the stream). */
 void rbe_destroy(rbe_ctx ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * Fourier-space step with no context and no allocation.  Same results, bit
+ * for bit, as rbe_init(cfg, d_q, box_host) + rbe_rescale_box(box_host) +
+ * rbe_sample_k(step) + rbe_forces_pressure(...) on the single-launch plan
+ * (rbe_set_fused): the batch of `step` for the cell box_host (exact sampler),
+ * rho, forces, virial tensor and energy.  DEVICE arrays: d_q [n] charges,
+ * d_x, d_y, d_z [n], d_fx, d_fy, d_fz [n] (overwritten, or added to when
+ * accumulate != 0), d_virial6 [6] and d_energy [1] (each nullable), d_rho
+ * [2p~] (nullable: rho of the batch); box_host is a HOST array of 3 sides
+ * (6 values for RBE_BOX_TRICLINIC).
+ * stream: hipStream_t (NULL: the null stream).  Asynchronous: two kernel
+ * launches, no copies, no allocation, no wait.
+ * Every intermediate (the batch, partial sums, rho, force constants,
+ * counters) lives in one file-scope device array of 4 MiB that each GPU the
+ * library runs on keeps until the process ends; a call clears what must
+ * start at zero.  Calls that overlap on one GPU (other streams, other host
+ * threads) share that array and race: serialise them.
+ * Limits: the single-launch plan (each particle chunk within one
+ * 512-particle tile, p~ <= 512, every block resident at once: up to about
+ * 131,000 charges on MI355X) and the 4 MiB; otherwise RBE_ERR_CAPACITY with
+ * nothing launched.  Configuration and cell errors as rbe_init
+ * (RBE_ERR_ARG); neutrality is NOT checked (it needs a device read; the
+ * caller guarantees it), and device-side flags (a cell beyond the sampler
+ * tables, a wait that gave up) are not reported. */
+rbe_status rbe_forces_pressure_noalloc(const rbe_config* cfg, const double* d_q,
+                                       const double* box_host, uint64_t step,
+                                       const double* d_x, const double* d_y, const double* d_z,
+                                       double* d_fx, double* d_fy, double* d_fz, int accumulate,
+                                       double* d_virial6, double* d_energy, double* d_rho,
+                                       void* stream);
+
 /* ---------------------------------------------------------------------------
  * Real-space part of the Ewald split (section 4.1 eq. (U2), eq. (force) second
  * term; section 4.2: computed with the nearest image only, for pairs closer

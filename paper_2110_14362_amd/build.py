@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbe.so")
 
 SOURCES = ["rbe_kernels.hip", "rbe_api.cpp", "rbe_real.hip", "rbe_real_api.cpp",
-           "rbe_md.hip", "rbe_md_api.cpp", "rbe_batch.cpp", "rbe_rates.hip"]
+           "rbe_md.hip", "rbe_md_api.cpp", "rbe_batch.cpp", "rbe_noalloc.hip",
+           "rbe_rates.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -34,7 +34,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ["rbe_init", "rbe_set_stream", "rbe_rescale_box", "rbe_rescale_box_dev",
            "rbe_sample_k", "rbe_set_k", "rbe_get_k", "rbe_forces_pressure", "rbe_get_rho",
            "rbe_get_box_info", "rbe_get_plan", "rbe_set_fused", "rbe_variance_probe",
-           "rbe_batch_size_for_variance", "rbe_measure_issue_rates",
+           "rbe_batch_size_for_variance", "rbe_forces_pressure_noalloc", "rbe_measure_issue_rates",
            "rbe_check",
            "rbe_timing_enable",
            "rbe_timing_read",
@@ -125,6 +125,8 @@ def load_library(path=LIB_PATH):
         "rbe_get_plan": [vp, ctypes.POINTER(i32)],
         "rbe_set_fused": [vp, i32],
         "rbe_measure_issue_rates": [dp],
+        "rbe_forces_pressure_noalloc": [vp, vp, vp, ctypes.c_uint64, vp, vp, vp, vp, vp, vp, i32,
+                                        vp, vp, vp, vp],
         "rbe_variance_probe": [vp, vp, vp, vp, i32, ctypes.c_uint64, dp, dp],
         "rbe_batch_size_for_variance": [i32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32)],
         "rbe_timing_enable": [vp, i32],
@@ -646,6 +648,29 @@ def batch_size_for_variance(p, var, target):
     out = ctypes.c_int32()
     _check(lib.rbe_batch_size_for_variance(int(p), float(var), float(target), ctypes.byref(out)))
     return int(out.value)
+
+
+def forces_pressure_noalloc(q, box, p, alpha, step, x, y, z, fx, fy, fz, coulomb=1.0,
+                            precision="fp32", box_mode="iso", seed=0, system_id=0, p_pressure=0,
+                            accumulate=False, virial6=None, energy=None, rho=None, stream=None):
+    """rbe_forces_pressure_noalloc: one Fourier-space step with no context and
+    no device allocation (intermediates in the library's static scratch).
+    rho: optional float64 device tensor of 2 p~ entries."""
+    lib = load_library()
+    n = int(q.numel())
+    cfg = Config(n=n, p=int(p), box_mode=BOX_MODES[box_mode], precision=PRECISIONS[precision],
+                 p_pressure=int(p_pressure), alpha=float(alpha), coulomb=float(coulomb),
+                 seed=int(seed) & (2**64 - 1), system_id=int(system_id) & (2**64 - 1))
+    boxarr = _cell(box, box_mode)
+    pb = max(int(p), int(p_pressure))
+    _check(lib.rbe_forces_pressure_noalloc(
+        ctypes.byref(cfg), _dptr(q, "q", n), boxarr, ctypes.c_uint64(int(step) & (2**64 - 1)),
+        _dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n),
+        _dptr(fx, "fx", n), _dptr(fy, "fy", n), _dptr(fz, "fz", n), int(bool(accumulate)),
+        _dptr(virial6, "virial6", 6) if virial6 is not None else None,
+        _dptr(energy, "energy", 1) if energy is not None else None,
+        _dptr(rho, "rho", 2 * pb) if rho is not None else None,
+        _stream_handle(stream)))
 
 
 def measure_issue_rates():
