@@ -67,6 +67,9 @@ def parse():
                          "served stream (0: cell lists every step)")
     ap.add_argument("--slab-steps", type=int, default=1000,
                     help="timed Fourier steps of the membrane-shaped slab (0: skip)")
+    ap.add_argument("--no-fixed-cell", action="store_true",
+                    help="skip the fixed-cell sub-record (its launches share the headline "
+                         "kernels' names in a profiler's per-kernel averages)")
     ap.add_argument("--issue-rates", action="store_true",
                     help="only measure the device's sine / FMA issue rates and exit")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
@@ -454,7 +457,19 @@ def main():
         ctx.timing_enable(0)
         ctx.check()
         results[prec] = dict(seconds=el, steps=K, kernels=kt, plan=ctx.plan())
-        if prec == args.precision:
+        if prec == args.precision and not args.no_fixed_cell:
+            # the same steps as one launch each (rbe_set_fused), where the plan
+            # allows it: a sub-record (the two-launch form is the default)
+            ctx.set_fused(True)
+            if ctx.plan()["fused"]:
+                el1 = time_steps(step, K, args.warmup, torch)
+                ctx.timing_enable(K)
+                time_steps(step, K, 0, torch)
+                kt1 = ctx.timing_read()
+                ctx.timing_enable(0)
+                ctx.check()
+                results["single_launch"] = dict(seconds=el1, steps=K, kernels=kt1)
+            ctx.set_fused(False)
             # the same step at a fixed cell (the batch drawn ahead by the
             # previous step is then used): a sub-record, not the headline
             fstep = make_step(ctx, box, x, y, z, fx, fy, fz, vir, en, fixed_cell=True)
@@ -474,16 +489,16 @@ def main():
     plan = main_r["plan"]
     f64 = args.precision == "fp64"
     tf = "true" if f64 else "false"
-    kname = {"sfac": "k_sfac<%s,%d>" % (tf, 1 if f64 else plan["R"]),
-             "force": "k_force<%s,%d>" % (tf, 1 if f64 else 2),
-             "step": "k_step<%s,%d>" % (tf, 1 if f64 else plan["R"])}[dom]
+    kname = {"sfac": "k_sfac<%s,%d,false>" % (tf, 1 if f64 else plan["R"]),
+             "force": "k_force<%s,%d,%d>" % (tf, 1 if f64 else 2, plan["k2reduce"]),
+             "step": "k_step<%s,%d,false>" % (tf, 1 if f64 else plan["R"])}[dom]
     roof = {"bound": "alu", "kernel": kname,
             "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
             "frac": achieved / TRANS_PEAK, "traffic": profiled_traffic(kname, args.workload + (
                 "_p%d" % args.p if args.p else "")),
             "per_unit": PER_UNIT[dom] + "; %d x %d pairs per launch" % (N, P),
-            "timing": "HIP events on the library stream around each launch, over %d steps"
-                      % main_r["steps"]}
+            "timing": "HIP events that each launch records itself (hipExtLaunchKernel) on the "
+                      "library stream, over %d steps" % main_r["steps"]}
     out = {
         "metric": METRIC, "value": value, "unit": "(N*P)/s", "n_gpus": 1,
         "steps": main_r["steps"], "warmup": args.warmup, "ms_per_step": ms,
@@ -503,12 +518,22 @@ def main():
         "kernels_us": kern,
         "plan": plan,
     }
-    fc = results.pop("fixed_cell")
-    out["fixed_cell"] = {"value": N * P / (fc["seconds"] / fc["steps"]),
-                         "ms_per_step": fc["seconds"] / fc["steps"] * 1e3, "steps": fc["steps"],
-                         "note": "the same step with the cell left unchanged between steps "
-                                 "(no table rebuild; the batch drawn ahead is used); the "
-                                 "headline value changes the cell every step, as NPT does"}
+    fc = results.pop("fixed_cell", None)
+    if fc is not None:
+        out["fixed_cell"] = {"value": N * P / (fc["seconds"] / fc["steps"]),
+                             "ms_per_step": fc["seconds"] / fc["steps"] * 1e3, "steps": fc["steps"],
+                             "note": "the same step with the cell left unchanged between steps "
+                                     "(no table rebuild; the batch drawn ahead is used); the "
+                                     "headline value changes the cell every step, as NPT does"}
+    sl = results.pop("single_launch", None)
+    if sl is not None:
+        out["single_launch"] = {
+            "value": N * P / (sl["seconds"] / sl["steps"]),
+            "ms_per_step": sl["seconds"] / sl["steps"] * 1e3, "steps": sl["steps"],
+            "kernels_us": {k: (v[0] / v[1] * 1e3) if v[1] else None
+                           for k, v in sl["kernels"].items()},
+            "note": "the same steps (changing cell) as one launch each (rbe_set_fused); "
+                    "identical results; the two-launch form is the default"}
     for prec, r in results.items():
         if prec != args.precision:
             ms2 = r["seconds"] / r["steps"] * 1e3

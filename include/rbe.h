@@ -299,8 +299,10 @@ rbe_status rbe_measure_issue_rates(double* h_out);
 rbe_status rbe_check(rbe_ctx ctx);
 
 /* Kernel timing for measurement.  While enabled, each kernel this context
- * launches is bracketed by two HIP events recorded on the context's stream
- * (the stream the kernel runs on).  max_launches (>= 1) bounds the launches
+ * launches carries two HIP events that the launch itself timestamps at the
+ * kernel's start and end (hipExtLaunchKernel, on the context's stream: the
+ * stream the kernel runs on), so queueing between launches is not counted.
+ * max_launches (>= 1) bounds the launches
  * recorded per kernel kind; later launches run untimed.  0 disables and
  * releases the events.  Creates host-side HIP events only (no device memory). */
 rbe_status rbe_timing_enable(rbe_ctx ctx, int32_t max_launches);

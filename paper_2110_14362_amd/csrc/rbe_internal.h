@@ -136,17 +136,26 @@ inline int64_t cnt_words(int Y, int NG) { return ((int64_t)Y * NG + Y + 4) * kCn
 
 size_t sfac_lds_bytes(const StepArgs& a);
 
+// Start and stop events of one launch for kernel timing: the launch itself
+// timestamps them (hipExtLaunchKernel), so they bracket the kernel's own
+// execution and not the queue around it.  Null when timing is off.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // charge sums (sum q, sum |q|, sum q^2) into d_out3, the FP32 copy of the
 // charges (d_qf, nullable), and nzero words of d_zero cleared first
 hipError_t launch_qsum(const double* d_q, float* d_qf, double* d_out3, int64_t n, hipStream_t s,
                        uint32_t* d_zero = nullptr, int64_t nzero = 0);
 // standalone table and draw kernels (used when a result is read before the
 // fused kernel has run)
-hipError_t launch_tables(const StepArgs& a, hipStream_t s);
-hipError_t launch_sample(const StepArgs& a, hipStream_t s);
+hipError_t launch_tables(const StepArgs& a, hipStream_t s, const LaunchEvents& ev = {});
+hipError_t launch_sample(const StepArgs& a, hipStream_t s, const LaunchEvents& ev = {});
 // the two kernels of a step
-hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s);
-hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s);
+hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s,
+                       const LaunchEvents& ev = {});
+hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s,
+                        const LaunchEvents& ev = {});
 // the whole step in one launch (k_step): whether the plan allows
 // it (particle chunks within one LDS tile, the batch within one block, the
 // force layout of 8 waves), how many of its blocks fit the device at once,
@@ -154,7 +163,8 @@ hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s);
 bool step_supported(int precision, const StepArgs& a);
 hipError_t step_max_blocks(int precision, const StepArgs& a, int* max_blocks);
 size_t step_lds_bytes(const StepArgs& a);
-hipError_t launch_step(int precision, const StepArgs& a, hipStream_t s);
+hipError_t launch_step(int precision, const StepArgs& a, hipStream_t s,
+                       const LaunchEvents& ev = {});
 // running sums of F*, F*^2 (per particle and component) and of P2*, P2*^2
 hipError_t launch_moments(const double* fx, const double* fy, const double* fz, const double* vir,
                           double V, int64_t n, double* sum, double* sq, double* psum,

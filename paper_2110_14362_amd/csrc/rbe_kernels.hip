@@ -15,6 +15,7 @@
 //            block, frequency constants uniform across the wave (eq. (appforce)).
 // Every sum has a fixed order, so results are bitwise reproducible and do not
 // depend on which block arrives last or on what else runs on the GPU.
+#include <hip/hip_ext.h>
 #include "rbe_internal.h"
 #include <math.h>
 #include <type_traits>
@@ -82,6 +83,8 @@ __device__ __forceinline__ void table_offsets(const int mc[3], int off[3]) {
   off[2] = off[1] + 4 * mc[1] + 1;
 }
 
+constexpr int kTableTasks = 6;     // (axis, table) pairs of build_tables, one wave each
+
 // Per-axis running sums of w_a(m) = exp(-pi^2 m^2 / (alpha l_a^2)) built by the
 // whole block into `tab` (LDS or global).  Axis a occupies [off[a], off[a] +
 // 4 mc_a + 1): the running sum over m = -mc..mc, then the running sum over the
@@ -108,7 +111,7 @@ __device__ void build_tables(const double l[3], const TriCell* tcp, double alpha
   }
   table_offsets(mc, off);
   const double pi2 = M_PI * M_PI;
-  for (int task = wave; task < 6; task += nw) {
+  for (int task = wave; task < kTableTasks; task += nw) {
     const int a = task >> 1, nz = task & 1;
     const int n = nz ? 2 * mc[a] : 2 * mc[a] + 1;
     double* t = tab + off[a] + (nz ? 2 * mc[a] + 1 : 0);
@@ -171,16 +174,14 @@ __device__ __forceinline__ int first_greater(const double* c, int n, double t) {
 // Uniforms: the four Philox outputs of counter (step, l, 'ksam', 0), top 53
 // bits.  A table draw is the first index whose running sum exceeds u times
 // the table total; the three axes' binary searches run in lockstep.
-__device__ __forceinline__ void propose_frequency(const BoxState& b, const double* tab, uint64_t seed,
-                                                  uint64_t sysid, uint64_t step, int l,
-                                                  uint64_t attempt, int m[3]) {
+// propose_from draws from the four Philox outputs c0..c3 given;
+// propose_frequency forms them for attempt `attempt` first.
+__device__ __forceinline__ void propose_from(const BoxState& b, const double* tab, uint64_t c0,
+                                             uint64_t c1, uint64_t c2, uint64_t c3, int m[3]) {
   int off[3];
   table_offsets(b.mcut, off);
-  uint64_t c[4] = {step, (uint64_t)l, kTagKSample, attempt};
-  philox4x64_10(c, seed, sysid);
-  double u[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) u[j] = (double)(c[j] >> 11) * 0x1.0p-53;
+  const double u[4] = {(double)(c0 >> 11) * 0x1.0p-53, (double)(c1 >> 11) * 0x1.0p-53,
+                       (double)(c2 >> 11) * 0x1.0p-53, (double)(c3 >> 11) * 0x1.0p-53};
   const double t = u[0] * (b.case_w[0] + b.case_w[1] + b.case_w[2]);
   const int pivot = (t < b.case_w[0]) ? 0 : ((t < b.case_w[0] + b.case_w[1]) ? 1 : 2);
   const double* base[3];
@@ -217,6 +218,14 @@ __device__ __forceinline__ void propose_frequency(const BoxState& b, const doubl
   }
 }
 
+__device__ __forceinline__ void propose_frequency(const BoxState& b, const double* tab, uint64_t seed,
+                                                  uint64_t sysid, uint64_t step, int l,
+                                                  uint64_t attempt, int m[3]) {
+  uint64_t c[4] = {step, (uint64_t)l, kTagKSample, attempt};
+  philox4x64_10(c, seed, sysid);
+  propose_from(b, tab, c[0], c[1], c[2], c[3], m);
+}
+
 constexpr uint64_t kTagKAccept = 0x6B616363ull;  // 'kacc': acceptance uniforms, triclinic draws
 constexpr int kMaxAttempts = 256;
 
@@ -225,15 +234,23 @@ constexpr int kMaxAttempts = 256;
 // envelope exp(-sum d_j m_j^2) with the uniforms of counter (step, l, 'ksam',
 // a) and accepts with probability exp(-(Q(m) - sum d_j m_j^2)), the uniform
 // from counter (step, l, 'kacc', a); the accepted m has law exp(-Q(m))/S.
-// After kMaxAttempts rejections the last proposal is kept.
+// After kMaxAttempts rejections the last proposal is kept.  TRI selects the
+// triclinic form at compile time (the cell values say which applies), so
+// that kernels for rectangular cells carry none of the rejection loop's
+// registers.
+//
+// pre (nullable): the Philox outputs of attempt 0, pre[j * pre_stride] for
+// output j, formed ahead by slice_uniforms; identical to forming them here.
+template <bool TRI>
 __device__ __forceinline__ void draw_frequency(const BoxState& b, const double* tab, uint64_t seed,
-                                               uint64_t sysid, uint64_t step, int l, int m[3]) {
-  if (!b.tri.on) {
-    propose_frequency(b, tab, seed, sysid, step, l, 0ull, m);
-    return;
-  }
+                                               uint64_t sysid, uint64_t step, int l, int m[3],
+                                               const uint64_t* pre = nullptr, int pre_stride = 0) {
   for (int att = 0; att < kMaxAttempts; ++att) {
-    propose_frequency(b, tab, seed, sysid, step, l, (uint64_t)att, m);
+    if (att == 0 && pre)        // the same Philox outputs, formed ahead
+      propose_from(b, tab, pre[0], pre[pre_stride], pre[2 * pre_stride], pre[3 * pre_stride], m);
+    else
+      propose_frequency(b, tab, seed, sysid, step, l, (uint64_t)att, m);
+    if (!TRI) return;
     const double x = m[0], y = m[1], z = m[2];
     const double* A = b.tri.A;
     const double Q = A[0] * x * x + A[1] * y * y + A[2] * z * z +
@@ -275,12 +292,42 @@ __device__ __forceinline__ const TriCell* stage_tri(const StepArgs& a, TriCell* 
   return s->on ? s : nullptr;
 }
 
+// Words of the cell values.  They are copied word by word by the block's
+// first threads: a one-thread copy of the whole struct would hold all of it
+// in registers at once.
+constexpr int kBoxWords = sizeof(BoxState) / 8;
+static_assert(sizeof(BoxState) % 8 == 0, "cell values copied as 8-byte words");
+
 // The cell values of this launch become the committed ones (keeping any
-// error flag already set); field by field, no local copy of the struct.
-__device__ __forceinline__ void commit_cell(const BoxState& b, BoxState* dst) {
-  const int32_t e0 = dst->err;
-  *dst = b;
-  dst->err = b.err | e0;
+// error flag already set), one 8-byte word per thread of the block's first
+// kBoxWords threads.
+__device__ __forceinline__ void commit_cell(const BoxState& b, BoxState* dst, int tid) {
+  constexpr int ew = __builtin_offsetof(BoxState, err) / 8;
+  if (tid >= kBoxWords) return;
+  const int32_t e0 = tid == ew ? dst->err : 0;
+  reinterpret_cast<uint64_t*>(dst)[tid] = reinterpret_cast<const uint64_t*>(&b)[tid];
+  if (tid == ew) dst->err = b.err | e0;
+}
+
+// A system's kernel arguments into LDS, 8 bytes per thread (a one-thread
+// copy of the struct would hold all of it in registers).
+__device__ __forceinline__ void copy_args(StepArgs* dst, const StepArgs* src) {
+  static_assert(sizeof(StepArgs) % 8 == 0, "arguments copied as 8-byte words");
+  constexpr int words = sizeof(StepArgs) / 8;
+  for (int w = threadIdx.x; w < words; w += blockDim.x)
+    reinterpret_cast<uint64_t*>(dst)[w] = reinterpret_cast<const uint64_t*>(src)[w];
+}
+
+// Cell values from global memory into LDS (dst), and from LDS to global
+// memory, one 8-byte word per thread of the block's first kBoxWords threads;
+// LDS results are read after a barrier.
+__device__ __forceinline__ void load_box(BoxState& dst, const BoxState* src, int tid) {
+  if (tid < kBoxWords)
+    reinterpret_cast<uint64_t*>(&dst)[tid] = reinterpret_cast<const uint64_t*>(src)[tid];
+}
+__device__ __forceinline__ void copy_box(BoxState* dst, const BoxState& src, int tid) {
+  if (tid < kBoxWords)
+    reinterpret_cast<uint64_t*>(dst)[tid] = reinterpret_cast<const uint64_t*>(&src)[tid];
 }
 
 // Whether a batch drawn ahead for cell pb is the batch of this launch's cell.
@@ -457,13 +504,33 @@ __device__ void mh_frequency(const StepArgs& a, const BoxState& b, int l, int m[
   }
 }
 
+// The attempt-0 Philox outputs (counter (step, l, 'ksam', 0)) of the
+// frequencies l = slice + s2 < p, s2 < FB, into su[j * FB + s2], formed by
+// the waves that build_tables leaves idle (one wave per (axis, table): six),
+// so that they run beside the table build instead of after it; the draw then
+// only searches the tables.  Reached by every thread before build_tables,
+// whose closing barrier makes su visible.  blockDim.x > kTableTasks waves.
+__device__ __forceinline__ void slice_uniforms(uint64_t* su, int FB, int64_t slice, int64_t p,
+                                               uint64_t seed, uint64_t sysid, uint64_t step) {
+  const int t = (int)threadIdx.x - kTableTasks * kWave;
+  const int nt = (int)blockDim.x - kTableTasks * kWave;
+  if (t < 0) return;
+  for (int s2 = t; s2 < FB && slice + s2 < p; s2 += nt) {
+    uint64_t c[4] = {step, (uint64_t)(slice + s2), kTagKSample, 0ull};
+    philox4x64_10(c, seed, sysid);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) su[j * FB + s2] = c[j];
+  }
+}
+
 // frequency l of the current step under the context's sampler (the chains
 // move in the standalone draw kernel only: inlined into the structure-factor
 // kernel, their FP64 transcendentals would raise its register budget)
 __device__ __forceinline__ void sample_frequency(const StepArgs& a, const BoxState& b,
                                                  const double* tab, int l, int m[3]) {
   if (a.sampler == RBE_SAMPLER_MH && !a.mh_init) mh_frequency(a, b, l, m);
-  else draw_frequency(b, tab, a.seed, a.sysid, a.step, l, m);
+  else if (b.tri.on) draw_frequency<true>(b, tab, a.seed, a.sysid, a.step, l, m);
+  else draw_frequency<false>(b, tab, a.seed, a.sysid, a.step, l, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -478,29 +545,31 @@ __global__ void __launch_bounds__(256) k_tables(StepArgs a) {
   const TriCell* tc = stage_tri(a, &stc);
   box_source(a, l);
   build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T);
-  if (threadIdx.x == 0) {
-    commit_cell(sbs, a.bs);
-  }
+  commit_cell(sbs, a.bs, threadIdx.x);
 }
 
-hipError_t launch_tables(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
+hipError_t launch_tables(const StepArgs& a, hipStream_t s, const LaunchEvents& ev) {
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(&k_tables), dim3(1), dim3(256), args, 0,
+                            s, ev.start, ev.stop, 0);
 }
 
 __global__ void __launch_bounds__(256) k_sample(StepArgs a) {
+  __shared__ BoxState sbs;
+  load_box(sbs, a.bs, threadIdx.x);
+  lds_barrier();
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= a.p) return;
-  const BoxState b = *a.bs;
   int m[3];
-  sample_frequency(a, b, a.tab, l, m);
+  sample_frequency(a, sbs, a.tab, l, m);
   a.m[3 * l] = m[0]; a.m[3 * l + 1] = m[1]; a.m[3 * l + 2] = m[2];
   if (a.sampler == RBE_SAMPLER_MH) { a.mh_new[3 * l] = m[0]; a.mh_new[3 * l + 1] = m[1]; a.mh_new[3 * l + 2] = m[2]; }
 }
 
-hipError_t launch_sample(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample, dim3((a.p + 255) / 256), dim3(256), 0, s, a);
-  return hipGetLastError();
+hipError_t launch_sample(const StepArgs& a, hipStream_t s, const LaunchEvents& ev) {
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(&k_sample), dim3((a.p + 255) / 256),
+                            dim3(256), args, 0, s, ev.start, ev.stop, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,17 +701,20 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
 __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const BoxState& b,
                                             double alpha, double coulomb, int p_force, FCoef64& f,
                                             FCoef32& h, double tv[7]) {
+  // k = 2 pi h^-T m (appendix C; h^-1 upper triangular, diagonal 1/l for a
+  // rectangular cell), selected per entry rather than by a branch so that
+  // both cell kinds share one register budget
   double km[3], kk[3];
-  for (int c = 0; c < 3; ++c) {
-    km[c] = (double)mi[c];
-    kk[c] = 2.0 * M_PI * km[c] * b.inv_l[c];
-  }
-  if (b.tri.on) {
-    // k = 2 pi h^-T m (appendix C), h^-1 upper triangular
+  for (int c = 0; c < 3; ++c) km[c] = (double)mi[c];
+  {
+    const bool tri = b.tri.on != 0;
     const double* hi = b.tri.hinv;
-    kk[0] = 2.0 * M_PI * (hi[0] * km[0]);
-    kk[1] = 2.0 * M_PI * (hi[1] * km[0] + hi[3] * km[1]);
-    kk[2] = 2.0 * M_PI * (hi[2] * km[0] + hi[4] * km[1] + hi[5] * km[2]);
+    const double t0 = tri ? hi[0] : b.inv_l[0], t3 = tri ? hi[3] : b.inv_l[1];
+    const double t5 = tri ? hi[5] : b.inv_l[2];
+    const double t1 = tri ? hi[1] : 0.0, t2 = tri ? hi[2] : 0.0, t4 = tri ? hi[4] : 0.0;
+    kk[0] = 2.0 * M_PI * (t0 * km[0]);
+    kk[1] = 2.0 * M_PI * (t1 * km[0] + t3 * km[1]);
+    kk[2] = 2.0 * M_PI * (t2 * km[0] + t4 * km[1] + t5 * km[2]);
   }
   const double k2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
   const double ik2 = 1.0 / k2;
@@ -778,7 +850,7 @@ __device__ __forceinline__ void store_block_partial(const double2 (&part)[R], do
   }
 }
 
-template <bool F64, int R>
+template <bool F64, int R, bool TRI>
 __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const int y,
                                           unsigned char* lds_raw) {
   __shared__ BoxState sbs;
@@ -806,11 +878,11 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     int32_t* mp = a.m_pre + (int64_t)slot * 3 * a.p;
     for (int l2 = tid; l2 < a.p; l2 += kSfacThreads) {
       int mv[3];
-      draw_frequency(sbs, tabs, a.seed, a.sysid, next, l2, mv);
+      draw_frequency<TRI>(sbs, tabs, a.seed, a.sysid, next, l2, mv);
       mp[3 * l2] = mv[0]; mp[3 * l2 + 1] = mv[1]; mp[3 * l2 + 2] = mv[2];
     }
+    copy_box(&a.pre[slot].bs, sbs, tid);
     if (tid == 0) {
-      a.pre[slot].bs = sbs;
       a.pre[slot].step = next;
       a.pre[slot].valid = 1;
     }
@@ -832,36 +904,38 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   if (tid == 0) {
     int ok = 0;
     if (a.sample && a.use_pre && a.pre[pslot].valid && a.pre[pslot].step == a.step) {
-      const PreDraw& pd = a.pre[pslot];
-      ok = same_cell(a, pd.bs) ? 1 : 0;
-      if (ok) sbs = pd.bs;
+      ok = same_cell(a, a.pre[pslot].bs) ? 1 : 0;
     }
     sh_flag = ok;
   }
   lds_barrier();
   const bool pre = sh_flag != 0;
+  if (pre) {
+    load_box(sbs, &a.pre[pslot].bs, tid);
+    lds_barrier();
+  }
   const int32_t* m_pre = a.m_pre + (int64_t)pslot * 3 * a.p;
 
-  // ---- cell values and tables
+  // ---- cell values and tables; the slice's Philox outputs beside them, in
+  // R0 (free until the tile is stored)
   const bool need_tables = !pre && (a.sample || a.box_src != BOX_COMMITTED);
+  const int64_t slice = (int64_t)y * FB;
+  const bool su_on = a.sample && !pre && (size_t)FB * 4 * sizeof(uint64_t) <= kR0;
+  uint64_t* su = reinterpret_cast<uint64_t*>(base);
   if (pre) {
-    if (x == 0 && y == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
-      commit_cell(sbs, a.bs);
-    }
+    if (x == 0 && y == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else if (need_tables) {
+    if (su_on) slice_uniforms(su, FB, slice, a.p, a.seed, a.sysid, a.step);
     double l[3];
     box_source(a, l);
     build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
-    if (x == 0 && y == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
-      commit_cell(sbs, a.bs);
-    }
+    if (x == 0 && y == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else {
-    if (tid == 0) sbs = *a.bs;
+    load_box(sbs, a.bs, tid);
     lds_barrier();
   }
 
   // ---- this block's slice of the batch
-  const int64_t slice = (int64_t)y * FB;
   for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
     const int64_t l = slice + s2;
     int mv[3] = {0, 0, 0};
@@ -870,7 +944,8 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
         mv[0] = m_pre[3 * l]; mv[1] = m_pre[3 * l + 1]; mv[2] = m_pre[3 * l + 2];
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else if (a.sample) {
-        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv);
+        draw_frequency<TRI>(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv,
+                            su_on ? su + s2 : nullptr, FB);
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else {
         mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
@@ -1020,10 +1095,10 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   if (tid == 0 && a.Y > 1) a.cnt[cnt_index(a, CNT_BATCH)] = 0u;
 }
 
-template <bool F64, int R>
+template <bool F64, int R, bool TRI>
 __global__ void __launch_bounds__(kSfacThreads) k_sfac(StepArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  sfac_body<F64, R>(a, blockIdx.x, blockIdx.y, lds_raw);
+  sfac_body<F64, R, TRI>(a, blockIdx.x, blockIdx.y, lds_raw);
 }
 
 // Many systems in one launch: block b belongs to system s with
@@ -1045,25 +1120,28 @@ __global__ void __launch_bounds__(kSfacThreads) k_sfac_multi(const StepArgs* tab
   __shared__ StepArgs sa;
   const int b = blockIdx.x;
   const int sys = find_system(bstart, nsys, b);
-  if (threadIdx.x == 0) sa = tab[sys];
+  copy_args(&sa, tab + sys);
   lds_barrier();
   const int local = b - bstart[sys];
   const int xs = sa.X + (sa.predraw ? 1 : 0);
-  sfac_body<F64, R>(sa, local % xs, local / xs, lds_raw);
+  sfac_body<F64, R, false>(sa, local % xs, local / xs, lds_raw);   // no triclinic systems
 }
 
-hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s) {
+// the kernel instance for a precision, lane width R and cell kind
+template <bool TRI>
+static const void* sfac_kernel(int precision, int R) {
+  if (precision == RBE_PREC_FP64) return reinterpret_cast<const void*>(&k_sfac<true, 1, TRI>);
+  if (R == 4) return reinterpret_cast<const void*>(&k_sfac<false, 4, TRI>);
+  if (R == 2) return reinterpret_cast<const void*>(&k_sfac<false, 2, TRI>);
+  return reinterpret_cast<const void*>(&k_sfac<false, 1, TRI>);
+}
+
+hipError_t launch_sfac(int precision, const StepArgs& a, hipStream_t s, const LaunchEvents& ev) {
   const dim3 grid(a.X + (a.predraw ? 1 : 0), a.Y);
   const size_t lds = sfac_lds_bytes(a);
-  if (precision == RBE_PREC_FP64)
-    hipLaunchKernelGGL((k_sfac<true, 1>), grid, dim3(kSfacThreads), lds, s, a);
-  else if (a.R == 4)
-    hipLaunchKernelGGL((k_sfac<false, 4>), grid, dim3(kSfacThreads), lds, s, a);
-  else if (a.R == 2)
-    hipLaunchKernelGGL((k_sfac<false, 2>), grid, dim3(kSfacThreads), lds, s, a);
-  else
-    hipLaunchKernelGGL((k_sfac<false, 1>), grid, dim3(kSfacThreads), lds, s, a);
-  return hipGetLastError();
+  const void* fn = a.tri_mode ? sfac_kernel<true>(precision, a.R) : sfac_kernel<false>(precision, a.R);
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  return hipExtLaunchKernel(fn, grid, dim3(kSfacThreads), args, lds, s, ev.start, ev.stop, 0);
 }
 
 int sfac_blocks(const StepArgs& a) { return (a.X + (a.predraw ? 1 : 0)) * a.Y; }
@@ -1091,11 +1169,16 @@ hipError_t launch_sfac_multi(int precision, int R, const StepArgs* d_tab, const 
 // constants in LDS; one extra block (the last) then does the batch-wide work
 // instead of forces: rho, the virial tensor and the energy.
 
-constexpr int kForceStageBytes = 32768;
+// Force constants staged per chunk: 512 of them in either precision (FP32
+// 32 B, FP64 64 B each), so that the small-batch mode's p <= 512 constants
+// fit one chunk; the FP32 kernel's 16 KB leave room for more blocks per CU
+// (10^6 charges, P = 2000: 2.5 % faster than 32 KB).
+template <bool F64>
+constexpr int force_stage_bytes() { return F64 ? 32768 : 16384; }
 // red_raw holds, in turn: the small-batch row sums (scratch of blockDim.x
 // double2, then rho of Ppad <= 512 double2) and the cross-wave sums (at most
 // 8 waves x 64 lanes x RP particles x 3 components, FP32 with RP = 2 or FP64
-// with RP = 1: 12 KB).  Blocks have at most 8 waves (KS <= 8, PW = 4 only with
+// with RP = 1: 12 KB).  Blocks have at most 8 waves (KS <= 8, PW = 8 only with
 // KS = 1; checked at launch).  Kept this small so that more blocks share a CU.
 constexpr int kForceMaxWaves = 8;
 constexpr int kForceRedBytes = kForceMaxWaves * kWave * 16 + 512 * 16;
@@ -1147,10 +1230,17 @@ __device__ __forceinline__ void force_slice64(const FCoef64* sc, int l0, int l1,
   }
 }
 
-template <bool F64, int RP>
+// K2: 1 = the block sums the group partials of rho itself (small batches,
+// a.k2reduce), 0 = it reads the force constants the structure-factor kernel
+// stored, -1 = as a.k2reduce says (multi-system launches, where systems of
+// both kinds share a launch).  The fixed modes keep the other mode's code,
+// and its registers, out of the kernel.
+template <bool F64, int RP, int K2>
 __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, const int nbx) {
+  const bool k2red = K2 < 0 ? a.k2reduce != 0 : K2 == 1;
   using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
-  constexpr int kChunk = kForceStageBytes / (int)sizeof(Coef);
+  constexpr int kChunk = force_stage_bytes<F64>() / (int)sizeof(Coef);
+  static_assert(kChunk >= 512, "the small-batch mode keeps up to 512 constants");
   __shared__ __align__(16) unsigned char red_raw[kForceRedBytes];
   __shared__ __align__(16) Coef scoef[kChunk];
   __shared__ BoxState sbs;
@@ -1159,7 +1249,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int nw = blockDim.x / kWave;
   const int PW = a.PW, KS = nw / PW;
-  const bool extra = a.k2reduce && bx == nbx - 1;
+  const bool extra = k2red && bx == nbx - 1;
   if (F64 && !extra) fill_sincos_tab(sctab);   // read after the barriers below
   // rows of rho partials left by k_sfac in k2reduce mode
   const double2* rows = a.NG > 1 ? a.gpart : a.partial;
@@ -1168,7 +1258,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   double2* srho = scratch + blockDim.x;                       // Ppad <= 512 entries
 
   if (extra) {
-    if (tid == 0) sbs = *a.bs;
+    load_box(sbs, a.bs, tid);
     lds_barrier();
     block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
     double tv[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1196,8 +1286,8 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
     xi[r] = yi[r] = zi[r] = 0.0;
     if (i < a.n) { xi[r] = a.x[i]; yi[r] = a.y[i]; zi[r] = a.z[i]; }
   }
-  if (a.k2reduce) {
-    if (tid == 0) sbs = *a.bs;
+  if (k2red) {
+    load_box(sbs, a.bs, tid);
     block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
     for (int l = tid; l < a.p; l += blockDim.x) {
       const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
@@ -1209,7 +1299,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       else reinterpret_cast<FCoef32*>(scoef)[l] = h;
     }
   } else {
-    if (tid == 0) sbs = *a.bs;
+    load_box(sbs, a.bs, tid);
   }
   lds_barrier();
   const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)
@@ -1230,11 +1320,11 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   float hx[RP], hy[RP], hz[RP];
 #pragma unroll
   for (int r = 0; r < RP; ++r) hx[r] = hy[r] = hz[r] = 0.f;
-  const int nchunk = a.k2reduce ? 1 : (a.pf + kChunk - 1) / kChunk;
+  const int nchunk = k2red ? 1 : (a.pf + kChunk - 1) / kChunk;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int cb = ch * kChunk;
     const int cnt = min(kChunk, a.pf - cb);
-    if (!a.k2reduce) {
+    if (!k2red) {
       lds_barrier();
       const int nvec = (int)((size_t)cnt * sizeof(Coef) / 16);
       const uint4* src = reinterpret_cast<const uint4*>(gcoef + cb);
@@ -1288,9 +1378,9 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   }
 }
 
-template <bool F64, int RP>
+template <bool F64, int RP, int K2>
 __global__ void __launch_bounds__(1024) k_force(StepArgs a) {
-  force_body<F64, RP>(a, blockIdx.x, gridDim.x);
+  force_body<F64, RP, K2>(a, blockIdx.x, gridDim.x);
 }
 
 template <bool F64, int RP>
@@ -1299,9 +1389,9 @@ __global__ void __launch_bounds__(1024) k_force_multi(const StepArgs* tab, const
   __shared__ StepArgs sa;
   const int b = blockIdx.x;
   const int sys = find_system(bstart, nsys, b);
-  if (threadIdx.x == 0) sa = tab[sys];
+  copy_args(&sa, tab + sys);
   lds_barrier();
-  force_body<F64, RP>(sa, b - bstart[sys], bstart[sys + 1] - bstart[sys]);
+  force_body<F64, RP, -1>(sa, b - bstart[sys], bstart[sys + 1] - bstart[sys]);
 }
 
 int force_blocks(int precision, const StepArgs& a) {
@@ -1310,15 +1400,19 @@ int force_blocks(int precision, const StepArgs& a) {
   return (int)((a.n + per_block - 1) / per_block + (a.k2reduce ? 1 : 0));
 }
 
-hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s) {
+hipError_t launch_force(int precision, const StepArgs& a, hipStream_t s, const LaunchEvents& ev) {
   if (a.KS * a.PW > kForceMaxWaves) return hipErrorInvalidConfiguration;
   const dim3 block(a.KS * a.PW * kWave);
   const dim3 grid((unsigned)force_blocks(precision, a));
+  const void* fn;
   if (precision == RBE_PREC_FP64)
-    hipLaunchKernelGGL((k_force<true, 1>), grid, block, 0, s, a);
+    fn = a.k2reduce ? reinterpret_cast<const void*>(&k_force<true, 1, 1>)
+                    : reinterpret_cast<const void*>(&k_force<true, 1, 0>);
   else
-    hipLaunchKernelGGL((k_force<false, 2>), grid, block, 0, s, a);
-  return hipGetLastError();
+    fn = a.k2reduce ? reinterpret_cast<const void*>(&k_force<false, 2, 1>)
+                    : reinterpret_cast<const void*>(&k_force<false, 2, 0>);
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  return hipExtLaunchKernel(fn, grid, block, args, 0, s, ev.start, ev.stop, 0);
 }
 
 // every system of a multi launch must use the same force block shape (KS, PW)
@@ -1409,7 +1503,7 @@ __device__ __forceinline__ void publish(uint32_t* c) {
     (void)__hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool F64, int R>
+template <bool F64, int R, bool TRI>
 __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   using Coef = typename std::conditional<F64, FCoef64, FCoef32>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1443,22 +1537,26 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   if (tid < cnt) {
     px = a.x[c0 + tid]; py = a.y[c0 + tid]; pz = a.z[c0 + tid]; pq = a.q[c0 + tid];
   }
+  // the batch's Philox outputs beside the table build, in the tile region
+  // (written only after the draw)
+  const bool su_on = a.sample && (size_t)FB * 4 * sizeof(uint64_t) <= kStepTile;
+  uint64_t* su = reinterpret_cast<uint64_t*>(tile);
   if (a.sample || a.box_src != BOX_COMMITTED) {
+    if (su_on) slice_uniforms(su, FB, 0, a.p, a.seed, a.sysid, a.step);
     double l[3];
     box_source(a, l);
     build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
-    if (x == 0 && tid == 0 && a.box_src != BOX_COMMITTED) {
-      commit_cell(sbs, a.bs);
-    }
+    if (x == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else {
-    if (tid == 0) sbs = *a.bs;
+    load_box(sbs, a.bs, tid);
     lds_barrier();
   }
   for (int l = tid; l < FB; l += kSfacThreads) {
     int mv[3] = {0, 0, 0};
     if (l < a.p) {
       if (a.sample) {
-        draw_frequency(sbs, tabs, a.seed, a.sysid, a.step, l, mv);
+        draw_frequency<TRI>(sbs, tabs, a.seed, a.sysid, a.step, l, mv, su_on ? su + l : nullptr,
+                            FB);
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       } else {
         mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
@@ -1466,6 +1564,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
     }
     sm[3 * l] = mv[0]; sm[3 * l + 1] = mv[1]; sm[3 * l + 2] = mv[2];
   }
+  if (su_on) lds_barrier();                 // su is read before the tile overwrites it
   // the whole tile, zero beyond the chunk (thread j owns entry j: blockDim
   // = kTile); the structure-factor loop reads the first cntp entries
   const int cntp = F64 ? (cnt + SUB - 1) / SUB * SUB
@@ -1650,10 +1749,15 @@ bool step_supported(int precision, const StepArgs& a) {
          (precision == RBE_PREC_FP64 ? a.R == 1 : (a.R == 1 || a.R == 2 || a.R == 4));
 }
 
-template <bool F64, int R>
-static hipError_t step_occupancy(const StepArgs& a, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step<F64, R>, kSfacThreads,
-                                                      step_lds_bytes(a));
+template <bool TRI>
+static const void* step_kernel(int precision, int R) {
+  if (precision == RBE_PREC_FP64) return reinterpret_cast<const void*>(&k_step<true, 1, TRI>);
+  if (R == 4) return reinterpret_cast<const void*>(&k_step<false, 4, TRI>);
+  if (R == 2) return reinterpret_cast<const void*>(&k_step<false, 2, TRI>);
+  return reinterpret_cast<const void*>(&k_step<false, 1, TRI>);
+}
+static const void* step_kernel(int precision, const StepArgs& a) {
+  return a.tri_mode ? step_kernel<true>(precision, a.R) : step_kernel<false>(precision, a.R);
 }
 
 hipError_t step_max_blocks(int precision, const StepArgs& a, int* max_blocks) {
@@ -1661,24 +1765,18 @@ hipError_t step_max_blocks(int precision, const StepArgs& a, int* max_blocks) {
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  if (precision == RBE_PREC_FP64) e = step_occupancy<true, 1>(a, &per);
-  else if (a.R == 4) e = step_occupancy<false, 4>(a, &per);
-  else if (a.R == 2) e = step_occupancy<false, 2>(a, &per);
-  else e = step_occupancy<false, 1>(a, &per);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_kernel(precision, a), kSfacThreads,
+                                                   step_lds_bytes(a));
   *max_blocks = cus * per;
   return e;
 }
 
-hipError_t launch_step(int precision, const StepArgs& a, hipStream_t s) {
+hipError_t launch_step(int precision, const StepArgs& a, hipStream_t s, const LaunchEvents& ev) {
   void* args[] = {const_cast<StepArgs*>(&a)};
   const dim3 grid(a.X), block(kSfacThreads);
   const size_t lds = step_lds_bytes(a);
-  const void* fn;
-  if (precision == RBE_PREC_FP64) fn = reinterpret_cast<const void*>(&k_step<true, 1>);
-  else if (a.R == 4) fn = reinterpret_cast<const void*>(&k_step<false, 4>);
-  else if (a.R == 2) fn = reinterpret_cast<const void*>(&k_step<false, 2>);
-  else fn = reinterpret_cast<const void*>(&k_step<false, 1>);
-  return hipLaunchKernel(fn, grid, block, args, lds, s);
+  return hipExtLaunchKernel(step_kernel(precision, a), grid, block, args, lds, s, ev.start, ev.stop,
+                            0);
 }
 
 

@@ -330,8 +330,8 @@ class RBE:
         return r
 
     def set_fused(self, enable):
-        """1: the whole step as one launch where the plan allows
-        it (default); 0: two launches.  Same results either way."""
+        """1: the whole step as one launch where the plan allows it;
+        0 (the default): two launches.  Same results either way."""
         _check(_lib.rbe_set_fused(self._ctx, int(enable)))
 
     def timing_enable(self, max_launches):
