@@ -57,6 +57,10 @@ struct rbe_ctx_s {
   int32_t* d_m_pre = nullptr;    // 3p
   bool pre_valid = false;        // a batch for step pre_step was drawn ahead (device checks the cell)
   uint64_t pre_step = 0;
+  // the cell of the last launch as the host knows it (passed by value), so
+  // that a changed cell skips the drawn-ahead batch without a device check
+  bool last_cell_known = false;
+  double last_cell[6] = {0, 0, 0, 0, 0, 0};
   // online Metropolis-Hastings sampler: chain states [2][3p], the buffer
   // holding the latest state, and whether the chains have started
   int32_t sampler = RBE_SAMPLER_EXACT;
@@ -359,6 +363,12 @@ rbe_status plan_flush(rbe_ctx_s* c, PendingLaunch* pl) {
   }
   pl->tables = 1;
   pl->table_args = a;
+  // the table kernel commits this cell: what the host knows of it
+  c->last_cell_known = a.box_src == BOX_ARGS || (a.box_src == BOX_COMMITTED && c->last_cell_known);
+  if (a.box_src == BOX_ARGS) {
+    for (int k = 0; k < 3; ++k) c->last_cell[k] = a.box_arg[k];
+    for (int k = 0; k < 3; ++k) c->last_cell[3 + k] = a.tri_arg.on ? a.tri_arg.tilt[k] : 0.0;
+  }
   if (c->pend_sample) {
     StepArgs d = a;
     if (reuse) { d.bs = c->d_bs_frozen; d.tab = c->d_tab_frozen; }
@@ -482,11 +492,35 @@ rbe_status kspace_step_args(rbe_ctx c, const double* d_x, const double* d_y, con
   a.fx = d_fx; a.fy = d_fy; a.fz = d_fz;
   a.accumulate = accumulate ? 1 : 0;
   a.virial6 = d_virial6; a.energy = d_energy;
-  // a sampled step of the two-launch path draws the next step's batch
-  // ahead, for its own cell (the single launch has no spare block for it)
-  a.predraw = a.sample && c->sampler == RBE_SAMPLER_EXACT && !single_launch ? 1 : 0;
-  if (single_launch) a.use_pre = 0;
-  if (a.predraw) { c->pre_valid = true; c->pre_step = a.step + 1; }
+  // The cell of this launch as far as the host knows it: given by value, or
+  // the committed one (that of the last launch); a device pointer is not
+  // known here.  A batch drawn ahead was drawn for the last launch's cell, so
+  // a known change of cell rules it out without the device's check (a
+  // dependent global read at the start of every block), and a sampled step
+  // of the two-launch path draws the next step's batch ahead only while the
+  // cell stays the same (under a barostat it changes every step and the
+  // batch drawn ahead would never be used).  The single launch has no spare
+  // block for it.
+  bool known = false;
+  double cell[6] = {0, 0, 0, 0, 0, 0};
+  if (a.box_src == BOX_ARGS) {
+    known = true;
+    for (int k = 0; k < 3; ++k) cell[k] = a.box_arg[k];
+    if (a.tri_arg.on)
+      for (int k = 0; k < 3; ++k) cell[3 + k] = a.tri_arg.tilt[k];
+  } else if (a.box_src == BOX_COMMITTED && c->last_cell_known) {
+    known = true;
+    for (int k = 0; k < 6; ++k) cell[k] = c->last_cell[k];
+  }
+  bool same = known && c->last_cell_known;
+  for (int k = 0; k < 6 && same; ++k) same = cell[k] == c->last_cell[k];
+  const bool changed = known && c->last_cell_known && !same;
+  if (changed || single_launch) a.use_pre = 0;
+  a.predraw = a.sample && c->sampler == RBE_SAMPLER_EXACT && !single_launch && !changed ? 1 : 0;
+  c->pre_valid = a.predraw != 0;
+  if (a.predraw) c->pre_step = a.step + 1;
+  c->last_cell_known = known;
+  for (int k = 0; k < 6; ++k) c->last_cell[k] = cell[k];
   clear_pending(c);
   *out = a;
   return RBE_OK;

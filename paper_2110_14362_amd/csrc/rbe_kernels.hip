@@ -92,9 +92,9 @@ constexpr int kTableTasks = 6;     // (axis, table) pairs of build_tables, one w
 // segment, the lane totals are scanned across the wave.  Writes the cell
 // values to *out (LDS).  Must be reached by every thread of the block.
 __device__ void build_tables(const double l[3], const TriCell* tcp, double alpha, double tail_ln,
-                             const int mcap[3], double* tab, BoxState* out, double* sh_T) {
+                             const int mcap[3], double* tab, BoxState* out, double* sh_T, int nt) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int nw = blockDim.x / kWave;
+  const int nw = nt / kWave;
   int err = 0, mc[3], off[3];
   const bool tri = tcp != nullptr && tcp->on;
   const TriCell& tc = *tcp;          // read only when tri
@@ -303,10 +303,16 @@ static_assert(sizeof(BoxState) % 8 == 0, "cell values copied as 8-byte words");
 // kBoxWords threads.
 __device__ __forceinline__ void commit_cell(const BoxState& b, BoxState* dst, int tid) {
   constexpr int ew = __builtin_offsetof(BoxState, err) / 8;
+  static_assert(__builtin_offsetof(BoxState, err) == 8 * ew + 4, "err: high half of its word");
   if (tid >= kBoxWords) return;
-  const int32_t e0 = tid == ew ? dst->err : 0;
-  reinterpret_cast<uint64_t*>(dst)[tid] = reinterpret_cast<const uint64_t*>(&b)[tid];
-  if (tid == ew) dst->err = b.err | e0;
+  if (tid != ew) {
+    reinterpret_cast<uint64_t*>(dst)[tid] = reinterpret_cast<const uint64_t*>(&b)[tid];
+  } else {
+    // the word's low half, then the error flags OR-ed in (no read of dst, so
+    // the block does not wait for its loads in flight)
+    reinterpret_cast<int32_t*>(dst)[2 * ew] = reinterpret_cast<const int32_t*>(&b)[2 * ew];
+    if (b.err) __hip_atomic_fetch_or(&dst->err, b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // A system's kernel arguments into LDS, 8 bytes per thread (a one-thread
@@ -399,8 +405,8 @@ __device__ __forceinline__ void kahan_add(float& sum, float& comp, float v) {
 // a few 1e-16 absolute.
 constexpr int kSinCosTab = 256;
 
-__device__ __forceinline__ void fill_sincos_tab(double2* tab) {
-  for (int k = threadIdx.x; k < kSinCosTab; k += blockDim.x) {
+__device__ __forceinline__ void fill_sincos_tab(double2* tab, int nt) {
+  for (int k = threadIdx.x; k < kSinCosTab; k += nt) {
     double sn, cs;
     sincospi((double)k * (2.0 / kSinCosTab), &sn, &cs);
     tab[k] = make_double2(cs, sn);
@@ -509,13 +515,13 @@ __device__ void mh_frequency(const StepArgs& a, const BoxState& b, int l, int m[
 // the waves that build_tables leaves idle (one wave per (axis, table): six),
 // so that they run beside the table build instead of after it; the draw then
 // only searches the tables.  Reached by every thread before build_tables,
-// whose closing barrier makes su visible.  blockDim.x > kTableTasks waves.
+// whose closing barrier makes su visible.  nt (the block's threads) > kTableTasks waves.
 __device__ __forceinline__ void slice_uniforms(uint64_t* su, int FB, int64_t slice, int64_t p,
-                                               uint64_t seed, uint64_t sysid, uint64_t step) {
+                                               uint64_t seed, uint64_t sysid, uint64_t step, int nt) {
   const int t = (int)threadIdx.x - kTableTasks * kWave;
-  const int nt = (int)blockDim.x - kTableTasks * kWave;
+  const int nu = nt - kTableTasks * kWave;
   if (t < 0) return;
-  for (int s2 = t; s2 < FB && slice + s2 < p; s2 += nt) {
+  for (int s2 = t; s2 < FB && slice + s2 < p; s2 += nu) {
     uint64_t c[4] = {step, (uint64_t)(slice + s2), kTagKSample, 0ull};
     philox4x64_10(c, seed, sysid);
 #pragma unroll
@@ -544,7 +550,7 @@ __global__ void __launch_bounds__(256) k_tables(StepArgs a) {
   double l[3];
   const TriCell* tc = stage_tri(a, &stc);
   box_source(a, l);
-  build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T);
+  build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T, 256);
   commit_cell(sbs, a.bs, threadIdx.x);
 }
 
@@ -641,7 +647,7 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, i
 // blocks of the same launch), else plainly (rows of an earlier launch, which
 // the L2 may then serve to several blocks); dst is written with coherent
 // stores when dst_coh, else plainly (LDS).  Reached by every thread;
-// scratch holds blockDim.x entries.
+// scratch holds nt entries (nt = the block's threads).
 template <bool SrcCoh = true>
 __device__ __forceinline__ double2 ld_row(const double2* p) {
   return SrcCoh ? ld_coh2(p) : *p;
@@ -649,7 +655,7 @@ __device__ __forceinline__ double2 ld_row(const double2* p) {
 
 template <bool SrcCoh = true, int kB = 8>
 __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
-                               bool dst_coh, double2* scratch) {
+                               bool dst_coh, double2* scratch, int nt) {
   // rows r0, r0 + step, ... (< R) of column col added in that order; loads
   // issued kB at a time (independent, all in flight) before the adds
   auto column_sum = [&](int col, int r0, int step) {
@@ -666,7 +672,7 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
     }
     return acc;
   };
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x;
   if (W >= nt) {
     for (int col = t; col < W; col += nt) {
       const double2 acc = column_sum(col, 0, 1);
@@ -743,11 +749,11 @@ __device__ __forceinline__ void freq_consts(const int mi[3], double2 r, const Bo
 // frequencies already summed in a fixed order, zero on idle threads), in a
 // fixed order: 7 x 8 strided partial sums over the threads through LDS, then
 // the 8 partials in order.  Writes the virial tensor and the energy.  Reached
-// by every thread; stv holds 7*blockDim.x doubles.
+// by every thread (nt of them); stv holds 7*nt doubles.
 __device__ void virial_energy(const double tv[7], double* stv, double (*sh_vs)[8],
                               const BoxState& b, double coulomb, int p, double self_energy,
-                              double* virial6, double* energy) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+                              double* virial6, double* energy, int nt) {
+  const int tid = threadIdx.x;
   lds_barrier();
   for (int c = 0; c < 7; ++c) stv[c * nt + tid] = tv[c];
   lds_barrier();
@@ -861,7 +867,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   __shared__ double2 sctab[F64 ? kSinCosTab : 1];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;
-  if (F64) fill_sincos_tab(sctab);        // read after the barriers below
+  if (F64) fill_sincos_tab(sctab, kSfacThreads);   // read after the barriers below
   const TriCell* tc = stage_tri(a, &stc);
   unsigned char* base = lds_raw;
   int* sm = reinterpret_cast<int*>(base + kR0);                     // batch slice, 3 ints each
@@ -872,7 +878,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     if (y != 0) return;
     double l[3];
     box_source(a, l);
-    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads);
     const uint64_t next = a.step + 1;
     const int slot = (int)(next & 1);
     int32_t* mp = a.m_pre + (int64_t)slot * 3 * a.p;
@@ -888,6 +894,14 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     }
     return;
   }
+
+  // ---- the cell's sides first: they may be global loads (a device or the
+  // committed cell), and a wait for a load also waits for every load issued
+  // before it, so the particle loads go out after them and the table build
+  // does not wait for the particles
+  double lc[3];
+  box_source(a, lc);
+  __builtin_amdgcn_sched_barrier(0);
 
   // ---- first tile of particles: loads issued now, consumed after the tables
   const int64_t c0 = (int64_t)x * a.chunk;
@@ -925,33 +939,39 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   if (pre) {
     if (x == 0 && y == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else if (need_tables) {
-    if (su_on) slice_uniforms(su, FB, slice, a.p, a.seed, a.sysid, a.step);
-    double l[3];
-    box_source(a, l);
-    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    if (su_on) slice_uniforms(su, FB, slice, a.p, a.seed, a.sysid, a.step, kSfacThreads);
+    build_tables(lc, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads);
     if (x == 0 && y == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else {
     load_box(sbs, a.bs, tid);
     lds_barrier();
   }
 
-  // ---- this block's slice of the batch
-  for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
-    const int64_t l = slice + s2;
-    int mv[3] = {0, 0, 0};
-    if (l < a.p) {
-      if (pre) {
-        mv[0] = m_pre[3 * l]; mv[1] = m_pre[3 * l + 1]; mv[2] = m_pre[3 * l + 2];
-        if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
-      } else if (a.sample) {
+  // ---- this block's slice of the batch: drawn here, or read (drawn ahead,
+  // or stored); one loop per case, so that the drawing loop has no global
+  // loads (whose waits would also wait for the particles)
+  if (!pre && a.sample) {
+    for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
+      const int64_t l = slice + s2;
+      int mv[3] = {0, 0, 0};
+      if (l < a.p) {
         draw_frequency<TRI>(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv,
                             su_on ? su + s2 : nullptr, FB);
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
-      } else {
-        mv[0] = a.m[3 * l]; mv[1] = a.m[3 * l + 1]; mv[2] = a.m[3 * l + 2];
       }
+      sm[3 * s2] = mv[0]; sm[3 * s2 + 1] = mv[1]; sm[3 * s2 + 2] = mv[2];
     }
-    sm[3 * s2] = mv[0]; sm[3 * s2 + 1] = mv[1]; sm[3 * s2 + 2] = mv[2];
+  } else {
+    const int32_t* msrc = pre ? m_pre : a.m;
+    for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
+      const int64_t l = slice + s2;
+      int mv[3] = {0, 0, 0};
+      if (l < a.p) {
+        mv[0] = msrc[3 * l]; mv[1] = msrc[3 * l + 1]; mv[2] = msrc[3 * l + 2];
+        if (pre && x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
+      }
+      sm[3 * s2] = mv[0]; sm[3 * s2 + 1] = mv[1]; sm[3 * s2 + 2] = mv[2];
+    }
   }
   lds_barrier();
 
@@ -1045,7 +1065,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     if (!arrive_last(a.cnt + cnt_index(a, CNT_GROUP, y * a.NG + g), (uint32_t)gsize, &sh_flag))
       return;
     block_sum_rows(a.partial + (int64_t)g * a.GX * a.Ppad + slice, a.Ppad, gsize, FB,
-                   a.gpart + (int64_t)g * a.Ppad + slice, true, red);
+                   a.gpart + (int64_t)g * a.Ppad + slice, true, red, kSfacThreads);
     if (tid == 0) a.cnt[cnt_index(a, CNT_GROUP, y * a.NG + g)] = 0u;
   }
 
@@ -1058,9 +1078,9 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   if (!arrive_last(a.cnt + cnt_index(a, CNT_SLICE, y), (uint32_t)a.NG, &sh_flag)) return;
   double2* srho = reinterpret_cast<double2*>(tabs);          // R2 (tables are dead)
   if (a.NG > 1)
-    block_sum_rows(a.gpart + slice, a.Ppad, a.NG, FB, srho, false, red);
+    block_sum_rows(a.gpart + slice, a.Ppad, a.NG, FB, srho, false, red, kSfacThreads);
   else
-    block_sum_rows(a.partial + slice, a.Ppad, a.X, FB, srho, false, red);
+    block_sum_rows(a.partial + slice, a.Ppad, a.X, FB, srho, false, red, kSfacThreads);
   double tv[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int s2 = tid; s2 < FB; s2 += kSfacThreads) {
     if (slice + s2 >= a.p) break;
@@ -1091,7 +1111,8 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     for (int l = tid; l < a.p; l += kSfacThreads)
       for (int c = 0; c < 7; ++c) tv[c] += ld_coh(a.terms + (int64_t)l * 8 + c);
   }
-  virial_energy(tv, tabs, sh_vs, sbs, a.coulomb, a.p, a.self_energy, a.virial6, a.energy);
+  virial_energy(tv, tabs, sh_vs, sbs, a.coulomb, a.p, a.self_energy, a.virial6, a.energy,
+                kSfacThreads);
   if (tid == 0 && a.Y > 1) a.cnt[cnt_index(a, CNT_BATCH)] = 0u;
 }
 
@@ -1175,7 +1196,7 @@ hipError_t launch_sfac_multi(int precision, int R, const StepArgs* d_tab, const 
 // (10^6 charges, P = 2000: 2.5 % faster than 32 KB).
 template <bool F64>
 constexpr int force_stage_bytes() { return F64 ? 32768 : 16384; }
-// red_raw holds, in turn: the small-batch row sums (scratch of blockDim.x
+// red_raw holds, in turn: the small-batch row sums (scratch of nt
 // double2, then rho of Ppad <= 512 double2) and the cross-wave sums (at most
 // 8 waves x 64 lanes x RP particles x 3 components, FP32 with RP = 2 or FP64
 // with RP = 1: 12 KB).  Blocks have at most 8 waves (KS <= 8, PW = 8 only with
@@ -1247,22 +1268,24 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   __shared__ double sh_vs[7][8];
   __shared__ double2 sctab[F64 ? kSinCosTab : 1];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  const int nw = blockDim.x / kWave;
-  const int PW = a.PW, KS = nw / PW;
+  // the block's threads from the plan (KS x PW waves, as launched): blockDim
+  // is a load from the dispatch packet, whose wait would also wait for the
+  // particle loads in flight
+  const int PW = a.PW, KS = a.KS, nt = KS * PW * kWave;
   const bool extra = k2red && bx == nbx - 1;
-  if (F64 && !extra) fill_sincos_tab(sctab);   // read after the barriers below
+  if (F64 && !extra) fill_sincos_tab(sctab, nt);   // read after the barriers below
   // rows of rho partials left by k_sfac in k2reduce mode
   const double2* rows = a.NG > 1 ? a.gpart : a.partial;
   const int Rr = a.NG > 1 ? a.NG : a.X;
-  double2* scratch = reinterpret_cast<double2*>(red_raw);   // blockDim.x entries
-  double2* srho = scratch + blockDim.x;                       // Ppad <= 512 entries
+  double2* scratch = reinterpret_cast<double2*>(red_raw);   // nt entries
+  double2* srho = scratch + nt;                               // Ppad <= 512 entries
 
   if (extra) {
     load_box(sbs, a.bs, tid);
     lds_barrier();
-    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
+    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt);
     double tv[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int l = tid; l < a.p; l += blockDim.x) {
+    for (int l = tid; l < a.p; l += nt) {
       const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
       const double2 r = srho[l];
       a.rho[l] = r;
@@ -1273,7 +1296,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       for (int c = 0; c < 7; ++c) tv[c] += tl[c];
     }
     virial_energy(tv, reinterpret_cast<double*>(scoef), sh_vs, sbs, a.coulomb, a.p,
-                  a.self_energy, a.virial6, a.energy);
+                  a.self_energy, a.virial6, a.energy, nt);
     return;
   }
 
@@ -1288,8 +1311,8 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   }
   if (k2red) {
     load_box(sbs, a.bs, tid);
-    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch);
-    for (int l = tid; l < a.p; l += blockDim.x) {
+    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt);
+    for (int l = tid; l < a.p; l += nt) {
       const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
       FCoef64 f;
       FCoef32 h;
@@ -1329,7 +1352,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       const int nvec = (int)((size_t)cnt * sizeof(Coef) / 16);
       const uint4* src = reinterpret_cast<const uint4*>(gcoef + cb);
       uint4* dst = reinterpret_cast<uint4*>(scoef);
-      for (int v = tid; v < nvec; v += blockDim.x) dst[v] = src[v];
+      for (int v = tid; v < nvec; v += nt) dst[v] = src[v];
       lds_barrier();
     }
     const int per = (cnt + KS - 1) / KS;
@@ -1516,7 +1539,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int x = blockIdx.x;
   const int KB = a.KB, SUB = kSfacWaves / KB, FB = KB * kWave * R;   // FB = Ppad >= p
-  if (F64) fill_sincos_tab(sctab);          // read after the barriers below
+  if (F64) fill_sincos_tab(sctab, kSfacThreads);   // read after the barriers below
   const TriCell* tc = stage_tri(a, &stc);
   unsigned char* tile = lds_raw;
   double* qd = reinterpret_cast<double*>(lds_raw + kStepTile);
@@ -1530,7 +1553,12 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   double* redd = reinterpret_cast<double*>(red_raw);
   float* redf = reinterpret_cast<float*>(red_raw);
 
-  // ---- 1. the chunk's particles: loads issued now, used after the tables
+  // ---- 1. the cell's sides, then the chunk's particles (loads issued now,
+  // used after the tables): the sides may be global loads, and a wait for a
+  // load also waits for every older one, so they go out first
+  double lc[3];
+  box_source(a, lc);
+  __builtin_amdgcn_sched_barrier(0);
   const int64_t c0 = (int64_t)x * a.chunk;
   const int cnt = (int)min((int64_t)a.chunk, a.n - c0);        // 1 .. kTile (plan)
   double px = 0.0, py = 0.0, pz = 0.0, pq = 0.0;
@@ -1542,10 +1570,8 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   const bool su_on = a.sample && (size_t)FB * 4 * sizeof(uint64_t) <= kStepTile;
   uint64_t* su = reinterpret_cast<uint64_t*>(tile);
   if (a.sample || a.box_src != BOX_COMMITTED) {
-    if (su_on) slice_uniforms(su, FB, 0, a.p, a.seed, a.sysid, a.step);
-    double l[3];
-    box_source(a, l);
-    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T);
+    if (su_on) slice_uniforms(su, FB, 0, a.p, a.seed, a.sysid, a.step, kSfacThreads);
+    build_tables(lc, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads);
     if (x == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else {
     load_box(sbs, a.bs, tid);
@@ -1646,7 +1672,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
     }
   }
   if (!ok) return;
-  block_sum_rows<true, 16>(a.partial, a.Ppad, a.X, a.Ppad, srho, false, red2);
+  block_sum_rows<true, 16>(a.partial, a.Ppad, a.X, a.Ppad, srho, false, red2, kSfacThreads);
   double tv[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int l = tid; l < a.p; l += kSfacThreads) {
     const int mi[3] = {sm[3 * l], sm[3 * l + 1], sm[3 * l + 2]};
@@ -1669,7 +1695,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   if (x == 0) {
     const double self = a.qsum_dev ? -a.coulomb * a.qsum_dev[2] * sqrt(a.alpha / M_PI)
                                    : a.self_energy;
-    virial_energy(tv, redd, sh_vs, sbs, a.coulomb, a.p, self, a.virial6, a.energy);
+    virial_energy(tv, redd, sh_vs, sbs, a.coulomb, a.p, self, a.virial6, a.energy, kSfacThreads);
   }
   lds_barrier();
 
