@@ -1280,13 +1280,22 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   double2* scratch = reinterpret_cast<double2*>(red_raw);   // nt entries
   double2* srho = scratch + nt;                               // Ppad <= 512 entries
 
+  // Loads issued before the rows are summed, consumed after: this thread's
+  // word of the cell values and, in the small-batch mode, the first frequency
+  // it forms constants for (a wait for a load also waits for every older one,
+  // so loads whose results are needed late go out first)
+  const uint64_t bw = tid < kBoxWords ? reinterpret_cast<const uint64_t*>(a.bs)[tid] : 0ull;
+  int mf[3] = {0, 0, 0};
+  if (k2red && tid < a.p) { mf[0] = a.m[3 * tid]; mf[1] = a.m[3 * tid + 1]; mf[2] = a.m[3 * tid + 2]; }
+
   if (extra) {
-    load_box(sbs, a.bs, tid);
-    lds_barrier();
     block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt);
+    if (tid < kBoxWords) reinterpret_cast<uint64_t*>(&sbs)[tid] = bw;
+    lds_barrier();
     double tv[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int l = tid; l < a.p; l += nt) {
-      const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
+      int mi[3] = {mf[0], mf[1], mf[2]};
+      if (l != tid) { mi[0] = a.m[3 * l]; mi[1] = a.m[3 * l + 1]; mi[2] = a.m[3 * l + 2]; }
       const double2 r = srho[l];
       a.rho[l] = r;
       FCoef64 f;
@@ -1310,10 +1319,12 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
     if (i < a.n) { xi[r] = a.x[i]; yi[r] = a.y[i]; zi[r] = a.z[i]; }
   }
   if (k2red) {
-    load_box(sbs, a.bs, tid);
     block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt);
+    if (tid < kBoxWords) reinterpret_cast<uint64_t*>(&sbs)[tid] = bw;
+    lds_barrier();
     for (int l = tid; l < a.p; l += nt) {
-      const int mi[3] = {a.m[3 * l], a.m[3 * l + 1], a.m[3 * l + 2]};
+      int mi[3] = {mf[0], mf[1], mf[2]};
+      if (l != tid) { mi[0] = a.m[3 * l]; mi[1] = a.m[3 * l + 1]; mi[2] = a.m[3 * l + 2]; }
       FCoef64 f;
       FCoef32 h;
       double tl[7];
@@ -1322,7 +1333,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       else reinterpret_cast<FCoef32*>(scoef)[l] = h;
     }
   } else {
-    load_box(sbs, a.bs, tid);
+    if (tid < kBoxWords) reinterpret_cast<uint64_t*>(&sbs)[tid] = bw;
   }
   lds_barrier();
   const Coef* gcoef = F64 ? reinterpret_cast<const Coef*>(a.fc64)

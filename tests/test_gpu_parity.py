@@ -375,6 +375,55 @@ def test_consecutive_steps(gpu, case, precision, p, fixed_cell):
         assert_parity(e, precision, step)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_drawn_ahead_batch_across_cell_changes(gpu, precision):
+    # The host skips the batch drawn ahead when it knows the cell changed, and
+    # draws ahead only while the cell stays the same; a cell given on the
+    # device is unknown to it (the device checks).  A sequence of unchanged,
+    # changed, device-given and repeated cells: every step's batch must be the
+    # oracle's exact draw for that step and cell, and the forces at parity.
+    import torch
+    from paper_2110_14362_amd.rbe import RBE
+    s = small_water()
+    p = 100
+    q = torch.tensor(s["q"], dtype=torch.float64, device=gpu)
+    ctx = RBE(q, s["box"], p, s["alpha"], coulomb=s["coulomb"], precision=precision,
+              seed=91, system_id=4)
+    rng = np.random.default_rng(8)
+    base = np.asarray(s["box"], dtype=np.float64)
+    # (scale of the cell, passed on the device?)
+    plan = [(1.0, False), (1.0, False), (1.002, False), (1.002, False), (1.002, True),
+            (1.002, False), (0.999, True), (0.999, False), (1.001, False), (1.0, False),
+            (1.0, False)]
+    for step, (scale, dev) in enumerate(plan):
+        box = base * scale
+        pos = np.mod(s["pos"] * scale + rng.normal(0, 0.05, s["pos"].shape), box)
+        x, y, z = (torch.tensor(pos[:, a], dtype=torch.float64, device=gpu) for a in range(3))
+        f = [torch.zeros_like(x) for _ in range(3)]
+        vir = torch.zeros(6, dtype=torch.float64, device=gpu)
+        en = torch.zeros(1, dtype=torch.float64, device=gpu)
+        dbox = torch.tensor(box, dtype=torch.float64, device=gpu)   # alive until the step ran
+        if dev:
+            ctx.rescale_box_dev(dbox)
+        else:
+            ctx.rescale_box(box)
+        ctx.sample_k(step)
+        ctx.forces_pressure(x, y, z, *f, virial6=vir, energy=en)
+        torch.cuda.synchronize()
+        m = ctx.get_k().astype(np.int64)
+        m_o = osamp.sample_k(s["alpha"], box, p, seed=91, system_id=4, step=step)
+        assert np.array_equal(m, m_o), (step, scale, dev)
+        o = oracle_eval(dict(s, pos=pos, box=box), m_o)
+        W6 = vir.cpu().numpy()
+        W = np.array([[W6[0], W6[3], W6[4]], [W6[3], W6[1], W6[5]], [W6[4], W6[5], W6[2]]])
+        g = dict(rho=ctx.get_rho(), forces=np.stack([t.cpu().numpy() for t in f], 1),
+                 virial=W, energy=float(en.cpu()[0]))
+        e = errors(g, o, s["q"])
+        report("cell sequence step %d scale %.3f device %s %s" % (step, scale, dev, precision), e)
+        assert_parity(e, precision, step)
+    ctx.check()
+
+
 # ------------------------------------------------------------------ one launch vs two
 
 def _steps(s, dev, precision, fused, steps, p):
