@@ -21,7 +21,7 @@
 //             virial are per-lane sums reduced in a fixed order by the
 //             last-arriving block
 #include "rbe_real_internal.h"
-#include "erfcx_cheb.h"
+#include "erfcx_poly.h"
 #include <math.h>
 
 namespace rbe {
@@ -228,8 +228,8 @@ __device__ __forceinline__ void wave_sync() {
 struct PairQueue {
   int j[kPairQueue];
   int s[kPairQueue];
-  double cheb[kErfcxTerms];
-  float cheb32[kErfcxTerms32];
+  double poly[kErfcxTerms];
+  float poly32[kErfcxTerms32];
   int seg_off[kSegments + 1];   // candidate offset of each neighbour segment (exclusive scan)
   int seg_j0[kSegments];        // its first cell-ordered index
   int seg_code[kSegments];      // its periodic shift
@@ -238,10 +238,11 @@ struct PairQueue {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// erfcx(x) = exp(x^2) erfc(x) for x >= 0 from its Chebyshev series in
-// t = (x - K)/(x + K) (Clenshaw); erfc(x) = exp(-x^2) erfcx(x) then shares
-// exp(-x^2) with the force term.  The coefficients are read from LDS, which
-// keeps them out of the scalar registers.
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0 as a polynomial in
+// t = (x - K)/(x + K) (Horner's rule: one FMA per term); erfc(x) =
+// exp(-x^2) erfcx(x) then shares exp(-x^2) with the force term.  The
+// coefficients are read from LDS, which keeps them out of the scalar
+// registers.
 // 1/d for d > 0: the hardware estimate refined by two Newton steps (an ulp or
 // two; the correctly rounded division takes twice the instructions)
 __device__ __forceinline__ double rcp_nr(double d) {
@@ -250,16 +251,12 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return fma(fma(-d, y, 1.0), y, y);
 }
 
-__device__ __forceinline__ double erfcx_pos(double x, const double* cheb) {
-  const double t = (x - kErfcxK) * rcp_nr(x + kErfcxK), t2 = 2.0 * t;
-  double b1 = 0.0, b2 = 0.0;
+__device__ __forceinline__ double erfcx_pos(double x, const double* poly) {
+  const double t = (x - kErfcxK) * rcp_nr(x + kErfcxK);
+  double y = poly[kErfcxTerms - 1];
 #pragma unroll
-  for (int k = kErfcxTerms - 1; k >= 1; --k) {
-    const double b0 = fma(t2, b1, cheb[k] - b2);
-    b2 = b1;
-    b1 = b0;
-  }
-  return fma(t, b1, cheb[0] - b2);
+  for (int k = kErfcxTerms - 2; k >= 0; --k) y = fma(y, t, poly[k]);
+  return y;
 }
 
 // A queued pair as loaded for evaluation: j's position and charge, its
@@ -291,7 +288,7 @@ __device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue
 // one pair's force on i (g), energy and virial terms (FP64)
 __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, double sa, double two_sa_pi,
-                                          const double* cheb, const double* lj, double& gx,
+                                          const double* poly, const double* lj, double& gx,
                                           double& gy, double& gz, double& u, double w[6]) {
   gx = 0.0; gy = 0.0; gz = 0.0;
   if (valid) {
@@ -301,7 +298,7 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
     // Coulomb: phi = C qi qj erfc(sa r)/r,  -phi' = C qi qj G(r)
     const double qq = a.coulomb * vi.w * p.qj;
     const double g2 = exp(-a.alpha * r2);
-    const double er = g2 * erfcx_pos(sa * r, cheb);
+    const double er = g2 * erfcx_pos(sa * r, poly);
     double dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
     u += qq * er * ir;
     if (a.ntypes > 0) {
@@ -321,10 +318,10 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
 
 __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, const double l[3], double sa,
-                                          double two_sa_pi, const double* cheb, double f[3],
+                                          double two_sa_pi, const double* poly, double f[3],
                                           double& u, double w[6]) {
   double gx, gy, gz;
-  pair_core(a, p, valid, vi, ti, sa, two_sa_pi, cheb, a.lj, gx, gy, gz, u, w);
+  pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, a.lj, gx, gy, gz, u, w);
   f[0] += wsum(gx);
   f[1] += wsum(gy);
   f[2] += wsum(gz);
@@ -335,16 +332,12 @@ __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, 
 // series, exp(-x^2) and 1/sqrt from the hardware approximations (a few ulp);
 // energy and virial summed per lane in FP32 over one particle's pairs, then
 // folded into FP64; the force's wave sum is formed in FP32 and added in FP64.
-__device__ __forceinline__ float erfcx_pos32(float x, const float* cheb) {
-  const float t = (x - (float)kErfcxK) * __builtin_amdgcn_rcpf(x + (float)kErfcxK), t2 = 2.0f * t;
-  float b1 = 0.0f, b2 = 0.0f;
+__device__ __forceinline__ float erfcx_pos32(float x, const float* poly) {
+  const float t = (x - (float)kErfcxK) * __builtin_amdgcn_rcpf(x + (float)kErfcxK);
+  float y = poly[kErfcxTerms32 - 1];
 #pragma unroll
-  for (int k = kErfcxTerms32 - 1; k >= 1; --k) {
-    const float b0 = fmaf(t2, b1, cheb[k] - b2);
-    b2 = b1;
-    b1 = b0;
-  }
-  return fmaf(t, b1, cheb[0] - b2);
+  for (int k = kErfcxTerms32 - 2; k >= 0; --k) y = fmaf(y, t, poly[k]);
+  return y;
 }
 
 __device__ __forceinline__ float wsumf(float v) {
@@ -355,7 +348,7 @@ __device__ __forceinline__ float wsumf(float v) {
 
 __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p, bool valid,
                                             const double4& vi, int ti, float sa, float two_sa_pi,
-                                            float alpha, const float* cheb, const double* lj,
+                                            float alpha, const float* poly, const double* lj,
                                             float& gx, float& gy, float& gz, float& u,
                                             float w[6]) {
   gx = 0.0f; gy = 0.0f; gz = 0.0f;
@@ -365,7 +358,7 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
     const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
     const float qq = (float)(a.coulomb * vi.w * p.qj);
     const float g2 = __expf(-alpha * r2);
-    const float er = g2 * erfcx_pos32(sa * r, cheb);
+    const float er = g2 * erfcx_pos32(sa * r, poly);
     float dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
     u += qq * er * ir;
     if (a.ntypes > 0) {
@@ -384,10 +377,10 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
 
 __device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p, bool valid,
                                             const double4& vi, int ti, const double l[3], float sa,
-                                            float two_sa_pi, float alpha, const float* cheb,
+                                            float two_sa_pi, float alpha, const float* poly,
                                             double f[3], float& u, float w[6]) {
   float gx, gy, gz;
-  pair_core32(a, p, valid, vi, ti, sa, two_sa_pi, alpha, cheb, a.lj, gx, gy, gz, u, w);
+  pair_core32(a, p, valid, vi, ti, sa, two_sa_pi, alpha, poly, a.lj, gx, gy, gz, u, w);
   f[0] += (double)wsumf(gx);
   f[1] += (double)wsumf(gy);
   f[2] += (double)wsumf(gz);
@@ -574,8 +567,8 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   if (a.skin > 0.0) return;                     // list mode: k_pairs_list
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
-  if (lane < kErfcxTerms) Q.cheb[lane] = kErfcxCheb[lane];
-  if (lane < kErfcxTerms32) Q.cheb32[lane] = kErfcxCheb32[lane];
+  if (lane < kErfcxTerms) Q.poly[lane] = kErfcxPoly[lane];
+  if (lane < kErfcxTerms32) Q.poly32[lane] = kErfcxPoly32[lane];
   wave_sync();
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   double l[3];
@@ -662,9 +655,9 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
         if (from + lane < m) cur = pair_load(a, Q, from + lane, vi, l);
         if (P32)
           pair_eval32(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
-                      (float)a.alpha, Q.cheb32, f, u32, w32);
+                      (float)a.alpha, Q.poly32, f, u32, w32);
         else
-          pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.cheb, f, u, w);
+          pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, f, u, w);
       }
       wave_sync();
       if (lane < qn - m) { Q.j[lane] = Q.j[m + lane]; Q.s[lane] = Q.s[m + lane]; }
@@ -840,15 +833,15 @@ __device__ __forceinline__ void list_to_lds(const RealArgs& a, int t, int c0, in
 template <bool P32, bool LJL>
 __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int nbx) {
   __shared__ int32_t lidx[kPairWaves][2][kListChunk];
-  __shared__ double cheb[kErfcxTerms];
-  __shared__ float cheb32[kErfcxTerms32];
+  __shared__ double poly[kErfcxTerms];
+  __shared__ float poly32[kErfcxTerms32];
   __shared__ double ljs[LJL ? 2 * kLjLds * kLjLds : 1];
   __shared__ double sh[kPairWaves][8];
   __shared__ int sh_last;
   if (!(a.skin > 0.0)) return;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  if (threadIdx.x < kErfcxTerms) cheb[threadIdx.x] = kErfcxCheb[threadIdx.x];
-  if (threadIdx.x < kErfcxTerms32) cheb32[threadIdx.x] = kErfcxCheb32[threadIdx.x];
+  if (threadIdx.x < kErfcxTerms) poly[threadIdx.x] = kErfcxPoly[threadIdx.x];
+  if (threadIdx.x < kErfcxTerms32) poly32[threadIdx.x] = kErfcxPoly32[threadIdx.x];
   if (LJL)
     for (int q = threadIdx.x; q < 2 * a.ntypes * a.ntypes; q += blockDim.x) ljs[q] = a.lj[q];
   __syncthreads();
@@ -911,12 +904,12 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
         p.tj = jc >> kListTypeShift;
         if (P32) {
           float gx, gy, gz;
-          pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, cheb32,
+          pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, poly32,
                       LJL ? ljs : a.lj, gx, gy, gz, u32, w32);
           fx32 += gx; fy32 += gy; fz32 += gz;
         } else {
           double gx, gy, gz;
-          pair_core(a, p, valid, vi, ti, sa, two_sa_pi, cheb, LJL ? ljs : a.lj, gx, gy, gz, u, w);
+          pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, LJL ? ljs : a.lj, gx, gy, gz, u, w);
           fx += gx; fy += gy; fz += gz;
         }
       }
