@@ -247,11 +247,11 @@ __device__ bool rigid_positions(const double r0[3][3], double r[3][3], const dou
 }
 
 // A_R on a molecule, then the position constraint and the momentum change
-// p += m (r_constrained - r_unconstrained) a / (e^{a h} - 1) per axis
+// p += m (r_constrained - r_unconstrained) a / (e^{a h} - 1) per axis;
+// e[d] = e^{a_d h}, f[d] = (e^{a_d h} - 1)/a_d
 __device__ __forceinline__ bool rigid_drift(const MDArgs& a, double r[3][3], double p[3][3],
-                                            const double m[3], const double rate[3], double h) {
-  double r0[3][3], ru[3][3], e[3], f[3];
-  for (int d = 0; d < 3; ++d) { e[d] = exp(rate[d] * h); f[d] = expm1_over(rate[d], h); }
+                                            const double m[3], const double e[3], const double f[3]) {
+  double r0[3][3], ru[3][3];
   for (int k = 0; k < 3; ++k)
     for (int d = 0; d < 3; ++d) {
       r0[k][d] = r[k][d];
@@ -269,60 +269,95 @@ __device__ __forceinline__ int64_t free_atom(const MDArgs& a, int64_t j) {
   return j < a.rig_first ? j : j + 3 * a.rig_count;
 }
 
+// The sub-flow factors of one cell rate a over the half step h, the same
+// for every particle: e^{-a h} and (e^{-a h} - 1)/(-a) (B_R), e^{a h} and
+// (e^{a h} - 1)/a (each A_R).
+struct MDFactors {
+  double eB[3], fB[3], eA1[3], fA1[3], eA2[3], fA2[3];
+};
+
+// Block of k_md_first: kMdThreads units and four waves.  Waves 0-2 draw the
+// noise of atom slot 0, 1, 2 of the block's units (an atom's counter is its
+// index, so which lane draws it does not change the numbers); wave 3 replays
+// the cell sub-steps in its first lane and forms the sub-flow factors in
+// nine lanes; after the barrier wave 0 moves the units.  The units' chains
+// no longer hold the noise and the exponentials, which are the same for
+// every unit or independent of the unit's state.
 __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   __shared__ MDCell sc;
   __shared__ double rate[3][3];
+  __shared__ MDFactors fac;
+  __shared__ double zs[3][kMdThreads][3];
   const double h = 0.5 * a.dt;
-  if (threadIdx.x == 0) {
-    MDCell c = *a.cell_in;
-    B_V(a, c, h);
-    cell_rates(c, rate[0]);                 // B_R
-    A_V(c, h);
-    cell_rates(c, rate[1]);                 // first A_R
-    double z[3];
-    normals3(a.seed, a.sysid, a.step, 0, kTagCell, z);
-    const double c1 = exp(-a.gc * a.dt);
-    const double amp = sqrt(a.ftm * a.kT * (1.0 - c1 * c1));
-    if (c.mode == 0) c.pV = c1 * c.pV + amp * sqrt(c.M) * z[0];
-    else if (c.mode == 2) {
-      for (int d = 0; d < 3; ++d) c.pl[d] = c1 * c.pl[d] + amp * sqrt(c.Ml[d]) * z[d];
-    } else {
-      c.pA = c1 * c.pA + amp * sqrt(c.MA) * z[0];
-      c.pL = c1 * c.pL + amp * sqrt(c.ML) * z[1];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t u = (int64_t)bx * kMdThreads + lane;
+  const int64_t units = md_units(a);
+  if (wave == 3) {
+    if (lane == 0) {
+      MDCell c = *a.cell_in;
+      B_V(a, c, h);
+      cell_rates(c, rate[0]);               // B_R
+      A_V(c, h);
+      cell_rates(c, rate[1]);               // first A_R
+      double z[3];
+      normals3(a.seed, a.sysid, a.step, 0, kTagCell, z);
+      const double c1 = exp(-a.gc * a.dt);
+      const double amp = sqrt(a.ftm * a.kT * (1.0 - c1 * c1));
+      if (c.mode == 0) c.pV = c1 * c.pV + amp * sqrt(c.M) * z[0];
+      else if (c.mode == 2) {
+        for (int d = 0; d < 3; ++d) c.pl[d] = c1 * c.pl[d] + amp * sqrt(c.Ml[d]) * z[d];
+      } else {
+        c.pA = c1 * c.pA + amp * sqrt(c.MA) * z[0];
+        c.pL = c1 * c.pL + amp * sqrt(c.ML) * z[1];
+      }
+      cell_rates(c, rate[2]);               // second A_R
+      A_V(c, h);
+      cell_lengths(c);
+      c.step = a.step;
+      sc = c;
+      if (bx == 0) *a.cell_out = c;
     }
-    cell_rates(c, rate[2]);                 // second A_R
-    A_V(c, h);
-    cell_lengths(c);
-    c.step = a.step;
-    sc = c;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 9) {
+      const int set = lane / 3, d = lane % 3;
+      const double ra = rate[set][d];
+      if (set == 0) { fac.eB[d] = exp(-ra * h); fac.fB[d] = expm1_over(-ra, h); }
+      else if (set == 1) { fac.eA1[d] = exp(ra * h); fac.fA1[d] = expm1_over(ra, h); }
+      else { fac.eA2[d] = exp(ra * h); fac.fA2[d] = expm1_over(ra, h); }
+    }
+  } else if (u < units) {
+    // the noise of atom slot `wave` of unit u (a free atom has slot 0 only)
+    int64_t i = -1;
+    if (u < a.rig_count) i = a.rig_first + 3 * u + wave;
+    else if (wave == 0) i = free_atom(a, u - a.rig_count);
+    if (i >= 0) normals3(a.seed, a.sysid, a.step, (uint64_t)i, kTagNoise, zs[wave][lane]);
   }
   __syncthreads();
-  if (bx == 0 && threadIdx.x == 0) *a.cell_out = sc;
-  const int64_t u = (int64_t)bx * blockDim.x + threadIdx.x;
-  if (u >= md_units(a)) return;
+  if (wave != 0 || u >= units) return;
   const double c1 = exp(-a.gp * a.dt);
   if (u < a.rig_count) {
     const int64_t i0 = a.rig_first + 3 * u;
-    double r[3][3], p[3][3], F[3][3], m[3], z[3][3];
+    double r[3][3], p[3][3], F[3][3], m[3];
     for (int k = 0; k < 3; ++k) {
       const int64_t i = i0 + k;
       m[k] = a.mass[i];
       r[k][0] = a.x[i]; r[k][1] = a.y[i]; r[k][2] = a.z[i];
       p[k][0] = a.px[i]; p[k][1] = a.py[i]; p[k][2] = a.pz[i];
       F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
-      normals3(a.seed, a.sysid, a.step, (uint64_t)i, kTagNoise, z[k]);
     }
     for (int k = 0; k < 3; ++k)
       for (int d = 0; d < 3; ++d)
-        p[k][d] = p[k][d] * exp(-rate[0][d] * h) + a.ftm * F[k][d] * expm1_over(-rate[0][d], h);  // B_R
+        p[k][d] = p[k][d] * fac.eB[d] + a.ftm * F[k][d] * fac.fB[d];                         // B_R
     rigid_momenta(r, p, m);
-    bool ok = rigid_drift(a, r, p, m, rate[1], h);                                              // A_R
+    bool ok = rigid_drift(a, r, p, m, fac.eA1, fac.fA1);                                       // A_R
     for (int k = 0; k < 3; ++k) {
       const double amp = sqrt(a.ftm * a.kT * m[k] * (1.0 - c1 * c1));
-      for (int d = 0; d < 3; ++d) p[k][d] = c1 * p[k][d] + amp * z[k][d];                      // O
+      for (int d = 0; d < 3; ++d) p[k][d] = c1 * p[k][d] + amp * zs[k][lane][d];             // O
     }
     rigid_momenta(r, p, m);
-    ok = rigid_drift(a, r, p, m, rate[2], h) && ok;                                             // A_R
+    ok = rigid_drift(a, r, p, m, fac.eA2, fac.fA2) && ok;                                      // A_R
     if (!ok) atomicOr(a.flags, 1);
     for (int k = 0; k < 3; ++k) {
       const int64_t i = i0 + k;
@@ -336,15 +371,13 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   double r[3] = {a.x[i], a.y[i], a.z[i]};
   double p[3] = {a.px[i], a.py[i], a.pz[i]};
   const double F[3] = {a.fx[i], a.fy[i], a.fz[i]};
-  double z[3];
-  normals3(a.seed, a.sysid, a.step, (uint64_t)i, kTagNoise, z);
   const double amp = sqrt(a.ftm * a.kT * m * (1.0 - c1 * c1));
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    p[d] = p[d] * exp(-rate[0][d] * h) + a.ftm * F[d] * expm1_over(-rate[0][d], h);   // B_R
-    r[d] = r[d] * exp(rate[1][d] * h) + p[d] * im * expm1_over(rate[1][d], h);        // A_R
-    p[d] = c1 * p[d] + amp * z[d];                                                    // O
-    r[d] = r[d] * exp(rate[2][d] * h) + p[d] * im * expm1_over(rate[2][d], h);        // A_R
+    p[d] = p[d] * fac.eB[d] + a.ftm * F[d] * fac.fB[d];          // B_R
+    r[d] = r[d] * fac.eA1[d] + p[d] * im * fac.fA1[d];           // A_R
+    p[d] = c1 * p[d] + amp * zs[0][lane][d];                     // O
+    r[d] = r[d] * fac.eA2[d] + p[d] * im * fac.fA2[d];           // A_R
   }
   a.x[i] = r[0]; a.y[i] = r[1]; a.z[i] = r[2];
   a.px[i] = p[0]; a.py[i] = p[1]; a.pz[i] = p[2];
@@ -501,14 +534,14 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   }
 }
 
-__global__ void __launch_bounds__(kMdThreads) k_md_first(MDArgs a) { md_first_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(kMdFirstThreads) k_md_first(MDArgs a) { md_first_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(kMdThreads) k_md_second(MDArgs a, int prime) {
   md_second_body(a, prime, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_md_first(const MDArgs& a, hipStream_t s) {
   const unsigned blocks = (unsigned)md_blocks(md_units(a));
-  hipLaunchKernelGGL(k_md_first, dim3(blocks), dim3(kMdThreads), 0, s, a);
+  hipLaunchKernelGGL(k_md_first, dim3(blocks), dim3(kMdFirstThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -528,7 +561,7 @@ __device__ __forceinline__ int find_sys_m(const int* bstart, int nsys, int b) {
   return lo;
 }
 
-__global__ void __launch_bounds__(kMdThreads) k_md_first_m(const MDArgs* tab, const int* bstart, int nsys) {
+__global__ void __launch_bounds__(kMdFirstThreads) k_md_first_m(const MDArgs* tab, const int* bstart, int nsys) {
   __shared__ MDArgs sa;
   const int sys = find_sys_m(bstart, nsys, blockIdx.x);
   if (threadIdx.x == 0) sa = tab[sys];
@@ -547,7 +580,7 @@ __global__ void __launch_bounds__(kMdThreads) k_md_second_m(const MDArgs* tab, c
 
 hipError_t launch_md_first_multi(const MDArgs* d_tab, const int* d_bstart, int nsys, int total,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_md_first_m, dim3(total), dim3(kMdThreads), 0, s, d_tab, d_bstart, nsys);
+  hipLaunchKernelGGL(k_md_first_m, dim3(total), dim3(kMdFirstThreads), 0, s, d_tab, d_bstart, nsys);
   return hipGetLastError();
 }
 

@@ -49,6 +49,9 @@ __host__ __device__ inline int64_t md_units(const MDArgs& a) { return a.n - 2 * 
 // integrator blocks are one wave: a rigid molecule's update is long FP64
 // work, so small blocks spread a system's molecules over more CUs
 constexpr int kMdThreads = 64;
+// threads of a k_md_first block (its kMdThreads units, four waves)
+constexpr int kMdFirstThreads = 4 * 64;
+static_assert(kMdThreads == 64, "k_md_first: a unit per lane of one wave");
 __host__ __device__ inline int64_t md_blocks(int64_t units) { return (units + kMdThreads - 1) / kMdThreads; }
 // pressure reduction: block partials summed by the last block of each group
 // of kMdGroup blocks, group partials by the last group

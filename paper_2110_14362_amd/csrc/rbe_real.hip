@@ -294,22 +294,24 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
   if (valid) {
     const double ex = p.ex, ey = p.ey, ez = p.ez;
     const double r2 = ex * ex + ey * ey + ez * ez;
-    const double ir = rsqrt(r2), r = r2 * ir;
-    // Coulomb: phi = C qi qj erfc(sa r)/r,  -phi' = C qi qj G(r)
+    const double ir = rsqrt(r2), ir2 = ir * ir, r = r2 * ir;
+    // Coulomb: U = C qi qj erfc(sa r)/r = qq A,
+    // U'(r)/r = -qq (A + (2 sa/sqrt(pi)) exp(-sa^2 r^2))/r^2
     const double qq = a.coulomb * vi.w * p.qj;
     const double g2 = exp(-a.alpha * r2);
-    const double er = g2 * erfcx_pos(sa * r, poly);
-    double dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
-    u += qq * er * ir;
+    const double A = g2 * erfcx_pos(sa * r, poly) * ir;
+    double rdU = -qq * fma(two_sa_pi, g2, A);                 // r U'(r)
+    u = fma(qq, A, u);
     if (a.ntypes > 0) {
+      // U = c12/r^12 - c6/r^6,  r U'(r) = -12 c12/r^12 + 6 c6/r^6
       const int k = ti * a.ntypes + p.tj;
-      const double c12 = lj[2 * k], c6 = lj[2 * k + 1];
-      const double i2 = ir * ir, i6 = i2 * i2 * i2;
-      u += c12 * i6 * i6 - c6 * i6;
-      dU += (-12.0 * c12 * i6 * i6 + 6.0 * c6 * i6) * ir;
+      const double i6 = ir2 * ir2 * ir2;
+      const double t12 = lj[2 * k] * i6 * i6, t6 = lj[2 * k + 1] * i6;
+      u += t12 - t6;
+      rdU = fma(-12.0, t12, fma(6.0, t6, rdU));
     }
     // force on i: U'(r) x/r;  virial: (1/2) (-U'(r)) x x^T / r per ordered pair
-    const double g = dU * ir;
+    const double g = rdU * ir2;
     gx = g * ex; gy = g * ey; gz = g * ez;
     w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
     w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
@@ -355,20 +357,20 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
   if (valid) {
     const float ex = (float)p.ex, ey = (float)p.ey, ez = (float)p.ez;
     const float r2 = ex * ex + ey * ey + ez * ez;
-    const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
+    const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir, r = r2 * ir;
     const float qq = (float)(a.coulomb * vi.w * p.qj);
     const float g2 = __expf(-alpha * r2);
-    const float er = g2 * erfcx_pos32(sa * r, poly);
-    float dU = -qq * (er * ir * ir + two_sa_pi * g2 * ir);   // U'(r)
-    u += qq * er * ir;
+    const float A = g2 * erfcx_pos32(sa * r, poly) * ir;
+    float rdU = -qq * fmaf(two_sa_pi, g2, A);                 // r U'(r)
+    u = fmaf(qq, A, u);
     if (a.ntypes > 0) {
       const int k = ti * a.ntypes + p.tj;
-      const float c12 = (float)lj[2 * k], c6 = (float)lj[2 * k + 1];
-      const float i2 = ir * ir, i6 = i2 * i2 * i2;
-      u += c12 * i6 * i6 - c6 * i6;
-      dU += (-12.0f * c12 * i6 * i6 + 6.0f * c6 * i6) * ir;
+      const float i6 = ir2 * ir2 * ir2;
+      const float t12 = (float)lj[2 * k] * i6 * i6, t6 = (float)lj[2 * k + 1] * i6;
+      u += t12 - t6;
+      rdU = fmaf(-12.0f, t12, fmaf(6.0f, t6, rdU));
     }
-    const float g = dU * ir;
+    const float g = rdU * ir2;
     gx = g * ex; gy = g * ey; gz = g * ez;
     w[0] -= g * ex * ex; w[1] -= g * ey * ey; w[2] -= g * ez * ez;
     w[3] -= g * ex * ey; w[4] -= g * ex * ez; w[5] -= g * ey * ez;
