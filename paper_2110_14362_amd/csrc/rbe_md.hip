@@ -133,21 +133,29 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
 // RATTLE for a rigid triangle in closed form (the part removed carries no
 // linear or angular momentum, and no bond has a relative velocity along it
 // afterwards).
-__device__ void rigid_momenta(const double r[3][3], double p[3][3], const double m[3]) {
-  const double M = m[0] + m[1] + m[2];
+// Divisions by the same value are multiplications by its reciprocal (an FP64
+// division is a dozen dependent instructions; these chains run one molecule
+// per lane), and every loop is unrolled so the arrays stay in registers.
+__device__ __forceinline__ void rigid_momenta(const double r[3][3], double p[3][3], const double m[3],
+                                              double iM) {
   double R[3], P[3], rho[3][3], L[3] = {0, 0, 0};
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    R[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) / M;
+    R[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) * iM;
     P[d] = p[0][d] + p[1][d] + p[2][d];
   }
   double I[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
+#pragma unroll
     for (int d = 0; d < 3; ++d) rho[k][d] = r[k][d] - R[d];
     double lk[3];
     cross3(rho[k], p[k], lk);
     const double r2 = dot3(rho[k], rho[k]);
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       L[d] += lk[d];
+#pragma unroll
       for (int e = 0; e < 3; ++e) I[d][e] += m[k] * ((d == e ? r2 : 0.0) - rho[k][d] * rho[k][e]);
     }
   }
@@ -158,14 +166,19 @@ __device__ void rigid_momenta(const double r[3][3], double p[3][3], const double
   const double c11 = I[0][0] * I[2][2] - I[0][2] * I[2][0];
   const double c12 = I[0][1] * I[2][0] - I[0][0] * I[2][1];
   const double c22 = I[0][0] * I[1][1] - I[0][1] * I[1][0];
-  const double det = I[0][0] * c00 + I[0][1] * c01 + I[0][2] * c02;
-  const double w[3] = {(c00 * L[0] + c01 * L[1] + c02 * L[2]) / det,
-                       (c01 * L[0] + c11 * L[1] + c12 * L[2]) / det,
-                       (c02 * L[0] + c12 * L[1] + c22 * L[2]) / det};
+  const double idet = 1.0 / (I[0][0] * c00 + I[0][1] * c01 + I[0][2] * c02);
+  const double w[3] = {(c00 * L[0] + c01 * L[1] + c02 * L[2]) * idet,
+                       (c01 * L[0] + c11 * L[1] + c12 * L[2]) * idet,
+                       (c02 * L[0] + c12 * L[1] + c22 * L[2]) * idet};
+  double V[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) V[d] = P[d] * iM;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     double v[3];
     cross3(w, rho[k], v);
-    for (int d = 0; d < 3; ++d) p[k][d] = m[k] * (P[d] / M + v[d]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[k][d] = m[k] * (V[d] + v[d]);
   }
 }
 
@@ -179,44 +192,51 @@ __device__ void rigid_momenta(const double r[3][3], double p[3][3], const double
 // centre of mass: its tilt follows from the three kept normal coordinates and
 // its turn about n from the torque condition.  Returns false if no tilt
 // matches (a drift far too long for the step).
-__device__ bool rigid_positions(const double r0[3][3], double r[3][3], const double m[3],
-                                double ra, double rb, double rc) {
-  const double M = m[0] + m[1] + m[2];
+__device__ __forceinline__ bool rigid_positions(const double r0[3][3], double r[3][3], const double m[3],
+                                                double iM, double ra, double rb, double rc,
+                                                double ira, double i2rc) {
   double b0[3], c0[3], Z[3], X[3], Y[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     b0[d] = r0[1][d] - r0[0][d];
     c0[d] = r0[2][d] - r0[0][d];
     X[d] = r0[2][d] - r0[1][d];
   }
   cross3(b0, c0, Z);
-  const double zn = sqrt(dot3(Z, Z)), xn = sqrt(dot3(X, X));
-  for (int d = 0; d < 3; ++d) { Z[d] /= zn; X[d] /= xn; }
+  const double izn = 1.0 / sqrt(dot3(Z, Z)), ixn = 1.0 / sqrt(dot3(X, X));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) { Z[d] *= izn; X[d] *= ixn; }
   cross3(Z, X, Y);
   double D[3], C0[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    D[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) / M;
-    C0[d] = (m[0] * r0[0][d] + m[1] * r0[1][d] + m[2] * r0[2][d]) / M;
+    D[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) * iM;
+    C0[d] = (m[0] * r0[0][d] + m[1] * r0[1][d] + m[2] * r0[2][d]) * iM;
   }
   double an[3][3], on[3][2];     // new (x, y, z) and old (x, y) in the frame
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     double u[3], v[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) { u[d] = r[k][d] - D[d]; v[d] = r0[k][d] - C0[d]; }
     an[k][0] = dot3(u, X); an[k][1] = dot3(u, Y); an[k][2] = dot3(u, Z);
     on[k][0] = dot3(v, X); on[k][1] = dot3(v, Y);
   }
   // tilt: the unit vector t (reference frame) with t . c_k = normal coordinate
-  const double ty = an[0][2] / ra;
-  const double tx = (an[2][2] - an[1][2]) / (2.0 * rc);
+  const double ty = an[0][2] * ira;
+  const double tx = (an[2][2] - an[1][2]) * i2rc;
   const double s2 = tx * tx + ty * ty;
   if (!(s2 < 1.0)) return false;
   const double tz = sqrt(1.0 - s2), sb = sqrt(s2);
+  const double isb = sb > 0.0 ? 1.0 / sb : 0.0;
   const double cref[3][2] = {{0.0, ra}, {-rc, -rb}, {rc, -rb}};
   double q[3][3];
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double cx = cref[k][0], cy = cref[k][1];
     if (sb > 0.0) {
       // rotation taking t to the normal, about the axis (ty, -tx, 0)/sb
-      const double kx = ty / sb, ky = -tx / sb;
+      const double kx = ty * isb, ky = -tx * isb;
       const double kc = kx * cx + ky * cy;
       q[k][0] = cx * tz + kx * kc * (1.0 - tz);
       q[k][1] = cy * tz + ky * kc * (1.0 - tz);
@@ -227,6 +247,7 @@ __device__ bool rigid_positions(const double r0[3][3], double r[3][3], const dou
   }
   // turn about the normal: sum_k m_k (o_k x p_k).n equals sum_k m_k (o_k x a_k).n
   double A = 0.0, B = 0.0, Lt = 0.0;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     A += m[k] * (on[k][0] * q[k][0] + on[k][1] * q[k][1]);
     B += m[k] * (on[k][0] * q[k][1] - on[k][1] * q[k][0]);
@@ -237,10 +258,12 @@ __device__ bool rigid_positions(const double r0[3][3], double r[3][3], const dou
   const double th = asin(sarg) - atan2(B, A);
   double sn, cs;
   sincos(th, &sn, &cs);
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double px = q[k][0] * cs - q[k][1] * sn;
     const double py = q[k][0] * sn + q[k][1] * cs;
     const double pz = q[k][2];
+#pragma unroll
     for (int d = 0; d < 3; ++d) r[k][d] = D[d] + px * X[d] + py * Y[d] + pz * Z[d];
   }
   return true;
@@ -248,19 +271,25 @@ __device__ bool rigid_positions(const double r0[3][3], double r[3][3], const dou
 
 // A_R on a molecule, then the position constraint and the momentum change
 // p += m (r_constrained - r_unconstrained) a / (e^{a h} - 1) per axis;
-// e[d] = e^{a_d h}, f[d] = (e^{a_d h} - 1)/a_d
+// e[d] = e^{a_d h}, f[d] = (e^{a_d h} - 1)/a_d, fi[d] = 1/f[d]; im[k] = 1/m[k]
 __device__ __forceinline__ bool rigid_drift(const MDArgs& a, double r[3][3], double p[3][3],
-                                            const double m[3], const double e[3], const double f[3]) {
+                                            const double m[3], const double im[3], double iM,
+                                            const double e[3], const double f[3], const double fi[3],
+                                            double ira, double i2rc) {
   double r0[3][3], ru[3][3];
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       r0[k][d] = r[k][d];
-      ru[k][d] = r[k][d] * e[d] + p[k][d] / m[k] * f[d];
+      ru[k][d] = r[k][d] * e[d] + p[k][d] * im[k] * f[d];
       r[k][d] = ru[k][d];
     }
-  const bool ok = rigid_positions(r0, r, m, a.ra, a.rb, a.rc);
+  const bool ok = rigid_positions(r0, r, m, iM, a.ra, a.rb, a.rc, ira, i2rc);
+#pragma unroll
   for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) p[k][d] += m[k] * (r[k][d] - ru[k][d]) / f[d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[k][d] += m[k] * (r[k][d] - ru[k][d]) * fi[d];
   return ok;
 }
 
@@ -273,7 +302,7 @@ __device__ __forceinline__ int64_t free_atom(const MDArgs& a, int64_t j) {
 // for every particle: e^{-a h} and (e^{-a h} - 1)/(-a) (B_R), e^{a h} and
 // (e^{a h} - 1)/a (each A_R).
 struct MDFactors {
-  double eB[3], fB[3], eA1[3], fA1[3], eA2[3], fA2[3];
+  double eB[3], fB[3], eA1[3], fA1[3], iA1[3], eA2[3], fA2[3], iA2[3];
 };
 
 // Block of k_md_first: kMdThreads units and four waves.  Waves 0-2 draw the
@@ -292,6 +321,21 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t u = (int64_t)bx * kMdThreads + lane;
   const int64_t units = md_units(a);
+  // wave 0 requests its unit's state first (the loads do not depend on the
+  // cell or the noise); a free atom uses slot 0
+  double r[3][3], p[3][3], F[3][3], m[3];
+  const bool rig = u < a.rig_count;
+  if (wave == 0 && u < units) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k > 0 && !rig) break;
+      const int64_t i = rig ? a.rig_first + 3 * u + k : free_atom(a, u - a.rig_count);
+      m[k] = a.mass[i];
+      r[k][0] = a.x[i]; r[k][1] = a.y[i]; r[k][2] = a.z[i];
+      p[k][0] = a.px[i]; p[k][1] = a.py[i]; p[k][2] = a.pz[i];
+      F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
+    }
+  }
   if (wave == 3) {
     if (lane == 0) {
       MDCell c = *a.cell_in;
@@ -324,8 +368,11 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
       const int set = lane / 3, d = lane % 3;
       const double ra = rate[set][d];
       if (set == 0) { fac.eB[d] = exp(-ra * h); fac.fB[d] = expm1_over(-ra, h); }
-      else if (set == 1) { fac.eA1[d] = exp(ra * h); fac.fA1[d] = expm1_over(ra, h); }
-      else { fac.eA2[d] = exp(ra * h); fac.fA2[d] = expm1_over(ra, h); }
+      else if (set == 1) {
+        fac.eA1[d] = exp(ra * h); fac.fA1[d] = expm1_over(ra, h); fac.iA1[d] = 1.0 / fac.fA1[d];
+      } else {
+        fac.eA2[d] = exp(ra * h); fac.fA2[d] = expm1_over(ra, h); fac.iA2[d] = 1.0 / fac.fA2[d];
+      }
     }
   } else if (u < units) {
     // the noise of atom slot `wave` of unit u (a free atom has slot 0 only)
@@ -337,27 +384,25 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
   __syncthreads();
   if (wave != 0 || u >= units) return;
   const double c1 = exp(-a.gp * a.dt);
-  if (u < a.rig_count) {
+  if (rig) {
     const int64_t i0 = a.rig_first + 3 * u;
-    double r[3][3], p[3][3], F[3][3], m[3];
-    for (int k = 0; k < 3; ++k) {
-      const int64_t i = i0 + k;
-      m[k] = a.mass[i];
-      r[k][0] = a.x[i]; r[k][1] = a.y[i]; r[k][2] = a.z[i];
-      p[k][0] = a.px[i]; p[k][1] = a.py[i]; p[k][2] = a.pz[i];
-      F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
-    }
+    const double im[3] = {1.0 / m[0], 1.0 / m[1], 1.0 / m[2]}, iM = 1.0 / (m[0] + m[1] + m[2]);
+    const double ira = 1.0 / a.ra, i2rc = 1.0 / (2.0 * a.rc);
+#pragma unroll
     for (int k = 0; k < 3; ++k)
+#pragma unroll
       for (int d = 0; d < 3; ++d)
         p[k][d] = p[k][d] * fac.eB[d] + a.ftm * F[k][d] * fac.fB[d];                         // B_R
-    rigid_momenta(r, p, m);
-    bool ok = rigid_drift(a, r, p, m, fac.eA1, fac.fA1);                                       // A_R
+    rigid_momenta(r, p, m, iM);
+    bool ok = rigid_drift(a, r, p, m, im, iM, fac.eA1, fac.fA1, fac.iA1, ira, i2rc);         // A_R
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double amp = sqrt(a.ftm * a.kT * m[k] * (1.0 - c1 * c1));
+#pragma unroll
       for (int d = 0; d < 3; ++d) p[k][d] = c1 * p[k][d] + amp * zs[k][lane][d];             // O
     }
-    rigid_momenta(r, p, m);
-    ok = rigid_drift(a, r, p, m, fac.eA2, fac.fA2) && ok;                                      // A_R
+    rigid_momenta(r, p, m, iM);
+    ok = rigid_drift(a, r, p, m, im, iM, fac.eA2, fac.fA2, fac.iA2, ira, i2rc) && ok;        // A_R
     if (!ok) atomicOr(a.flags, 1);
     for (int k = 0; k < 3; ++k) {
       const int64_t i = i0 + k;
@@ -367,20 +412,19 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
     return;
   }
   const int64_t i = free_atom(a, u - a.rig_count);
-  const double m = a.mass[i], im = 1.0 / m;
-  double r[3] = {a.x[i], a.y[i], a.z[i]};
-  double p[3] = {a.px[i], a.py[i], a.pz[i]};
-  const double F[3] = {a.fx[i], a.fy[i], a.fz[i]};
-  const double amp = sqrt(a.ftm * a.kT * m * (1.0 - c1 * c1));
+  const double im = 1.0 / m[0];
+  const double amp = sqrt(a.ftm * a.kT * m[0] * (1.0 - c1 * c1));
+  double* rr = r[0];
+  double* pp = p[0];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    p[d] = p[d] * fac.eB[d] + a.ftm * F[d] * fac.fB[d];          // B_R
-    r[d] = r[d] * fac.eA1[d] + p[d] * im * fac.fA1[d];           // A_R
-    p[d] = c1 * p[d] + amp * zs[0][lane][d];                     // O
-    r[d] = r[d] * fac.eA2[d] + p[d] * im * fac.fA2[d];           // A_R
+    pp[d] = pp[d] * fac.eB[d] + a.ftm * F[0][d] * fac.fB[d];     // B_R
+    rr[d] = rr[d] * fac.eA1[d] + pp[d] * im * fac.fA1[d];        // A_R
+    pp[d] = c1 * pp[d] + amp * zs[0][lane][d];                   // O
+    rr[d] = rr[d] * fac.eA2[d] + pp[d] * im * fac.fA2[d];        // A_R
   }
-  a.x[i] = r[0]; a.y[i] = r[1]; a.z[i] = r[2];
-  a.px[i] = p[0]; a.py[i] = p[1]; a.pz[i] = p[2];
+  a.x[i] = rr[0]; a.y[i] = rr[1]; a.z[i] = rr[2];
+  a.px[i] = pp[0]; a.py[i] = pp[1]; a.pz[i] = pp[2];
 }
 
 __device__ __forceinline__ double wsum_md(double v) {
@@ -396,16 +440,13 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   __shared__ int sh_last;
   const double h = 0.5 * a.dt;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  if (threadIdx.x == 0) sc = *a.cell_in;
-  __syncthreads();
-  double rate[3];
-  cell_rates(sc, rate);
   const int64_t u = (int64_t)bx * blockDim.x + threadIdx.x;
-  double k6[6] = {0, 0, 0, 0, 0, 0};   // kinetic tensor
-  double c6[6] = {0, 0, 0, 0, 0, 0};   // molecular correction sum sym((r - R) F)
-  if (u < md_units(a) && u < a.rig_count) {
+  // the unit's state is requested before the cell (independent loads)
+  const bool rig = u < md_units(a) && u < a.rig_count;
+  double r[3][3], p[3][3], F[3][3], m[3];
+  if (rig) {
     const int64_t i0 = a.rig_first + 3 * u;
-    double r[3][3], p[3][3], F[3][3], m[3];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int64_t i = i0 + k;
       m[k] = a.mass[i];
@@ -413,19 +454,32 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
       p[k][0] = a.px[i]; p[k][1] = a.py[i]; p[k][2] = a.pz[i];
       F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
     }
+  }
+  if (threadIdx.x == 0) sc = *a.cell_in;
+  __syncthreads();
+  double rate[3];
+  cell_rates(sc, rate);
+  double k6[6] = {0, 0, 0, 0, 0, 0};   // kinetic tensor
+  double c6[6] = {0, 0, 0, 0, 0, 0};   // molecular correction sum sym((r - R) F)
+  if (rig) {
+    const int64_t i0 = a.rig_first + 3 * u;
     if (!prime)
+#pragma unroll
       for (int k = 0; k < 3; ++k)
+#pragma unroll
         for (int d = 0; d < 3; ++d)
           p[k][d] = p[k][d] * exp(-rate[d] * h) + a.ftm * F[k][d] * expm1_over(-rate[d], h);
-    rigid_momenta(r, p, m);
-    const double M = m[0] + m[1] + m[2];
+    const double iM = 1.0 / (m[0] + m[1] + m[2]);
+    rigid_momenta(r, p, m, iM);
     double P[3], R[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       P[d] = p[0][d] + p[1][d] + p[2][d];
-      R[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) / M;
+      R[d] = (m[0] * r[0][d] + m[1] * r[1][d] + m[2] * r[2][d]) * iM;
     }
-    k6[0] = P[0] * P[0] / M; k6[1] = P[1] * P[1] / M; k6[2] = P[2] * P[2] / M;
-    k6[3] = P[0] * P[1] / M; k6[4] = P[0] * P[2] / M; k6[5] = P[1] * P[2] / M;
+    k6[0] = P[0] * P[0] * iM; k6[1] = P[1] * P[1] * iM; k6[2] = P[2] * P[2] * iM;
+    k6[3] = P[0] * P[1] * iM; k6[4] = P[0] * P[2] * iM; k6[5] = P[1] * P[2] * iM;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double x0 = r[k][0] - R[0], x1 = r[k][1] - R[1], x2 = r[k][2] - R[2];
       c6[0] += x0 * F[k][0]; c6[1] += x1 * F[k][1]; c6[2] += x2 * F[k][2];
