@@ -337,8 +337,17 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
     }
   }
   if (wave == 3) {
+    // the cell state is copied word by word into LDS and replayed there by
+    // one lane (a register copy of the whole struct went to scratch memory)
+    constexpr int kCellWords = sizeof(MDCell) / 8;
+    static_assert(sizeof(MDCell) % 8 == 0 && kCellWords <= 64, "cell copied by one wave");
+    if (lane < kCellWords)
+      reinterpret_cast<uint64_t*>(&sc)[lane] = reinterpret_cast<const uint64_t*>(a.cell_in)[lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane == 0) {
-      MDCell c = *a.cell_in;
+      MDCell& c = sc;
       B_V(a, c, h);
       cell_rates(c, rate[0]);               // B_R
       A_V(c, h);
@@ -358,12 +367,12 @@ __device__ __forceinline__ void md_first_body(const MDArgs& a, int bx) {
       A_V(c, h);
       cell_lengths(c);
       c.step = a.step;
-      sc = c;
-      if (bx == 0) *a.cell_out = c;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (bx == 0 && lane < kCellWords)
+      reinterpret_cast<uint64_t*>(a.cell_out)[lane] = reinterpret_cast<const uint64_t*>(&sc)[lane];
     if (lane < 9) {
       const int set = lane / 3, d = lane % 3;
       const double ra = rate[set][d];
@@ -455,7 +464,17 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
       F[k][0] = a.fx[i]; F[k][1] = a.fy[i]; F[k][2] = a.fz[i];
     }
   }
-  if (threadIdx.x == 0) sc = *a.cell_in;
+  // the cell, word by word; the virials (outputs of earlier launches, read
+  // only by the block that closes the step) are requested now as well
+  constexpr int kCellWords = sizeof(MDCell) / 8;
+  static_assert(sizeof(MDCell) % 8 == 0 && kCellWords <= kMdThreads, "cell copied by one block");
+  if (threadIdx.x < kCellWords)
+    reinterpret_cast<uint64_t*>(&sc)[threadIdx.x] = reinterpret_cast<const uint64_t*>(a.cell_in)[threadIdx.x];
+  double wv = 0.0;
+  if (threadIdx.x < 6) {
+    if (a.virial_k) wv += a.virial_k[threadIdx.x];
+    if (a.virial_r) wv += a.virial_r[threadIdx.x];
+  }
   __syncthreads();
   double rate[3];
   cell_rates(sc, rate);
@@ -520,7 +539,7 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
   // block per thread, all loads in flight at once), the last group sums the
   // groups; both in a fixed order
   __shared__ double red[12][kMdThreads + 1];
-  __shared__ double ksum[12];
+  __shared__ double ksum[18];
   const int g = bx / kMdGroup, ng = (nbx + kMdGroup - 1) / kMdGroup;
   const int gsize = min(kMdGroup, nbx - g * kMdGroup);
   if (threadIdx.x == 0)
@@ -570,22 +589,23 @@ __device__ __forceinline__ void md_second_body(const MDArgs& a, int prime, int b
     for (int j = 0; j < m; ++j) s += red[threadIdx.x][j];
     ksum[threadIdx.x] = s;
   }
+  if (threadIdx.x < 6) ksum[12 + threadIdx.x] = wv;
   __syncthreads();
   if (threadIdx.x == 0) {
-    MDCell c = sc;
-    const double V = cell_volume(c);
+    MDCell& c = sc;
+    const double iV = 1.0 / cell_volume(c);
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double w = 0.0;
-      if (a.virial_k) w += a.virial_k[k];
-      if (a.virial_r) w += a.virial_r[k];
       c.K[k] = ksum[k];
       c.C[k] = ksum[6 + k];
-      c.P_ins[k] = (ksum[k] + a.ftm * (w - ksum[6 + k])) / V;
+      c.P_ins[k] = (ksum[k] + a.ftm * (ksum[12 + k] - ksum[6 + k])) * iV;
     }
     if (!prime) B_V(a, c, h);
-    *a.cell_out = c;
     __hip_atomic_store(&a.cnt[ng], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  __syncthreads();
+  if (threadIdx.x < kCellWords)
+    reinterpret_cast<uint64_t*>(a.cell_out)[threadIdx.x] = reinterpret_cast<const uint64_t*>(&sc)[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kMdFirstThreads) k_md_first(MDArgs a) { md_first_body(a, blockIdx.x); }
