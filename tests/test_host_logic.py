@@ -1,6 +1,7 @@
 """Host-side logic that needs no GPU: the served stream's request recipe
 (cutoff, splitting parameter, neighbour-list skin that the cell allows),
-Poisson arrivals, and the benchmark's refusal of several GPUs."""
+Poisson arrivals, the benchmark's refusal of several GPUs, and the generated
+erfcx polynomial that the pair kernels evaluate."""
 import math
 import os
 import subprocess
@@ -54,3 +55,34 @@ def test_bench_refuses_several_gpus():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr
+
+
+def _header_array(text, name):
+    body = text.split(name + "[")[1].split("{", 1)[1].split("}", 1)[0]
+    return [float(v.strip().rstrip("f")) for v in body.split(",") if v.strip()]
+
+
+def test_erfcx_polynomial_of_the_pair_kernels():
+    # the pair kernels' erfc(x) = exp(-x^2) erfcx(x) takes erfcx from the
+    # generated polynomial in t = (x - K)/(x + K); checked here against
+    # scipy's erfcx (an independent implementation) over the range the
+    # kernels reach (x = g r up to g rc ~ 3-6) and beyond
+    from scipy.special import erfcx
+    text = open(os.path.join(ROOT, "paper_2110_14362_amd", "csrc", "erfcx_poly.h")).read()
+    K = float(text.split("kErfcxK =")[1].split(";")[0])
+    c64 = np.array(_header_array(text, "kErfcxPoly"), dtype=np.float64)
+    c32 = np.array(_header_array(text, "kErfcxPoly32"), dtype=np.float32)
+    assert len(c64) == int(text.split("kErfcxTerms =")[1].split(";")[0])
+    assert len(c32) == int(text.split("kErfcxTerms32 =")[1].split(";")[0])
+    x = np.concatenate([np.linspace(0.0, 12.0, 20001), np.geomspace(1e-8, 1.0, 2001)])
+    ref = erfcx(x)
+    t = (x - K) / (x + K)
+    y = np.full_like(x, c64[-1])
+    for c in c64[-2::-1]:
+        y = y * t + c
+    assert np.max(np.abs(y / ref - 1.0)) < 4e-15
+    t32 = ((x.astype(np.float32) - np.float32(K)) / (x.astype(np.float32) + np.float32(K))).astype(np.float32)
+    y32 = np.full_like(t32, c32[-1])
+    for c in c32[-2::-1]:
+        y32 = (y32 * t32 + c).astype(np.float32)
+    assert np.max(np.abs(y32.astype(np.float64) / erfcx(x.astype(np.float32).astype(np.float64)) - 1.0)) < 2e-6
