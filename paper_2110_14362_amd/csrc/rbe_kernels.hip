@@ -69,12 +69,14 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 constexpr uint64_t kTagKSample = 0x6B73616Dull;  // 'ksam': stream of the batch draws
 
 // ceil(sqrt(53 ln2 alpha) l / pi): weights exp(-pi^2 m^2/(alpha l^2)) >= 2^-53
+// Without branches, so that the three axes' chains (square root, division,
+// ceiling) overlap: a non-finite or non-positive cell gives 1, an oversized
+// one mcap, and both set err.
 __device__ __forceinline__ int table_halfwidth(double alpha, double tail_ln, double l, int mcap,
                                                int& err) {
   const double mcd = ceil(sqrt(tail_ln * alpha * l * l) / M_PI);
-  if (mcd >= 1.0 && mcd <= (double)mcap) return (int)mcd;
-  err |= 1;                       // non-finite, non-positive or oversized cell
-  return mcd >= 1.0 ? mcap : 1;
+  err |= (mcd >= 1.0 && mcd <= (double)mcap) ? 0 : 1;
+  return (int)fmin(fmax(mcd, 1.0), (double)mcap);
 }
 
 __device__ __forceinline__ void table_offsets(const int mc[3], int off[3]) {
@@ -199,14 +201,23 @@ __device__ __forceinline__ void propose_from(const BoxState& b, const double* ta
     tgt[a] = u[a + 1] * base[a][n - 1];
     nmax = max(nmax, n);
   }
+  // each step reads the three axes' midpoints together (one LDS round trip
+  // per step, not three) and updates them by selection; an axis whose range
+  // has closed reads its own entry and keeps it
   const int iters = 32 - __clz(nmax);
   for (int it = 0; it < iters; ++it) {
+    int mid[3];
+    double v[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (lo[a] < hi[a]) {
-        const int mid = (lo[a] + hi[a]) >> 1;
-        if (base[a][mid] > tgt[a]) hi[a] = mid; else lo[a] = mid + 1;
-      }
+      mid[a] = (lo[a] + hi[a]) >> 1;
+      v[a] = base[a][mid[a]];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const bool open = lo[a] < hi[a], gt = v[a] > tgt[a];
+      hi[a] = open && gt ? mid[a] : hi[a];
+      lo[a] = open && !gt ? mid[a] + 1 : lo[a];
     }
   }
 #pragma unroll
