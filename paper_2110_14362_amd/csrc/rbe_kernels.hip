@@ -184,6 +184,14 @@ __device__ __forceinline__ void propose_from(const BoxState& b, const double* ta
   table_offsets(b.mcut, off);
   const double u[4] = {(double)(c0 >> 11) * 0x1.0p-53, (double)(c1 >> 11) * 0x1.0p-53,
                        (double)(c2 >> 11) * 0x1.0p-53, (double)(c3 >> 11) * 0x1.0p-53};
+  // both tables' totals of every axis are read before the pivot is known
+  // (their addresses depend only on the half-widths): one LDS round trip
+  double tot_full[3], tot_nz[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    tot_full[a] = tab[off[a] + 2 * b.mcut[a]];
+    tot_nz[a] = tab[off[a] + 4 * b.mcut[a]];
+  }
   const double t = u[0] * (b.case_w[0] + b.case_w[1] + b.case_w[2]);
   const int pivot = (t < b.case_w[0]) ? 0 : ((t < b.case_w[0] + b.case_w[1]) ? 1 : 2);
   const double* base[3];
@@ -198,7 +206,7 @@ __device__ __forceinline__ void propose_from(const BoxState& b, const double* ta
     base[a] = tab + off[a] + (nz ? 2 * mc + 1 : 0);
     lo[a] = 0;
     hi[a] = (a < pivot) ? 0 : n - 1;
-    tgt[a] = u[a + 1] * base[a][n - 1];
+    tgt[a] = u[a + 1] * (nz ? tot_nz[a] : tot_full[a]);
     nmax = max(nmax, n);
   }
   // each step reads the three axes' midpoints together (one LDS round trip
