@@ -46,8 +46,9 @@ struct MDArgs {
 // threads (units) of the integrator kernels: molecules plus free atoms
 __host__ __device__ inline int64_t md_units(const MDArgs& a) { return a.n - 2 * a.rig_count; }
 
-// integrator blocks are one wave: a rigid molecule's update is long FP64
-// work, so small blocks spread a system's molecules over more CUs
+// integrator blocks hold one wave of units: a rigid molecule's update is
+// long FP64 work, so small blocks spread a system's molecules over more CUs
+// (k_md_first adds three waves for the noise and the cell replay)
 constexpr int kMdThreads = 64;
 // threads of a k_md_first block (its kMdThreads units, four waves)
 constexpr int kMdFirstThreads = 4 * 64;
