@@ -2,8 +2,7 @@
 // (99999); section 3.3 splitting B_V B_R A_V A_R O^p O A_R A_V | forces |
 // B_R B_V), FP64.  Two kernels per step around the force evaluation:
 //   k_md_first   every block replays the cell sub-steps (B_V, A_V, O^p, A_V:
-//                scalar work, identical in every block, on a wave of its own
-//                beside the waves that draw the noise) and applies B_R, A_R,
+//                scalar work, identical in every block) and applies B_R, A_R,
 //                O, A_R to its particles; block 0 stores the mid-step cell
 //   k_md_second  B_R on every particle, the kinetic tensor summed in a fixed
 //                order by the last-arriving block, which forms the pressure
