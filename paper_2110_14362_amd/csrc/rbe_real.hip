@@ -22,6 +22,7 @@
 //             last-arriving block
 #include "rbe_real_internal.h"
 #include "erfcx_poly.h"
+#include "exp_table.h"
 #include <math.h>
 
 namespace rbe {
@@ -230,6 +231,7 @@ struct PairQueue {
   int s[kPairQueue];
   double poly[kErfcxTerms];
   float poly32[kErfcxTerms32];
+  double etab[64];              // 2^(j/64) for exp_nonpos
   int seg_off[kSegments + 1];   // candidate offset of each neighbour segment (exclusive scan)
   int seg_j0[kSegments];        // its first cell-ordered index
   int seg_code[kSegments];      // its periodic shift
@@ -249,6 +251,25 @@ __device__ __forceinline__ double rcp_nr(double d) {
   double y = __builtin_amdgcn_rcp(d);
   y = fma(fma(-d, y, 1.0), y, y);
   return fma(fma(-d, y, 1.0), y, y);
+}
+
+// e^x for x <= 0 by Tang's table-driven method (ACM TOMS 15 (1989) 144):
+// x = (64 m + j) ln2/64 + r with |r| <= ln2/128 and e^x = 2^m 2^(j/64) e^r,
+// e^r - 1 from its Taylor polynomial of degree 6 (truncated below 2e-20 of
+// it); 2^(j/64) is read from the table in LDS.  Within about an ulp; 0 below
+// e^-745.  Two thirds of the instructions of the library exp, which also
+// handles overflow and non-finite arguments that a pair's -alpha r^2 never is.
+__device__ __forceinline__ double exp_nonpos(double x, const double* etab) {
+  const double n = rint(x * kExpInvL);
+  const double r = fma(-n, kExpLlo, fma(-n, kExpLhi, x));
+  const int ni = (int)n;
+  double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  const double t = etab[ni & 63];
+  return ldexp(fma(t, p * r, t), ni >> 6);
 }
 
 __device__ __forceinline__ double erfcx_pos(double x, const double* poly) {
@@ -288,8 +309,9 @@ __device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue
 // one pair's force on i (g), energy and virial terms (FP64)
 __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, double sa, double two_sa_pi,
-                                          const double* poly, const double* lj, double& gx,
-                                          double& gy, double& gz, double& u, double w[6]) {
+                                          const double* poly, const double* etab, const double* lj,
+                                          double& gx, double& gy, double& gz, double& u,
+                                          double w[6]) {
   gx = 0.0; gy = 0.0; gz = 0.0;
   if (valid) {
     const double ex = p.ex, ey = p.ey, ez = p.ez;
@@ -298,7 +320,7 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
     // Coulomb: U = C qi qj erfc(sa r)/r = qq A,
     // U'(r)/r = -qq (A + (2 sa/sqrt(pi)) exp(-sa^2 r^2))/r^2
     const double qq = a.coulomb * vi.w * p.qj;
-    const double g2 = exp(-a.alpha * r2);
+    const double g2 = exp_nonpos(-a.alpha * r2, etab);
     const double A = g2 * erfcx_pos(sa * r, poly) * ir;
     double rdU = -qq * fma(two_sa_pi, g2, A);                 // r U'(r)
     u = fma(qq, A, u);
@@ -320,10 +342,10 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
 
 __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, const double l[3], double sa,
-                                          double two_sa_pi, const double* poly, double f[3],
-                                          double& u, double w[6]) {
+                                          double two_sa_pi, const double* poly, const double* etab,
+                                          double f[3], double& u, double w[6]) {
   double gx, gy, gz;
-  pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, a.lj, gx, gy, gz, u, w);
+  pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, a.lj, gx, gy, gz, u, w);
   f[0] += wsum(gx);
   f[1] += wsum(gy);
   f[2] += wsum(gz);
@@ -570,6 +592,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
   if (lane < kErfcxTerms) Q.poly[lane] = kErfcxPoly[lane];
+  Q.etab[lane] = kExpTab[lane];
   if (lane < kErfcxTerms32) Q.poly32[lane] = kErfcxPoly32[lane];
   wave_sync();
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -659,7 +682,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
           pair_eval32(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
                       (float)a.alpha, Q.poly32, f, u32, w32);
         else
-          pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, f, u, w);
+          pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, Q.etab, f, u, w);
       }
       wave_sync();
       if (lane < qn - m) { Q.j[lane] = Q.j[m + lane]; Q.s[lane] = Q.s[m + lane]; }
@@ -836,6 +859,7 @@ template <bool P32, bool LJL>
 __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int nbx) {
   __shared__ int32_t lidx[kPairWaves][2][kListChunk];
   __shared__ double poly[kErfcxTerms];
+  __shared__ double etab[64];
   __shared__ float poly32[kErfcxTerms32];
   __shared__ double ljs[LJL ? 2 * kLjLds * kLjLds : 1];
   __shared__ double sh[kPairWaves][8];
@@ -843,6 +867,7 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
   if (!(a.skin > 0.0)) return;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   if (threadIdx.x < kErfcxTerms) poly[threadIdx.x] = kErfcxPoly[threadIdx.x];
+  if (threadIdx.x < 64) etab[threadIdx.x] = kExpTab[threadIdx.x];
   if (threadIdx.x < kErfcxTerms32) poly32[threadIdx.x] = kErfcxPoly32[threadIdx.x];
   if (LJL)
     for (int q = threadIdx.x; q < 2 * a.ntypes * a.ntypes; q += blockDim.x) ljs[q] = a.lj[q];
@@ -911,7 +936,8 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
           fx32 += gx; fy32 += gy; fz32 += gz;
         } else {
           double gx, gy, gz;
-          pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, LJL ? ljs : a.lj, gx, gy, gz, u, w);
+          pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, LJL ? ljs : a.lj, gx, gy, gz, u,
+                    w);
           fx += gx; fy += gy; fz += gz;
         }
       }

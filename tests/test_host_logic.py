@@ -86,3 +86,43 @@ def test_erfcx_polynomial_of_the_pair_kernels():
     for c in c32[-2::-1]:
         y32 = (y32 * t32 + c).astype(np.float32)
     assert np.max(np.abs(y32.astype(np.float64) / erfcx(x.astype(np.float32).astype(np.float64)) - 1.0)) < 2e-6
+
+
+def test_exponential_table_of_the_pair_kernels():
+    # the FP64 pair kernels take exp(-alpha r^2) from a table-driven
+    # exponential (2^(j/64) table, ln2/64 split in two); its steps, with each
+    # fused multiply-add rounded once (mpmath at 200 bits, then to FP64),
+    # reproduce mpmath's exp within 2 ulp over [-745, 0]
+    import math
+    import random
+    import mpmath as mp
+    text = open(os.path.join(ROOT, "paper_2110_14362_amd", "csrc", "exp_table.h")).read()
+    const = lambda name: float(text.split(name + " =")[1].split(";")[0])
+    inv, hi, lo = const("kExpInvL"), const("kExpLhi"), const("kExpLlo")
+    tab = _header_array(text, "kExpTab")
+    assert len(tab) == 64 and tab[0] == 1.0
+    mant = int(float.hex(hi).split("p")[0].split(".")[1], 16)
+    assert (mant & -mant).bit_length() - 1 >= 20             # short head: n * hi exact
+    mp.mp.prec = 200
+    fma = lambda a, b, c: float(mp.mpf(a) * mp.mpf(b) + mp.mpf(c))
+
+    def exp_nonpos(x):
+        n = float(round(x * inv))                 # rint: ties never occur here
+        r = fma(-n, lo, fma(-n, hi, x))
+        ni = int(n)
+        p = fma(r, 1.0 / 720.0, 1.0 / 120.0)
+        for c in (1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0):
+            p = fma(p, r, c)
+        t = tab[ni & 63]
+        return math.ldexp(fma(t, p * r, t), ni >> 6)
+
+    rng = random.Random(7)
+    xs = [0.0, -1e-300, -1e-12, -0.5, -math.log(2) / 128, -10.9, -700.0, -708.3]
+    xs += [-rng.uniform(0.0, 12.0) for _ in range(3000)] + [-rng.uniform(0.0, 708.0) for _ in range(1000)]
+    worst = 0.0
+    for x in xs:
+        ref = mp.exp(mp.mpf(x))
+        got = exp_nonpos(x)
+        worst = max(worst, float(abs(mp.mpf(got) - ref) / (mp.mpf(2) ** (mp.floor(mp.log(ref, 2)) - 52))))
+    assert worst < 2.0
+    assert exp_nonpos(-800.0) == 0.0
