@@ -238,6 +238,17 @@ struct PairQueue {
   float4 seg_io[kSegments];     // i seen from the segment's image, FP32
 };
 
+// The list build's segments of a wave (reach R cells): as PairQueue's, for
+// 2 (2R+1)^2 segments
+template <int R>
+struct ListSegs {
+  static constexpr int kSeg = 2 * (2 * R + 1) * (2 * R + 1);
+  int seg_off[kSeg + 1];
+  int seg_j0[kSeg];
+  int seg_code[kSeg];
+  float4 seg_io[kSeg];
+};
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // erfcx(x) = exp(x^2) erfc(x) for x >= 0 as a polynomial in
@@ -473,6 +484,92 @@ __device__ __forceinline__ int segment_table(const RealArgs& a, PairQueue& Q, co
   if (lane == 0) Q.seg_off[kSegments] = total;
   wave_sync();
   return total;
+}
+
+// The list build's segment table: the (2R+1)^3 cells around particle vi's
+// cell c, trimmed to the cells that can hold a neighbour: a row of cells
+// along x (fixed dy, dz) is dropped when its y-z distance from the particle
+// reaches rs, and a kept row keeps only the cells whose x distance from the
+// particle is below what rs leaves (distances from the particle's own
+// position to the nearest faces of the cells, with a relative margin of
+// 1e-12 on rs^2, so the set only shrinks by cells that cannot hold a pair
+// closer than rs).  Segments in the order of the untrimmed table (rows by dz,
+// then dy; a row's part before a wrap in x, then after), so the accepted
+// candidates keep their order.  Lane s + 64 k describes segment s + 64 k;
+// returns the number of candidates.
+template <int R>
+__device__ __forceinline__ int list_segment_table(const RealArgs& a, ListSegs<R>& S,
+                                                  const double4& vi, int c, int nx, int ny, int nz,
+                                                  const double l[3], double rs, int lane) {
+  constexpr int kRow = 2 * R + 1, kSeg = ListSegs<R>::kSeg;
+  const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+  const double wx = l[0] / nx, wy = l[1] / ny, wz = l[2] / nz;
+  const double rs2 = rs * rs * (1.0 + 1e-12);
+  int carry = 0;
+#pragma unroll
+  for (int pass = 0; pass < (kSeg + 63) / 64; ++pass) {
+    const int sgi = pass * 64 + lane;
+    int len = 0;
+    if (sgi < kSeg) {
+      const int row = sgi >> 1, half = sgi & 1;
+      const int dz = row / kRow - R, dy = row % kRow - R;
+      // the particle's distance to the row's nearest y and z faces
+      const double gy = dy > 0 ? (cy + dy) * wy - vi.y : (dy < 0 ? vi.y - (cy + dy + 1) * wy : 0.0);
+      const double gz = dz > 0 ? (cz + dz) * wz - vi.z : (dz < 0 ? vi.z - (cz + dz + 1) * wz : 0.0);
+      const double hy = fmax(gy, 0.0), hz = fmax(gz, 0.0);
+      const double rem = rs2 - hy * hy - hz * hz;
+      bool on = false;
+      int c0 = 0, c1 = -1, code = 13;
+      if (rem > 0.0) {
+        const double h = sqrt(rem);
+        const int xa = cx + max(-R, (int)floor((vi.x - h) / wx) - cx);
+        const int xb = cx + min(R, (int)floor((vi.x + h) / wx) - cx);
+        int zz = cz + dz, yy = cy + dy, kz = 1, ky = 1, kx = 1;
+        if (zz < 0) { zz += nz; kz = 0; } else if (zz >= nz) { zz -= nz; kz = 2; }
+        if (yy < 0) { yy += ny; ky = 0; } else if (yy >= ny) { yy -= ny; ky = 2; }
+        int x0 = 0, x1 = -1;
+        if (xa < 0) {                              // cells xa .. -1 wrap to the far end
+          if (half == 0) { x0 = nx + xa; x1 = nx - 1; kx = 0; } else { x0 = 0; x1 = xb; }
+          on = true;
+        } else if (xb > nx - 1) {                  // cells nx .. xb wrap to the start
+          if (half == 0) { x0 = xa; x1 = nx - 1; } else { x0 = 0; x1 = xb - nx; kx = 2; }
+          on = true;
+        } else if (half == 0) {
+          x0 = xa; x1 = xb;
+          on = true;
+        }
+        if (on) {
+          const int rbase = (zz * ny + yy) * nx;
+          c0 = rbase + x0;
+          c1 = rbase + x1;
+          code = (kz * 3 + ky) * 3 + kx;
+        }
+      }
+      if (on) {
+        const int j0 = a.start[c0];
+        len = a.start[c1 + 1] - j0;
+        S.seg_j0[sgi] = j0;
+        S.seg_io[sgi] = make_float4((float)(vi.x - l[0] * (double)(code % 3 - 1)),
+                                    (float)(vi.y - l[1] * (double)((code / 3) % 3 - 1)),
+                                    (float)(vi.z - l[2] * (double)(code / 9 - 1)), 0.0f);
+      } else {
+        S.seg_j0[sgi] = 0;
+        S.seg_io[sgi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+      S.seg_code[sgi] = code;
+    }
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (sgi < kSeg) S.seg_off[sgi] = carry + incl - len;
+    carry += __shfl(incl, 63, 64);
+  }
+  if (lane == 0) S.seg_off[kSeg] = carry;
+  wave_sync();
+  return uniform(carry);
 }
 
 // FP32 bounds of the squared search radius outside of which the FP32 test
@@ -764,10 +861,10 @@ __device__ __forceinline__ void vcheck_body(const RealArgs& a, int bx, int nbx) 
 // appends the cell-ordered indices in candidate order; it records the
 // reference positions and, in block 0, the reference cell.
 __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
-  __shared__ PairQueue queue[kPairWaves];
+  __shared__ ListSegs<kListReach> queue[kPairWaves];
   if (!(a.skin > 0.0) || skip_cells(a)) return;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  PairQueue& Q = queue[wave];
+  ListSegs<kListReach>& Q = queue[wave];
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   double l[3];
   real_box(a, l);
@@ -781,7 +878,7 @@ __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
     if (t >= a.n) goto done;
     const double4 vi = a.xq[t];
     const int c = uniform(a.cs[t]);
-    const int total = segment_table(a, Q, vi, c, nx, ny, nz, l, lane);
+    const int total = list_segment_table<kListReach>(a, Q, vi, c, nx, ny, nz, l, rs, lane);
     int cnt = 0, sg = 0;
     int32_t* out = a.nbr + (int64_t)t * a.kcap;
     for (int base = 0; base < total; base += 64) {

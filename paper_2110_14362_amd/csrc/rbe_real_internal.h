@@ -22,6 +22,9 @@ constexpr int kListIdxMask = (1 << kListTypeShift) - 1;
 constexpr int kListMin = 128;
 constexpr int kLjLds = 16;         // list pair kernel: LJ table in LDS up to this many types
 constexpr int kSegments = 50;      // neighbour segments: 25 rows of 5 cells, split at x wraps
+// list mode: cells at least (rc + skin)/kListReach wide, the list build's
+// neighbourhood kListReach cells each way
+constexpr int kListReach = 2;
 
 constexpr int kBinPer = 2048;      // particles a binning block takes (256 threads)
 constexpr int kBinLds = 8192;      // cells counted in LDS by the binning kernels
