@@ -421,73 +421,9 @@ __device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p
   f[2] += (double)wsumf(gz);
 }
 
-// The 125 neighbour cells of cell (cx, cy, cz) (cells at least rc/2 wide,
-// so every pair closer than rc is in them) as 25 rows of five cells along
-// x; a row is one contiguous range of the cell-ordered arrays unless it
-// wraps in x, then two.  Segment `seg` (0..49) of that list: the cell range
-// [c0, c1] and the periodic shift code (3 trits); false if empty.
-__device__ __forceinline__ bool neighbour_segment(int seg, int cx, int cy, int cz, int nx, int ny,
-                                                  int nz, int& c0, int& c1, int& code) {
-  const int row = seg >> 1, half = seg & 1;
-  const int dz = row / 5 - 2, dy = row % 5 - 2;
-  int zz = cz + dz, yy = cy + dy, kz = 1, ky = 1, kx = 1;
-  if (zz < 0) { zz += nz; kz = 0; } else if (zz >= nz) { zz -= nz; kz = 2; }
-  if (yy < 0) { yy += ny; ky = 0; } else if (yy >= ny) { yy -= ny; ky = 2; }
-  int x0, x1;
-  if (cx < 2) {                                   // cells cx-2 .. -1 wrap to the far end
-    if (half == 0) { x0 = nx + cx - 2; x1 = nx - 1; kx = 0; } else { x0 = 0; x1 = cx + 2; }
-  } else if (cx > nx - 3) {                       // cells nx .. cx+2 wrap to the start
-    if (half == 0) { x0 = cx - 2; x1 = nx - 1; } else { x0 = 0; x1 = cx + 2 - nx; kx = 2; }
-  } else {
-    if (half == 1) return false;
-    x0 = cx - 2; x1 = cx + 2;
-  }
-  const int rbase = (zz * ny + yy) * nx;
-  c0 = rbase + x0;
-  c1 = rbase + x1;
-  code = (kz * 3 + ky) * 3 + kx;
-  return true;
-}
-
-// The wave's segment table for particle vi in cell c (lane s describes
-// segment s) and the segments' candidate offsets (an exclusive scan): the
-// candidates of the 125 cells become one flat list.  Returns its length.
-__device__ __forceinline__ int segment_table(const RealArgs& a, PairQueue& Q, const double4& vi,
-                                             int c, int nx, int ny, int nz, const double l[3],
-                                             int lane) {
-  const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-  int len = 0;
-  {
-    int c0 = 0, c1 = -1, code = 0;
-    if (lane < kSegments && neighbour_segment(lane, cx, cy, cz, nx, ny, nz, c0, c1, code)) {
-      const int j0 = a.start[c0];
-      len = a.start[c1 + 1] - j0;
-      Q.seg_j0[lane] = j0;
-      Q.seg_code[lane] = code;
-      Q.seg_io[lane] = make_float4((float)(vi.x - l[0] * (double)(code % 3 - 1)),
-                                   (float)(vi.y - l[1] * (double)((code / 3) % 3 - 1)),
-                                   (float)(vi.z - l[2] * (double)(code / 9 - 1)), 0.0f);
-    } else if (lane < kSegments) {
-      Q.seg_j0[lane] = 0;
-      Q.seg_code[lane] = 13;
-      Q.seg_io[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-  }
-  int incl = len;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += v;
-  }
-  if (lane < kSegments) Q.seg_off[lane] = incl - len;
-  const int total = uniform(__shfl(incl, kSegments - 1, 64));
-  if (lane == 0) Q.seg_off[kSegments] = total;
-  wave_sync();
-  return total;
-}
-
-// The list build's segment table: the (2R+1)^3 cells around particle vi's
-// cell c, trimmed to the cells that can hold a neighbour: a row of cells
+// The segment table of particle vi in cell c, trimmed: of the (2R+1)^3
+// cells around c, only those that can hold a partner closer than rs (the
+// cutoff on the cell path, rc + skin for the list build): a row of cells
 // along x (fixed dy, dz) is dropped when its y-z distance from the particle
 // reaches rs, and a kept row keeps only the cells whose x distance from the
 // particle is below what rs leaves (distances from the particle's own
@@ -496,11 +432,11 @@ __device__ __forceinline__ int segment_table(const RealArgs& a, PairQueue& Q, co
 // closer than rs).  Segments in the order of the untrimmed table (rows by dz,
 // then dy; a row's part before a wrap in x, then after), so the accepted
 // candidates keep their order.  Lane s + 64 k describes segment s + 64 k;
-// returns the number of candidates.
-template <int R>
-__device__ __forceinline__ int list_segment_table(const RealArgs& a, ListSegs<R>& S,
-                                                  const double4& vi, int c, int nx, int ny, int nz,
-                                                  const double l[3], double rs, int lane) {
+// returns the number of candidates.  T: a PairQueue or ListSegs<R>.
+template <int R, class T>
+__device__ __forceinline__ int trimmed_segment_table(const RealArgs& a, T& S, const double4& vi,
+                                                     int c, int nx, int ny, int nz,
+                                                     const double l[3], double rs, int lane) {
   constexpr int kRow = 2 * R + 1, kSeg = ListSegs<R>::kSeg;
   const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
   const double wx = l[0] / nx, wy = l[1] / ny, wz = l[2] / nz;
@@ -712,9 +648,11 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
     double f[3] = {0.0, 0.0, 0.0};
     int qn = 0;                                   // queued pairs (wave-uniform)
     // the neighbour segments, lane s describing segment s, and their
-    // candidate offsets (an exclusive scan): the candidates of the 125 cells
-    // become one flat list, tested 64 at a time with every lane in use
-    const int total = segment_table(a, Q, vi, c, nx, ny, nz, l, lane);
+    // candidate offsets (an exclusive scan): the candidates of the cells that
+    // can hold a partner become one flat list, tested 64 at a time with every
+    // lane in use
+    static_assert(ListSegs<2>::kSeg == kSegments, "the cell path's segments");
+    const int total = trimmed_segment_table<2>(a, Q, vi, c, nx, ny, nz, l, a.rc, lane);
     // Alternate between testing candidates into the queue until it is
     // nearly full (or the candidates are exhausted) and evaluating the
     // queue, so the two phases' registers are never live together.
@@ -878,7 +816,7 @@ __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
     if (t >= a.n) goto done;
     const double4 vi = a.xq[t];
     const int c = uniform(a.cs[t]);
-    const int total = list_segment_table<kListReach>(a, Q, vi, c, nx, ny, nz, l, rs, lane);
+    const int total = trimmed_segment_table<kListReach>(a, Q, vi, c, nx, ny, nz, l, rs, lane);
     int cnt = 0, sg = 0;
     int32_t* out = a.nbr + (int64_t)t * a.kcap;
     for (int base = 0; base < total; base += 64) {
