@@ -206,7 +206,10 @@ __device__ __forceinline__ void csort_body(const RealArgs& a, int c) {
     v.z = frac_coord(a.z[i], 1.0 / l[2]) * l[2];
     v.w = a.q[i];
     a.xq[d] = v;
-    a.xf[d] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
+    // the type rides in the FP32 copy's fourth word (the list build stores it
+    // with each entry and so needs no load of its own)
+    a.xf[d] = make_float4((float)v.x, (float)v.y, (float)v.z,
+                          __int_as_float(a.type ? a.type[i] : 0));
     a.ts[d] = a.type ? a.type[i] : 0;
     a.cs[d] = c;
   }
@@ -819,33 +822,45 @@ __device__ __forceinline__ void build_body(const RealArgs& a, int bx) {
     const int total = trimmed_segment_table<kListReach>(a, Q, vi, c, nx, ny, nz, l, rs, lane);
     int cnt = 0, sg = 0;
     int32_t* out = a.nbr + (int64_t)t * a.kcap;
-    for (int base = 0; base < total; base += 64) {
-      const int cf = base + lane;
-      bool acc = false;
-      int j = -1;
+    // candidate b + lane: its index, segment and FP32 position (with the
+    // type), requested one batch ahead of its test
+    int nj = -1, nsg = 0;
+    float4 nv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    auto fetch = [&](int b) {
+      const int cf = b + lane;
+      nj = -1;
       if (cf < total) {
         while (Q.seg_off[sg + 1] <= cf) ++sg;
-        j = Q.seg_j0[sg] + (cf - Q.seg_off[sg]);
-        if (j != t) {
-          const float4 v = a.xf[j];
-          const float4 io = Q.seg_io[sg];
-          const float ex = v.x - io.x, ey = v.y - io.y, ez = v.z - io.z;
-          const float r2 = ex * ex + ey * ey + ez * ez;
-          if (r2 < lo) acc = true;
-          else if (r2 <= hi) {
-            const int code = Q.seg_code[sg];
-            const double4 d = a.xq[j];
-            const double dx = d.x - (vi.x - l[0] * (double)(code % 3 - 1));
-            const double dy = d.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1));
-            const double dz = d.z - (vi.z - l[2] * (double)(code / 9 - 1));
-            acc = dx * dx + dy * dy + dz * dz < rs2;
-          }
+        nj = Q.seg_j0[sg] + (cf - Q.seg_off[sg]);
+        nsg = sg;
+        nv = a.xf[nj];
+      }
+    };
+    fetch(0);
+    for (int base = 0; base < total; base += 64) {
+      const int j = nj, sj = nsg;
+      const float4 v = nv;
+      fetch(base + 64);
+      bool acc = false;
+      if (j >= 0 && j != t) {
+        const float4 io = Q.seg_io[sj];
+        const float ex = v.x - io.x, ey = v.y - io.y, ez = v.z - io.z;
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        if (r2 < lo) acc = true;
+        else if (r2 <= hi) {
+          const int code = Q.seg_code[sj];
+          const double4 d = a.xq[j];
+          const double dx = d.x - (vi.x - l[0] * (double)(code % 3 - 1));
+          const double dy = d.y - (vi.y - l[1] * (double)((code / 3) % 3 - 1));
+          const double dz = d.z - (vi.z - l[2] * (double)(code / 9 - 1));
+          acc = dx * dx + dy * dy + dz * dz < rs2;
         }
       }
       const uint64_t bal = __ballot(acc);
       if (acc) {
         const int pos = cnt + __popcll(bal & below);
-        if (pos < a.kcap) out[pos] = a.ntypes > 0 ? (j | (a.ts[j] << kListTypeShift)) : j;
+        if (pos < a.kcap)
+          out[pos] = a.ntypes > 0 ? (j | (__float_as_int(v.w) << kListTypeShift)) : j;
       }
       cnt += __popcll(bal);
     }
