@@ -286,11 +286,15 @@ __device__ __forceinline__ double exp_nonpos(double x, const double* etab) {
   return ldexp(fma(t, p * r, t), ni >> 6);
 }
 
+// S: the series for 0 <= x <= kErfcxShortX only, in u = (A x - K)/(x + K)
+// (six fewer terms), which the kernels take when sqrt(alpha) rc is in that range
+template <bool S>
 __device__ __forceinline__ double erfcx_pos(double x, const double* poly) {
-  const double t = (x - kErfcxK) * rcp_nr(x + kErfcxK);
-  double y = poly[kErfcxTerms - 1];
+  constexpr int n = S ? kErfcxTermsS : kErfcxTerms;
+  const double t = (S ? fma(kErfcxShortA, x, -kErfcxK) : x - kErfcxK) * rcp_nr(x + kErfcxK);
+  double y = poly[n - 1];
 #pragma unroll
-  for (int k = kErfcxTerms - 2; k >= 0; --k) y = fma(y, t, poly[k]);
+  for (int k = n - 2; k >= 0; --k) y = fma(y, t, poly[k]);
   return y;
 }
 
@@ -321,6 +325,7 @@ __device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue
 // the force on i is added as a wave sum (the same value in every lane, summed
 // in a fixed order); energy and virial accumulate per lane.
 // one pair's force on i (g), energy and virial terms (FP64)
+template <bool S>
 __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, double sa, double two_sa_pi,
                                           const double* poly, const double* etab, const double* lj,
@@ -335,7 +340,7 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
     // U'(r)/r = -qq (A + (2 sa/sqrt(pi)) exp(-sa^2 r^2))/r^2
     const double qq = a.coulomb * vi.w * p.qj;
     const double g2 = exp_nonpos(-a.alpha * r2, etab);
-    const double A = g2 * erfcx_pos(sa * r, poly) * ir;
+    const double A = g2 * erfcx_pos<S>(sa * r, poly) * ir;
     double rdU = -qq * fma(two_sa_pi, g2, A);                 // r U'(r)
     u = fma(qq, A, u);
     if (a.ntypes > 0) {
@@ -354,12 +359,13 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
   }
 }
 
+template <bool S>
 __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, const double l[3], double sa,
                                           double two_sa_pi, const double* poly, const double* etab,
                                           double f[3], double& u, double w[6]) {
   double gx, gy, gz;
-  pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, a.lj, gx, gy, gz, u, w);
+  pair_core<S>(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, a.lj, gx, gy, gz, u, w);
   f[0] += wsum(gx);
   f[1] += wsum(gy);
   f[2] += wsum(gz);
@@ -370,11 +376,14 @@ __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, 
 // series, exp(-x^2) and 1/sqrt from the hardware approximations (a few ulp);
 // energy and virial summed per lane in FP32 over one particle's pairs, then
 // folded into FP64; the force's wave sum is formed in FP32 and added in FP64.
+template <bool S>
 __device__ __forceinline__ float erfcx_pos32(float x, const float* poly) {
-  const float t = (x - (float)kErfcxK) * __builtin_amdgcn_rcpf(x + (float)kErfcxK);
-  float y = poly[kErfcxTerms32 - 1];
+  constexpr int n = S ? kErfcxTermsS32 : kErfcxTerms32;
+  const float t = (S ? fmaf((float)kErfcxShortA, x, -(float)kErfcxK) : x - (float)kErfcxK) *
+                  __builtin_amdgcn_rcpf(x + (float)kErfcxK);
+  float y = poly[n - 1];
 #pragma unroll
-  for (int k = kErfcxTerms32 - 2; k >= 0; --k) y = fmaf(y, t, poly[k]);
+  for (int k = n - 2; k >= 0; --k) y = fmaf(y, t, poly[k]);
   return y;
 }
 
@@ -384,6 +393,7 @@ __device__ __forceinline__ float wsumf(float v) {
   return v;
 }
 
+template <bool S>
 __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p, bool valid,
                                             const double4& vi, int ti, float sa, float two_sa_pi,
                                             float alpha, const float* poly, const double* lj,
@@ -396,7 +406,7 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
     const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir, r = r2 * ir;
     const float qq = (float)(a.coulomb * vi.w * p.qj);
     const float g2 = __expf(-alpha * r2);
-    const float A = g2 * erfcx_pos32(sa * r, poly) * ir;
+    const float A = g2 * erfcx_pos32<S>(sa * r, poly) * ir;
     float rdU = -qq * fmaf(two_sa_pi, g2, A);                 // r U'(r)
     u = fmaf(qq, A, u);
     if (a.ntypes > 0) {
@@ -413,12 +423,13 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
   }
 }
 
+template <bool S>
 __device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p, bool valid,
                                             const double4& vi, int ti, const double l[3], float sa,
                                             float two_sa_pi, float alpha, const float* poly,
                                             double f[3], float& u, float w[6]) {
   float gx, gy, gz;
-  pair_core32(a, p, valid, vi, ti, sa, two_sa_pi, alpha, poly, a.lj, gx, gy, gz, u, w);
+  pair_core32<S>(a, p, valid, vi, ti, sa, two_sa_pi, alpha, poly, a.lj, gx, gy, gz, u, w);
   f[0] += (double)wsumf(gx);
   f[1] += (double)wsumf(gy);
   f[2] += (double)wsumf(gz);
@@ -619,7 +630,7 @@ __device__ __forceinline__ void block_energy_virial(const RealArgs& a, double u,
   if (threadIdx.x == 0) __hip_atomic_store(&a.cnt[ng], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool P32>
+template <bool P32, bool S>
 __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   __shared__ PairQueue queue[kPairWaves];
   __shared__ double sh[kPairWaves][8];
@@ -627,9 +638,10 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   if (a.skin > 0.0) return;                     // list mode: k_pairs_list
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
-  if (lane < kErfcxTerms) Q.poly[lane] = kErfcxPoly[lane];
+  if (lane < (S ? kErfcxTermsS : kErfcxTerms)) Q.poly[lane] = S ? kErfcxPolyS[lane] : kErfcxPoly[lane];
   Q.etab[lane] = kExpTab[lane];
-  if (lane < kErfcxTerms32) Q.poly32[lane] = kErfcxPoly32[lane];
+  if (lane < (S ? kErfcxTermsS32 : kErfcxTerms32))
+    Q.poly32[lane] = S ? kErfcxPolyS32[lane] : kErfcxPoly32[lane];
   wave_sync();
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   double l[3];
@@ -717,10 +729,10 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
         PairLoad cur;
         if (from + lane < m) cur = pair_load(a, Q, from + lane, vi, l);
         if (P32)
-          pair_eval32(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
+          pair_eval32<S>(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
                       (float)a.alpha, Q.poly32, f, u32, w32);
         else
-          pair_eval(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, Q.etab, f, u, w);
+          pair_eval<S>(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, Q.etab, f, u, w);
       }
       wave_sync();
       if (lane < qn - m) { Q.j[lane] = Q.j[m + lane]; Q.s[lane] = Q.s[m + lane]; }
@@ -905,7 +917,7 @@ __device__ __forceinline__ void list_to_lds(const RealArgs& a, int t, int c0, in
 // the wave once per particle.  LJL: the Lennard-Jones table (at most
 // kLjLds types) is read from LDS, which keeps its loads off the vector-memory
 // counter the prefetched batch waits on.
-template <bool P32, bool LJL>
+template <bool P32, bool LJL, bool S>
 __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int nbx) {
   __shared__ int32_t lidx[kPairWaves][2][kListChunk];
   __shared__ double poly[kErfcxTerms];
@@ -916,9 +928,11 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
   __shared__ int sh_last;
   if (!(a.skin > 0.0)) return;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  if (threadIdx.x < kErfcxTerms) poly[threadIdx.x] = kErfcxPoly[threadIdx.x];
+  if (threadIdx.x < (S ? kErfcxTermsS : kErfcxTerms))
+    poly[threadIdx.x] = S ? kErfcxPolyS[threadIdx.x] : kErfcxPoly[threadIdx.x];
   if (threadIdx.x < 64) etab[threadIdx.x] = kExpTab[threadIdx.x];
-  if (threadIdx.x < kErfcxTerms32) poly32[threadIdx.x] = kErfcxPoly32[threadIdx.x];
+  if (threadIdx.x < (S ? kErfcxTermsS32 : kErfcxTerms32))
+    poly32[threadIdx.x] = S ? kErfcxPolyS32[threadIdx.x] : kErfcxPoly32[threadIdx.x];
   if (LJL)
     for (int q = threadIdx.x; q < 2 * a.ntypes * a.ntypes; q += blockDim.x) ljs[q] = a.lj[q];
   __syncthreads();
@@ -981,12 +995,12 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
         p.tj = jc >> kListTypeShift;
         if (P32) {
           float gx, gy, gz;
-          pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, poly32,
+          pair_core32<S>(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, poly32,
                       LJL ? ljs : a.lj, gx, gy, gz, u32, w32);
           fx32 += gx; fy32 += gy; fz32 += gz;
         } else {
           double gx, gy, gz;
-          pair_core(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, LJL ? ljs : a.lj, gx, gy, gz, u,
+          pair_core<S>(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, LJL ? ljs : a.lj, gx, gy, gz, u,
                     w);
           fx += gx; fy += gy; fz += gz;
         }
@@ -1013,25 +1027,27 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
 
 // four waves per SIMD: the register budget that keeps the pair evaluation
 // from spilling beyond a few registers
-template <bool P32>
+template <bool P32, bool S>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_pairs(RealArgs a) {
-  pairs_body<P32>(a, blockIdx.x, gridDim.x);
+  pairs_body<P32, S>(a, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(256) k_vcheck(RealArgs a) { vcheck_body(a, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(kPairWaves * 64) k_build(RealArgs a) { build_body(a, blockIdx.x); }
-template <bool P32, bool LJL>
+template <bool P32, bool LJL, bool S>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pairs_list(RealArgs a) {
-  pairs_list_body<P32, LJL>(a, blockIdx.x, gridDim.x);
+  pairs_list_body<P32, LJL, S>(a, blockIdx.x, gridDim.x);
 }
 
-template <bool LJL>
+bool short_series(const RealArgs& a) { return sqrt(a.alpha) * a.rc <= kErfcxShortX; }
+
+template <bool LJL, bool S>
 void launch_pairs_list(const RealArgs& a, hipStream_t s) {
   const dim3 g((unsigned)list_blocks(a.n, a.prec32 != 0)), b(kPairWaves * 64);
-  if (a.prec32) hipLaunchKernelGGL((k_pairs_list<true, LJL>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_pairs_list<false, LJL>), g, b, 0, s, a);
+  if (a.prec32) hipLaunchKernelGGL((k_pairs_list<true, LJL, S>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_pairs_list<false, LJL, S>), g, b, 0, s, a);
 }
 
 hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s) {
@@ -1043,8 +1059,12 @@ hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_build, dim3(qb), dim3(kPairWaves * 64), 0, s, a);
-  if (a.ntypes <= kLjLds) launch_pairs_list<true>(a, s);
-  else launch_pairs_list<false>(a, s);
+  const bool sr = short_series(a);
+  if (a.ntypes <= kLjLds) {
+    if (sr) launch_pairs_list<true, true>(a, s); else launch_pairs_list<true, false>(a, s);
+  } else {
+    if (sr) launch_pairs_list<false, true>(a, s); else launch_pairs_list<false, false>(a, s);
+  }
   return hipGetLastError();
 }
 
@@ -1055,10 +1075,15 @@ hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_fill, dim3(pb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_csort, dim3(ncell_cap), dim3(256), 0, s, a);
-  if (a.prec32)
-    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)pair_blocks(a.n, true)), dim3(kPairWaves * 64), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)pair_blocks(a.n, false)), dim3(kPairWaves * 64), 0, s, a);
+  const dim3 g((unsigned)pair_blocks(a.n, a.prec32 != 0)), b(kPairWaves * 64);
+  const bool sr = short_series(a);
+  if (a.prec32) {
+    if (sr) hipLaunchKernelGGL((k_pairs<true, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_pairs<true, false>), g, b, 0, s, a);
+  } else {
+    if (sr) hipLaunchKernelGGL((k_pairs<false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_pairs<false, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -1106,11 +1131,11 @@ __global__ void __launch_bounds__(256) k_csort_m(const RealArgs* tab, const int*
   (void)nb;
   csort_body(sa, lb);
 }
-template <bool P32>
+template <bool P32, bool S>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_pairs_m(const RealArgs* tab, const int* bstart, int nsys) {
   REAL_MULTI_PROLOGUE
-  pairs_body<P32>(sa, lb, nb);
+  pairs_body<P32, S>(sa, lb, nb);
 }
 
 __global__ void __launch_bounds__(256) k_vcheck_m(const RealArgs* tab, const int* bstart, int nsys) {
@@ -1123,22 +1148,39 @@ __global__ void __launch_bounds__(kPairWaves * 64) k_build_m(const RealArgs* tab
   (void)nb;
   build_body(sa, lb);
 }
-template <bool P32, bool LJL>
+template <bool P32, bool LJL, bool S>
 __global__ void __launch_bounds__(kPairWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pairs_list_m(const RealArgs* tab, const int* bstart, int nsys) {
   REAL_MULTI_PROLOGUE
-  pairs_list_body<P32, LJL>(sa, lb, nb);
+  pairs_list_body<P32, LJL, S>(sa, lb, nb);
+}
+
+template <bool LJL, bool S>
+void launch_pairs_list_m(int prec32, dim3 g, hipStream_t s, const RealArgs* d_tab,
+                         const int* d_bstart_q, int nsys) {
+  const dim3 b(kPairWaves * 64);
+  if (prec32) hipLaunchKernelGGL((k_pairs_list_m<true, LJL, S>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+  else hipLaunchKernelGGL((k_pairs_list_m<false, LJL, S>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+}
+
+template <bool S>
+void launch_pairs_m(int prec32, dim3 g, hipStream_t s, const RealArgs* d_tab, const int* d_bstart_q,
+                    int nsys) {
+  const dim3 b(kPairWaves * 64);
+  if (prec32) hipLaunchKernelGGL((k_pairs_m<true, S>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+  else hipLaunchKernelGGL((k_pairs_m<false, S>), g, b, 0, s, d_tab, d_bstart_q, nsys);
 }
 
 // bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
 // bstart_q: pair blocks (pair_blocks(n, prec32) each for a cell-list
 // system, list_blocks(n, prec32) for a neighbour-list one); bstart_b:
-// list-build blocks (build_blocks(n) each)
+// list-build blocks (build_blocks(n) each); short_sr: every system has
+// sqrt(alpha) rc <= kErfcxShortX
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
                              const int* d_bstart_b, int total_b,
                              const int* d_bstart_v, int total_v, int any_list, int any_cells,
-                             int max_types, int nsys, int prec32, hipStream_t s) {
+                             int max_types, int nsys, int prec32, int short_sr, hipStream_t s) {
   if (any_list) hipLaunchKernelGGL(k_vcheck_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
   hipLaunchKernelGGL(k_bin_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_scan_m, dim3(nsys), dim3(1024), 0, s, d_tab, nsys);
@@ -1146,20 +1188,18 @@ hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int t
   hipLaunchKernelGGL(k_csort_m, dim3(total_c), dim3(256), 0, s, d_tab, d_bstart_c, nsys);
   if (any_list) {
     hipLaunchKernelGGL(k_build_m, dim3(total_b), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_b, nsys);
-    const dim3 g((unsigned)total_q), b(kPairWaves * 64);
+    const dim3 g((unsigned)total_q);
     if (max_types <= kLjLds) {
-      if (prec32) hipLaunchKernelGGL((k_pairs_list_m<true, true>), g, b, 0, s, d_tab, d_bstart_q, nsys);
-      else hipLaunchKernelGGL((k_pairs_list_m<false, true>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+      if (short_sr) launch_pairs_list_m<true, true>(prec32, g, s, d_tab, d_bstart_q, nsys);
+      else launch_pairs_list_m<true, false>(prec32, g, s, d_tab, d_bstart_q, nsys);
     } else {
-      if (prec32) hipLaunchKernelGGL((k_pairs_list_m<true, false>), g, b, 0, s, d_tab, d_bstart_q, nsys);
-      else hipLaunchKernelGGL((k_pairs_list_m<false, false>), g, b, 0, s, d_tab, d_bstart_q, nsys);
+      if (short_sr) launch_pairs_list_m<false, true>(prec32, g, s, d_tab, d_bstart_q, nsys);
+      else launch_pairs_list_m<false, false>(prec32, g, s, d_tab, d_bstart_q, nsys);
     }
   }
   if (any_cells) {
-    if (prec32)
-      hipLaunchKernelGGL(k_pairs_m<true>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
-    else
-      hipLaunchKernelGGL(k_pairs_m<false>, dim3(total_q), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_q, nsys);
+    if (short_sr) launch_pairs_m<true>(prec32, dim3(total_q), s, d_tab, d_bstart_q, nsys);
+    else launch_pairs_m<false>(prec32, dim3(total_q), s, d_tab, d_bstart_q, nsys);
   }
   return hipGetLastError();
 }

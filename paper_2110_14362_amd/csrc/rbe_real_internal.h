@@ -100,13 +100,16 @@ struct RealArgs {
 __host__ __device__ inline double search_radius(const RealArgs& a) { return a.rc + a.skin; }
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
+// the pair kernels take the bounded-range erfcx series (fewer terms): every
+// evaluated pair has sqrt(alpha) r < sqrt(alpha) rc within its range
+bool short_series(const RealArgs& a);
 // list-mode evaluation (a.skin > 0): check (and gather), conditional rebuild, pairs
 hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
                              const int* d_bstart_b, int total_b,
                              const int* d_bstart_v, int total_v, int any_list, int any_cells,
-                             int max_types, int nsys, int prec32, hipStream_t s);
+                             int max_types, int nsys, int prec32, int short_sr, hipStream_t s);
 
 // host side of rbe_real_forces without the launches
 rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,

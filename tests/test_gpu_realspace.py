@@ -99,6 +99,25 @@ def test_electrolyte_coulomb(gpu, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("skin", [0.0, 1.0])
+def test_wide_splitting_takes_the_full_erfcx_series(gpu, precision, skin):
+    # sqrt(alpha) rc = 5.4 lies beyond the bounded-range erfcx series (x <= 4)
+    # that the other cases take: the cell and list kernels then evaluate the
+    # series over all x >= 0
+    s = dict(workloads.make("electrolyte_1k"))
+    s["alpha"] = 0.81
+    g = run_gpu(s, gpu, 6.0, precision=precision, skin=skin)
+    o = oracle(s, 6.0)
+    print("wide splitting %s skin %.1f: force %.2e virial %.2e energy %.2e" %
+          (precision, skin, rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
+           abs(g["energy"] - o["energy"]) / abs(o["energy"])))
+    tol = TOLR[precision]
+    assert rel(g["forces"], o["forces"]) < tol
+    assert rel(g["virial"], o["virial"]) < tol
+    assert abs(g["energy"] - o["energy"]) < tol * abs(o["energy"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_water_with_lj(gpu, precision):
     s = workloads.water(1000, seed=7)
     s.update(alpha=0.09, coulomb=332.0637)
