@@ -403,12 +403,12 @@ rbe_status batch_step_impl(rbe_batch b, int32_t fused, bool fourier_only) {
   // the capacity
   std::vector<int> pb(nsys), ub(nsys), cb(nsys), qb(nsys), vb(nsys), bb(nsys);
   const bool p32 = b->cfg.real_precision == RBE_PREC_FP32;
-  int any_list = 0, any_cells = 0, max_types = 0, short_sr = 1;
+  int any_list = 0, any_cells = 0, max_types = 0, series = 0;
   for (int j = 0; j < nsys && !fourier_only; ++j) {
     vb[j] = (int)((b->slots[act[j]].desc.n + 255) / 256);
     if (ra[j].skin > 0.0) any_list = 1; else any_cells = 1;
     max_types = std::max(max_types, ra[j].ntypes);
-    if (!short_series(ra[j])) short_sr = 0;
+    series |= short_series(ra[j]) ? 1 : 2;
     pb[j] = (int)bin_blocks(b->slots[act[j]].desc.n);
     ub[j] = (int)md_blocks(md_units(md1[j]));
     cb[j] = ncap[j];
@@ -489,7 +489,7 @@ rbe_status batch_step_impl(rbe_batch b, int32_t fused, bool fourier_only) {
     e = launch_real_multi(d_ra, d_pstart, pstart.back(), d_cstart, cstart.back(), d_qstart,
                           qstart.back(), d_bstart_b, bstart.back(), d_vstart, vstart.back(), any_list,
                           any_cells, max_types, nsys,
-                          b->cfg.real_precision == RBE_PREC_FP32, short_sr, b->stream);
+                          b->cfg.real_precision == RBE_PREC_FP32, series, b->stream);
   mark(4);
   if (e == hipSuccess && !fourier_only)
     e = launch_md_second_multi(d_md2, d_ustart, nsys, ustart.back(), 0, b->stream);

@@ -636,6 +636,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   __shared__ double sh[kPairWaves][8];
   __shared__ int sh_last;
   if (a.skin > 0.0) return;                     // list mode: k_pairs_list
+  if (short_series(a) != S) return;             // the other series' instance
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   PairQueue& Q = queue[wave];
   if (lane < (S ? kErfcxTermsS : kErfcxTerms)) Q.poly[lane] = S ? kErfcxPolyS[lane] : kErfcxPoly[lane];
@@ -927,6 +928,7 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
   __shared__ double sh[kPairWaves][8];
   __shared__ int sh_last;
   if (!(a.skin > 0.0)) return;
+  if (short_series(a) != S) return;             // the other series' instance
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   if (threadIdx.x < (S ? kErfcxTermsS : kErfcxTerms))
     poly[threadIdx.x] = S ? kErfcxPolyS[threadIdx.x] : kErfcxPoly[threadIdx.x];
@@ -1041,7 +1043,7 @@ k_pairs_list(RealArgs a) {
   pairs_list_body<P32, LJL, S>(a, blockIdx.x, gridDim.x);
 }
 
-bool short_series(const RealArgs& a) { return sqrt(a.alpha) * a.rc <= kErfcxShortX; }
+static_assert(kErfcxRange == kErfcxShortX, "the range of the bounded erfcx series");
 
 template <bool LJL, bool S>
 void launch_pairs_list(const RealArgs& a, hipStream_t s) {
@@ -1174,13 +1176,15 @@ void launch_pairs_m(int prec32, dim3 g, hipStream_t s, const RealArgs* d_tab, co
 // bstart_p: binning blocks (bin_blocks(n) each); bstart_c: cell blocks;
 // bstart_q: pair blocks (pair_blocks(n, prec32) each for a cell-list
 // system, list_blocks(n, prec32) for a neighbour-list one); bstart_b:
-// list-build blocks (build_blocks(n) each); short_sr: every system has
-// sqrt(alpha) rc <= kErfcxShortX
+// list-build blocks (build_blocks(n) each); series: bit 0 set if some
+// system takes the bounded-range erfcx series, bit 1 if some takes the full
+// one (each instance's blocks of the other kind's systems return at once, so
+// a system's results do not depend on the others in the launch)
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
                              const int* d_bstart_b, int total_b,
                              const int* d_bstart_v, int total_v, int any_list, int any_cells,
-                             int max_types, int nsys, int prec32, int short_sr, hipStream_t s) {
+                             int max_types, int nsys, int prec32, int series, hipStream_t s) {
   if (any_list) hipLaunchKernelGGL(k_vcheck_m, dim3(total_v), dim3(256), 0, s, d_tab, d_bstart_v, nsys);
   hipLaunchKernelGGL(k_bin_m, dim3(total_p), dim3(256), 0, s, d_tab, d_bstart_p, nsys);
   hipLaunchKernelGGL(k_scan_m, dim3(nsys), dim3(1024), 0, s, d_tab, nsys);
@@ -1190,16 +1194,16 @@ hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int t
     hipLaunchKernelGGL(k_build_m, dim3(total_b), dim3(kPairWaves * 64), 0, s, d_tab, d_bstart_b, nsys);
     const dim3 g((unsigned)total_q);
     if (max_types <= kLjLds) {
-      if (short_sr) launch_pairs_list_m<true, true>(prec32, g, s, d_tab, d_bstart_q, nsys);
-      else launch_pairs_list_m<true, false>(prec32, g, s, d_tab, d_bstart_q, nsys);
+      if (series & 1) launch_pairs_list_m<true, true>(prec32, g, s, d_tab, d_bstart_q, nsys);
+      if (series & 2) launch_pairs_list_m<true, false>(prec32, g, s, d_tab, d_bstart_q, nsys);
     } else {
-      if (short_sr) launch_pairs_list_m<false, true>(prec32, g, s, d_tab, d_bstart_q, nsys);
-      else launch_pairs_list_m<false, false>(prec32, g, s, d_tab, d_bstart_q, nsys);
+      if (series & 1) launch_pairs_list_m<false, true>(prec32, g, s, d_tab, d_bstart_q, nsys);
+      if (series & 2) launch_pairs_list_m<false, false>(prec32, g, s, d_tab, d_bstart_q, nsys);
     }
   }
   if (any_cells) {
-    if (short_sr) launch_pairs_m<true>(prec32, dim3(total_q), s, d_tab, d_bstart_q, nsys);
-    else launch_pairs_m<false>(prec32, dim3(total_q), s, d_tab, d_bstart_q, nsys);
+    if (series & 1) launch_pairs_m<true>(prec32, dim3(total_q), s, d_tab, d_bstart_q, nsys);
+    if (series & 2) launch_pairs_m<false>(prec32, dim3(total_q), s, d_tab, d_bstart_q, nsys);
   }
   return hipGetLastError();
 }

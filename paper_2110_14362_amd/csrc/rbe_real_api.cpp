@@ -135,6 +135,7 @@ rbe_status rbe_real_init(const rbe_real_config* cfg, const double* d_q, const in
   a.n = cfg->n; a.ntypes = cfg->ntypes;
   a.prec32 = cfg->precision == RBE_PREC_FP32 ? 1 : 0;
   a.alpha = cfg->alpha; a.rc = cfg->rc; a.coulomb = cfg->coulomb;
+  a.erfcx_short = std::sqrt(cfg->alpha) * cfg->rc <= kErfcxRange ? 1 : 0;
   long cap = 1;
   for (int d = 0; d < 3; ++d) {
     long v = (long)std::floor(4.0 * box_host[d] / cfg->rc);   // cells at least rc/2 wide, box up to 2x

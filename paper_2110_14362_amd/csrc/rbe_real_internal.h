@@ -65,7 +65,8 @@ struct RealArgs {
   const double* q; const int32_t* type;   // type may be NULL
   const double* lj;                        // [ntypes*ntypes][2] = (c12, c6)
   int32_t ntypes, accumulate;
-  int32_t prec32, pad;                     // 1: single-precision pair arithmetic
+  int32_t prec32;                          // 1: single-precision pair arithmetic
+  int32_t erfcx_short;                     // 1: the bounded-range erfcx series (short_series)
   int64_t n;
   double alpha, rc, coulomb;
   double box[3];                           // used when box_ptr is NULL
@@ -100,16 +101,19 @@ struct RealArgs {
 __host__ __device__ inline double search_radius(const RealArgs& a) { return a.rc + a.skin; }
 
 hipError_t launch_real(const RealArgs& a, int ncell_cap, hipStream_t s);
-// the pair kernels take the bounded-range erfcx series (fewer terms): every
-// evaluated pair has sqrt(alpha) r < sqrt(alpha) rc within its range
-bool short_series(const RealArgs& a);
+// The pair kernels take the bounded-range erfcx series (fewer terms) when
+// every evaluated pair has x = sqrt(alpha) r < sqrt(alpha) rc within its
+// range [0, 4]: decided once on the host at set-up (RealArgs::erfcx_short),
+// per system, and read by the launches and the kernels alike.
+constexpr double kErfcxRange = 4.0;
+__host__ __device__ inline bool short_series(const RealArgs& a) { return a.erfcx_short != 0; }
 // list-mode evaluation (a.skin > 0): check (and gather), conditional rebuild, pairs
 hipError_t launch_real_list(const RealArgs& a, int ncell_cap, hipStream_t s);
 hipError_t launch_real_multi(const RealArgs* d_tab, const int* d_bstart_p, int total_p,
                              const int* d_bstart_c, int total_c, const int* d_bstart_q, int total_q,
                              const int* d_bstart_b, int total_b,
                              const int* d_bstart_v, int total_v, int any_list, int any_cells,
-                             int max_types, int nsys, int prec32, int short_sr, hipStream_t s);
+                             int max_types, int nsys, int prec32, int series, hipStream_t s);
 
 // host side of rbe_real_forces without the launches
 rbe_status real_step_args(rbe_real_ctx c, const double* d_x, const double* d_y, const double* d_z,

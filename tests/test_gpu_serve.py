@@ -67,6 +67,46 @@ def test_alone_equals_mix_bitwise(gpu):
               % (r.rid, r.n, steps, got["box"]), flush=True)
 
 
+def wide_splitting(r, g_rc=4.5):
+    """The request with alpha raised so that sqrt(alpha) rc = g_rc."""
+    sysd = dict(r.sysd)
+    sysd["alpha"] = (g_rc / sysd["rc"]) ** 2
+    w = serve.Request(r.rid, 0.0, sysd, r.md, r.steps)
+    w.desc.system_id = r.rid
+    return w
+
+
+def test_mixed_erfcx_series_alone_equals_mix_bitwise(gpu):
+    # systems with sqrt(alpha) rc > 4 take the full-range erfcx series, the
+    # others the bounded-range one; in a fused launch each instance evaluates
+    # only its own systems, so every system's trajectory stays bitwise its own
+    reqs = [request(0, 1500), request(1, 3000, kinds=("water",), skin=2.0),
+            wide_splitting(request(2, 2000)),
+            wide_splitting(request(3, 3000, kinds=("water",), skin=2.0))]
+    g_rc = [float(np.sqrt(r.sysd["alpha"]) * r.sysd["rc"]) for r in reqs]
+    assert g_rc[0] <= 4.0 and g_rc[1] <= 4.0 and g_rc[2] > 4.0 and g_rc[3] > 4.0
+    print("sizes", [r.n for r in reqs], "g rc", np.round(g_rc, 3).tolist(), flush=True)
+    b = Batch(BUDGET, max_systems=8, precision="fp32")
+    slots = [serve._admit(b, r) for r in reqs]
+    for _ in range(3):
+        b.step()
+    b.sync()
+    mix = {}
+    for r, sl in zip(reqs, slots):
+        b.check(sl)
+        mix[r.rid] = b.read(sl)
+    b.close()
+    for r in reqs:
+        got = mix[r.rid]
+        for fused in (True, False):
+            ref = run_alone(r, 3, fused=fused)
+            np.testing.assert_array_equal(got["pos"], ref["pos"])
+            np.testing.assert_array_equal(got["mom"], ref["mom"])
+            np.testing.assert_array_equal(got["box"], ref["box"])
+        print("request %d (N=%d, g rc %.2f): identical alone and in the mix"
+              % (r.rid, r.n, g_rc[r.rid]), flush=True)
+
+
 def test_served_equals_one_system_api(gpu):
     # the served runtime launches the Fourier step as two kernels; the
     # one-system API in that form gives the same bits, and in its default
