@@ -267,6 +267,16 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return fma(fma(-d, y, 1.0), y, y);
 }
 
+// 1/sqrt(d) for a finite d > 0: the hardware estimate y refined by one
+// second-order Newton step, y (1 + e/2 + 3 e^2/8) with e = 1 - d y^2 (the
+// library's steps without its handling of zero, infinite and denormal d, which
+// a pair separation never is)
+__device__ __forceinline__ double rsqrt_pos(double d) {
+  const double y = __builtin_amdgcn_rsq(d);
+  const double e = fma(-d * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // e^x for x <= 0 by Tang's table-driven method (ACM TOMS 15 (1989) 144):
 // x = (64 m + j) ln2/64 + r with |r| <= ln2/128 and e^x = 2^m 2^(j/64) e^r,
 // e^r - 1 from its Taylor polynomial of degree 6 (truncated below 2e-20 of
@@ -335,7 +345,7 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
   if (valid) {
     const double ex = p.ex, ey = p.ey, ez = p.ez;
     const double r2 = ex * ex + ey * ey + ez * ez;
-    const double ir = rsqrt(r2), ir2 = ir * ir, r = r2 * ir;
+    const double ir = rsqrt_pos(r2), ir2 = ir * ir, r = r2 * ir;
     // Coulomb: U = C qi qj erfc(sa r)/r = qq A,
     // U'(r)/r = -qq (A + (2 sa/sqrt(pi)) exp(-sa^2 r^2))/r^2
     const double qq = a.coulomb * vi.w * p.qj;
