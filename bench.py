@@ -422,8 +422,8 @@ def main():
         print(json.dumps(issue_rates()), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); the multi-GPU "
-              "sharding of the Fourier-space step is described, not built.", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (--gpus 1); sharding the "
+              "Fourier-space step over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2110_14362_amd import workloads
