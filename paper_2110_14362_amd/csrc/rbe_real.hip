@@ -331,6 +331,20 @@ __device__ __forceinline__ PairLoad pair_load(const RealArgs& a, const PairQueue
   return p;
 }
 
+// Whether type t has a nonzero Lennard-Jones pair with some type (wave-
+// uniform for a uniform t).  In the FP64 pair kernels a particle whose row is
+// all zeros, such as a water hydrogen, skips the Lennard-Jones terms (they
+// would add exact zeros); the FP32 ones measured slower with the branch.
+__device__ __forceinline__ bool lj_row_nonzero(const RealArgs& a, const double* lj, int t) {
+  if (a.ntypes <= 0) return false;
+  int any = 0;
+  for (int v = 0; v < a.ntypes; ++v) {
+    const int k = t * a.ntypes + v;
+    any |= (lj[2 * k] != 0.0 || lj[2 * k + 1] != 0.0) ? 1 : 0;
+  }
+  return uniform(any) != 0;
+}
+
 // Evaluate one loaded pair per lane (lanes with valid = false add nothing):
 // the force on i is added as a wave sum (the same value in every lane, summed
 // in a fixed order); energy and virial accumulate per lane.
@@ -339,7 +353,7 @@ template <bool S>
 __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, double sa, double two_sa_pi,
                                           const double* poly, const double* etab, const double* lj,
-                                          double& gx, double& gy, double& gz, double& u,
+                                          bool lj_on, double& gx, double& gy, double& gz, double& u,
                                           double w[6]) {
   gx = 0.0; gy = 0.0; gz = 0.0;
   if (valid) {
@@ -353,7 +367,7 @@ __device__ __forceinline__ void pair_core(const RealArgs& a, const PairLoad& p, 
     const double A = g2 * erfcx_pos<S>(sa * r, poly) * ir;
     double rdU = -qq * fma(two_sa_pi, g2, A);                 // r U'(r)
     u = fma(qq, A, u);
-    if (a.ntypes > 0) {
+    if (lj_on) {
       // U = c12/r^12 - c6/r^6,  r U'(r) = -12 c12/r^12 + 6 c6/r^6
       const int k = ti * a.ntypes + p.tj;
       const double i6 = ir2 * ir2 * ir2;
@@ -373,9 +387,9 @@ template <bool S>
 __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, bool valid,
                                           const double4& vi, int ti, const double l[3], double sa,
                                           double two_sa_pi, const double* poly, const double* etab,
-                                          double f[3], double& u, double w[6]) {
+                                          bool lj_on, double f[3], double& u, double w[6]) {
   double gx, gy, gz;
-  pair_core<S>(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, a.lj, gx, gy, gz, u, w);
+  pair_core<S>(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, a.lj, lj_on, gx, gy, gz, u, w);
   f[0] += wsum(gx);
   f[1] += wsum(gy);
   f[2] += wsum(gz);
@@ -386,14 +400,13 @@ __device__ __forceinline__ void pair_eval(const RealArgs& a, const PairLoad& p, 
 // series, exp(-x^2) and 1/sqrt from the hardware approximations (a few ulp);
 // energy and virial summed per lane in FP32 over one particle's pairs, then
 // folded into FP64; the force's wave sum is formed in FP32 and added in FP64.
-template <bool S>
+// erfcx is always the full-range series here: the bounded-range one measured
+// no faster in this kernel, which waits on its loads more than it issues.
 __device__ __forceinline__ float erfcx_pos32(float x, const float* poly) {
-  constexpr int n = S ? kErfcxTermsS32 : kErfcxTerms32;
-  const float t = (S ? fmaf((float)kErfcxShortA, x, -(float)kErfcxK) : x - (float)kErfcxK) *
-                  __builtin_amdgcn_rcpf(x + (float)kErfcxK);
-  float y = poly[n - 1];
+  const float t = (x - (float)kErfcxK) * __builtin_amdgcn_rcpf(x + (float)kErfcxK);
+  float y = poly[kErfcxTerms32 - 1];
 #pragma unroll
-  for (int k = n - 2; k >= 0; --k) y = fmaf(y, t, poly[k]);
+  for (int k = kErfcxTerms32 - 2; k >= 0; --k) y = fmaf(y, t, poly[k]);
   return y;
 }
 
@@ -403,11 +416,10 @@ __device__ __forceinline__ float wsumf(float v) {
   return v;
 }
 
-template <bool S>
 __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p, bool valid,
                                             const double4& vi, int ti, float sa, float two_sa_pi,
                                             float alpha, const float* poly, const double* lj,
-                                            float& gx, float& gy, float& gz, float& u,
+                                            bool lj_on, float& gx, float& gy, float& gz, float& u,
                                             float w[6]) {
   gx = 0.0f; gy = 0.0f; gz = 0.0f;
   if (valid) {
@@ -416,10 +428,10 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
     const float ir = __builtin_amdgcn_rsqf(r2), ir2 = ir * ir, r = r2 * ir;
     const float qq = (float)(a.coulomb * vi.w * p.qj);
     const float g2 = __expf(-alpha * r2);
-    const float A = g2 * erfcx_pos32<S>(sa * r, poly) * ir;
+    const float A = g2 * erfcx_pos32(sa * r, poly) * ir;
     float rdU = -qq * fmaf(two_sa_pi, g2, A);                 // r U'(r)
     u = fmaf(qq, A, u);
-    if (a.ntypes > 0) {
+    if (lj_on) {
       const int k = ti * a.ntypes + p.tj;
       const float i6 = ir2 * ir2 * ir2;
       const float t12 = (float)lj[2 * k] * i6 * i6, t6 = (float)lj[2 * k + 1] * i6;
@@ -433,13 +445,12 @@ __device__ __forceinline__ void pair_core32(const RealArgs& a, const PairLoad& p
   }
 }
 
-template <bool S>
 __device__ __forceinline__ void pair_eval32(const RealArgs& a, const PairLoad& p, bool valid,
                                             const double4& vi, int ti, const double l[3], float sa,
                                             float two_sa_pi, float alpha, const float* poly,
-                                            double f[3], float& u, float w[6]) {
+                                            bool lj_on, double f[3], float& u, float w[6]) {
   float gx, gy, gz;
-  pair_core32<S>(a, p, valid, vi, ti, sa, two_sa_pi, alpha, poly, a.lj, gx, gy, gz, u, w);
+  pair_core32(a, p, valid, vi, ti, sa, two_sa_pi, alpha, poly, a.lj, lj_on, gx, gy, gz, u, w);
   f[0] += (double)wsumf(gx);
   f[1] += (double)wsumf(gy);
   f[2] += (double)wsumf(gz);
@@ -651,8 +662,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
   PairQueue& Q = queue[wave];
   if (lane < (S ? kErfcxTermsS : kErfcxTerms)) Q.poly[lane] = S ? kErfcxPolyS[lane] : kErfcxPoly[lane];
   Q.etab[lane] = kExpTab[lane];
-  if (lane < (S ? kErfcxTermsS32 : kErfcxTerms32))
-    Q.poly32[lane] = S ? kErfcxPolyS32[lane] : kErfcxPoly32[lane];
+  if (lane < kErfcxTerms32) Q.poly32[lane] = kErfcxPoly32[lane];
   wave_sync();
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   double l[3];
@@ -670,6 +680,7 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
     if (t >= a.n) break;
     const double4 vi = a.xq[t];
     const int ti = uniform(a.ts[t]);
+    const bool lj_i = P32 ? a.ntypes > 0 : lj_row_nonzero(a, a.lj, ti);
     const int c = uniform(a.cs[t]);
     double f[3] = {0.0, 0.0, 0.0};
     int qn = 0;                                   // queued pairs (wave-uniform)
@@ -740,10 +751,11 @@ __device__ __forceinline__ void pairs_body(const RealArgs& a, int bx, int nbx) {
         PairLoad cur;
         if (from + lane < m) cur = pair_load(a, Q, from + lane, vi, l);
         if (P32)
-          pair_eval32<S>(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
-                      (float)a.alpha, Q.poly32, f, u32, w32);
+          pair_eval32(a, cur, from + lane < m, vi, ti, l, (float)sa, (float)two_sa_pi,
+                      (float)a.alpha, Q.poly32, lj_i, f, u32, w32);
         else
-          pair_eval<S>(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, Q.etab, f, u, w);
+          pair_eval<S>(a, cur, from + lane < m, vi, ti, l, sa, two_sa_pi, Q.poly, Q.etab, lj_i, f, u,
+                       w);
       }
       wave_sync();
       if (lane < qn - m) { Q.j[lane] = Q.j[m + lane]; Q.s[lane] = Q.s[m + lane]; }
@@ -943,8 +955,7 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
   if (threadIdx.x < (S ? kErfcxTermsS : kErfcxTerms))
     poly[threadIdx.x] = S ? kErfcxPolyS[threadIdx.x] : kErfcxPoly[threadIdx.x];
   if (threadIdx.x < 64) etab[threadIdx.x] = kExpTab[threadIdx.x];
-  if (threadIdx.x < (S ? kErfcxTermsS32 : kErfcxTerms32))
-    poly32[threadIdx.x] = S ? kErfcxPolyS32[threadIdx.x] : kErfcxPoly32[threadIdx.x];
+  if (threadIdx.x < kErfcxTerms32) poly32[threadIdx.x] = kErfcxPoly32[threadIdx.x];
   if (LJL)
     for (int q = threadIdx.x; q < 2 * a.ntypes * a.ntypes; q += blockDim.x) ljs[q] = a.lj[q];
   __syncthreads();
@@ -972,6 +983,7 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
     wave_sync();
     const double4 vi = vi_n;
     const int ti = uniform(ti_n);
+    const bool lj_i = P32 ? a.ntypes > 0 : lj_row_nonzero(a, LJL ? ljs : a.lj, ti);
     const int total = uniform(tot_n);
     if (k + 1 < nt) {
       vi_n = a.xc[t + 1]; ti_n = a.ts[t + 1]; tot_n = a.ncount[t + 1];
@@ -1007,13 +1019,13 @@ __device__ __forceinline__ void pairs_list_body(const RealArgs& a, int bx, int n
         p.tj = jc >> kListTypeShift;
         if (P32) {
           float gx, gy, gz;
-          pair_core32<S>(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, poly32,
-                      LJL ? ljs : a.lj, gx, gy, gz, u32, w32);
+          pair_core32(a, p, valid, vi, ti, (float)sa, (float)two_sa_pi, (float)a.alpha, poly32,
+                      LJL ? ljs : a.lj, lj_i, gx, gy, gz, u32, w32);
           fx32 += gx; fy32 += gy; fz32 += gz;
         } else {
           double gx, gy, gz;
-          pair_core<S>(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, LJL ? ljs : a.lj, gx, gy, gz, u,
-                    w);
+          pair_core<S>(a, p, valid, vi, ti, sa, two_sa_pi, poly, etab, LJL ? ljs : a.lj, lj_i, gx, gy,
+                       gz, u, w);
           fx += gx; fy += gy; fz += gz;
         }
       }

@@ -87,13 +87,11 @@ def test_erfcx_polynomial_of_the_pair_kernels():
         y32 = (y32 * t32 + c).astype(np.float32)
     assert np.max(np.abs(y32.astype(np.float64) / erfcx(x.astype(np.float32).astype(np.float64)) - 1.0)) < 2e-6
     # the bounded-range series (0 <= x <= XS, in u = (A x - K)/(x + K)) that
-    # the kernels take when g rc <= XS
+    # the FP64 kernels take when g rc <= XS
     XS = float(text.split("kErfcxShortX =")[1].split(";")[0])
     A = float(text.split("kErfcxShortA =")[1].split(";")[0])
     s64 = np.array(_header_array(text, "kErfcxPolyS"), dtype=np.float64)
-    s32 = np.array(_header_array(text, "kErfcxPolyS32"), dtype=np.float32)
     assert len(s64) == int(text.split("kErfcxTermsS =")[1].split(";")[0]) < len(c64)
-    assert len(s32) == int(text.split("kErfcxTermsS32 =")[1].split(";")[0]) < len(c32)
     x = np.concatenate([np.linspace(0.0, XS, 40001), np.geomspace(1e-8, 1.0, 2001)])
     u = (A * x - K) / (x + K)
     assert u.min() >= -1.0 and u.max() <= 1.0 + 1e-15
@@ -101,12 +99,6 @@ def test_erfcx_polynomial_of_the_pair_kernels():
     for c in s64[-2::-1]:
         y = y * u + c
     assert np.max(np.abs(y / erfcx(x) - 1.0)) < 4e-15
-    x32 = x.astype(np.float32)
-    u32 = ((np.float32(A) * x32 - np.float32(K)) / (x32 + np.float32(K))).astype(np.float32)
-    y32 = np.full_like(u32, s32[-1])
-    for c in s32[-2::-1]:
-        y32 = (y32 * u32 + c).astype(np.float32)
-    assert np.max(np.abs(y32.astype(np.float64) / erfcx(x32.astype(np.float64)) - 1.0)) < 2e-6
 
 
 def test_exponential_table_of_the_pair_kernels():
