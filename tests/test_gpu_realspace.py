@@ -118,6 +118,24 @@ def test_wide_splitting_takes_the_full_erfcx_series(gpu, precision, skin):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_splitting_at_the_bounded_series_range_end(gpu, precision):
+    # sqrt(alpha) rc = 4 exactly (rc = 8 = 2 L / 5, alpha = 0.25): the FP64
+    # kernels take the bounded-range erfcx series up to the end of its range
+    s = dict(workloads.make("electrolyte_1k"))
+    s["alpha"] = 0.25
+    assert np.sqrt(s["alpha"]) * 8.0 == 4.0
+    g = run_gpu(s, gpu, 8.0, precision=precision)
+    o = oracle(s, 8.0)
+    print("g rc = 4 %s: force %.2e virial %.2e energy %.2e" %
+          (precision, rel(g["forces"], o["forces"]), rel(g["virial"], o["virial"]),
+           abs(g["energy"] - o["energy"]) / abs(o["energy"])))
+    tol = TOLR[precision]
+    assert rel(g["forces"], o["forces"]) < tol
+    assert rel(g["virial"], o["virial"]) < tol
+    assert abs(g["energy"] - o["energy"]) < tol * abs(o["energy"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_water_with_lj(gpu, precision):
     s = workloads.water(1000, seed=7)
     s.update(alpha=0.09, coulomb=332.0637)
