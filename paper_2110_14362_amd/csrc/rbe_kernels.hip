@@ -93,8 +93,22 @@ constexpr int kTableTasks = 6;     // (axis, table) pairs of build_tables, one w
 // same m without m = 0.  One wave per (axis, table); a lane owns a contiguous
 // segment, the lane totals are scanned across the wave.  Writes the cell
 // values to *out (LDS).  Must be reached by every thread of the block.
+// Without the closing barrier the cell values other than the sides, V and
+// the half-widths (written before the tables' barrier when the block has a
+// wave without a table task) are not yet visible to the other threads.
+// The weights of the nonzero event split by its first nonzero axis, from the
+// per-axis totals T = H - 1 of the m != 0 tables (one expression for every
+// caller, so that all of them form the same values).
+__device__ __forceinline__ void case_weights(const double* T, double cw[3]) {
+  const double Hy = 1.0 + T[1], Hz = 1.0 + T[2];
+  cw[0] = T[0] * Hy * Hz;
+  cw[1] = T[1] * Hz;
+  cw[2] = T[2];
+}
+
 __device__ void build_tables(const double l[3], const TriCell* tcp, double alpha, double tail_ln,
-                             const int mcap[3], double* tab, BoxState* out, double* sh_T, int nt) {
+                             const int mcap[3], double* tab, BoxState* out, double* sh_T, int nt,
+                             bool closing_barrier) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int nw = nt / kWave;
   int err = 0, mc[3], off[3];
@@ -117,14 +131,14 @@ __device__ void build_tables(const double l[3], const TriCell* tcp, double alpha
     const int a = task >> 1, nz = task & 1;
     const int n = nz ? 2 * mc[a] : 2 * mc[a] + 1;
     double* t = tab + off[a] + (nz ? 2 * mc[a] + 1 : 0);
-    const double den = alpha * l[a] * l[a];
+    const double c = -pi2 / (alpha * l[a] * l[a]);   // w(m) = exp(c m^2)
     const int seg = (n + kWave - 1) / kWave;
     const int b0 = min(n, lane * seg), b1 = min(n, b0 + seg);
     double loc = 0.0;
     for (int i = b0; i < b1; ++i) {
       const int m = nz ? (i < mc[a] ? i - mc[a] : i - mc[a] + 1) : i - mc[a];
       const double w = tri ? exp(-(tc.d[a] * ((double)m * (double)m)))
-                           : exp(-(pi2 * ((double)m * (double)m)) / den);
+                           : exp(c * ((double)m * (double)m));
       t[i] = w;
       loc += w;
     }
@@ -137,17 +151,23 @@ __device__ void build_tables(const double l[3], const TriCell* tcp, double alpha
     }
     if (nz && lane == kWave - 1) sh_T[a] = incl;
   }
+  // the cell values that do not need the tables (sides, their reciprocals,
+  // half-widths, V): written before the barrier by the first lane of a wave
+  // without a table task when the block has one, else after it by thread 0
+  const int early = nw > kTableTasks ? kTableTasks * kWave : 0;
+  auto sides = [&](BoxState& b) {
+    for (int a = 0; a < 3; ++a) { b.l[a] = l[a]; b.inv_l[a] = 1.0 / l[a]; b.mcut[a] = mc[a]; }
+    b.V = l[0] * l[1] * l[2];
+  };
+  if (early > 0 && (int)threadIdx.x == early) sides(*out);
   lds_barrier();
   if (threadIdx.x == 0) {
     const double Tx = sh_T[0], Ty = sh_T[1], Tz = sh_T[2];
     const double Hx = 1.0 + Tx, Hy = 1.0 + Ty, Hz = 1.0 + Tz;
     BoxState& b = *out;
-    for (int a = 0; a < 3; ++a) { b.l[a] = l[a]; b.inv_l[a] = 1.0 / l[a]; b.mcut[a] = mc[a]; }
-    b.V = l[0] * l[1] * l[2];
+    if (early == 0) sides(b);
     b.H[0] = Hx; b.H[1] = Hy; b.H[2] = Hz;
-    b.case_w[0] = Tx * Hy * Hz;
-    b.case_w[1] = Ty * Hz;
-    b.case_w[2] = Tz;
+    case_weights(sh_T, b.case_w);
     b.S = b.case_w[0] + b.case_w[1] + b.case_w[2];
     b.err = err;
     if (tri) {
@@ -157,7 +177,7 @@ __device__ void build_tables(const double l[3], const TriCell* tcp, double alpha
       b.tri.on = 0;
     }
   }
-  lds_barrier();
+  if (closing_barrier) lds_barrier();
 }
 
 __device__ __forceinline__ int first_greater(const double* c, int n, double t) {
@@ -178,8 +198,11 @@ __device__ __forceinline__ int first_greater(const double* c, int n, double t) {
 // the table total; the three axes' binary searches run in lockstep.
 // propose_from draws from the four Philox outputs c0..c3 given;
 // propose_frequency forms them for attempt `attempt` first.
+// cw: the case weights, if not b's
 __device__ __forceinline__ void propose_from(const BoxState& b, const double* tab, uint64_t c0,
-                                             uint64_t c1, uint64_t c2, uint64_t c3, int m[3]) {
+                                             uint64_t c1, uint64_t c2, uint64_t c3, int m[3],
+                                             const double* cw = nullptr) {
+  const double* w = cw ? cw : b.case_w;
   int off[3];
   table_offsets(b.mcut, off);
   const double u[4] = {(double)(c0 >> 11) * 0x1.0p-53, (double)(c1 >> 11) * 0x1.0p-53,
@@ -192,8 +215,8 @@ __device__ __forceinline__ void propose_from(const BoxState& b, const double* ta
     tot_full[a] = tab[off[a] + 2 * b.mcut[a]];
     tot_nz[a] = tab[off[a] + 4 * b.mcut[a]];
   }
-  const double t = u[0] * (b.case_w[0] + b.case_w[1] + b.case_w[2]);
-  const int pivot = (t < b.case_w[0]) ? 0 : ((t < b.case_w[0] + b.case_w[1]) ? 1 : 2);
+  const double t = u[0] * (w[0] + w[1] + w[2]);
+  const int pivot = (t < w[0]) ? 0 : ((t < w[0] + w[1]) ? 1 : 2);
   const double* base[3];
   int lo[3], hi[3];
   double tgt[3];
@@ -239,10 +262,11 @@ __device__ __forceinline__ void propose_from(const BoxState& b, const double* ta
 
 __device__ __forceinline__ void propose_frequency(const BoxState& b, const double* tab, uint64_t seed,
                                                   uint64_t sysid, uint64_t step, int l,
-                                                  uint64_t attempt, int m[3]) {
+                                                  uint64_t attempt, int m[3],
+                                                  const double* cw = nullptr) {
   uint64_t c[4] = {step, (uint64_t)l, kTagKSample, attempt};
   philox4x64_10(c, seed, sysid);
-  propose_from(b, tab, c[0], c[1], c[2], c[3], m);
+  propose_from(b, tab, c[0], c[1], c[2], c[3], m, cw);
 }
 
 constexpr uint64_t kTagKAccept = 0x6B616363ull;  // 'kacc': acceptance uniforms, triclinic draws
@@ -263,12 +287,14 @@ constexpr int kMaxAttempts = 256;
 template <bool TRI>
 __device__ __forceinline__ void draw_frequency(const BoxState& b, const double* tab, uint64_t seed,
                                                uint64_t sysid, uint64_t step, int l, int m[3],
-                                               const uint64_t* pre = nullptr, int pre_stride = 0) {
+                                               const uint64_t* pre = nullptr, int pre_stride = 0,
+                                               const double* cw = nullptr) {
   for (int att = 0; att < kMaxAttempts; ++att) {
     if (att == 0 && pre)        // the same Philox outputs, formed ahead
-      propose_from(b, tab, pre[0], pre[pre_stride], pre[2 * pre_stride], pre[3 * pre_stride], m);
+      propose_from(b, tab, pre[0], pre[pre_stride], pre[2 * pre_stride], pre[3 * pre_stride], m,
+                   cw);
     else
-      propose_frequency(b, tab, seed, sysid, step, l, (uint64_t)att, m);
+      propose_frequency(b, tab, seed, sysid, step, l, (uint64_t)att, m, cw);
     if (!TRI) return;
     const double x = m[0], y = m[1], z = m[2];
     const double* A = b.tri.A;
@@ -569,7 +595,7 @@ __global__ void __launch_bounds__(256) k_tables(StepArgs a) {
   double l[3];
   const TriCell* tc = stage_tri(a, &stc);
   box_source(a, l);
-  build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T, 256);
+  build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, a.tab, &sbs, sh_T, 256, true);
   commit_cell(sbs, a.bs, threadIdx.x);
 }
 
@@ -897,7 +923,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     if (y != 0) return;
     double l[3];
     box_source(a, l);
-    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads);
+    build_tables(l, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads, true);
     const uint64_t next = a.step + 1;
     const int slot = (int)(next & 1);
     int32_t* mp = a.m_pre + (int64_t)slot * 3 * a.p;
@@ -952,6 +978,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
   // ---- cell values and tables; the slice's Philox outputs beside them, in
   // R0 (free until the tile is stored)
   const bool need_tables = !pre && (a.sample || a.box_src != BOX_COMMITTED);
+  double cw[3] = {0.0, 0.0, 0.0};   // case weights for this block's draws
   const int64_t slice = (int64_t)y * FB;
   const bool su_on = a.sample && !pre && (size_t)FB * 4 * sizeof(uint64_t) <= kR0;
   uint64_t* su = reinterpret_cast<uint64_t*>(base);
@@ -959,8 +986,15 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     if (x == 0 && y == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else if (need_tables) {
     if (su_on) slice_uniforms(su, FB, slice, a.p, a.seed, a.sysid, a.step, kSfacThreads);
-    build_tables(lc, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads);
-    if (x == 0 && y == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
+    // the draw needs only the half-widths (visible after the tables'
+    // barrier) and the case weights, formed here from the tables' totals, so
+    // the block skips the closing barrier unless it commits the cell
+    const bool commit = x == 0 && y == 0 && a.box_src != BOX_COMMITTED;
+    const bool own_cw = !TRI && kSfacThreads / kWave > kTableTasks && !commit;
+    build_tables(lc, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads, !own_cw);
+    if (own_cw) case_weights(sh_T, cw);
+    else { cw[0] = sbs.case_w[0]; cw[1] = sbs.case_w[1]; cw[2] = sbs.case_w[2]; }
+    if (commit) commit_cell(sbs, a.bs, tid);
   } else {
     load_box(sbs, a.bs, tid);
     lds_barrier();
@@ -975,7 +1009,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
       int mv[3] = {0, 0, 0};
       if (l < a.p) {
         draw_frequency<TRI>(sbs, tabs, a.seed, a.sysid, a.step, (int)l, mv,
-                            su_on ? su + s2 : nullptr, FB);
+                            su_on ? su + s2 : nullptr, FB, cw);
         if (x == 0) { a.m[3 * l] = mv[0]; a.m[3 * l + 1] = mv[1]; a.m[3 * l + 2] = mv[2]; }
       }
       sm[3 * s2] = mv[0]; sm[3 * s2 + 1] = mv[1]; sm[3 * s2 + 2] = mv[2];
@@ -1601,7 +1635,7 @@ __global__ void __launch_bounds__(kSfacThreads) k_step(StepArgs a) {
   uint64_t* su = reinterpret_cast<uint64_t*>(tile);
   if (a.sample || a.box_src != BOX_COMMITTED) {
     if (su_on) slice_uniforms(su, FB, 0, a.p, a.seed, a.sysid, a.step, kSfacThreads);
-    build_tables(lc, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads);
+    build_tables(lc, tc, a.alpha, a.tail_ln, a.mcap, tabs, &sbs, sh_T, kSfacThreads, true);
     if (x == 0 && a.box_src != BOX_COMMITTED) commit_cell(sbs, a.bs, tid);
   } else {
     load_box(sbs, a.bs, tid);
