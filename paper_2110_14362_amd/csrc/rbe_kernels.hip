@@ -960,15 +960,17 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
 
   // ---- batch drawn ahead: usable when its step and cell equal this call's
   const int pslot = (int)(a.step & 1);
-  if (tid == 0) {
-    int ok = 0;
-    if (a.sample && a.use_pre && a.pre[pslot].valid && a.pre[pslot].step == a.step) {
-      ok = same_cell(a, a.pre[pslot].bs) ? 1 : 0;
+  // (no check, and no barrier, when the host has ruled the batch out)
+  bool pre = false;
+  if (a.sample && a.use_pre) {
+    if (tid == 0) {
+      int ok = 0;
+      if (a.pre[pslot].valid && a.pre[pslot].step == a.step) ok = same_cell(a, a.pre[pslot].bs) ? 1 : 0;
+      sh_flag = ok;
     }
-    sh_flag = ok;
+    lds_barrier();
+    pre = sh_flag != 0;
   }
-  lds_barrier();
-  const bool pre = sh_flag != 0;
   if (pre) {
     load_box(sbs, &a.pre[pslot].bs, tid);
     lds_barrier();
@@ -1051,7 +1053,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
       const int cnt = (int)min((int64_t)kTile, c1 - t0);
       const int cntp = (cnt + runlen - 1) / runlen * runlen;
-      lds_barrier();
+      if (t0 != c0) lds_barrier();     // the first tile: the barrier after the draw
       for (int j = tid; j < cntp; j += kSfacThreads) {
         float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j < cnt) {
@@ -1086,7 +1088,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     for (int64_t t0 = c0; t0 < c1; t0 += kTile) {
       const int cnt = (int)min((int64_t)kTile, c1 - t0);
       const int cntp = (cnt + SUB - 1) / SUB * SUB;
-      lds_barrier();
+      if (t0 != c0) lds_barrier();     // the first tile: the barrier after the draw
       for (int j = tid; j < cntp; j += kSfacThreads) {
         double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
         if (j < cnt) {
