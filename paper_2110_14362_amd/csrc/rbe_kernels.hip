@@ -877,26 +877,31 @@ __device__ __forceinline__ void sfac_tile64(const double2* tA, const double2* tB
 }
 
 // Block partial of rho: the SUB particle sub-slices of every frequency slot
-// summed in order (through red, kSfacThreads entries of LDS) and stored with
-// coherent stores to dst[slot] (slot = kg*64R + r*64 + lane).  Reached by
-// every thread.
-template <int R>
+// summed in order (through red, G x kSfacThreads entries of LDS: G of the R
+// parts per pair of barriers) and stored with coherent stores to dst[slot]
+// (slot = kg*64R + r*64 + lane).  Reached by every thread.
+template <int R, int G = 1>
 __device__ __forceinline__ void store_block_partial(const double2 (&part)[R], double2* red, int KB,
                                                     int SUB, double2* dst) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
+  for (int r0 = 0; r0 < R; r0 += G) {
     lds_barrier();
-    red[tid] = part[r];
+#pragma unroll
+    for (int r = r0; r < r0 + G && r < R; ++r) red[(r - r0) * kSfacThreads + tid] = part[r];
     lds_barrier();
     if (tid < KB * kWave) {                // (kg', lane') = (tid / 64, tid % 64)
-      double2 s2 = make_double2(0.0, 0.0);
-      for (int sb = 0; sb < SUB; ++sb) {   // wave = sb*KB + kg'  ->  index sb*KB*64 + tid
-        const double2 v = red[sb * KB * kWave + tid];
-        s2.x += v.x; s2.y += v.y;
+#pragma unroll
+      for (int r = r0; r < r0 + G && r < R; ++r) {
+        const double2* rr = red + (r - r0) * kSfacThreads;
+        double2 s2 = make_double2(0.0, 0.0);
+        for (int sb = 0; sb < SUB; ++sb) { // wave = sb*KB + kg'  ->  index sb*KB*64 + tid
+          const double2 v = rr[sb * KB * kWave + tid];
+          s2.x += v.x; s2.y += v.y;
+        }
+        const int sl = (tid / kWave) * kWave * R + r * kWave + (tid % kWave);
+        st_coh2(dst + sl, s2);
       }
-      const int sl = (tid / kWave) * kWave * R + r * kWave + (tid % kWave);
-      st_coh2(dst + sl, s2);
     }
   }
 }
@@ -1111,7 +1116,8 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
 
   // ---- block partial: sum the SUB particle sub-slices, in order, per slot
   double2* red = reinterpret_cast<double2*>(base);          // kSfacThreads entries (R0)
-  store_block_partial<R>(part, red, KB, SUB, a.partial + (int64_t)x * a.Ppad + slice);
+  static_assert(2 * kSfacThreads * sizeof(double2) <= kR0, "two parts per pass in R0");
+  store_block_partial<R, 2>(part, red, KB, SUB, a.partial + (int64_t)x * a.Ppad + slice);
 
   // ---- level 1: the last block of each chunk group sums the group's partials
   const int g = x / a.GX;
