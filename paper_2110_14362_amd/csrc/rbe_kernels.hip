@@ -1444,8 +1444,10 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
       }
     }
   }
-  // cross-wave (k-slice) sums, fixed order, then -q_i times the sum
-  lds_barrier();                          // scratch / srho in red_raw are dead
+  // cross-wave (k-slice) sums, fixed order, then -q_i times the sum.  With the
+  // rows summed here, scratch and srho (in red_raw) were last read before the
+  // barrier that published the constants; otherwise wait until they are dead.
+  if (!k2red) lds_barrier();
   float* redf = reinterpret_cast<float*>(red_raw);
   double* redd = reinterpret_cast<double*>(red_raw);
 #pragma unroll
