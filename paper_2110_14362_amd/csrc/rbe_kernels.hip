@@ -692,7 +692,9 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter, uint32_t total, i
 // blocks of the same launch), else plainly (rows of an earlier launch, which
 // the L2 may then serve to several blocks); dst is written with coherent
 // stores when dst_coh, else plainly (LDS).  Reached by every thread;
-// scratch holds nt entries (nt = the block's threads).
+// scratch holds nt entries (nt = the block's threads); scratch_free: no
+// thread reads scratch any more (nothing has used it yet, or a barrier has
+// passed since), so the barrier before it is written is skipped.
 template <bool SrcCoh = true>
 __device__ __forceinline__ double2 ld_row(const double2* p) {
   return SrcCoh ? ld_coh2(p) : *p;
@@ -700,7 +702,7 @@ __device__ __forceinline__ double2 ld_row(const double2* p) {
 
 template <bool SrcCoh = true, int kB = 8>
 __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W, double2* dst,
-                               bool dst_coh, double2* scratch, int nt) {
+                               bool dst_coh, double2* scratch, int nt, bool scratch_free = false) {
   // rows r0, r0 + step, ... (< R) of column col added in that order; loads
   // issued kB at a time (independent, all in flight) before the adds
   auto column_sum = [&](int col, int r0, int step) {
@@ -729,7 +731,7 @@ __device__ void block_sum_rows(const double2* src, int64_t stride, int R, int W,
   const int RG = nt / W;
   const int col = t % W, rg = t / W;
   const double2 acc = column_sum(col, rg, RG);
-  lds_barrier();
+  if (!scratch_free) lds_barrier();      // scratch's earlier readers are done
   scratch[t] = acc;
   lds_barrier();
   if (t < W) {
@@ -1126,7 +1128,7 @@ __device__ __forceinline__ void sfac_body(const StepArgs& a, const int x, const 
     if (!arrive_last(a.cnt + cnt_index(a, CNT_GROUP, y * a.NG + g), (uint32_t)gsize, &sh_flag))
       return;
     block_sum_rows(a.partial + (int64_t)g * a.GX * a.Ppad + slice, a.Ppad, gsize, FB,
-                   a.gpart + (int64_t)g * a.Ppad + slice, true, red, kSfacThreads);
+                   a.gpart + (int64_t)g * a.Ppad + slice, true, red, kSfacThreads, true);
     if (tid == 0) a.cnt[cnt_index(a, CNT_GROUP, y * a.NG + g)] = 0u;
   }
 
@@ -1350,7 +1352,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
   if (k2red && tid < a.p) { mf[0] = a.m[3 * tid]; mf[1] = a.m[3 * tid + 1]; mf[2] = a.m[3 * tid + 2]; }
 
   if (extra) {
-    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt);
+    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt, true);
     if (tid < kBoxWords) reinterpret_cast<uint64_t*>(&sbs)[tid] = bw;
     lds_barrier();
     double tv[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1380,7 +1382,7 @@ __device__ __forceinline__ void force_body(const StepArgs& a, const int bx, cons
     if (i < a.n) { xi[r] = a.x[i]; yi[r] = a.y[i]; zi[r] = a.z[i]; }
   }
   if (k2red) {
-    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt);
+    block_sum_rows<false>(rows, a.Ppad, Rr, a.Ppad, srho, false, scratch, nt, true);
     if (tid < kBoxWords) reinterpret_cast<uint64_t*>(&sbs)[tid] = bw;
     lds_barrier();
     for (int l = tid; l < a.p; l += nt) {
